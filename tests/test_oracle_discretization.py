@@ -1,0 +1,113 @@
+"""Pins of the oracle's matrix entries against closed forms (CPU).
+
+These fix the kernels, the column weighting and the diagonal rules of oracle.green
+independently of the oracle's own code: each expected value is a fact of potential
+theory on a circle or sphere, not a re-evaluation of the same formula.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Problem, dense
+
+
+def _sl2(g):
+    return Problem("lap2d_sl", g.points, g.weights)
+
+
+def _dl2(g, c=-0.5):
+    return Problem("lap2d_dl", g.points, g.weights, g.normals, g.curvature, identity=c)
+
+
+@pytest.mark.parametrize("n", [64, 333, 1024])
+def test_unit_circle_double_layer_closed_form(n):
+    # On the unit circle (x-y).nu_y / |x-y|^2 = -1/2 for every pair, so with the
+    # curvature diagonal the interior equation matrix is -1/2 I - (1/2N) 1 1^T exactly.
+    g = W.circle(n)
+    A = dense.matrix(_dl2(g))
+    expect = -0.5 * np.eye(n) - np.ones((n, n)) / (2 * n)
+    assert np.abs(A - expect).max() < 1e-14
+
+
+def test_double_layer_gauss_lemma_on_star():
+    # Gauss: the double-layer potential of a unit density is -1/2 on the boundary.
+    g = W.star_curve(1024)
+    A = dense.matrix(_dl2(g, c=0.0))
+    assert np.abs(A.sum(axis=1) + 0.5).max() < 1e-12
+
+
+def test_double_layer_gauss_lemma_on_ellipse():
+    g = W.ellipse(1024)
+    A = dense.matrix(_dl2(g, c=0.0))
+    assert np.abs(A.sum(axis=1) + 0.5).max() < 1e-12
+
+
+def test_unit_circle_single_layer_constant_mode_exact():
+    # The log single layer annihilates constants on the unit circle; the diagonal rule
+    # is the one that makes the equispaced sum exact for that mode.
+    for n in (100, 1024):
+        A = dense.matrix(_sl2(W.circle(n)))
+        assert np.abs(A @ np.ones(n)).max() < 1e-14
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 10])
+def test_unit_circle_single_layer_eigenvalues(m):
+    # S[cos m t] = cos(m t) / (2m) on the unit circle; third-order convergence.
+    errs = []
+    for n in (256, 1024):
+        A = dense.matrix(_sl2(W.circle(n)))
+        t = 2 * np.pi * np.arange(n) / n
+        v = np.cos(m * t)
+        errs.append(np.abs(A @ v - v / (2 * m)).max())
+    assert errs[1] < 1e-6
+    assert errs[0] / errs[1] > 30.0          # ~ 4^3
+
+
+def test_single_layer_sign_and_scale_off_circle():
+    # On a circle of radius R the constant mode has eigenvalue -R log R (log kernel).
+    R = 0.5
+    n = 512
+    A = dense.matrix(_sl2(W.circle(n, radius=R)))
+    assert np.abs(A @ np.ones(n) - (-R * np.log(R))).max() < 1e-12
+
+
+def test_sphere_single_layer_constant_and_dipole():
+    # On the unit sphere S[1] = 1 and S[Y_1] = Y_1 / 3; first-order in the mesh size
+    # with the flat-disc diagonal.
+    errs1, errsy = [], []
+    for n in (512, 2048):
+        g = W.fibonacci_sphere(n)
+        A = dense.matrix(Problem("lap3d_sl", g.points, g.weights))
+        z = g.points[:, 2]
+        errs1.append(np.abs(A.sum(axis=1) - 1.0).max())
+        errsy.append(np.abs(A @ z - z / 3.0).max())
+    assert errs1[1] < 3e-3 and errsy[1] < 3e-3
+    assert errs1[0] / errs1[1] > 1.8 and errsy[0] / errsy[1] > 1.8
+
+
+def test_nystrom_weights_on_columns():
+    # A_ij = K(x_i, x_j) w_j: scaling one weight scales exactly one column.
+    g = W.star_curve(64)
+    p = _sl2(g)
+    A = dense.matrix(p)
+    w2 = g.weights.copy()
+    w2[7] *= 3.0
+    A2 = dense.matrix(Problem("lap2d_sl", g.points, w2))
+    off = np.ones(64, dtype=bool)
+    off[7] = False
+    assert np.allclose(A2[off, 7], 3.0 * A[off, 7], rtol=1e-15, atol=0)
+    assert np.array_equal(np.delete(A2, 7, axis=1), np.delete(A, 7, axis=1))
+
+
+def test_curve_generators_closed_forms():
+    # Circle of radius 1: weights 2 pi / N, curvature 1, normal = position.
+    g = W.circle(37)
+    assert np.allclose(g.weights, 2 * np.pi / 37, rtol=1e-15)
+    assert np.allclose(g.curvature, 1.0, rtol=1e-14)
+    assert np.allclose(g.normals, g.points, atol=1e-15)
+    # Star: total length by the trapezoid rule converges spectrally; area via normals.
+    s = W.star_curve(4096)
+    area = 0.5 * np.sum(np.sum(s.points * s.normals, axis=1) * s.weights)
+    assert abs(area - np.pi * (1 + 0.3 ** 2 / 2)) < 1e-12
+    # Total curvature of a simple closed curve is 2 pi.
+    assert abs(np.sum(s.curvature * s.weights) - 2 * np.pi) < 1e-10

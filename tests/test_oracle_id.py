@@ -1,0 +1,113 @@
+"""Pins of the oracle's interpolative decomposition (CPU).
+
+Checked against what the mathematics fixes: the exact column-residual bound of
+column-pivoted QR, exact recovery of low-rank matrices, LAPACK's pivoted QR
+(geqp3, via scipy) on untied inputs, and the singular-value bracket of an ID.
+"""
+import numpy as np
+import pytest
+from scipy.linalg import qr, svdvals
+
+from oracle.interp import cpqr_id
+
+
+def _lowrank(m, n, q, rng, decay=None):
+    U, _ = np.linalg.qr(rng.standard_normal((m, q)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, q)))
+    s = np.ones(q) if decay is None else decay ** np.arange(q)
+    return (U * s) @ V.T
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_residual_columns_bounded_by_next_pivot(seed):
+    # After k steps, M[:, r] - M[:, s] T = Q [0; R22], whose column norms are bounded
+    # by the largest remaining column norm |R_{k+1,k+1}| <= eps |R_00|.
+    rng = np.random.default_rng(seed)
+    M = _lowrank(80, 50, 50, rng, decay=0.6)
+    eps = 1e-7
+    idr = cpqr_id(M, eps)
+    assert 0 < idr.k < 50
+    res = M[:, idr.redund] - M[:, idr.skel] @ idr.T
+    bound = idr.rdiag[idr.k]
+    assert np.all(np.linalg.norm(res, axis=0) <= bound * (1 + 1e-10) + 1e-14)
+    assert bound <= eps * idr.rdiag[0]
+    assert idr.rdiag[idr.k - 1] > eps * idr.rdiag[0]
+
+
+def test_rdiag_nonincreasing_and_skeleton_columns_exact():
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((60, 40)) @ np.diag(0.8 ** np.arange(40))
+    idr = cpqr_id(M, 1e-9)
+    assert np.all(np.diff(idr.rdiag) <= 1e-12 * idr.rdiag[0])
+    # the projection matrix P holds the identity on the skeleton columns
+    P = np.zeros((idr.k, 40))
+    P[:, idr.skel] = np.eye(idr.k)
+    P[:, idr.redund] = idr.T
+    approx = M[:, idr.skel] @ P
+    assert np.array_equal(approx[:, idr.skel], M[:, idr.skel])
+
+
+@pytest.mark.parametrize("q", [1, 5, 17])
+def test_exact_low_rank_recovered(q):
+    rng = np.random.default_rng(q)
+    M = _lowrank(70, 45, q, rng)
+    idr = cpqr_id(M, 1e-12)
+    assert idr.k == q
+    res = M[:, idr.redund] - M[:, idr.skel] @ idr.T
+    assert np.abs(res).max() < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_pivots_match_lapack_geqp3(seed):
+    rng = np.random.default_rng(100 + seed)
+    M = rng.standard_normal((50, 30)) * (0.7 ** np.arange(30))[None, :]
+    idr = cpqr_id(M, 0.0)
+    _, R, piv = qr(M, pivoting=True, mode="economic")
+    assert idr.k == 30
+    assert list(idr.pivots) == list(piv)
+    assert np.allclose(idr.rdiag[:30], np.abs(np.diag(R)), rtol=1e-12)
+
+
+def test_id_error_bracketed_by_singular_values():
+    # ||M - M_s P|| >= sigma_{k+1} always, and is within a modest factor of it.
+    rng = np.random.default_rng(3)
+    M = _lowrank(100, 60, 60, rng, decay=0.5)
+    idr = cpqr_id(M, 1e-6)
+    P = np.zeros((idr.k, 60))
+    P[:, idr.skel] = np.eye(idr.k)
+    P[:, idr.redund] = idr.T
+    err = np.linalg.norm(M - M[:, idr.skel] @ P, 2)
+    sv = svdvals(M)
+    assert err >= sv[idr.k] * (1 - 1e-8)
+    assert err <= 50 * sv[idr.k]
+
+
+def test_degenerate_inputs():
+    z = cpqr_id(np.zeros((10, 4)), 1e-9)
+    assert z.k == 0 and z.T.shape == (0, 4) and list(z.redund) == [0, 1, 2, 3]
+    e = cpqr_id(np.eye(4), 0.0)
+    assert e.k == 4 and e.T.shape == (4, 0)
+    # wide matrix: rank limited by the row count
+    w = cpqr_id(np.random.default_rng(0).standard_normal((3, 8)), 0.0)
+    assert w.k == 3
+
+
+def test_exact_ties_break_to_lowest_original_index():
+    M = np.zeros((4, 3))
+    M[0, 2] = 2.0
+    M[1, 0] = 2.0
+    M[2, 1] = 1.0
+    idr = cpqr_id(M, 0.0)
+    assert list(idr.pivots[:2]) == [0, 2]
+    assert idr.first_tie == 0
+
+
+def test_complex_id():
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((40, 10)) + 1j * rng.standard_normal((40, 10))
+    Y = rng.standard_normal((10, 30)) + 1j * rng.standard_normal((10, 30))
+    A = X @ Y
+    idr = cpqr_id(A, 1e-12)
+    assert idr.k == 10
+    res = A[:, idr.redund] - A[:, idr.skel] @ idr.T
+    assert np.abs(res).max() < 1e-13 * np.abs(A).max()
