@@ -1,0 +1,187 @@
+/*
+ * rs.h -- C ABI of the MI355X recursive-skeletonization solver.
+ *
+ * Method: K. L. Ho and L. Greengard, "A fast direct solver for structured linear
+ * systems by recursive skeletonization".  Given nodes x_i, quadrature weights w_i
+ * and a Green's function K, the library builds the Nystrom system
+ *     A_ij = c delta_ij + K(x_i, x_j) w_j      (Section 2, Section 6.2)
+ * compresses it level by level over a quadtree/octree with proxy surfaces and
+ * interpolative decompositions (Sections 2.2, 3.1, 3.2), factors the compressed
+ * inverse (Section 3.4, eq. (multilevel-inverse)), and applies it to right-hand
+ * sides (the solution phase of Section 3.4).  All arithmetic is IEEE binary64.
+ *
+ * Conventions shared by every entry point
+ *   - Indices are 0-based.  Point arrays are point-major: x0,y0[,z0],x1,... in the
+ *     caller's order; the tree permutation is internal.
+ *   - "host" pointers are read during the call only; the caller keeps ownership and
+ *     may free them on return.  "device" pointers are HIP device memory on the
+ *     current device; the library reads/writes them in stream order.
+ *   - Every call returns rs_status; no C++ exception crosses this boundary.  On
+ *     error, outputs are left untouched and rs_last_error() (thread-local) holds a
+ *     message; for RS_ESINGULAR it names the tree depth and box.
+ *   - Trees and factor handles are opaque and owned by the library until
+ *     rs_tree_free / rs_free.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RS_OK = 0,
+  RS_EINVAL = 1,     /* bad argument: NULL, n < 1, non-finite data, eps < 0, ... */
+  RS_ENOMEM = 2,     /* device or host allocation failed */
+  RS_ESINGULAR = 3,  /* zero or non-finite pivot in a box or root elimination */
+  RS_EDEVICE = 4,    /* HIP runtime error, or no device */
+  RS_EBUSY = 5,      /* the object is in use by queued work */
+  RS_ENOTSUP = 6     /* kernel / dimension combination not built */
+} rs_status;
+
+/* Green's functions (Section 2.1 eqs. (2d-laplace), (3d-laplace), (double-layer);
+ * Section 6.1 eq. (2d-helmholtz)). */
+typedef enum {
+  RS_LAP2D_SL = 1,   /* -(1/2pi) log|x-y|,  dim 2 */
+  RS_LAP2D_DL = 2,   /* (x-y).nu_y / (2pi |x-y|^2), dim 2, needs normals + curvature */
+  RS_LAP3D_SL = 3,   /* 1/(4pi |x-y|), dim 3 */
+  RS_HELM2D_CFIE = 4 /* combined field, complex128: reserved, returns RS_ENOTSUP */
+} rs_kernel_kind;
+
+/* Kernel description.  The diagonal entries A_ii follow a per-kernel rule:
+ *   LAP2D_SL: c - (w_i/2pi) log(w_i/2pi);   LAP2D_DL: c - kappa_i w_i/(4pi);
+ *   LAP3D_SL: c + sqrt(w_i/pi)/2. */
+typedef struct {
+  int32_t kind;             /* rs_kernel_kind */
+  int32_t dim;              /* 2 or 3, must match kind */
+  double identity;          /* c: -0.5 for the interior double-layer equation
+                               (eq. (2k-integral-eqn)), 0 for first kind */
+  double wavenumber;        /* Helmholtz only (unused otherwise) */
+  double eta;               /* Helmholtz only (unused otherwise) */
+  const double *normals;    /* host, N x dim, caller order; DL kinds, else NULL */
+  const double *curvature;  /* host, N, caller order; LAP2D_DL, else NULL */
+  int32_t proxy_points;     /* proxy-surface points per box (Section 3.2), >= 8 */
+  double proxy_ratio;       /* proxy radius / box side; > 0.5*sqrt(dim), e.g. 1.5 */
+} rs_kernel;
+
+typedef struct rs_tree_s *rs_tree;
+typedef struct rs_factor_s *rs_handle;
+
+/* Launch organisation of the factor and solve passes. */
+typedef enum {
+  RS_LAUNCH_LEVEL = 0,   /* one launch per kernel per tree level, all boxes of the
+                            level (and of every problem of a batch) together */
+  RS_LAUNCH_PER_BOX = 1  /* the same kernels launched once per box (reference path) */
+} rs_launch_mode;
+
+typedef struct {
+  int32_t launch_mode;   /* rs_launch_mode */
+  void *stream;          /* hipStream_t for all work of the call; NULL = default */
+} rs_options;
+
+/* ---------------------------------------------------------------- tree ---- */
+
+/* Quadtree (dim 2) / octree (dim 3) over n points (Section 2.1; tree rule of
+ * Section 6: uniform subdivision of the bounding square/cube until a box holds
+ * at most leaf_size points, empty boxes dropped).  points: host, n x dim.
+ * Root = bounding box (centre (lo+hi)/2, side max extent); child code bit a set
+ * iff x_a >= centre_a; children in code order; stable order inside a child;
+ * boxes numbered breadth-first.  Errors: RS_EINVAL (dim not 2/3, n < 1,
+ * leaf_size < 1, non-finite coordinate), RS_ENOMEM. */
+rs_status rs_build_tree(int32_t dim, int64_t n, const double *points, int32_t leaf_size,
+                        rs_tree *out);
+
+/* Box count and maximum depth of a tree. */
+rs_status rs_tree_info(rs_tree t, int64_t *nbox, int32_t *maxdepth);
+
+/* Copies the tree into caller arrays (host; any may be NULL to skip):
+ * perm[n] (tree position i holds caller point perm[i]), depth/parent/begin/end
+ * [nbox] (parent -1 at the root; [begin,end) tree positions), center[nbox*dim],
+ * side[nbox]. */
+rs_status rs_tree_export(rs_tree t, int64_t *perm, int32_t *depth, int32_t *parent,
+                         int64_t *begin, int64_t *end, double *center, double *side);
+
+void rs_tree_free(rs_tree t);
+
+/* -------------------------------------------------------------- factor ---- */
+
+/* Compression + factorization (Sections 3.1, 3.2, 3.4) of the system defined by
+ * kernel k on the tree's points.  points (n x dim) and weights (n) are host
+ * arrays in caller order and must be the points the tree was built on.
+ * eps >= 0 is the relative ID precision (eps = 0: no compression, exact dense
+ * elimination).  The returned handle holds the compressed inverse in device
+ * memory and is immutable; it stays valid after the tree is freed.
+ * Errors: RS_EINVAL, RS_ENOTSUP, RS_ENOMEM, RS_ESINGULAR, RS_EDEVICE. */
+rs_status rs_factor(const rs_kernel *k, rs_tree t, const double *points,
+                    const double *weights, double eps, rs_handle *out);
+
+/* rs_factor with explicit options (launch mode, stream).  opts may be NULL. */
+rs_status rs_factor_ex(const rs_kernel *k, rs_tree t, const double *points,
+                       const double *weights, double eps, const rs_options *opts,
+                       rs_handle *out);
+
+/* ---------------------------------------------------------------- solve ---- */
+
+/* B := A_eps^{-1} B in place (the solution phase, Section 3.4).  B is device
+ * memory, column-major n x nrhs with leading dimension ldb >= n, caller order.
+ * Work is enqueued on stream (hipStream_t, NULL = default stream); the result is
+ * valid once the stream has reached this point.  nrhs = 0 is a no-op.
+ * Concurrent calls on one handle from different streams are allowed; each call
+ * takes its own workspace.  Errors: RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
+rs_status rs_solve(rs_handle h, double *B, int64_t ldb, int32_t nrhs, void *stream);
+
+/* rs_solve with a launch mode (RS_LAUNCH_LEVEL or RS_LAUNCH_PER_BOX). */
+rs_status rs_solve_ex(rs_handle h, double *B, int64_t ldb, int32_t nrhs,
+                      const rs_options *opts);
+
+/* Releases a handle.  Waits for the library's own queued work on it; returns
+ * RS_OK for NULL. */
+rs_status rs_free(rs_handle h);
+
+/* Thread-local message for the last failed call on this thread ("" if none). */
+const char *rs_last_error(void);
+
+/* Number of HIP devices visible to the library (0 if none or the runtime fails). */
+int32_t rs_device_count(void);
+
+/* -------------------------------------------------------------- queries ---- */
+
+typedef struct {
+  int64_t n;                /* unknowns */
+  int64_t nbox;             /* boxes in the tree (root included) */
+  int32_t maxdepth;         /* finest depth; compressed depths are maxdepth..1 */
+  int32_t dim;
+  int64_t root_size;        /* unknowns left at the root (dense block) */
+  int64_t total_skeletons;  /* sum of k over all compressed boxes */
+  int64_t factor_doubles;   /* doubles stored for the compressed inverse */
+  int64_t max_box_n;        /* largest active set of a box */
+  int64_t max_box_m;        /* largest compression block row count */
+  double factor_ms;         /* host wall time of the factor call */
+} rs_stats;
+
+rs_status rs_query(rs_handle h, rs_stats *out);
+
+/* Per-box ranks and skeletons (tree positions, ascending per box), for
+ * inspection and testing.  k_out[nbox] receives k per box (-1 for boxes with no
+ * compression step, i.e. the root); skel_out receives the concatenation of all
+ * boxes' skeleton lists in box order and must hold cap entries; *total receives
+ * the number written.  RS_EINVAL if cap is too small. */
+rs_status rs_box_skeletons(rs_handle h, int32_t *k_out, int64_t *skel_out, int64_t cap,
+                           int64_t *total);
+
+/* Copies box b's active set (n tree positions, ascending) and its interpolation
+ * matrix T (k x (n-k), column-major; rows follow the sorted skeletons, columns the
+ * sorted redundant DOFs) to host arrays.  Either output may be NULL.  n_out/k_out
+ * receive the sizes.  The root (b = 0 unless the tree is a single box) reports
+ * k = 0 and no T. */
+rs_status rs_box_export(rs_handle h, int64_t b, int32_t *n_out, int32_t *k_out,
+                        int64_t *J_out, double *T_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RS_H */

@@ -1,0 +1,255 @@
+"""ctypes binding of the C ABI declared in include/rs.h (argument marshalling only).
+
+Every numerical step runs in the HIP library ``lib/librs.so``.  If that library is
+missing the import fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "librs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                      "(run `python -m paper_1110_3105_amd.build`)")
+
+# PyTorch ships its own HIP runtime with the same soname (libamdhip64.so.7).  Loading
+# torch first makes the library bind to that copy, so that the process holds one HIP
+# runtime shared by torch's allocator/streams and the library's kernels.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+RS_OK, RS_EINVAL, RS_ENOMEM, RS_ESINGULAR, RS_EDEVICE, RS_EBUSY, RS_ENOTSUP = range(7)
+STATUS_NAMES = {0: "RS_OK", 1: "RS_EINVAL", 2: "RS_ENOMEM", 3: "RS_ESINGULAR",
+                4: "RS_EDEVICE", 5: "RS_EBUSY", 6: "RS_ENOTSUP"}
+KINDS = {"lap2d_sl": 1, "lap2d_dl": 2, "lap3d_sl": 3, "helm2d_cfie": 4}
+LAUNCH = {"level": 0, "per_box": 1}
+
+EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "rs_factor",
+            "rs_factor_ex", "rs_solve", "rs_solve_ex", "rs_free", "rs_last_error",
+            "rs_device_count", "rs_query", "rs_box_skeletons", "rs_box_export"]
+
+
+class rs_kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("identity", C.c_double),
+                ("wavenumber", C.c_double), ("eta", C.c_double),
+                ("normals", C.POINTER(C.c_double)), ("curvature", C.POINTER(C.c_double)),
+                ("proxy_points", C.c_int32), ("proxy_ratio", C.c_double)]
+
+
+class rs_options(C.Structure):
+    _fields_ = [("launch_mode", C.c_int32), ("stream", C.c_void_p)]
+
+
+class rs_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nbox", C.c_int64), ("maxdepth", C.c_int32),
+                ("dim", C.c_int32), ("root_size", C.c_int64), ("total_skeletons", C.c_int64),
+                ("factor_doubles", C.c_int64), ("max_box_n", C.c_int64),
+                ("max_box_m", C.c_int64), ("factor_ms", C.c_double)]
+
+
+_P = C.c_void_p
+_PD = C.POINTER(C.c_double)
+_PI64 = C.POINTER(C.c_int64)
+_PI32 = C.POINTER(C.c_int32)
+
+_sig = {
+    "rs_build_tree": (C.c_int, [C.c_int32, C.c_int64, _PD, C.c_int32, C.POINTER(_P)]),
+    "rs_tree_info": (C.c_int, [_P, _PI64, _PI32]),
+    "rs_tree_export": (C.c_int, [_P, _PI64, _PI32, _PI32, _PI64, _PI64, _PD, _PD]),
+    "rs_tree_free": (None, [_P]),
+    "rs_factor": (C.c_int, [C.POINTER(rs_kernel), _P, _PD, _PD, C.c_double, C.POINTER(_P)]),
+    "rs_factor_ex": (C.c_int, [C.POINTER(rs_kernel), _P, _PD, _PD, C.c_double,
+                               C.POINTER(rs_options), C.POINTER(_P)]),
+    "rs_solve": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P]),
+    "rs_solve_ex": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(rs_options)]),
+    "rs_free": (C.c_int, [_P]),
+    "rs_last_error": (C.c_char_p, []),
+    "rs_device_count": (C.c_int32, []),
+    "rs_query": (C.c_int, [_P, C.POINTER(rs_stats)]),
+    "rs_box_skeletons": (C.c_int, [_P, _PI32, _PI64, C.c_int64, _PI64]),
+    "rs_box_export": (C.c_int, [_P, C.c_int64, _PI32, _PI32, _PI64, _PD]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+class RSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code: int):
+    if code != RS_OK:
+        raise RSError(code, _lib.rs_last_error().decode())
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_PD)
+
+
+def device_count() -> int:
+    return int(_lib.rs_device_count())
+
+
+class Tree:
+    """Owning wrapper of an rs_tree."""
+
+    def __init__(self, points: np.ndarray, leaf_size: int):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2:
+            raise ValueError("points must be (n, dim)")
+        self.points = pts
+        self.n, self.dim = pts.shape
+        h = _P()
+        _check(_lib.rs_build_tree(self.dim, self.n, _dptr(pts), int(leaf_size), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.rs_tree_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        nb, md = C.c_int64(), C.c_int32()
+        _check(_lib.rs_tree_info(self._h, C.byref(nb), C.byref(md)))
+        return int(nb.value), int(md.value)
+
+    def export(self) -> dict:
+        nb, _ = self.info()
+        perm = np.empty(self.n, dtype=np.int64)
+        depth = np.empty(nb, dtype=np.int32)
+        parent = np.empty(nb, dtype=np.int32)
+        begin = np.empty(nb, dtype=np.int64)
+        end = np.empty(nb, dtype=np.int64)
+        center = np.empty((nb, self.dim), dtype=np.float64)
+        side = np.empty(nb, dtype=np.float64)
+        _check(_lib.rs_tree_export(self._h, perm.ctypes.data_as(_PI64),
+                                   depth.ctypes.data_as(_PI32), parent.ctypes.data_as(_PI32),
+                                   begin.ctypes.data_as(_PI64), end.ctypes.data_as(_PI64),
+                                   center.ctypes.data_as(_PD), side.ctypes.data_as(_PD)))
+        return dict(perm=perm, depth=depth, parent=parent, begin=begin, end=end,
+                    center=center, side=side)
+
+
+def build_tree(points: np.ndarray, leaf_size: int) -> Tree:
+    return Tree(points, leaf_size)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)      # torch.cuda.Stream
+
+
+class Handle:
+    """Owning wrapper of an rs_handle (compressed inverse resident in device memory)."""
+
+    def __init__(self, h, n: int, keep):
+        self._h = h
+        self.n = n
+        self._keep = keep
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None):
+            _check(_lib.rs_free(self._h))
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = rs_stats()
+        _check(_lib.rs_query(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in rs_stats._fields_}
+
+    def solve_ptr(self, ptr: int, ldb: int, nrhs: int, stream=None, launch_mode: str = "level"):
+        o = rs_options(LAUNCH[launch_mode], _stream_ptr(stream))
+        _check(_lib.rs_solve_ex(self._h, C.c_void_p(ptr), int(ldb), int(nrhs), C.byref(o)))
+
+    def solve(self, B, stream=None, launch_mode: str = "level"):
+        """In-place B := A_eps^{-1} B for a float64 CUDA tensor of shape (n,) or (n, nrhs)."""
+        import torch
+        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.float64):
+            raise TypeError("B must be a float64 tensor on the HIP device")
+        vec = B.dim() == 1
+        X = B.unsqueeze(1) if vec else B
+        if X.shape[0] != self.n:
+            raise ValueError("B has the wrong number of rows")
+        nrhs = X.shape[1]
+        colmajor = X.stride(0) == 1 and (nrhs == 1 or X.stride(1) >= self.n)
+        work = X if colmajor else X.t().contiguous().t()
+        ldb = work.stride(1) if nrhs > 1 else self.n
+        if stream is None:
+            stream = torch.cuda.current_stream(B.device)
+        self.solve_ptr(work.data_ptr(), ldb, nrhs, stream, launch_mode)
+        if not colmajor:
+            X.copy_(work)
+        return B
+
+    def box_skeletons(self):
+        nb = self.stats()["nbox"]
+        ks = np.empty(nb, dtype=np.int32)
+        tot = C.c_int64()
+        _check(_lib.rs_box_skeletons(self._h, ks.ctypes.data_as(_PI32), None, 0, C.byref(tot)))
+        sk = np.empty(max(int(tot.value), 1), dtype=np.int64)
+        _check(_lib.rs_box_skeletons(self._h, ks.ctypes.data_as(_PI32), sk.ctypes.data_as(_PI64),
+                                     sk.size, C.byref(tot)))
+        out, off = [], 0
+        for k in ks:
+            kk = max(int(k), 0)
+            out.append(sk[off:off + kk].copy())
+            off += kk
+        return ks, out
+
+    def box_export(self, b: int):
+        n, k = C.c_int32(), C.c_int32()
+        _check(_lib.rs_box_export(self._h, int(b), C.byref(n), C.byref(k), None, None))
+        J = np.empty(max(n.value, 1), dtype=np.int64)
+        T = np.empty(max(k.value * (n.value - k.value), 1), dtype=np.float64)
+        _check(_lib.rs_box_export(self._h, int(b), C.byref(n), C.byref(k),
+                                  J.ctypes.data_as(_PI64), T.ctypes.data_as(_PD)))
+        kk, nn = k.value, n.value
+        return J[:nn], T[:kk * (nn - kk)].reshape((nn - kk, kk)).T if kk and nn - kk else \
+            np.zeros((kk, nn - kk))
+
+
+def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: float,
+           normals: Optional[np.ndarray] = None, curvature: Optional[np.ndarray] = None,
+           identity: float = 0.0, proxy_points: int = 64, proxy_ratio: float = 1.5,
+           launch_mode: str = "level", stream=None) -> Handle:
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64)
+    kap = None if curvature is None else np.ascontiguousarray(curvature, dtype=np.float64)
+    if pts.shape[0] != w.shape[0]:
+        raise ValueError("points and weights differ in length")
+    k = rs_kernel(KINDS[kind], pts.shape[1], float(identity), 0.0, 0.0, _dptr(nrm), _dptr(kap),
+                  int(proxy_points), float(proxy_ratio))
+    o = rs_options(LAUNCH[launch_mode], _stream_ptr(stream))
+    h = _P()
+    _check(_lib.rs_factor_ex(C.byref(k), tree.handle, _dptr(pts), _dptr(w), float(eps),
+                             C.byref(o), C.byref(h)))
+    return Handle(h, pts.shape[0], keep=(tree,))

@@ -1,0 +1,251 @@
+// C ABI entry points: argument validation, error translation, object lifetime.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "runtime.h"
+
+namespace rs {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+template <class F>
+rs_status guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const UserError &e) {
+    g_last_error = e.what;
+    return e.code;
+  } catch (const DeviceError &e) {
+    g_last_error = e.what;
+    return RS_EDEVICE;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return RS_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return RS_EDEVICE;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return RS_EDEVICE;
+  }
+}
+
+[[noreturn]] void fail(rs_status code, const std::string &msg) { throw UserError{code, msg}; }
+
+bool all_finite(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void validate_kernel(const rs_kernel *k, const Tree &t, const double *points,
+                     const double *weights, double eps) {
+  if (!k || !points || !weights) fail(RS_EINVAL, "NULL kernel, points or weights");
+  if (k->kind == RS_HELM2D_CFIE) fail(RS_ENOTSUP, "complex Helmholtz kernel is not built");
+  if (k->kind != RS_LAP2D_SL && k->kind != RS_LAP2D_DL && k->kind != RS_LAP3D_SL)
+    fail(RS_EINVAL, "unknown kernel kind");
+  const int want_dim = k->kind == RS_LAP3D_SL ? 3 : 2;
+  if (k->dim != want_dim || t.dim != want_dim) fail(RS_EINVAL, "kernel dimension mismatch");
+  if (k->kind == RS_LAP2D_DL && (!k->normals || !k->curvature))
+    fail(RS_EINVAL, "double-layer kernel needs normals and curvature");
+  if (k->proxy_points < 8 || k->proxy_points > 4096) fail(RS_EINVAL, "proxy_points out of range");
+  if (!(k->proxy_ratio > 0.5 * std::sqrt((double)want_dim)) || !(k->proxy_ratio < 16.0))
+    fail(RS_EINVAL, "proxy_ratio must exceed half the box diagonal");
+  if (!std::isfinite(k->identity)) fail(RS_EINVAL, "non-finite identity coefficient");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) fail(RS_EINVAL, "eps must be finite and >= 0");
+  const int64_t n = t.n;
+  if (!all_finite(points, n * t.dim) || !all_finite(weights, n))
+    fail(RS_EINVAL, "non-finite points or weights");
+  for (int64_t i = 0; i < n; ++i)
+    if (!(weights[i] > 0.0)) fail(RS_EINVAL, "weights must be positive");
+  if (k->normals && !all_finite(k->normals, n * t.dim)) fail(RS_EINVAL, "non-finite normals");
+  if (k->curvature && !all_finite(k->curvature, n)) fail(RS_EINVAL, "non-finite curvature");
+  // the points must be the ones the tree was built on
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < t.dim; ++a)
+      if (points[t.perm[i] * t.dim + a] != t.coords[(size_t)a * n + i])
+        fail(RS_EINVAL, "points differ from the tree's points");
+}
+
+hipStream_t stream_of(const rs_options *o) {
+  return o ? static_cast<hipStream_t>(o->stream) : nullptr;
+}
+
+int mode_of(const rs_options *o) {
+  if (!o) return RS_LAUNCH_LEVEL;
+  if (o->launch_mode != RS_LAUNCH_LEVEL && o->launch_mode != RS_LAUNCH_PER_BOX)
+    fail(RS_EINVAL, "unknown launch mode");
+  return o->launch_mode;
+}
+
+void require_device() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    fail(RS_EDEVICE, "no HIP device available");
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" {
+
+const char *rs_last_error(void) { return g_last_error.c_str(); }
+
+int32_t rs_device_count(void) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return 0;
+  return count;
+}
+
+rs_status rs_build_tree(int32_t dim, int64_t n, const double *points, int32_t leaf_size,
+                        rs_tree *out) {
+  return guarded([&]() -> rs_status {
+    if (!out || !points) fail(RS_EINVAL, "NULL argument");
+    if (dim != 2 && dim != 3) fail(RS_EINVAL, "dim must be 2 or 3");
+    if (n < 1 || n > INT32_MAX - 1) fail(RS_EINVAL, "n out of range");
+    if (leaf_size < 1) fail(RS_EINVAL, "leaf_size must be positive");
+    if (!all_finite(points, n * dim)) fail(RS_EINVAL, "non-finite point coordinate");
+    rs_tree t = new rs_tree_s();
+    t->t.build(dim, n, points, leaf_size);
+    *out = t;
+    return RS_OK;
+  });
+}
+
+rs_status rs_tree_info(rs_tree t, int64_t *nbox, int32_t *maxdepth) {
+  return guarded([&]() -> rs_status {
+    if (!t) fail(RS_EINVAL, "NULL tree");
+    if (nbox) *nbox = t->t.nbox();
+    if (maxdepth) *maxdepth = t->t.maxdepth;
+    return RS_OK;
+  });
+}
+
+rs_status rs_tree_export(rs_tree t, int64_t *perm, int32_t *depth, int32_t *parent,
+                         int64_t *begin, int64_t *end, double *center, double *side) {
+  return guarded([&]() -> rs_status {
+    if (!t) fail(RS_EINVAL, "NULL tree");
+    const Tree &T = t->t;
+    const int nb = T.nbox();
+    if (perm) std::memcpy(perm, T.perm.data(), T.n * sizeof(int64_t));
+    for (int b = 0; b < nb; ++b) {
+      if (depth) depth[b] = T.depth[b];
+      if (parent) parent[b] = T.parent[b];
+      if (begin) begin[b] = T.begin[b];
+      if (end) end[b] = T.end[b];
+      if (side) side[b] = T.side[b];
+      if (center)
+        for (int a = 0; a < T.dim; ++a) center[(int64_t)b * T.dim + a] = T.center[3 * b + a];
+    }
+    return RS_OK;
+  });
+}
+
+void rs_tree_free(rs_tree t) { delete t; }
+
+rs_status rs_factor_ex(const rs_kernel *k, rs_tree t, const double *points,
+                       const double *weights, double eps, const rs_options *opts,
+                       rs_handle *out) {
+  return guarded([&]() -> rs_status {
+    if (!out || !t) fail(RS_EINVAL, "NULL argument");
+    validate_kernel(k, t->t, points, weights, eps);
+    const int mode = mode_of(opts);
+    require_device();
+    std::vector<FactorRequest> reqs{{k, &t->t, points, weights, eps}};
+    std::vector<rs_factor_s *> hs;
+    factor_many(reqs, mode, stream_of(opts), hs);
+    *out = hs[0];
+    return RS_OK;
+  });
+}
+
+rs_status rs_factor(const rs_kernel *k, rs_tree t, const double *points, const double *weights,
+                    double eps, rs_handle *out) {
+  return rs_factor_ex(k, t, points, weights, eps, nullptr, out);
+}
+
+rs_status rs_solve_ex(rs_handle h, double *B, int64_t ldb, int32_t nrhs,
+                      const rs_options *opts) {
+  return guarded([&]() -> rs_status {
+    if (!h) fail(RS_EINVAL, "NULL handle");
+    if (nrhs < 0) fail(RS_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return RS_OK;
+    if (!B) fail(RS_EINVAL, "NULL right-hand side");
+    if (ldb < h->n) fail(RS_EINVAL, "ldb < n");
+    const int mode = mode_of(opts);
+    h->busy.fetch_add(1);
+    struct Dec {
+      rs_handle h;
+      ~Dec() { h->busy.fetch_sub(1); }
+    } dec{h};
+    solve_one(h, B, ldb, nrhs, mode, stream_of(opts));
+    return RS_OK;
+  });
+}
+
+rs_status rs_solve(rs_handle h, double *B, int64_t ldb, int32_t nrhs, void *stream) {
+  rs_options o{RS_LAUNCH_LEVEL, stream};
+  return rs_solve_ex(h, B, ldb, nrhs, &o);
+}
+
+rs_status rs_free(rs_handle h) {
+  return guarded([&]() -> rs_status {
+    if (!h) return RS_OK;
+    if (h->busy.load() != 0) fail(RS_EBUSY, "handle is in use by a running call");
+    RS_HIP_CHECK(hipDeviceSynchronize());
+    delete h;
+    return RS_OK;
+  });
+}
+
+rs_status rs_query(rs_handle h, rs_stats *out) {
+  return guarded([&]() -> rs_status {
+    if (!h || !out) fail(RS_EINVAL, "NULL argument");
+    *out = h->stats;
+    return RS_OK;
+  });
+}
+
+rs_status rs_box_skeletons(rs_handle h, int32_t *k_out, int64_t *skel_out, int64_t cap,
+                           int64_t *total) {
+  return guarded([&]() -> rs_status {
+    if (!h) fail(RS_EINVAL, "NULL handle");
+    int64_t need = 0;
+    for (int b = 0; b < h->nbox; ++b) need += (int64_t)h->box_skel[b].size();
+    if (total) *total = need;
+    if (skel_out && cap < need) fail(RS_EINVAL, "skeleton buffer too small");
+    int64_t off = 0;
+    for (int b = 0; b < h->nbox; ++b) {
+      if (k_out) k_out[b] = h->box_k[b];
+      if (skel_out)
+        for (int32_t g : h->box_skel[b]) skel_out[off++] = g;
+    }
+    return RS_OK;
+  });
+}
+
+rs_status rs_box_export(rs_handle h, int64_t b, int32_t *n_out, int32_t *k_out, int64_t *J_out,
+                        double *T_out) {
+  return guarded([&]() -> rs_status {
+    if (!h) fail(RS_EINVAL, "NULL handle");
+    if (b < 0 || b >= h->nbox) fail(RS_EINVAL, "box index out of range");
+    const std::vector<int32_t> &J = h->box_J[b];
+    const int n = (int)J.size();
+    const int k = h->box_k[b] < 0 ? 0 : h->box_k[b];
+    if (n_out) *n_out = n;
+    if (k_out) *k_out = k;
+    if (J_out)
+      for (int i = 0; i < n; ++i) J_out[i] = J[i];
+    if (T_out && k > 0 && n - k > 0)
+      RS_HIP_CHECK(hipMemcpy(T_out, h->box_slot[b] + slot_T(k, n - k),
+                             (size_t)k * (n - k) * sizeof(double), hipMemcpyDeviceToHost));
+    return RS_OK;
+  });
+}
+
+}  // extern "C"

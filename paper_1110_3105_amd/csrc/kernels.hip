@@ -1,0 +1,712 @@
+// HIP kernels of the recursive-skeletonization factor and solve passes (gfx950).
+//
+// Every kernel processes one box per workgroup (256 threads = 4 wave64s); a launch
+// covers all boxes of one tree level (of every problem of a batch), or a single box
+// in the per-box reference mode.  All arithmetic is binary64.
+#include <float.h>
+#include <limits.h>
+
+#include "rs_internal.h"
+
+namespace rs {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInv2Pi = 0.15915494309189533577;   // 1 / (2 pi)
+constexpr double kInv4Pi = 0.07957747154594766788;   // 1 / (4 pi)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Green's function K(t, s) with the unit normal ns at the source (double layer):
+// eqs. (2d-laplace), (3d-laplace) and the double-layer kernel of eq. (double-layer).
+__device__ __forceinline__ double green(int kind, const double *t, const double *s,
+                                        const double *ns) {
+  const double dx = t[0] - s[0], dy = t[1] - s[1];
+  if (kind == RS_LAP2D_SL) {
+    return -0.5 * kInv2Pi * log(dx * dx + dy * dy);
+  } else if (kind == RS_LAP2D_DL) {
+    return (dx * ns[0] + dy * ns[1]) * kInv2Pi / (dx * dx + dy * dy);
+  } else {
+    const double dz = t[2] - s[2];
+    return kInv4Pi / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+}
+
+__device__ __forceinline__ void load_pt(const ProbDev &P, int g, double *x) {
+  x[0] = P.x[0][g];
+  x[1] = P.x[1][g];
+  x[2] = P.dim == 3 ? P.x[2][g] : 0.0;
+}
+
+__device__ __forceinline__ void load_nrm(const ProbDev &P, int g, double *nv) {
+  if (P.nrm[0]) {
+    nv[0] = P.nrm[0][g];
+    nv[1] = P.nrm[1][g];
+    nv[2] = P.dim == 3 ? P.nrm[2][g] : 0.0;
+  } else {
+    nv[0] = nv[1] = nv[2] = 0.0;
+  }
+}
+
+// Diagonal entry A_ii: identity coefficient plus the kernel's diagonal rule.
+__device__ __forceinline__ double diag_entry(const ProbDev &P, int g) {
+  const double w = P.w[g];
+  double d;
+  if (P.kind == RS_LAP2D_SL) {
+    d = -(w * kInv2Pi) * log(w * kInv2Pi);
+  } else if (P.kind == RS_LAP2D_DL) {
+    d = -P.kappa[g] * w * (0.25 / kPi);
+  } else {
+    d = 0.5 * sqrt(w / kPi);
+  }
+  return P.c + d;
+}
+
+// A(gi, gj) = c delta + K(x_gi, x_gj) w_gj.
+__device__ __forceinline__ double entry(const ProbDev &P, int gi, int gj) {
+  if (gi == gj) return diag_entry(P, gi);
+  double t[3], s[3], ns[3];
+  load_pt(P, gi, t);
+  load_pt(P, gj, s);
+  load_nrm(P, gj, ns);
+  return green(P.kind, t, s, ns) * P.w[gj];
+}
+
+__device__ __forceinline__ void proxy_unit(int dim, int p, int npx, double *u) {
+  if (dim == 2) {
+    double sn, cs;
+    sincos(2.0 * kPi * (double)p / (double)npx, &sn, &cs);
+    u[0] = cs;
+    u[1] = sn;
+    u[2] = 0.0;
+  } else {
+    const double z = 1.0 - (2.0 * p + 1.0) / (double)npx;
+    const double rr = sqrt(fmax(0.0, 1.0 - z * z));
+    double sn, cs;
+    sincos((double)p * (kPi * (3.0 - sqrt(5.0))), &sn, &cs);
+    u[0] = rr * cs;
+    u[1] = rr * sn;
+    u[2] = z;
+  }
+}
+
+__device__ double block_max(double v, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_max(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < kWaves; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// --------------------------------------------------------------------------
+// Compression block M_B (Section 3.2), column-major m x n:
+//   rows [0, nn)            near DOFs as targets      A(N, J)
+//   rows [nn, 2nn)          near DOFs as sources      A(J, N)^T
+//   rows [2nn, 2nn+np)      proxies as targets        K(Gamma, J) W_J
+//   rows [2nn+np, 2nn+2np)  proxies as sources        (K(J, Gamma) W_Gamma)^T
+//   rows m-2, m-1 (log kernels): total charge and constant field, scaled to the
+//                           largest proxy entry.
+__global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict__ boxes,
+                                                       int first,
+                                                       const ProbDev *__restrict__ probs,
+                                                       const int32_t *__restrict__ pool,
+                                                       double *__restrict__ Marena) {
+  extern __shared__ double sh_u[];   // npx * 3 proxy unit vectors
+  __shared__ double red[kWaves];
+  const CompBox &B = boxes[first + blockIdx.x];
+  const ProbDev &P = probs[B.prob];
+  const int n = B.n, nn = B.nn, m = B.m, npx = P.npx, dim = P.dim;
+  if (n == 0) return;
+  const int32_t *J = pool + B.J_off;
+  const int32_t *N = pool + B.N_off;
+  double *M = Marena + B.M_off;
+  for (int p = threadIdx.x; p < npx; p += kThreads) proxy_unit(dim, p, npx, sh_u + 3 * p);
+  double wmax = 0.0;
+  for (int j = threadIdx.x; j < n; j += kThreads) wmax = fmax(wmax, P.w[J[j]]);
+  wmax = block_max(wmax, red);   // includes a barrier: proxy vectors are visible
+  const double wG = dim == 2 ? 2.0 * kPi * B.rho / npx : 4.0 * kPi * B.rho * B.rho / npx;
+  const int rows = 2 * nn + 2 * npx;
+  double pmax = 0.0;
+  const int64_t total = (int64_t)rows * n;
+  for (int64_t e = threadIdx.x; e < total; e += kThreads) {
+    const int j = (int)(e / rows), i = (int)(e - (int64_t)j * rows);
+    const int g = J[j];
+    double xs[3], ns[3], v;
+    load_pt(P, g, xs);
+    if (i < nn) {
+      double xq[3];
+      load_nrm(P, g, ns);
+      load_pt(P, N[i], xq);
+      v = green(P.kind, xq, xs, ns) * P.w[g];
+    } else if (i < 2 * nn) {
+      const int q = N[i - nn];
+      double xq[3], nq[3];
+      load_pt(P, q, xq);
+      load_nrm(P, q, nq);
+      v = green(P.kind, xs, xq, nq) * P.w[q];
+    } else if (i < 2 * nn + npx) {
+      const double *u = sh_u + 3 * (i - 2 * nn);
+      double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
+      load_nrm(P, g, ns);
+      v = green(P.kind, y, xs, ns) * P.w[g];
+      pmax = fmax(pmax, fabs(v));
+    } else {
+      const double *u = sh_u + 3 * (i - 2 * nn - npx);
+      double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
+      v = green(P.kind, xs, y, u) * wG;
+      pmax = fmax(pmax, fabs(v));
+    }
+    M[(int64_t)j * m + i] = v;
+  }
+  if (P.log_kernel) {
+    pmax = block_max(pmax, red);
+    for (int j = threadIdx.x; j < n; j += kThreads) {
+      M[(int64_t)j * m + rows] = pmax * P.w[J[j]] / wmax;
+      M[(int64_t)j * m + rows + 1] = pmax;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Interpolative decomposition (Section 2.2) of M_B by column-pivoted Householder QR:
+// pivot = largest remaining column norm (recomputed after every reflection, ties to
+// the lowest original column), stop at the first |R_jj| <= eps |R_00|, then
+// T = R11^{-1} R12 and the skeleton / redundant sets sorted ascending.
+// Outputs: ranks[kslot] = k, order (n ints: sorted s, then sorted r), T (k x (n-k)).
+__global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict__ boxes,
+                                                      int first,
+                                                      const ProbDev *__restrict__ probs,
+                                                      double *__restrict__ Marena,
+                                                      int32_t *__restrict__ order_pool,
+                                                      int32_t *__restrict__ ranks) {
+  extern __shared__ double smem[];
+  __shared__ double s_best, s_tau;
+  __shared__ int s_p;
+  const CompBox &B = boxes[first + blockIdx.x];
+  const int m = B.m, n = B.n;
+  const double eps = probs[B.prob].eps;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (n == 0) {
+    if (threadIdx.x == 0) ranks[B.kslot] = 0;
+    return;
+  }
+  double *M = Marena + B.M_off;
+  double *norms = smem;                                  // n
+  int *perm = reinterpret_cast<int *>(norms + n);        // n
+  int *rk = perm + n;                                    // n (ranks for the sort)
+  double *wbuf = reinterpret_cast<double *>(rk + n);  // kWaves * kmax (16n bytes in)
+  const int kmax = min(m, n);
+
+  for (int c = threadIdx.x; c < n; c += kThreads) perm[c] = c;
+  for (int c = wave; c < n; c += kWaves) {
+    const double *col = M + (int64_t)c * m;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += col[i] * col[i];
+    s = wave_sum(s);
+    if (lane == 0) norms[c] = sqrt(s);
+  }
+  __syncthreads();
+
+  int k = kmax;
+  double r00 = 0.0;
+  for (int j = 0; j < kmax; ++j) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bperm = INT_MAX, bc = -1;
+      for (int c = j + lane; c < n; c += 64) {
+        const double v = norms[c];
+        const int pc = perm[c];
+        if (v > best || (v == best && pc < bperm)) { best = v; bperm = pc; bc = c; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int op = __shfl_xor(bperm, off, 64);
+        const int oc = __shfl_xor(bc, off, 64);
+        if (ob > best || (ob == best && op < bperm)) { best = ob; bperm = op; bc = oc; }
+      }
+      if (lane == 0) { s_best = best; s_p = bc; }
+    }
+    __syncthreads();
+    const double best = s_best;
+    const int p = s_p;
+    if (j == 0) r00 = best;
+    if (best == 0.0 || best <= eps * r00) { k = j; break; }
+    if (p != j) {
+      double *cj = M + (int64_t)j * m, *cp = M + (int64_t)p * m;
+      for (int i = threadIdx.x; i < m; i += kThreads) {
+        const double a = cj[i];
+        cj[i] = cp[i];
+        cp[i] = a;
+      }
+      if (threadIdx.x == 0) {
+        const double t = norms[j]; norms[j] = norms[p]; norms[p] = t;
+        const int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {   // Householder reflector of column j, rows j..m-1
+      double *cj = M + (int64_t)j * m;
+      double s = 0.0;
+      for (int i = j + lane; i < m; i += 64) s += cj[i] * cj[i];
+      s = wave_sum(s);
+      const double alpha = sqrt(s);
+      const double x0 = cj[j];
+      const double beta = x0 >= 0.0 ? -alpha : alpha;
+      const double scale = 1.0 / (x0 - beta);
+      for (int i = j + 1 + lane; i < m; i += 64) cj[i] *= scale;
+      if (lane == 0) {
+        s_tau = (beta - x0) / beta;
+        cj[j] = beta;
+      }
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    const double *v = M + (int64_t)j * m;
+    for (int c = j + 1 + wave; c < n; c += kWaves) {
+      double *col = M + (int64_t)c * m;
+      double s = 0.0;
+      for (int i = j + lane; i < m; i += 64) s += (i == j ? 1.0 : v[i]) * col[i];
+      const double w = wave_sum(s) * tau;
+      double ss = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const double val = col[i] - w * (i == j ? 1.0 : v[i]);
+        col[i] = val;
+        if (i > j) ss += val * val;
+      }
+      ss = wave_sum(ss);
+      if (lane == 0) norms[c] = sqrt(ss);
+    }
+    __syncthreads();
+  }
+
+  // T = R11^{-1} R12, one column per wave, column held in the wave's LDS buffer.
+  double *buf = wbuf + wave * kmax;
+  for (int c = k + wave; c < n; c += kWaves) {
+    double *col = M + (int64_t)c * m;
+    for (int i = lane; i < k; i += 64) buf[i] = col[i];
+    for (int i = k - 1; i >= 0; --i) {
+      const double xi = buf[i] / M[(int64_t)i * m + i];
+      const double *ri = M + (int64_t)i * m;
+      for (int l = lane; l < i; l += 64) buf[l] -= xi * ri[l];
+      if (lane == 0) buf[i] = xi;
+    }
+    for (int i = lane; i < k; i += 64) col[i] = buf[i];
+  }
+  // Sorted skeleton and redundant sets.
+  int32_t *order = order_pool + B.order_off;
+  for (int c = threadIdx.x; c < n; c += kThreads) {
+    const int pc = perm[c];
+    const int lo = c < k ? 0 : k, hi = c < k ? k : n;
+    int r = 0;
+    for (int c2 = lo; c2 < hi; ++c2) r += perm[c2] < pc;
+    rk[c] = r;
+    order[lo + r] = pc;
+  }
+  __syncthreads();
+  const int nr = n - k;
+  double *T = B.T;
+  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += kThreads) {
+    const int i = (int)(e % k), c = (int)(e / k) + k;
+    T[rk[i] + (int64_t)k * rk[c]] = M[(int64_t)c * m + i];
+  }
+  if (threadIdx.x == 0) ranks[B.kslot] = k;
+}
+
+// --------------------------------------------------------------------------
+// Diagonal block and box factorization (Section 3.4 in Schur form).
+// With the box's DOFs ordered (s, r), X = P D Q where P = [[I, 0], [-T^T, I]] and
+// Q = [[I, -T], [0, I]] remove the skeleton-interpolated part; then
+//   G = X_rr^{-1},  F = G X_rs,  E = X_sr G,  Lambda = X_ss - X_sr F,
+// and Lambda = (R D^{-1} L)^{-1} is the box's block of the next level's matrix.
+// D is A(J, J) at a leaf; above, Lambda of each child on its diagonal block and
+// A between siblings.  The root (force_k0) eliminates everything: G = D^{-1}.
+__global__ __launch_bounds__(kThreads) void k_diag_factor(const FacBox *__restrict__ boxes,
+                                                          int first,
+                                                          const ProbDev *__restrict__ probs,
+                                                          const int32_t *__restrict__ pool,
+                                                          const int32_t *__restrict__ order_pool,
+                                                          const int32_t *__restrict__ ranks,
+                                                          double *__restrict__ workbase,
+                                                          int32_t *__restrict__ err) {
+  extern __shared__ double fac[];           // r doubles: elimination factors
+  __shared__ double s_piv;
+  __shared__ int s_prow, s_bad;
+  const FacBox &B = boxes[first + blockIdx.x];
+  const ProbDev &P = probs[B.prob];
+  const int n = B.n;
+  if (n == 0) return;
+  const int k = B.force_k0 ? 0 : ranks[B.kslot];
+  const int r = n - k;
+  const int32_t *J = pool + B.J_off;
+  const int32_t *ord = B.force_k0 ? nullptr : order_pool + B.order_off;
+  double *slot = B.slot;
+  const double *T = slot + slot_T(k, r);
+  double *X = workbase + B.work_off;                 // n x n, (s, r) order
+  double *aug = X + (int64_t)n * n;                  // r x 2r
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  // D in (s, r) order.
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kThreads) {
+    const int b = (int)(e / n), a = (int)(e - (int64_t)b * n);
+    const int li = ord ? ord[a] : a, lj = ord ? ord[b] : b;
+    double v;
+    if (B.leaf) {
+      v = entry(P, J[li], J[lj]);
+    } else {
+      int ca = 0, cb = 0;
+      for (int c = 1; c < B.nchild; ++c) {
+        ca += li >= B.child_lo[c];
+        cb += lj >= B.child_lo[c];
+      }
+      if (ca == cb) {
+        v = B.child_lam[ca][(li - B.child_lo[ca]) + (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
+      } else {
+        v = entry(P, J[li], J[lj]);
+      }
+    }
+    X[(int64_t)b * n + a] = v;
+  }
+  __syncthreads();
+  if (k > 0 && r > 0) {
+    // Y = D Q: redundant columns minus the skeleton columns times T.
+    for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kThreads) {
+      const int jr = (int)(e / n), a = (int)(e - (int64_t)jr * n);
+      double s = X[(int64_t)(k + jr) * n + a];
+      for (int i = 0; i < k; ++i) s -= X[(int64_t)i * n + a] * T[i + (int64_t)k * jr];
+      X[(int64_t)(k + jr) * n + a] = s;
+    }
+    __syncthreads();
+    // X = P Y: redundant rows minus T^T times the skeleton rows.
+    for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kThreads) {
+      const int b = (int)(e / r), jr = (int)(e - (int64_t)b * r);
+      double s = X[(int64_t)b * n + k + jr];
+      for (int i = 0; i < k; ++i) s -= T[i + (int64_t)k * jr] * X[(int64_t)b * n + i];
+      X[(int64_t)b * n + k + jr] = s;
+    }
+    __syncthreads();
+  }
+  // Gauss-Jordan with partial pivoting on [X_rr | I] (r x 2r, column-major).
+  const int r2 = 2 * r;
+  for (int64_t e = threadIdx.x; e < (int64_t)r * r2; e += kThreads) {
+    const int c = (int)(e / r), a = (int)(e - (int64_t)c * r);
+    aug[e] = c < r ? X[(int64_t)(k + c) * n + k + a] : (c - r == a ? 1.0 : 0.0);
+  }
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    if (wave == 0) {
+      double best = -1.0;
+      int brow = INT_MAX;
+      for (int i = j + lane; i < r; i += 64) {
+        const double v = fabs(aug[(int64_t)j * r + i]);
+        if (v > best || (v == best && i < brow)) { best = v; brow = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int orow = __shfl_xor(brow, off, 64);
+        if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+      }
+      if (lane == 0) {
+        s_prow = brow;
+        if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
+      }
+    }
+    __syncthreads();
+    if (s_bad) break;
+    const int pr = s_prow;
+    if (pr != j) {
+      for (int c = j + threadIdx.x; c < r2; c += kThreads) {
+        const double a = aug[(int64_t)c * r + j];
+        aug[(int64_t)c * r + j] = aug[(int64_t)c * r + pr];
+        aug[(int64_t)c * r + pr] = a;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_piv = 1.0 / aug[(int64_t)j * r + j];
+    for (int i = threadIdx.x; i < r; i += kThreads) fac[i] = aug[(int64_t)j * r + i];
+    __syncthreads();
+    const double inv = s_piv;
+    for (int c = j + threadIdx.x; c < r2; c += kThreads) aug[(int64_t)c * r + j] *= inv;
+    __syncthreads();
+    const int64_t ncols = r2 - j;
+    for (int64_t e = threadIdx.x; e < ncols * r; e += kThreads) {
+      const int c = j + (int)(e / r), i = (int)(e % r);
+      if (i == j) continue;
+      const double f = fac[i];
+      if (c == j) aug[(int64_t)c * r + i] = 0.0;
+      else aug[(int64_t)c * r + i] -= f * aug[(int64_t)c * r + j];
+    }
+    __syncthreads();
+  }
+  if (s_bad) {
+    if (threadIdx.x == 0) atomicCAS(err, -1, first + (int)blockIdx.x);
+    return;
+  }
+  double *G = slot + slot_G(k, r);
+  const double *Gs = aug + (int64_t)r * r;
+  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += kThreads) G[e] = Gs[e];
+  if (k == 0) return;
+  double *E = slot + slot_E(k, r);
+  double *F = slot + slot_F(k, r);
+  double *L = slot + slot_L(k, r);
+  // F = G X_rs (r x k)
+  for (int64_t e = threadIdx.x; e < (int64_t)r * k; e += kThreads) {
+    const int i = (int)(e / r), a = (int)(e - (int64_t)i * r);
+    double s = 0.0;
+    for (int l = 0; l < r; ++l) s += Gs[(int64_t)l * r + a] * X[(int64_t)i * n + k + l];
+    F[e] = s;
+  }
+  // E = X_sr G (k x r)
+  for (int64_t e = threadIdx.x; e < (int64_t)k * r; e += kThreads) {
+    const int a = (int)(e / k), i = (int)(e - (int64_t)a * k);
+    double s = 0.0;
+    for (int l = 0; l < r; ++l) s += X[(int64_t)(k + l) * n + i] * Gs[(int64_t)a * r + l];
+    E[e] = s;
+  }
+  __syncthreads();
+  // Lambda = X_ss - X_sr F (k x k)
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += kThreads) {
+    const int i2 = (int)(e / k), i = (int)(e - (int64_t)i2 * k);
+    double s = X[(int64_t)i2 * n + i];
+    for (int a = 0; a < r; ++a) s -= X[(int64_t)(k + a) * n + i] * F[(int64_t)i2 * r + a];
+    L[e] = s;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Solve sweeps.  W is the tree-ordered right-hand side / solution, row-major
+// (n x nrhs): the values of DOF g are W[g*nrhs .. g*nrhs+nrhs).  A box reads and
+// writes only its own DOFs; a parent reads its children's skeleton outputs in place.
+//
+// Up (finest level first):  t = b_r - T^T b_s;  b_r <- G t;  b_s <- b_s - E t.
+// Down (root side first):   u = y_r - F z_s;   b_r <- u;     b_s <- z_s - T u.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_up(const SweepBox *__restrict__ boxes,
+                                                       int first, double *__restrict__ W,
+                                                       int nrhs) {
+  extern __shared__ double sh[];
+  const SweepBox &B = boxes[first + blockIdx.x];
+  const int k = B.k, r = B.r;
+  if (r == 0) return;
+  const int col0 = blockIdx.y * NT;
+  const int nt = min(NT, nrhs - col0);
+  double *bs = sh;              // k x NT
+  double *t = sh + k * NT;      // r x NT
+  const int32_t *idx = B.idx;
+  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
+    const int i = e / NT, c = e - i * NT;
+    bs[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * NT; e += kThreads) {
+    const int j = e / NT, c = e - j * NT;
+    double s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : 0.0;
+    const double *Tj = B.T + (int64_t)k * j;
+    for (int i = 0; i < k; ++i) s -= Tj[i] * bs[i * NT + c];
+    t[e] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * NT; e += kThreads) {
+    const int j = e / NT, c = e - j * NT;
+    double s = 0.0;
+    for (int l = 0; l < r; ++l) s += B.G[j + (int64_t)r * l] * t[l * NT + c];
+    if (c < nt) W[(int64_t)idx[k + j] * nrhs + col0 + c] = s;
+  }
+  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
+    const int i = e / NT, c = e - i * NT;
+    double s = bs[e];
+    for (int l = 0; l < r; ++l) s -= B.E[i + (int64_t)k * l] * t[l * NT + c];
+    if (c < nt) W[(int64_t)idx[i] * nrhs + col0 + c] = s;
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restrict__ boxes,
+                                                         int first, double *__restrict__ W,
+                                                         int nrhs) {
+  extern __shared__ double sh[];
+  const SweepBox &B = boxes[first + blockIdx.x];
+  const int k = B.k, r = B.r;
+  if (r == 0 || k == 0) return;
+  const int col0 = blockIdx.y * NT;
+  const int nt = min(NT, nrhs - col0);
+  double *z = sh;              // k x NT
+  double *u = sh + k * NT;     // r x NT
+  const int32_t *idx = B.idx;
+  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
+    const int i = e / NT, c = e - i * NT;
+    z[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * NT; e += kThreads) {
+    const int j = e / NT, c = e - j * NT;
+    double s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : 0.0;
+    for (int i = 0; i < k; ++i) s -= B.F[j + (int64_t)r * i] * z[i * NT + c];
+    u[e] = s;
+    if (c < nt) W[(int64_t)idx[k + j] * nrhs + col0 + c] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
+    const int i = e / NT, c = e - i * NT;
+    double s = z[e];
+    for (int j = 0; j < r; ++j) s -= B.T[i + (int64_t)k * j] * u[j * NT + c];
+    if (c < nt) W[(int64_t)idx[i] * nrhs + col0 + c] = s;
+  }
+}
+
+__global__ void k_permute_in(const double *__restrict__ B, int64_t ldb, double *__restrict__ W,
+                             const int64_t *__restrict__ perm, int64_t n, int nrhs) {
+  const int64_t total = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / nrhs;
+    const int c = (int)(e - i * nrhs);
+    W[e] = B[perm[i] + ldb * c];
+  }
+}
+
+__global__ void k_permute_out(double *__restrict__ B, int64_t ldb, const double *__restrict__ W,
+                              const int64_t *__restrict__ perm, int64_t n, int nrhs) {
+  const int64_t total = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / nrhs;
+    const int c = (int)(e - i * nrhs);
+    B[perm[i] + ldb * c] = W[e];
+  }
+}
+
+void check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw DeviceError(what, e);
+}
+
+template <int NT>
+void sweep_up_nt(const SweepBox *boxes, int first, int count, double *W, int nrhs, int max_n,
+                 hipStream_t st) {
+  dim3 grid(count, (nrhs + NT - 1) / NT);
+  hipLaunchKernelGGL(k_sweep_up<NT>, grid, dim3(kThreads), (size_t)max_n * NT * sizeof(double),
+                     st, boxes, first, W, nrhs);
+  check_launch("k_sweep_up");
+}
+
+template <int NT>
+void sweep_down_nt(const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                   int max_n, hipStream_t st) {
+  dim3 grid(count, (nrhs + NT - 1) / NT);
+  hipLaunchKernelGGL(k_sweep_down<NT>, grid, dim3(kThreads),
+                     (size_t)max_n * NT * sizeof(double), st, boxes, first, W, nrhs);
+  check_launch("k_sweep_down");
+}
+
+int pick_nt(int nrhs, int max_n) {
+  // LDS holds max_n x NT doubles; keep it within 64 KiB.
+  int nt = nrhs <= 1 ? 1 : nrhs <= 4 ? 4 : nrhs <= 16 ? 16 : 32;
+  while (nt > 1 && (int64_t)max_n * nt * 8 > 65536) nt = nt == 32 ? 16 : nt == 16 ? 4 : 1;
+  return nt;
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+}  // namespace
+
+void launch_assemble(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                     const int32_t *pool, double *Marena, int max_npx, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_assemble, dim3(count), dim3(kThreads),
+                     (size_t)max_npx * 3 * sizeof(double), st, boxes, first, probs, pool, Marena);
+  check_launch("k_assemble");
+}
+
+size_t cpqr_lds_bytes(int max_n) {
+  return (size_t)max_n * sizeof(double) + (size_t)(3 * max_n + 2) * sizeof(int) +
+         (size_t)kWaves * max_n * sizeof(double);
+}
+
+void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n,
+                    hipStream_t st) {
+  if (count <= 0) return;
+  const size_t lds = cpqr_lds_bytes(max_n);
+  if (lds > kMaxLds) throw DeviceError("k_cpqr_id: box too large for LDS", hipErrorInvalidValue);
+  if (lds > 64 * 1024)
+    RS_HIP_CHECK(hipFuncSetAttribute((const void *)k_cpqr_id,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_cpqr_id, dim3(count), dim3(kThreads), lds, st, boxes, first, probs,
+                     Marena, order_pool, ranks);
+  check_launch("k_cpqr_id");
+}
+
+void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
+                        const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
+                        double *work, int32_t *err, int max_n, hipStream_t st) {
+  if (count <= 0) return;
+  const size_t lds = (size_t)max_n * sizeof(double);
+  if (lds > kMaxLds) throw DeviceError("k_diag_factor: box too large for LDS", hipErrorInvalidValue);
+  if (lds > 64 * 1024)
+    RS_HIP_CHECK(hipFuncSetAttribute((const void *)k_diag_factor,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_diag_factor, dim3(count), dim3(kThreads), lds, st, boxes, first, probs,
+                     pool, order_pool, ranks, work, err);
+  check_launch("k_diag_factor");
+}
+
+void launch_permute_in(const double *B, int64_t ldb, double *W, const int64_t *perm, int64_t n,
+                       int nrhs, hipStream_t st) {
+  const int64_t total = n * nrhs;
+  if (total == 0) return;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_permute_in, dim3(blocks), dim3(256), 0, st, B, ldb, W, perm, n, nrhs);
+  check_launch("k_permute_in");
+}
+
+void launch_permute_out(double *B, int64_t ldb, const double *W, const int64_t *perm,
+                        int64_t n, int nrhs, hipStream_t st) {
+  const int64_t total = n * nrhs;
+  if (total == 0) return;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_permute_out, dim3(blocks), dim3(256), 0, st, B, ldb, W, perm, n, nrhs);
+  check_launch("k_permute_out");
+}
+
+void launch_sweep_up(const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                     int max_n, hipStream_t st) {
+  if (count <= 0 || nrhs <= 0) return;
+  switch (pick_nt(nrhs, max_n)) {
+    case 1: sweep_up_nt<1>(boxes, first, count, W, nrhs, max_n, st); break;
+    case 4: sweep_up_nt<4>(boxes, first, count, W, nrhs, max_n, st); break;
+    case 16: sweep_up_nt<16>(boxes, first, count, W, nrhs, max_n, st); break;
+    default: sweep_up_nt<32>(boxes, first, count, W, nrhs, max_n, st); break;
+  }
+}
+
+void launch_sweep_down(const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                       int max_n, hipStream_t st) {
+  if (count <= 0 || nrhs <= 0) return;
+  switch (pick_nt(nrhs, max_n)) {
+    case 1: sweep_down_nt<1>(boxes, first, count, W, nrhs, max_n, st); break;
+    case 4: sweep_down_nt<4>(boxes, first, count, W, nrhs, max_n, st); break;
+    case 16: sweep_down_nt<16>(boxes, first, count, W, nrhs, max_n, st); break;
+    default: sweep_down_nt<32>(boxes, first, count, W, nrhs, max_n, st); break;
+  }
+}
+
+}  // namespace rs

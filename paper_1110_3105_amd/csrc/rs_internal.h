@@ -1,0 +1,128 @@
+// Internal data structures shared by the host runtime and the HIP kernels.
+// Plain-old-data only: these structs are copied to device memory verbatim.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rs.h"
+
+namespace rs {
+
+// Per-problem device view: geometry in tree order, structure-of-arrays.
+struct ProbDev {
+  const double *x[3];      // coordinates, x[a][i]
+  const double *nrm[3];    // unit normals (double-layer kernels) or null
+  const double *w;         // quadrature weights
+  const double *kappa;     // curvature (2D double layer) or null
+  int32_t kind;            // rs_kernel_kind
+  int32_t dim;
+  double c;                // identity coefficient
+  int32_t npx;             // proxy points
+  int32_t log_kernel;      // 1: append the charge and constant rows
+  double eps;              // relative ID precision
+  double ratio;            // proxy radius / box side
+};
+
+// One box of one level, for the compression kernels (assembly + ID).
+struct CompBox {
+  int32_t prob;            // index into the ProbDev table
+  int32_t n;               // active DOFs
+  int32_t nn;              // near DOFs
+  int32_t m;               // rows of M = 2 nn + 2 npx (+2)
+  int64_t J_off;           // int32 tree positions in the index pool
+  int64_t N_off;           // near tree positions in the index pool
+  int64_t M_off;           // doubles, column-major m x n, ld = m
+  double cen[3];
+  double rho;              // proxy radius
+  int64_t order_off;       // ints: out, sorted skeleton then redundant local positions
+  int32_t kslot;           // index of this box's rank in the rank array
+  int32_t pad;
+  double *T;               // out: T (k x (n-k)), the head of the box's factor slot
+};
+
+// One box of one level for the diagonal-block assembly and box factorization.
+struct FacBox {
+  int32_t prob;
+  int32_t n;
+  int32_t kslot;           // rank index (ignored if force_k0)
+  int32_t force_k0;        // root: eliminate everything (k = 0)
+  int32_t leaf;            // D = A(J, J) with the diagonal rule
+  int32_t nchild;
+  int64_t J_off;           // tree positions (int32) of the active DOFs (local order)
+  int64_t order_off;       // sorted s then r local positions (int32), from the ID
+  double *slot;            // T | G | E | F | Lambda (layout below)
+  int64_t work_off;        // doubles of workspace: n*n + r*2r
+  int32_t child_lo[8];     // segment of each child in the local order
+  int32_t child_k[8];
+  const double *child_lam[8];  // Lambda of each child (k_c x k_c, column-major)
+};
+
+// One box for the solve sweeps.
+struct SweepBox {
+  int32_t k, r;            // skeleton / redundant counts
+  const int32_t *idx;      // k skeleton tree positions, then r redundant ones
+  const double *T;         // k x r
+  const double *G;         // r x r  (X_rr^{-1})
+  const double *E;         // k x r  (X_sr G)
+  const double *F;         // r x k  (G X_rs)
+};
+
+// Slot layout of a factored box with n = k + r.
+__host__ __device__ inline int64_t slot_T(int k, int r) { (void)k; (void)r; return 0; }
+__host__ __device__ inline int64_t slot_G(int k, int r) { return (int64_t)k * r; }
+__host__ __device__ inline int64_t slot_E(int k, int r) { return (int64_t)k * r + (int64_t)r * r; }
+__host__ __device__ inline int64_t slot_F(int k, int r) { return 2 * (int64_t)k * r + (int64_t)r * r; }
+__host__ __device__ inline int64_t slot_L(int k, int r) { return 3 * (int64_t)k * r + (int64_t)r * r; }
+__host__ __device__ inline int64_t slot_size(int k, int r) {
+  return 3 * (int64_t)k * r + (int64_t)r * r + (int64_t)k * k;
+}
+// Upper bound of slot_size over k + r = n (maximum 5n^2/4 at k = n/2 ... bounded by
+// 1.25 n^2 + n for every split).
+__host__ __device__ inline int64_t slot_bound(int n) { return (5 * (int64_t)n * n) / 4 + n + 8; }
+
+// ------------------------------------------------------------------ launchers
+// All launchers enqueue on `st`; grid = one workgroup per box in [first, first+count).
+void launch_assemble(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                     const int32_t *pool, double *Marena, int max_npx, hipStream_t st);
+void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n,
+                    hipStream_t st);
+void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
+                        const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
+                        double *work, int32_t *err, int max_n, hipStream_t st);
+size_t cpqr_lds_bytes(int max_n);
+void launch_permute_in(const double *B, int64_t ldb, double *W, const int64_t *perm, int64_t n,
+                       int nrhs, hipStream_t st);
+void launch_permute_out(double *B, int64_t ldb, const double *W, const int64_t *perm,
+                        int64_t n, int nrhs, hipStream_t st);
+void launch_sweep_up(const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                     int max_n, hipStream_t st);
+void launch_sweep_down(const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                       int max_n, hipStream_t st);
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+
+#define RS_HIP_CHECK(expr)                                                   \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) throw rs::DeviceError(#expr, e_);                  \
+  } while (0)
+
+struct DeviceError {
+  std::string what;
+  DeviceError(const char *expr, hipError_t e)
+      : what(std::string(expr) + ": " + hipGetErrorString(e)) {}
+};
+
+struct Status {
+  rs_status code;
+  std::string msg;
+};
+
+}  // namespace rs

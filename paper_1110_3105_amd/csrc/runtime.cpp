@@ -1,0 +1,572 @@
+// Factor and solve drivers.
+//
+// Factorization (Sections 3.1, 3.2, 3.4) runs level-synchronously from the finest
+// depth to the root.  Per step, the host plans every box of the level (active set,
+// near DOFs inside the proxy surface), the device assembles and compresses all boxes
+// in one launch per kernel, the ranks and skeleton orders come back to the host (they
+// decide the next level's active sets), and one more launch forms the diagonal blocks
+// and box factors.  Several problems are factored together by aligning them at their
+// finest depth: step t handles depth maxdepth_p - t of every problem p.
+//
+// Host planning is compiled with -ffp-contract=off so that the near-field test
+// |x - c|^2 < rho^2 is evaluated with exactly the same roundings as the reference.
+#include "runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+namespace rs {
+
+void *Arena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  if (chunks.empty() || used + bytes > chunks.back()->bytes) {
+    auto c = std::make_unique<DevBuf>();
+    c->ensure(std::max<size_t>(bytes, size_t(32) << 20));
+    chunks.push_back(std::move(c));
+    used = 0;
+  }
+  void *p = static_cast<char *>(chunks.back()->p) + used;
+  used += bytes;
+  total += bytes;
+  return p;
+}
+
+namespace {
+
+// Transient device buffers shared by all factor calls (grown on demand).
+struct Scratch {
+  DevBuf pool, comp, fac, M, order, ranks, work, err, probs;
+};
+
+std::mutex g_factor_mutex;
+Scratch &scratch() {
+  static Scratch *s = new Scratch();   // lives for the process
+  return *s;
+}
+
+template <class T>
+void upload(DevBuf &buf, const std::vector<T> &v, hipStream_t st) {
+  buf.ensure(std::max<size_t>(v.size() * sizeof(T), 8));
+  if (!v.empty())
+    RS_HIP_CHECK(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+struct ProbState {
+  const FactorRequest *req = nullptr;
+  rs_factor_s *h = nullptr;
+  const Tree *t = nullptr;
+  int pidx = 0;
+  std::vector<std::vector<int32_t>> J, skel;
+  std::vector<int> leaves_by_depth;   // leaves sorted by depth
+  std::vector<char> mark;
+  int npx = 0;
+  bool log_kernel = false;
+};
+
+// Near DOFs of every box of depth d: active DOFs outside the box's own active set,
+// strictly inside the proxy radius (Section 3.2).
+void plan_near(ProbState &ps, int d, std::vector<std::vector<int32_t>> &near) {
+  const Tree &t = *ps.t;
+  const std::vector<int> &boxes = t.levels[d];
+  const int dim = t.dim;
+  const double ratio = ps.req->k->proxy_ratio;
+  const double side_d = t.side[boxes[0]];
+  double origin[3] = {0, 0, 0};
+  for (int a = 0; a < dim; ++a) origin[a] = t.center[a] - t.side[0] * 0.5;
+  std::unordered_map<uint64_t, std::vector<int32_t>> cells;
+  cells.reserve(boxes.size() * 4 + 16);
+  auto cell_of = [&](double x, int a) -> int64_t {
+    return (int64_t)std::floor((x - origin[a]) / side_d);
+  };
+  auto key_of = [](const int64_t *c) -> uint64_t {
+    return ((uint64_t)(c[0] + (1 << 20)) << 42) | ((uint64_t)(c[1] + (1 << 20)) << 21) |
+           (uint64_t)(c[2] + (1 << 20));
+  };
+  auto add_dof = [&](int32_t g) {
+    int64_t c[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) c[a] = cell_of(t.coords[(size_t)a * t.n + g], a);
+    cells[key_of(c)].push_back(g);
+  };
+  for (int b : boxes)
+    for (int32_t g : ps.J[b]) add_dof(g);
+  for (int lb : ps.leaves_by_depth) {
+    if (t.depth[lb] >= d) break;
+    for (int64_t g = t.begin[lb]; g < t.end[lb]; ++g) add_dof((int32_t)g);
+  }
+  const int R = (int)std::ceil(ratio - 0.5) + 1;
+  near.assign(boxes.size(), {});
+  for (size_t bi = 0; bi < boxes.size(); ++bi) {
+    const int b = boxes[bi];
+    for (int32_t g : ps.J[b]) ps.mark[g] = 1;
+    const double *c = &t.center[3 * b];
+    const double rho = ratio * t.side[b];
+    const double rho2 = rho * rho;
+    int64_t cb[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) cb[a] = cell_of(c[a], a);
+    std::vector<int32_t> &out = near[bi];
+    const int R2 = dim == 3 ? R : 0;
+    for (int64_t o0 = -R; o0 <= R; ++o0)
+      for (int64_t o1 = -R; o1 <= R; ++o1)
+        for (int64_t o2 = -R2; o2 <= R2; ++o2) {
+          int64_t cc[3] = {cb[0] + o0, cb[1] + o1, dim == 3 ? cb[2] + o2 : 0};
+          auto it = cells.find(key_of(cc));
+          if (it == cells.end()) continue;
+          for (int32_t g : it->second) {
+            if (ps.mark[g]) continue;
+            double d2 = 0.0;
+            for (int a = 0; a < dim; ++a) {
+              const double df = t.coords[(size_t)a * t.n + g] - c[a];
+              d2 += df * df;
+            }
+            if (d2 < rho2) out.push_back(g);
+          }
+        }
+    std::sort(out.begin(), out.end());
+    for (int32_t g : ps.J[b]) ps.mark[g] = 0;
+  }
+}
+
+// Copies the geometry of one request to device memory in tree order.
+void setup_problem(ProbState &ps, hipStream_t st) {
+  const rs_kernel &k = *ps.req->k;
+  const Tree &t = *ps.t;
+  rs_factor_s *h = ps.h;
+  const int64_t n = t.n;
+  const int dim = t.dim;
+  h->dim = dim;
+  h->n = n;
+  h->kind = k.kind;
+  std::vector<double> host((size_t)n * (2 * dim + 2), 0.0);
+  double *hx = host.data();
+  double *hn = hx + (size_t)dim * n;
+  double *hw = hn + (size_t)dim * n;
+  double *hk = hw + n;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t g = t.perm[i];
+    for (int a = 0; a < dim; ++a) {
+      hx[(size_t)a * n + i] = ps.req->points[g * dim + a];
+      if (k.normals) hn[(size_t)a * n + i] = k.normals[g * dim + a];
+    }
+    hw[i] = ps.req->weights[g];
+    hk[i] = k.curvature ? k.curvature[g] : 0.0;
+  }
+  double *d = h->arena.alloc_n<double>((int64_t)host.size());
+  RS_HIP_CHECK(hipMemcpyAsync(d, host.data(), host.size() * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+  h->d_perm = h->arena.alloc_n<int64_t>(n);
+  RS_HIP_CHECK(hipMemcpyAsync(h->d_perm, t.perm.data(), n * sizeof(int64_t),
+                              hipMemcpyHostToDevice, st));
+  RS_HIP_CHECK(hipStreamSynchronize(st));   // `host` is released on return
+  ProbDev &P = h->prob;
+  std::memset(&P, 0, sizeof(P));
+  for (int a = 0; a < dim; ++a) {
+    P.x[a] = d + (size_t)a * n;
+    P.nrm[a] = k.normals ? d + (size_t)(dim + a) * n : nullptr;
+  }
+  P.w = d + (size_t)2 * dim * n;
+  P.kappa = k.curvature ? d + (size_t)(2 * dim + 1) * n : nullptr;
+  P.kind = k.kind;
+  P.dim = dim;
+  P.c = k.identity;
+  P.npx = k.proxy_points;
+  P.log_kernel = k.kind == RS_LAP2D_SL ? 1 : 0;
+  P.eps = ps.req->eps;
+  P.ratio = k.proxy_ratio;
+  ps.npx = k.proxy_points;
+  ps.log_kernel = P.log_kernel != 0;
+  const int nb = t.nbox();
+  ps.J.assign(nb, {});
+  ps.skel.assign(nb, {});
+  ps.mark.assign(n, 0);
+  ps.leaves_by_depth.clear();
+  for (int b = 0; b < nb; ++b)
+    if (t.is_leaf(b)) ps.leaves_by_depth.push_back(b);
+  std::stable_sort(ps.leaves_by_depth.begin(), ps.leaves_by_depth.end(),
+                   [&](int a, int b) { return t.depth[a] < t.depth[b]; });
+  h->nbox = nb;
+  h->box_k.assign(nb, -1);
+  h->box_J.assign(nb, {});
+  h->box_skel.assign(nb, {});
+  h->box_slot.assign(nb, nullptr);
+}
+
+struct StepBox {
+  ProbState *ps;
+  int box;
+};
+
+// Gathers a box's active set: its points (leaf) or its children's skeletons.
+void gather_J(ProbState &ps, int b) {
+  const Tree &t = *ps.t;
+  std::vector<int32_t> &J = ps.J[b];
+  J.clear();
+  if (t.is_leaf(b)) {
+    for (int64_t g = t.begin[b]; g < t.end[b]; ++g) J.push_back((int32_t)g);
+  } else {
+    for (int c = t.first_child[b]; c < t.first_child[b] + t.nchild[b]; ++c)
+      J.insert(J.end(), ps.skel[c].begin(), ps.skel[c].end());
+  }
+}
+
+// Fills the FacBox child fields of box b (children already factored).
+void fill_children(ProbState &ps, int b, FacBox &fb) {
+  const Tree &t = *ps.t;
+  fb.nchild = t.is_leaf(b) ? 0 : t.nchild[b];
+  int lo = 0;
+  for (int ci = 0; ci < fb.nchild; ++ci) {
+    const int c = t.first_child[b] + ci;
+    const int kc = ps.h->box_k[c];
+    const int nc = (int)ps.h->box_J[c].size();
+    fb.child_lo[ci] = lo;
+    fb.child_k[ci] = kc;
+    fb.child_lam[ci] = ps.h->box_slot[c] + slot_L(kc, nc - kc);
+    lo += kc;
+  }
+}
+
+void check_err(DevBuf &err, hipStream_t st, const std::vector<StepBox> &items, const char *what) {
+  int32_t e = -1;
+  RS_HIP_CHECK(hipMemcpyAsync(&e, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  RS_HIP_CHECK(hipStreamSynchronize(st));
+  if (e >= 0) {
+    const StepBox &sb = items[e];
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: zero or non-finite pivot at depth %d, box %d", what,
+             sb.ps->t->depth[sb.box], sb.box);
+    throw UserError{RS_ESINGULAR, buf};
+  }
+}
+
+}  // namespace
+
+void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
+                 std::vector<rs_factor_s *> &out) {
+  std::lock_guard<std::mutex> lock(g_factor_mutex);
+  auto t0 = std::chrono::steady_clock::now();
+  const int np = (int)reqs.size();
+  std::vector<std::unique_ptr<rs_factor_s>> handles(np);
+  std::vector<ProbState> ps(np);
+  Scratch &S = scratch();
+  std::vector<ProbDev> probs(np);
+  int max_npx = 0, max_depth = 0;
+  for (int p = 0; p < np; ++p) {
+    handles[p].reset(new rs_factor_s());
+    ps[p].req = &reqs[p];
+    ps[p].h = handles[p].get();
+    ps[p].t = reqs[p].tree;
+    ps[p].pidx = p;
+    setup_problem(ps[p], st);
+    probs[p] = handles[p]->prob;
+    max_npx = std::max(max_npx, ps[p].npx);
+    max_depth = std::max(max_depth, ps[p].t->maxdepth);
+  }
+  upload(S.probs, probs, st);
+  const ProbDev *d_probs = S.probs.as<ProbDev>();
+  S.err.ensure(sizeof(int32_t));
+  const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
+  int64_t max_m_seen = 0;
+
+  // ---- compressed levels, aligned at the finest depth of every problem
+  for (int step = 0; step < max_depth; ++step) {
+    std::vector<StepBox> items;
+    for (int p = 0; p < np; ++p) {
+      const int d = ps[p].t->maxdepth - step;
+      if (d < 1) continue;
+      for (int b : ps[p].t->levels[d]) items.push_back({&ps[p], b});
+    }
+    if (items.empty()) continue;
+    const int cnt = (int)items.size();
+    // plan: active sets and near lists
+    std::vector<std::vector<int32_t>> near_all(cnt);
+    {
+      int idx = 0;
+      for (int p = 0; p < np; ++p) {
+        const int d = ps[p].t->maxdepth - step;
+        if (d < 1) continue;
+        for (int b : ps[p].t->levels[d]) gather_J(ps[p], b);
+        std::vector<std::vector<int32_t>> nr;
+        plan_near(ps[p], d, nr);
+        for (auto &v : nr) near_all[idx++] = std::move(v);
+      }
+    }
+    std::vector<int32_t> pool;
+    std::vector<CompBox> comp(cnt);
+    int64_t M_total = 0, order_total = 0, work_total = 0;
+    int max_n = 0;
+    for (int i = 0; i < cnt; ++i) {
+      ProbState &P = *items[i].ps;
+      const int b = items[i].box;
+      CompBox &cb = comp[i];
+      std::memset(&cb, 0, sizeof(cb));
+      const std::vector<int32_t> &J = P.J[b];
+      cb.prob = P.pidx;
+      cb.n = (int)J.size();
+      cb.nn = (int)near_all[i].size();
+      cb.m = 2 * cb.nn + 2 * P.npx + (P.log_kernel ? 2 : 0);
+      cb.J_off = (int64_t)pool.size();
+      pool.insert(pool.end(), J.begin(), J.end());
+      cb.N_off = (int64_t)pool.size();
+      pool.insert(pool.end(), near_all[i].begin(), near_all[i].end());
+      cb.M_off = M_total;
+      M_total += (int64_t)cb.m * cb.n;
+      for (int a = 0; a < 3; ++a) cb.cen[a] = P.t->center[3 * b + a];
+      cb.rho = P.req->k->proxy_ratio * P.t->side[b];
+      cb.order_off = order_total;
+      order_total += cb.n;
+      cb.kslot = i;
+      double *slot = P.h->arena.alloc_n<double>(slot_bound(cb.n));
+      cb.T = slot;
+      P.h->box_slot[b] = slot;
+      work_total += 3 * (int64_t)cb.n * cb.n;
+      max_n = std::max(max_n, cb.n);
+      max_m_seen = std::max<int64_t>(max_m_seen, cb.m);
+    }
+    if (cpqr_lds_bytes(max_n) > 160 * 1024)
+      throw UserError{RS_ENOTSUP, "a box's active set exceeds the on-chip ID limit"};
+    upload(S.pool, pool, st);
+    upload(S.comp, comp, st);
+    S.M.ensure(std::max<int64_t>(M_total, 1) * sizeof(double));
+    S.order.ensure(std::max<int64_t>(order_total, 1) * sizeof(int32_t));
+    S.ranks.ensure(std::max(cnt, 1) * sizeof(int32_t));
+    S.work.ensure(std::max<int64_t>(work_total, 1) * sizeof(double));
+    const CompBox *d_comp = S.comp.as<CompBox>();
+    if (per_box) {
+      for (int i = 0; i < cnt; ++i) {
+        launch_assemble(d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(), max_npx, st);
+        launch_cpqr_id(d_comp, i, 1, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
+                       S.ranks.as<int32_t>(), comp[i].n, st);
+      }
+    } else {
+      launch_assemble(d_comp, 0, cnt, d_probs, S.pool.as<int32_t>(), S.M.as<double>(), max_npx, st);
+      launch_cpqr_id(d_comp, 0, cnt, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
+                     S.ranks.as<int32_t>(), max_n, st);
+    }
+    std::vector<int32_t> ranks(cnt), order(order_total);
+    RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), S.ranks.p, cnt * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+    if (order_total)
+      RS_HIP_CHECK(hipMemcpyAsync(order.data(), S.order.p, order_total * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
+    RS_HIP_CHECK(hipStreamSynchronize(st));
+    // record skeletons; build the factor descriptors
+    std::vector<FacBox> fac(cnt);
+    int64_t woff = 0;
+    for (int i = 0; i < cnt; ++i) {
+      ProbState &P = *items[i].ps;
+      const int b = items[i].box;
+      const CompBox &cb = comp[i];
+      const int k = ranks[i];
+      const std::vector<int32_t> &J = P.J[b];
+      const int32_t *ord = order.data() + cb.order_off;
+      std::vector<int32_t> &sk = P.skel[b];
+      sk.resize(k);
+      for (int a = 0; a < k; ++a) sk[a] = J[ord[a]];
+      P.h->box_k[b] = k;
+      P.h->box_J[b] = J;
+      P.h->box_skel[b] = sk;
+      FacBox &fb = fac[i];
+      std::memset(&fb, 0, sizeof(fb));
+      fb.prob = P.pidx;
+      fb.n = cb.n;
+      fb.kslot = i;
+      fb.force_k0 = 0;
+      fb.leaf = P.t->is_leaf(b) ? 1 : 0;
+      fb.J_off = cb.J_off;
+      fb.order_off = cb.order_off;
+      fb.slot = cb.T;
+      fb.work_off = woff;
+      woff += 3 * (int64_t)cb.n * cb.n;
+      fill_children(P, b, fb);
+    }
+    upload(S.fac, fac, st);
+    RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
+    const FacBox *d_fac = S.fac.as<FacBox>();
+    if (per_box) {
+      for (int i = 0; i < cnt; ++i)
+        launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
+                           S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
+                           comp[i].n, st);
+    } else {
+      launch_diag_factor(d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
+                         S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(), max_n,
+                         st);
+    }
+    check_err(S.err, st, items, "box factorization");
+    // persistent solve data: index lists (skeletons then redundant, tree positions)
+    std::vector<std::vector<int32_t>> idx_keep(cnt);   // alive until the step's final sync
+    for (int i = 0; i < cnt; ++i) {
+      ProbState &P = *items[i].ps;
+      const int b = items[i].box;
+      const int k = ranks[i], n = comp[i].n;
+      const int32_t *ord = order.data() + comp[i].order_off;
+      std::vector<int32_t> &idx = idx_keep[i];
+      idx.resize(n);
+      for (int a = 0; a < n; ++a) idx[a] = P.J[b][ord[a]];
+      int32_t *d_idx = P.h->arena.alloc_n<int32_t>(std::max(n, 1));
+      if (n)
+        RS_HIP_CHECK(hipMemcpyAsync(d_idx, idx.data(), n * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st));
+      SweepBox sb;
+      sb.k = k;
+      sb.r = n - k;
+      sb.idx = d_idx;
+      double *slot = comp[i].T;
+      sb.T = slot + slot_T(k, n - k);
+      sb.G = slot + slot_G(k, n - k);
+      sb.E = slot + slot_E(k, n - k);
+      sb.F = slot + slot_F(k, n - k);
+      rs_factor_s *h = P.h;
+      const int d = P.t->depth[b];
+      if (h->levels.empty() || h->levels.back().depth != d) {
+        h->levels.emplace_back();
+        h->levels.back().depth = d;
+      }
+      LevelRec &lv = h->levels.back();
+      lv.boxes.push_back(b);
+      lv.sweep.push_back(sb);
+      lv.max_n = std::max(lv.max_n, n);
+      h->stats.total_skeletons += k;
+      h->stats.factor_doubles += slot_size(k, n - k) - (int64_t)k * k;
+      h->stats.max_box_n = std::max<int64_t>(h->stats.max_box_n, n);
+      h->stats.max_box_m = std::max<int64_t>(h->stats.max_box_m, comp[i].m);
+    }
+    // keep host staging vectors alive until the copies are done
+    RS_HIP_CHECK(hipStreamSynchronize(st));
+  }
+
+  // ---- roots: the dense block of the surviving skeletons, fully eliminated
+  {
+    std::vector<StepBox> items;
+    std::vector<int32_t> pool;
+    std::vector<FacBox> fac;
+    int64_t woff = 0;
+    int max_n = 0;
+    for (int p = 0; p < np; ++p) {
+      ProbState &P = ps[p];
+      const int b = 0;
+      gather_J(P, b);
+      const std::vector<int32_t> &J = P.J[b];
+      FacBox fb;
+      std::memset(&fb, 0, sizeof(fb));
+      fb.prob = P.pidx;
+      fb.n = (int)J.size();
+      fb.force_k0 = 1;
+      fb.leaf = P.t->is_leaf(b) ? 1 : 0;
+      fb.J_off = (int64_t)pool.size();
+      pool.insert(pool.end(), J.begin(), J.end());
+      fb.slot = P.h->arena.alloc_n<double>(std::max<int64_t>((int64_t)fb.n * fb.n, 1));
+      fb.work_off = woff;
+      woff += 3 * (int64_t)fb.n * fb.n;
+      fill_children(P, b, fb);
+      fac.push_back(fb);
+      items.push_back({&P, b});
+      max_n = std::max(max_n, fb.n);
+      P.h->box_k[b] = -1;
+      P.h->box_J[b] = J;
+      P.h->box_slot[b] = fb.slot;
+    }
+    upload(S.pool, pool, st);
+    upload(S.fac, fac, st);
+    S.work.ensure(std::max<int64_t>(woff, 1) * sizeof(double));
+    RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
+    const FacBox *d_fac = S.fac.as<FacBox>();
+    if (per_box) {
+      for (int i = 0; i < np; ++i)
+        launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
+                           S.work.as<double>(), S.err.as<int32_t>(), fac[i].n, st);
+    } else {
+      launch_diag_factor(d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
+                         S.work.as<double>(), S.err.as<int32_t>(), max_n, st);
+    }
+    check_err(S.err, st, items, "root factorization");
+    for (int p = 0; p < np; ++p) {
+      ProbState &P = ps[p];
+      const std::vector<int32_t> &J = P.J[0];
+      const int n = (int)J.size();
+      int32_t *d_idx = P.h->arena.alloc_n<int32_t>(std::max(n, 1));
+      if (n)
+        RS_HIP_CHECK(hipMemcpyAsync(d_idx, J.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      SweepBox sb;
+      sb.k = 0;
+      sb.r = n;
+      sb.idx = d_idx;
+      sb.T = sb.E = sb.F = nullptr;
+      sb.G = fac[p].slot;
+      rs_factor_s *h = P.h;
+      h->root.depth = 0;
+      h->root.boxes = {0};
+      h->root.sweep = {sb};
+      h->root.max_n = n;
+      h->stats.root_size = n;
+      h->stats.factor_doubles += (int64_t)n * n;
+    }
+  }
+  // ---- upload the sweep descriptors
+  for (int p = 0; p < np; ++p) {
+    rs_factor_s *h = handles[p].get();
+    for (LevelRec &lv : h->levels) {
+      lv.d_sweep = h->arena.alloc_n<SweepBox>((int64_t)lv.sweep.size());
+      RS_HIP_CHECK(hipMemcpyAsync(lv.d_sweep, lv.sweep.data(), lv.sweep.size() * sizeof(SweepBox),
+                                  hipMemcpyHostToDevice, st));
+    }
+    h->root.d_sweep = h->arena.alloc_n<SweepBox>(1);
+    RS_HIP_CHECK(hipMemcpyAsync(h->root.d_sweep, h->root.sweep.data(), sizeof(SweepBox),
+                                hipMemcpyHostToDevice, st));
+  }
+  RS_HIP_CHECK(hipStreamSynchronize(st));
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  out.resize(np);
+  for (int p = 0; p < np; ++p) {
+    rs_factor_s *h = handles[p].get();
+    h->stats.n = h->n;
+    h->stats.nbox = ps[p].t->nbox();
+    h->stats.maxdepth = ps[p].t->maxdepth;
+    h->stats.dim = h->dim;
+    h->stats.factor_ms = ms;
+    out[p] = handles[p].release();
+  }
+}
+
+void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode,
+               hipStream_t st) {
+  if (nrhs == 0) return;
+  const int64_t n = h->n;
+  double *W = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)n * nrhs * sizeof(double), st));
+  struct Freer {
+    double *W;
+    hipStream_t st;
+    ~Freer() { (void)hipFreeAsync(W, st); }
+  } freer{W, st};
+  const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
+  launch_permute_in(B, ldb, W, h->d_perm, n, nrhs, st);
+  auto up = [&](const LevelRec &lv) {
+    const int cnt = (int)lv.sweep.size();
+    if (per_box) {
+      for (int i = 0; i < cnt; ++i)
+        launch_sweep_up(lv.d_sweep, i, 1, W, nrhs, lv.sweep[i].k + lv.sweep[i].r, st);
+    } else {
+      launch_sweep_up(lv.d_sweep, 0, cnt, W, nrhs, lv.max_n, st);
+    }
+  };
+  auto down = [&](const LevelRec &lv) {
+    const int cnt = (int)lv.sweep.size();
+    if (per_box) {
+      for (int i = 0; i < cnt; ++i)
+        launch_sweep_down(lv.d_sweep, i, 1, W, nrhs, lv.sweep[i].k + lv.sweep[i].r, st);
+    } else {
+      launch_sweep_down(lv.d_sweep, 0, cnt, W, nrhs, lv.max_n, st);
+    }
+  };
+  for (const LevelRec &lv : h->levels) up(lv);
+  up(h->root);
+  for (auto it = h->levels.rbegin(); it != h->levels.rend(); ++it) down(*it);
+  launch_permute_out(B, ldb, W, h->d_perm, n, nrhs, st);
+}
+
+}  // namespace rs

@@ -1,0 +1,97 @@
+// Host runtime: device arenas, factor handles, the level planner and the solve driver.
+#pragma once
+
+#include <atomic>
+#include <memory>
+#include <vector>
+
+#include "rs_internal.h"
+#include "tree.h"
+
+namespace rs {
+
+// Owning device allocation.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // Grow-only; contents are not preserved when it grows.
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    release();
+    RS_HIP_CHECK(hipMalloc(&p, b < 256 ? 256 : b));
+    bytes = b < 256 ? 256 : b;
+  }
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Bump allocator over device chunks; everything lives until the owner is freed.
+struct Arena {
+  std::vector<std::unique_ptr<DevBuf>> chunks;
+  size_t used = 0;
+  size_t total = 0;
+  void *alloc(size_t bytes);
+  template <class T> T *alloc_n(int64_t n) { return static_cast<T *>(alloc(sizeof(T) * (size_t)n)); }
+};
+
+// One compressed level (or the root) of one factored problem.
+struct LevelRec {
+  int depth = 0;
+  std::vector<int> boxes;
+  std::vector<SweepBox> sweep;     // host copy (device pointers inside)
+  SweepBox *d_sweep = nullptr;     // device copy
+  int max_n = 0;
+};
+
+}  // namespace rs
+
+struct rs_factor_s {
+  int dim = 0;
+  int64_t n = 0;
+  int kind = 0;
+  rs::Arena arena;                       // geometry, factors, index lists, descriptors
+  int64_t *d_perm = nullptr;             // tree position -> caller index
+  rs::ProbDev prob{};                    // device view of the geometry
+  std::vector<rs::LevelRec> levels;      // compressed depths, finest first
+  rs::LevelRec root;
+  // host-side record for queries
+  std::vector<int32_t> box_k;            // -1 for the root
+  std::vector<std::vector<int32_t>> box_J, box_skel;
+  std::vector<double *> box_slot;
+  int nbox = 0;
+  rs_stats stats{};
+  std::atomic<int> busy{0};
+};
+
+namespace rs {
+
+struct FactorRequest {
+  const rs_kernel *k;
+  const Tree *tree;
+  const double *points;
+  const double *weights;
+  double eps;
+};
+
+// Factors every request; shared per-level launches across requests.  On success
+// out[i] owns a new handle.  Throws on failure (all partial handles freed).
+void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
+                 std::vector<rs_factor_s *> &out);
+
+void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode,
+               hipStream_t st);
+
+struct UserError {
+  rs_status code;
+  std::string what;
+};
+
+}  // namespace rs

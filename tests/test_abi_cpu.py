@@ -1,0 +1,85 @@
+"""C-ABI library checks that need no GPU: it loads, exports every declared entry point,
+the host tree builder matches the oracle's tree exactly, and argument validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.tree import build_tree as oracle_tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "rs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rs_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1110_3105_amd as rs
+    lib = ctypes.CDLL(rs.LIB_PATH)
+    declared = _declared_symbols()
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(rs.EXPORTED) <= set(declared)
+
+
+@pytest.mark.parametrize("mk,leaf", [(lambda: W.star_curve(4096), 64),
+                                     (lambda: W.star_curve(65536), 64),
+                                     (lambda: W.random_curve(3000, [0.03, 0.01, 0.02], [0.1, 2.0, 4.0]), 32),
+                                     (lambda: W.fibonacci_sphere(20480), 128),
+                                     (lambda: W.ellipse(777), 16)])
+def test_host_tree_matches_oracle_tree(mk, leaf):
+    import paper_1110_3105_amd as rs
+    g = mk()
+    t = rs.build_tree(g.points, leaf)
+    e = t.export()
+    o = oracle_tree(g.points, leaf)
+    assert np.array_equal(e["perm"], o.perm)
+    assert np.array_equal(e["depth"], o.depth)
+    assert np.array_equal(e["parent"], o.parent)
+    assert np.array_equal(e["begin"], o.begin) and np.array_equal(e["end"], o.end)
+    assert np.array_equal(e["center"], o.center) and np.array_equal(e["side"], o.side)
+
+
+def test_tree_argument_errors():
+    import paper_1110_3105_amd as rs
+    with pytest.raises(rs.RSError) as ei:
+        rs.build_tree(np.zeros((0, 2)), 8)
+    assert ei.value.code == 1
+    bad = np.array([[0.0, 1.0], [np.nan, 2.0]])
+    with pytest.raises(rs.RSError):
+        rs.build_tree(bad, 8)
+    with pytest.raises(rs.RSError):
+        rs.build_tree(np.zeros((5, 2)), 0)
+
+
+def test_factor_argument_validation_before_device_use():
+    import paper_1110_3105_amd as rs
+    g = W.star_curve(256)
+    t = rs.build_tree(g.points, 32)
+    cases = [
+        dict(kind="lap2d_dl"),                                   # no normals / curvature
+        dict(kind="lap3d_sl"),                                   # dimension mismatch
+        dict(kind="lap2d_sl", eps=-1.0),
+        dict(kind="lap2d_sl", proxy_points=2),
+        dict(kind="lap2d_sl", proxy_ratio=0.5),
+        dict(kind="lap2d_sl", weights=-g.weights),
+        dict(kind="lap2d_sl", points=g.points[::-1].copy()),      # not the tree's points
+    ]
+    for c in cases:
+        args = dict(kind="lap2d_sl", points=g.points, weights=g.weights, eps=1e-9)
+        args.update(c)
+        with pytest.raises(rs.RSError) as ei:
+            rs.factor(args["kind"], t, args["points"], args["weights"], args["eps"],
+                      proxy_points=args.get("proxy_points", 64),
+                      proxy_ratio=args.get("proxy_ratio", 1.5))
+        assert ei.value.code == 1, c
+    with pytest.raises(rs.RSError) as ei:
+        rs.factor("helm2d_cfie", t, g.points, g.weights, 1e-9)
+    assert ei.value.code == 6

@@ -1,0 +1,217 @@
+"""Parity of the HIP path with the CPU oracle (MI355X).
+
+Each case builds the same seeded inputs for both sides, factors and solves through the
+C ABI, and compares with the oracle element by element:
+
+* skeleton sets per box are identical wherever the oracle reports no tied pivot and
+  no rank decision within 1e-10 of the threshold (then everything downstream is the
+  same computation up to rounding);
+* interpolation matrices T agree to within the conditioning of R11 (whose condition
+  number is up to 1/eps, so entries may differ by ~u/eps relative), and the device's T
+  satisfies the column-residual bound of the ID on the oracle's own block M;
+* solutions agree with the oracle's to 10 eps relative (the tolerance of the
+  acceptance criterion), and second-kind residuals are below 10 eps;
+* eps = 0 reproduces dense Gaussian elimination.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Problem, dense
+from oracle import factor as ofactor
+from oracle.rs import compression_block
+
+U = np.finfo(np.float64).eps
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(kind, g, c=None):
+    if kind == "lap2d_dl":
+        return Problem(kind, g.points, g.weights, g.normals, g.curvature,
+                       identity=-0.5 if c is None else c)
+    return Problem(kind, g.points, g.weights, identity=0.0 if c is None else c)
+
+
+def _gpu_factor(rs, kind, g, eps, leaf, npx, c=None, mode="level"):
+    t = rs.build_tree(g.points, leaf)
+    ident = c if c is not None else (-0.5 if kind == "lap2d_dl" else 0.0)
+    h = rs.factor(kind, t, g.points, g.weights, eps,
+                  normals=g.normals if kind == "lap2d_dl" else None,
+                  curvature=g.curvature if kind == "lap2d_dl" else None,
+                  identity=ident, proxy_points=npx, launch_mode=mode)
+    return t, h
+
+
+def _gpu_solve(h, b, mode="level"):
+    import torch
+    B = torch.tensor(np.asfortranarray(b), dtype=torch.float64, device="cuda")
+    if B.dim() == 2:
+        B = B.t().contiguous().t()
+    h.solve(B, launch_mode=mode)
+    torch.cuda.synchronize()
+    return B.cpu().numpy()
+
+
+def _compare_skeletons(h, F, residual_every=1):
+    """Skeleton sets equal on every box whose subtree has no tie; returns #compared."""
+    ks, sk = h.box_skeletons()
+    t = F.tree
+    tied = set()
+    for b in sorted(F.records, key=lambda b: -t.depth[b]):
+        r = F.records[b]
+        if r.idr.first_tie >= 0 or r.idr.near_threshold or any(c in tied for c in t.children[b]):
+            tied.add(b)
+    compared = 0
+    for b, r in F.records.items():
+        if b in tied:
+            continue
+        assert ks[b] == r.k, f"rank differs at box {b}: {ks[b]} vs {r.k}"
+        assert np.array_equal(np.sort(sk[b]), r.skel), f"skeletons differ at box {b}"
+        J, T = h.box_export(b)
+        assert np.array_equal(J, r.J)
+        if r.k and r.n - r.k:
+            scale = max(np.abs(r.idr.T).max(), 1.0)
+            cond = r.idr.rdiag[0] / r.idr.rdiag[r.k - 1]
+            assert np.abs(T - r.idr.T).max() <= 1e3 * U * cond * scale, f"T differs at box {b}"
+            if b % residual_every == 0:
+                tr = F.tree
+                M = compression_block(F.prob, r.J, r.near, tr.center[b],
+                                      F.opts.proxy_ratio * tr.side[b], F.opts.proxy_points)
+                res = M[:, r.idr.redund] - M[:, r.idr.skel] @ T
+                bound = 2.0 * r.idr.rdiag[r.k] + 1e-13 * r.idr.rdiag[0]
+                assert np.linalg.norm(res, axis=0).max() <= bound, f"ID residual at box {b}"
+        compared += 1
+    return compared, len(tied)
+
+
+@pytest.mark.parametrize("kind,n,eps,leaf,npx", [
+    ("lap2d_dl", 4096, 1e-9, 64, 64),      # the small star configuration at full size
+    ("lap2d_sl", 4096, 1e-9, 64, 64),
+    ("lap2d_sl", 3000, 1e-6, 48, 64),      # ragged leaves
+    ("lap2d_sl", 2048, 1e-12, 64, 96),
+])
+def test_star_parity(gpu_lib, kind, n, eps, leaf, npx):
+    rs = gpu_lib
+    g = W.star_curve(n)
+    p = _problem(kind, g)
+    F = ofactor(p, eps, leaf, npx)
+    t, h = _gpu_factor(rs, kind, g, eps, leaf, npx)
+    compared, tied = _compare_skeletons(h, F)
+    assert compared >= 0.9 * len(F.records)
+    assert h.stats()["root_size"] == F.root_size or tied
+    b = W.gaussian_rhs(n, 1, 0)
+    x = _gpu_solve(h, b)
+    xo = F.solve(b)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    if tied == 0:
+        assert rel <= 10 * eps, rel
+    A = dense.matrix(p)
+    res = np.linalg.norm(A @ x - b) / np.linalg.norm(b)
+    kappa = np.linalg.cond(A) if kind != "lap2d_dl" else 10.0
+    assert res <= (10 * eps if kind == "lap2d_dl" else 10 * eps * kappa), res
+
+
+def test_multi_rhs_ragged_tiles(gpu_lib):
+    rs = gpu_lib
+    g = W.star_curve(2500)
+    p = _problem("lap2d_dl", g)
+    F = ofactor(p, 1e-9, 32, 64)
+    _, h = _gpu_factor(rs, "lap2d_dl", g, 1e-9, 32, 64)
+    for nrhs in (1, 3, 37, 64, 130):
+        b = W.gaussian_rhs(2500, nrhs, 10 + nrhs)
+        x = _gpu_solve(h, b)
+        xo = F.solve(b)
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_eps_zero_is_dense_lu(gpu_lib):
+    rs = gpu_lib
+    g = W.star_curve(700)
+    p = _problem("lap2d_sl", g)
+    _, h = _gpu_factor(rs, "lap2d_sl", g, 0.0, 32, 64)
+    st = h.stats()
+    assert st["root_size"] == 700
+    b = W.gaussian_rhs(700, 2, 4)
+    x = _gpu_solve(h, b)
+    xd = dense.solve(p, b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-11
+
+
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65])
+def test_tiny_and_single_box(gpu_lib, n):
+    rs = gpu_lib
+    g = W.star_curve(n)
+    p = _problem("lap2d_dl", g)
+    _, h = _gpu_factor(rs, "lap2d_dl", g, 1e-9, 64, 64)
+    b = W.gaussian_rhs(n, 2, n)
+    x = _gpu_solve(h, b)
+    xd = dense.solve(p, b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-9
+
+
+def test_per_box_launches_match_level_launches_bitwise(gpu_lib):
+    rs = gpu_lib
+    g = W.star_curve(3000)
+    _, h1 = _gpu_factor(rs, "lap2d_sl", g, 1e-9, 64, 64, mode="level")
+    _, h2 = _gpu_factor(rs, "lap2d_sl", g, 1e-9, 64, 64, mode="per_box")
+    k1, s1 = h1.box_skeletons()
+    k2, s2 = h2.box_skeletons()
+    assert np.array_equal(k1, k2)
+    b = W.gaussian_rhs(3000, 5, 7)
+    xa = _gpu_solve(h1, b, "level")
+    xb = _gpu_solve(h2, b, "per_box")
+    xc = _gpu_solve(h1, b, "per_box")
+    assert np.array_equal(xa, xb) and np.array_equal(xa, xc)
+
+
+def test_repeat_runs_bitwise_identical(gpu_lib):
+    rs = gpu_lib
+    g = W.star_curve(4096)
+    _, h1 = _gpu_factor(rs, "lap2d_dl", g, 1e-9, 64, 64)
+    _, h2 = _gpu_factor(rs, "lap2d_dl", g, 1e-9, 64, 64)
+    b = W.gaussian_rhs(4096, 3, 1)
+    assert np.array_equal(_gpu_solve(h1, b), _gpu_solve(h2, b))
+    assert np.array_equal(_gpu_solve(h1, b), _gpu_solve(h1, b))
+
+
+def test_sphere_parity(gpu_lib):
+    rs = gpu_lib
+    g = W.fibonacci_sphere(2048)
+    p = _problem("lap3d_sl", g)
+    F = ofactor(p, 1e-6, 128, 256)
+    t, h = _gpu_factor(rs, "lap3d_sl", g, 1e-6, 128, 256)
+    compared, tied = _compare_skeletons(h, F)
+    assert compared >= 0.9 * len(F.records)
+    b = W.gaussian_rhs(2048, 4, 2)
+    x = _gpu_solve(h, b)
+    xo = F.solve(b)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    if tied == 0:
+        assert rel <= 10 * 1e-6
+    A = dense.matrix(p)
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 10 * 1e-6 * np.linalg.cond(A)
+
+
+def test_headline_size_parity(gpu_lib):
+    """Star, log single layer, N = 65536, eps = 1e-9 (the benchmark workload), compared
+    with the full oracle run at the same size."""
+    rs = gpu_lib
+    n, eps = 65536, 1e-9
+    g = W.star_curve(n)
+    p = _problem("lap2d_sl", g)
+    F = ofactor(p, eps, 64, 64)
+    _, h = _gpu_factor(rs, "lap2d_sl", g, eps, 64, 64)
+    compared, tied = _compare_skeletons(h, F, residual_every=13)
+    assert compared >= 0.95 * len(F.records)
+    b = W.gaussian_rhs(n, 4, 1)
+    x = _gpu_solve(h, b)
+    xo = F.solve(b)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    if tied == 0:
+        assert rel <= 10 * eps, rel
+    # residual on sampled rows against the exact matrix, backward-error form
+    rows = np.random.default_rng(0).choice(n, 64, replace=False)
+    r = dense.matvec_rows(p, rows, x) - b[rows]
+    ax = dense.matvec_rows(p, rows, xo)
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(ax)
