@@ -1,0 +1,217 @@
+#!/usr/bin/env python
+"""Benchmark of the recursive-skeletonization factor + solve on one MI355X.
+
+Workload (synthetic, seeded): star curve r(t) = 1 + 0.3 cos 5t with N = 65536
+equispaced nodes and trapezoid weights, 2D Laplace single layer (log kernel, first
+kind), eps = 1e-9, leaf size 64, 64 proxy points at 1.5 x box side, 512 Gaussian
+right-hand sides (seed 1).  The paper's own 2D workload is an ellipse with the double
+layer (Table 5); this star curve stands in for it.
+
+One step = the whole hot path on one batch: build the tree, compress + factor
+(level-batched launches), solve the 512 right-hand sides, free the factor.  The RHS
+block is device resident; a device copy restores it before each solve.
+
+Printed: one JSON line with the step throughput (RHS solved per second, factor
+included), plus batched-vs-plain (per-level launches vs one launch per box) factor and
+solve figures, p50/p99 single-solve latency, the dominant kernel's roofline from HIP
+events and algorithmic work counts, and the CPU oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "RHS solves/s + factor time at eps=1e-9, batched vs plain; p50/p99 solve latency"
+N, EPS, LEAF, NPX, NRHS, SEED = 65536, 1e-9, 64, 64, 512, 1
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+# families whose dominant resource is HBM traffic rather than FP64 arithmetic
+HBM_FAMILIES = {"assemble", "permute"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed steps (used under rocprofv3)")
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def cpu_baseline(g, b_host):
+    """The oracle, untuned, on the same workload: one factor + one 512-RHS solve."""
+    import numpy as np
+    from oracle import Problem
+    from oracle import factor as ofactor
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:                                    # pragma: no cover
+        cores = 1
+    p = Problem("lap2d_sl", g.points, g.weights)
+    t0 = time.perf_counter()
+    F = ofactor(p, EPS, LEAF, NPX)
+    t1 = time.perf_counter()
+    F.solve(b_host)
+    t2 = time.perf_counter()
+    return {"value": NRHS / (t2 - t0), "unit": "RHS/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"full workload: one oracle factor ({t1 - t0:.1f} s) and one "
+                      f"{NRHS}-RHS solve ({t2 - t1:.2f} s), NumPy/SciPy float64",
+            "factor_s": t1 - t0, "solve_s": t2 - t1,
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1110_3105_amd as rs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    g = W.star_curve(N)
+    b_host = W.gaussian_rhs(N, NRHS, SEED)
+    B0 = torch.tensor(b_host.T.copy(), device=dev).t()        # column-major, ld = N
+    B = torch.empty_like(B0.t()).t()
+    stream = torch.cuda.current_stream(dev)
+
+    def step(mode="level"):
+        t = rs.build_tree(g.points, LEAF)
+        h = rs.factor("lap2d_sl", t, g.points, g.weights, EPS, proxy_points=NPX,
+                      launch_mode=mode, stream=stream)
+        B.copy_(B0)
+        h.solve(B, stream=stream, launch_mode=mode)
+        torch.cuda.synchronize()
+        st = h.stats()
+        h.free()
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    rs.profile_reset()
+    rs.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rs.profile_enable(False)
+    prof = rs.profile_read()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    fams = {}
+    for name, d in prof.items():
+        if d["launches"] == 0:
+            continue
+        avg_ms = d["total_ms"] / d["launches"]
+        if name in HBM_FAMILIES:
+            achieved = d["bytes"] / (d["total_ms"] * 1e-3) / 1e9
+            peak, unit, bound = PEAK_HBM_GBS, "GB/s", "hbm"
+        else:
+            achieved = d["flops"] / (d["total_ms"] * 1e-3) / 1e12
+            peak, unit, bound = PEAK_FP64_VECTOR_TFLOPS, "TFLOP/s", "alu"
+        fams[name] = {"launches_per_step": d["launches"] / args.steps,
+                      "ms_per_step": d["total_ms"] / args.steps, "avg_launch_ms": avg_ms,
+                      "flops_per_launch": d["flops"] / d["launches"],
+                      "bytes_per_launch": d["bytes"] / d["launches"],
+                      "achieved": achieved, "unit": unit, "peak": peak, "bound": bound,
+                      "frac": achieved / peak}
+    dom = max(fams, key=lambda k: fams[k]["ms_per_step"])
+    D = fams[dom]
+    roofline = {"kernel": dom, "bound": D["bound"], "achieved": D["achieved"], "peak": D["peak"],
+                "unit": D["unit"], "frac": D["frac"], "traffic": None,
+                "avg_launch_ms": D["avg_launch_ms"],
+                "work_per_launch": D["bytes_per_launch"] if D["bound"] == "hbm"
+                else D["flops_per_launch"]}
+
+    out = {"metric": METRIC, "value": NRHS / (ms_per_step * 1e-3), "unit": "RHS/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "star r=1+0.3cos5t, N=65536, 2D Laplace single layer, "
+                                  "eps=1e-9, leaf 64, 64 proxies at 1.5x, nrhs=512",
+                      "n": N, "eps": EPS, "leaf": LEAF, "proxy_points": NPX, "nrhs": NRHS,
+                      "step": "tree + factor + solve(512) + free"},
+           "roofline": roofline, "kernels": fams,
+           "factor_stats": {k: st[k] for k in ("nbox", "maxdepth", "root_size",
+                                               "total_skeletons", "factor_doubles",
+                                               "max_box_n", "max_box_m")}}
+
+    if not args.no_extras:
+        extras = {}
+        t = rs.build_tree(g.points, LEAF)
+        for mode, reps in (("level", 5), ("per_box", 2)):
+            fms = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                h = rs.factor("lap2d_sl", t, g.points, g.weights, EPS, proxy_points=NPX,
+                              launch_mode=mode, stream=stream)
+                torch.cuda.synchronize()
+                fms.append((time.perf_counter() - a) * 1e3)
+            solve = {}
+            for nrhs in (1, 64, 512):
+                X = torch.empty_like(B0[:, :nrhs].t()).t()
+                X.copy_(B0[:, :nrhs])
+                h.solve(X, stream=stream, launch_mode=mode)
+                torch.cuda.synchronize()
+                reps_s = 20 if mode == "level" else 3
+                a = time.perf_counter()
+                for _ in range(reps_s):
+                    h.solve(X, stream=stream, launch_mode=mode)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - a) * 1e3 / reps_s
+                solve[str(nrhs)] = {"ms": ms, "rhs_per_s": nrhs / (ms * 1e-3)}
+            lat = {}
+            if mode == "level":
+                for nrhs in (1, 64):
+                    X = torch.empty_like(B0[:, :nrhs].t()).t()
+                    X.copy_(B0[:, :nrhs])
+                    xs = []
+                    for _ in range(200):
+                        a = time.perf_counter()
+                        h.solve(X, stream=stream)
+                        stream.synchronize()
+                        xs.append((time.perf_counter() - a) * 1e3)
+                    lat[str(nrhs)] = {"p50_ms": percentile(xs, 50), "p99_ms": percentile(xs, 99)}
+            h.free()
+            extras[mode] = {"factor_ms_median": float(np.median(fms)), "solve": solve}
+            if lat:
+                extras[mode]["latency"] = lat
+        out["batched_vs_plain"] = {
+            "batched": extras["level"], "plain": extras["per_box"],
+            "factor_speedup": extras["per_box"]["factor_ms_median"]
+            / extras["level"]["factor_ms_median"],
+            "solve_speedup_512": extras["per_box"]["solve"]["512"]["ms"]
+            / extras["level"]["solve"]["512"]["ms"]}
+        out["latency_ms"] = extras["level"]["latency"]
+        out["paper_context"] = {"hardware": "2.66 GHz single CPU core, Fortran (Section 6)",
+                                "table5_N65536_ellipse_dl": {"T_cm_s": 2.3, "T_lu_s": 1.8,
+                                                             "T_sv_s": 0.038}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, b_host)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

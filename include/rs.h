@@ -180,6 +180,35 @@ rs_status rs_box_skeletons(rs_handle h, int32_t *k_out, int64_t *skel_out, int64
 rs_status rs_box_export(rs_handle h, int64_t b, int32_t *n_out, int32_t *k_out,
                         int64_t *J_out, double *T_out);
 
+/* ------------------------------------------------------------ profiling ---- */
+
+/* Kernel families of the library, for rs_profile_read. */
+typedef enum {
+  RS_K_ASSEMBLE = 0,   /* proxy + near compression block (Section 3.2) */
+  RS_K_ID = 1,         /* column-pivoted QR interpolative decomposition (Section 2.2) */
+  RS_K_FACTOR = 2,     /* diagonal block + box factorization (Section 3.4) */
+  RS_K_SWEEP_UP = 3,   /* upward solve sweep */
+  RS_K_SWEEP_DOWN = 4, /* downward solve sweep */
+  RS_K_PERMUTE = 5,    /* caller <-> tree order of right-hand sides */
+  RS_K_COUNT = 6
+} rs_kernel_family;
+
+/* When enabled (process-wide), every kernel launch of the library is bracketed by
+ * two HIP events recorded on the launch's own stream, and the algorithmic work of
+ * the launch is counted from the box sizes: flops (FP64 operations the algorithm
+ * needs; one kernel evaluation counts as one "entry", reported separately) and
+ * bytes (the minimum HBM traffic: operands read once, results written once).
+ * Enabling adds a host-side event record per launch. */
+rs_status rs_profile_enable(int32_t on);
+
+/* Clears all counters (waits for pending events first). */
+rs_status rs_profile_reset(void);
+
+/* Accumulated totals of one kernel family since the last reset; waits for the
+ * recorded events.  Any output may be NULL. */
+rs_status rs_profile_read(int32_t family, int64_t *launches, double *total_ms,
+                          double *flops, double *bytes, double *entries);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,7 +33,9 @@ LAUNCH = {"level": 0, "per_box": 1}
 
 EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "rs_factor",
             "rs_factor_ex", "rs_solve", "rs_solve_ex", "rs_free", "rs_last_error",
-            "rs_device_count", "rs_query", "rs_box_skeletons", "rs_box_export"]
+            "rs_device_count", "rs_query", "rs_box_skeletons", "rs_box_export",
+            "rs_profile_enable", "rs_profile_reset", "rs_profile_read"]
+FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
 class rs_kernel(C.Structure):
@@ -75,6 +77,9 @@ _sig = {
     "rs_query": (C.c_int, [_P, C.POINTER(rs_stats)]),
     "rs_box_skeletons": (C.c_int, [_P, _PI32, _PI64, C.c_int64, _PI64]),
     "rs_box_export": (C.c_int, [_P, C.c_int64, _PI32, _PI32, _PI64, _PD]),
+    "rs_profile_enable": (C.c_int, [C.c_int32]),
+    "rs_profile_reset": (C.c_int, []),
+    "rs_profile_read": (C.c_int, [C.c_int32, _PI64, _PD, _PD, _PD, _PD]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -102,6 +107,27 @@ def _dptr(a: Optional[np.ndarray]):
 
 def device_count() -> int:
     return int(_lib.rs_device_count())
+
+
+def profile_enable(on: bool = True):
+    _check(_lib.rs_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(_lib.rs_profile_reset())
+
+
+def profile_read() -> dict:
+    """Per kernel family: launches, total_ms, flops, bytes, entries since the last reset."""
+    out = {}
+    for i, name in enumerate(FAMILIES):
+        n = C.c_int64()
+        ms, fl, by, en = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.rs_profile_read(i, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by),
+                                    C.byref(en)))
+        out[name] = dict(launches=int(n.value), total_ms=ms.value, flops=fl.value,
+                         bytes=by.value, entries=en.value)
+    return out
 
 
 class Tree:

@@ -248,4 +248,27 @@ rs_status rs_box_export(rs_handle h, int64_t b, int32_t *n_out, int32_t *k_out, 
   });
 }
 
+rs_status rs_profile_enable(int32_t on) {
+  return guarded([&]() -> rs_status {
+    prof_enable(on != 0);
+    return RS_OK;
+  });
+}
+
+rs_status rs_profile_reset(void) {
+  return guarded([&]() -> rs_status {
+    prof_reset();
+    return RS_OK;
+  });
+}
+
+rs_status rs_profile_read(int32_t family, int64_t *launches, double *total_ms, double *flops,
+                          double *bytes, double *entries) {
+  return guarded([&]() -> rs_status {
+    if (family < 0 || family >= RS_K_COUNT) fail(RS_EINVAL, "unknown kernel family");
+    prof_read(family, launches, total_ms, flops, bytes, entries);
+    return RS_OK;
+  });
+}
+
 }  // extern "C"

@@ -1,0 +1,132 @@
+// Launch profiler: HIP events on the launch stream around each kernel launch, plus
+// the algorithmic work of the launch counted by the caller from the box sizes.
+#include <vector>
+
+#include "runtime.h"
+
+namespace rs {
+
+namespace {
+
+struct Pending {
+  int family;
+  hipEvent_t start, stop;
+};
+
+struct Totals {
+  int64_t launches = 0;
+  double ms = 0, flops = 0, bytes = 0, entries = 0;
+};
+
+std::mutex g_prof_mutex;
+std::atomic<bool> g_prof_on{false};
+std::vector<Pending> g_pending;
+Totals g_totals[RS_K_COUNT];
+
+void drain_locked() {
+  for (Pending &p : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.stop) == hipSuccess &&
+        hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      Totals &t = g_totals[p.family];
+      t.launches += 1;
+      t.ms += ms;
+    }
+    (void)hipEventDestroy(p.start);
+    (void)hipEventDestroy(p.stop);
+  }
+  g_pending.clear();
+}
+
+}  // namespace
+
+bool prof_on() { return g_prof_on.load(std::memory_order_relaxed); }
+
+ProfScope::ProfScope(int family, hipStream_t st) : family_(family), st_(st) {
+  if (!prof_on()) return;
+  RS_HIP_CHECK(hipEventCreate(&start_));
+  RS_HIP_CHECK(hipEventCreate(&stop_));
+  RS_HIP_CHECK(hipEventRecord(start_, st_));
+  active_ = true;
+}
+
+ProfScope::~ProfScope() {
+  if (!active_) return;
+  (void)hipEventRecord(stop_, st_);
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  g_pending.push_back({family_, start_, stop_});
+}
+
+void prof_add_work(int family, const Work &w) {
+  if (!prof_on()) return;
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  Totals &t = g_totals[family];
+  t.flops += w.flops;
+  t.bytes += w.bytes;
+  t.entries += w.entries;
+}
+
+Work work_assemble(int m, int n) {
+  Work w;
+  w.entries = (double)m * n;
+  w.bytes = 8.0 * m * n;
+  return w;
+}
+
+Work work_id(int m, int n, int k) {
+  Work w;
+  double f = 2.0 * m * n;                       // initial column norms
+  for (int j = 0; j < k; ++j)                   // reflector + update + recomputed norms
+    f += 2.0 * (m - j) + 6.0 * (double)(m - j) * (n - j - 1);
+  f += (double)k * k * (n - k);                 // T = R11^{-1} R12
+  w.flops = f;
+  w.bytes = 8.0 * m * n + 8.0 * k * (n - k) + 4.0 * n;
+  return w;
+}
+
+Work work_factor(int n, int k) {
+  const double r = n - k, kk = k, nn = n;
+  Work w;
+  w.flops = 4.0 * nn * r * kk + 2.0 * r * r * r + 4.0 * r * r * kk + 2.0 * kk * kk * r;
+  w.entries = nn * nn;
+  w.bytes = 8.0 * (3.0 * kk * r + r * r + kk * kk) + 8.0 * kk * r;
+  return w;
+}
+
+Work work_sweep_up(int k, int r, int nrhs) {
+  Work w;
+  const double ops = (double)r * r + 2.0 * k * r;
+  w.flops = 2.0 * nrhs * ops;
+  w.bytes = 8.0 * ops + 16.0 * (k + r) * (double)nrhs;
+  return w;
+}
+
+Work work_sweep_down(int k, int r, int nrhs) {
+  Work w;
+  const double ops = 2.0 * k * r;
+  w.flops = 2.0 * nrhs * ops;
+  w.bytes = 8.0 * ops + 16.0 * (k + r) * (double)nrhs;
+  return w;
+}
+
+void prof_enable(bool on) { g_prof_on.store(on); }
+
+void prof_reset() {
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  drain_locked();
+  for (Totals &t : g_totals) t = Totals();
+}
+
+void prof_read(int family, int64_t *launches, double *ms, double *flops, double *bytes,
+               double *entries) {
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  drain_locked();
+  const Totals &t = g_totals[family];
+  if (launches) *launches = t.launches;
+  if (ms) *ms = t.ms;
+  if (flops) *flops = t.flops;
+  if (bytes) *bytes = t.bytes;
+  if (entries) *entries = t.entries;
+}
+
+}  // namespace rs

@@ -336,12 +336,22 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     const CompBox *d_comp = S.comp.as<CompBox>();
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
-        launch_assemble(d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(), max_npx, st);
+        {
+          ProfScope ps_(RS_K_ASSEMBLE, st);
+          launch_assemble(d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
+                          max_npx, st);
+        }
+        ProfScope ps_(RS_K_ID, st);
         launch_cpqr_id(d_comp, i, 1, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
                        S.ranks.as<int32_t>(), comp[i].n, st);
       }
     } else {
-      launch_assemble(d_comp, 0, cnt, d_probs, S.pool.as<int32_t>(), S.M.as<double>(), max_npx, st);
+      {
+        ProfScope ps_(RS_K_ASSEMBLE, st);
+        launch_assemble(d_comp, 0, cnt, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
+                        max_npx, st);
+      }
+      ProfScope ps_(RS_K_ID, st);
       launch_cpqr_id(d_comp, 0, cnt, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
                      S.ranks.as<int32_t>(), max_n, st);
     }
@@ -355,11 +365,15 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     // record skeletons; build the factor descriptors
     std::vector<FacBox> fac(cnt);
     int64_t woff = 0;
+    Work w_asm, w_id, w_fac;
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
       const CompBox &cb = comp[i];
       const int k = ranks[i];
+      w_asm += work_assemble(cb.m, cb.n);
+      w_id += work_id(cb.m, cb.n, k);
+      w_fac += work_factor(cb.n, k);
       const std::vector<int32_t> &J = P.J[b];
       const int32_t *ord = order.data() + cb.order_off;
       std::vector<int32_t> &sk = P.skel[b];
@@ -385,12 +399,18 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     upload(S.fac, fac, st);
     RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
     const FacBox *d_fac = S.fac.as<FacBox>();
+    prof_add_work(RS_K_ASSEMBLE, w_asm);
+    prof_add_work(RS_K_ID, w_id);
+    prof_add_work(RS_K_FACTOR, w_fac);
     if (per_box) {
-      for (int i = 0; i < cnt; ++i)
+      for (int i = 0; i < cnt; ++i) {
+        ProfScope ps_(RS_K_FACTOR, st);
         launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
                            S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
                            comp[i].n, st);
+      }
     } else {
+      ProfScope ps_(RS_K_FACTOR, st);
       launch_diag_factor(d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
                          S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(), max_n,
                          st);
@@ -474,11 +494,19 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     S.work.ensure(std::max<int64_t>(woff, 1) * sizeof(double));
     RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
     const FacBox *d_fac = S.fac.as<FacBox>();
+    {
+      Work w;
+      for (const FacBox &f : fac) w += work_factor(f.n, 0);
+      prof_add_work(RS_K_FACTOR, w);
+    }
     if (per_box) {
-      for (int i = 0; i < np; ++i)
+      for (int i = 0; i < np; ++i) {
+        ProfScope ps_(RS_K_FACTOR, st);
         launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
                            S.work.as<double>(), S.err.as<int32_t>(), fac[i].n, st);
+      }
     } else {
+      ProfScope ps_(RS_K_FACTOR, st);
       launch_diag_factor(d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
                          S.work.as<double>(), S.err.as<int32_t>(), max_n, st);
     }
@@ -544,29 +572,56 @@ void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode
     ~Freer() { (void)hipFreeAsync(W, st); }
   } freer{W, st};
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
-  launch_permute_in(B, ldb, W, h->d_perm, n, nrhs, st);
+  const bool prof = prof_on();
+  Work wperm;
+  wperm.bytes = 16.0 * n * nrhs + 8.0 * n;
+  prof_add_work(RS_K_PERMUTE, wperm);
+  {
+    ProfScope ps_(RS_K_PERMUTE, st);
+    launch_permute_in(B, ldb, W, h->d_perm, n, nrhs, st);
+  }
   auto up = [&](const LevelRec &lv) {
     const int cnt = (int)lv.sweep.size();
+    if (prof) {
+      Work w;
+      for (const SweepBox &sb : lv.sweep) w += work_sweep_up(sb.k, sb.r, nrhs);
+      prof_add_work(RS_K_SWEEP_UP, w);
+    }
     if (per_box) {
-      for (int i = 0; i < cnt; ++i)
+      for (int i = 0; i < cnt; ++i) {
+        ProfScope ps_(RS_K_SWEEP_UP, st);
         launch_sweep_up(lv.d_sweep, i, 1, W, nrhs, lv.sweep[i].k + lv.sweep[i].r, st);
+      }
     } else {
+      ProfScope ps_(RS_K_SWEEP_UP, st);
       launch_sweep_up(lv.d_sweep, 0, cnt, W, nrhs, lv.max_n, st);
     }
   };
   auto down = [&](const LevelRec &lv) {
     const int cnt = (int)lv.sweep.size();
+    if (prof) {
+      Work w;
+      for (const SweepBox &sb : lv.sweep) w += work_sweep_down(sb.k, sb.r, nrhs);
+      prof_add_work(RS_K_SWEEP_DOWN, w);
+    }
     if (per_box) {
-      for (int i = 0; i < cnt; ++i)
+      for (int i = 0; i < cnt; ++i) {
+        ProfScope ps_(RS_K_SWEEP_DOWN, st);
         launch_sweep_down(lv.d_sweep, i, 1, W, nrhs, lv.sweep[i].k + lv.sweep[i].r, st);
+      }
     } else {
+      ProfScope ps_(RS_K_SWEEP_DOWN, st);
       launch_sweep_down(lv.d_sweep, 0, cnt, W, nrhs, lv.max_n, st);
     }
   };
   for (const LevelRec &lv : h->levels) up(lv);
   up(h->root);
   for (auto it = h->levels.rbegin(); it != h->levels.rend(); ++it) down(*it);
-  launch_permute_out(B, ldb, W, h->d_perm, n, nrhs, st);
+  prof_add_work(RS_K_PERMUTE, wperm);
+  {
+    ProfScope ps_(RS_K_PERMUTE, st);
+    launch_permute_out(B, ldb, W, h->d_perm, n, nrhs, st);
+  }
 }
 
 }  // namespace rs

@@ -94,4 +94,42 @@ struct UserError {
   std::string what;
 };
 
+// ---- launch profiler (see rs_profile_enable)
+struct Work {
+  double flops = 0, bytes = 0, entries = 0;
+  Work &operator+=(const Work &o) {
+    flops += o.flops;
+    bytes += o.bytes;
+    entries += o.entries;
+    return *this;
+  }
+};
+bool prof_on();
+void prof_enable(bool on);
+void prof_reset();
+void prof_read(int family, int64_t *launches, double *ms, double *flops, double *bytes,
+               double *entries);
+void prof_add_work(int family, const Work &w);
+// Brackets the launches issued during its lifetime with events on `st`.
+class ProfScope {
+ public:
+  ProfScope(int family, hipStream_t st);
+  ~ProfScope();
+  ProfScope(const ProfScope &) = delete;
+  ProfScope &operator=(const ProfScope &) = delete;
+
+ private:
+  int family_;
+  hipStream_t st_;
+  hipEvent_t start_ = nullptr, stop_ = nullptr;
+  bool active_ = false;
+};
+
+// Algorithmic work of one box (counts documented with rs_profile_read).
+Work work_assemble(int m, int n);
+Work work_id(int m, int n, int k);
+Work work_factor(int n, int k);
+Work work_sweep_up(int k, int r, int nrhs);
+Work work_sweep_down(int k, int r, int nrhs);
+
 }  // namespace rs
