@@ -160,6 +160,8 @@ typedef struct {
   int64_t max_box_n;        /* largest active set of a box */
   int64_t max_box_m;        /* largest compression block row count */
   double factor_ms;         /* host wall time of the factor call */
+  double plan_ms;           /* of which: host planning (active sets, near lists, descriptors) */
+  double wait_ms;           /* of which: host blocked waiting for the device */
 } rs_stats;
 
 rs_status rs_query(rs_handle h, rs_stats *out);

@@ -53,7 +53,8 @@ class rs_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("nbox", C.c_int64), ("maxdepth", C.c_int32),
                 ("dim", C.c_int32), ("root_size", C.c_int64), ("total_skeletons", C.c_int64),
                 ("factor_doubles", C.c_int64), ("max_box_n", C.c_int64),
-                ("max_box_m", C.c_int64), ("factor_ms", C.c_double)]
+                ("max_box_m", C.c_int64), ("factor_ms", C.c_double), ("plan_ms", C.c_double),
+                ("wait_ms", C.c_double)]
 
 
 _P = C.c_void_p

@@ -189,12 +189,18 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict
 // the lowest original column), stop at the first |R_jj| <= eps |R_00|, then
 // T = R11^{-1} R12 and the skeleton / redundant sets sorted ascending.
 // Outputs: ranks[kslot] = k, order (n ints: sorted s, then sorted r), T (k x (n-k)).
-__global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict__ boxes,
-                                                      int first,
-                                                      const ProbDev *__restrict__ probs,
-                                                      double *__restrict__ Marena,
-                                                      int32_t *__restrict__ order_pool,
-                                                      int32_t *__restrict__ ranks) {
+//
+// Trailing update: each wave takes CB columns at a time; a lane holds up to RT rows of
+// each of them in registers, so one step reads and writes the trailing matrix once
+// (dot product with the reflector, update, and the recomputed norm in one pass).  The
+// reflector is staged in LDS when VLDS.  Rows beyond 64*RT are streamed in two passes.
+template <int NTH, int RT, int CB, bool VLDS>
+__global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ boxes, int first,
+                                                 const ProbDev *__restrict__ probs,
+                                                 double *__restrict__ Marena,
+                                                 int32_t *__restrict__ order_pool,
+                                                 int32_t *__restrict__ ranks) {
+  constexpr int NW = NTH / 64;
   extern __shared__ double smem[];
   __shared__ double s_best, s_tau;
   __shared__ int s_p;
@@ -207,14 +213,15 @@ __global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict_
     return;
   }
   double *M = Marena + B.M_off;
-  double *norms = smem;                                  // n
-  int *perm = reinterpret_cast<int *>(norms + n);        // n
-  int *rk = perm + n;                                    // n (ranks for the sort)
-  double *wbuf = reinterpret_cast<double *>(rk + n);  // kWaves * kmax (16n bytes in)
   const int kmax = min(m, n);
+  double *norms = smem;                                    // n
+  int *perm = reinterpret_cast<int *>(norms + n);          // n
+  int *rk = perm + n;                                      // n
+  double *wbuf = reinterpret_cast<double *>(rk + n);       // NW * kmax (16n bytes in)
+  double *sv = wbuf + NW * kmax;                           // m (VLDS only)
 
-  for (int c = threadIdx.x; c < n; c += kThreads) perm[c] = c;
-  for (int c = wave; c < n; c += kWaves) {
+  for (int c = threadIdx.x; c < n; c += NTH) perm[c] = c;
+  for (int c = wave; c < n; c += NW) {
     const double *col = M + (int64_t)c * m;
     double s = 0.0;
     for (int i = lane; i < m; i += 64) s += col[i] * col[i];
@@ -250,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict_
     if (best == 0.0 || best <= eps * r00) { k = j; break; }
     if (p != j) {
       double *cj = M + (int64_t)j * m, *cp = M + (int64_t)p * m;
-      for (int i = threadIdx.x; i < m; i += kThreads) {
+      for (int i = threadIdx.x; i < m; i += NTH) {
         const double a = cj[i];
         cj[i] = cp[i];
         cp[i] = a;
@@ -270,35 +277,106 @@ __global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict_
       const double x0 = cj[j];
       const double beta = x0 >= 0.0 ? -alpha : alpha;
       const double scale = 1.0 / (x0 - beta);
-      for (int i = j + 1 + lane; i < m; i += 64) cj[i] *= scale;
+      for (int i = j + 1 + lane; i < m; i += 64) {
+        const double v = cj[i] * scale;
+        cj[i] = v;
+        if (VLDS) sv[i] = v;
+      }
       if (lane == 0) {
         s_tau = (beta - x0) / beta;
         cj[j] = beta;
+        if (VLDS) sv[j] = 1.0;
       }
     }
     __syncthreads();
     const double tau = s_tau;
-    const double *v = M + (int64_t)j * m;
-    for (int c = j + 1 + wave; c < n; c += kWaves) {
-      double *col = M + (int64_t)c * m;
-      double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) s += (i == j ? 1.0 : v[i]) * col[i];
-      const double w = wave_sum(s) * tau;
-      double ss = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        const double val = col[i] - w * (i == j ? 1.0 : v[i]);
-        col[i] = val;
-        if (i > j) ss += val * val;
+    const double *vg = M + (int64_t)j * m;
+    auto vload = [&](int i) -> double { return i == j ? 1.0 : (VLDS ? sv[i] : vg[i]); };
+    const int rows = m - j;
+    for (int c0 = j + 1 + wave * CB; c0 < n; c0 += NW * CB) {
+      double dot[CB], nrm[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) { dot[cb] = 0.0; nrm[cb] = 0.0; }
+      if (rows <= 64 * RT) {
+        double val[CB][RT], vi[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = j + lane + 64 * t;
+          const bool ok = i < m;
+          vi[t] = ok ? vload(i) : 0.0;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int c = c0 + cb;
+            val[cb][t] = (ok && c < n) ? M[(int64_t)c * m + i] : 0.0;
+            dot[cb] += vi[t] * val[cb][t];
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) dot[cb] = wave_sum(dot[cb]) * tau;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = j + lane + 64 * t;
+          if (i < m) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+              const int c = c0 + cb;
+              if (c < n) {
+                const double nv = val[cb][t] - dot[cb] * vi[t];
+                M[(int64_t)c * m + i] = nv;
+                if (i > j) nrm[cb] += nv * nv;
+              }
+            }
+          }
+        }
+      } else {
+        for (int base = j; base < m; base += 64 * RT) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int i = base + lane + 64 * t;
+            if (i < m) {
+              const double v = vload(i);
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb) {
+                const int c = c0 + cb;
+                if (c < n) dot[cb] += v * M[(int64_t)c * m + i];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) dot[cb] = wave_sum(dot[cb]) * tau;
+        for (int base = j; base < m; base += 64 * RT) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int i = base + lane + 64 * t;
+            if (i < m) {
+              const double v = vload(i);
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb) {
+                const int c = c0 + cb;
+                if (c < n) {
+                  double *pc = M + (int64_t)c * m + i;
+                  const double nv = *pc - dot[cb] * v;
+                  *pc = nv;
+                  if (i > j) nrm[cb] += nv * nv;
+                }
+              }
+            }
+          }
+        }
       }
-      ss = wave_sum(ss);
-      if (lane == 0) norms[c] = sqrt(ss);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const double s = wave_sum(nrm[cb]);
+        if (lane == 0 && c0 + cb < n) norms[c0 + cb] = sqrt(s);
+      }
     }
     __syncthreads();
   }
 
   // T = R11^{-1} R12, one column per wave, column held in the wave's LDS buffer.
   double *buf = wbuf + wave * kmax;
-  for (int c = k + wave; c < n; c += kWaves) {
+  for (int c = k + wave; c < n; c += NW) {
     double *col = M + (int64_t)c * m;
     for (int i = lane; i < k; i += 64) buf[i] = col[i];
     for (int i = k - 1; i >= 0; --i) {
@@ -311,7 +389,7 @@ __global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict_
   }
   // Sorted skeleton and redundant sets.
   int32_t *order = order_pool + B.order_off;
-  for (int c = threadIdx.x; c < n; c += kThreads) {
+  for (int c = threadIdx.x; c < n; c += NTH) {
     const int pc = perm[c];
     const int lo = c < k ? 0 : k, hi = c < k ? k : n;
     int r = 0;
@@ -320,13 +398,14 @@ __global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict_
     order[lo + r] = pc;
   }
   __syncthreads();
-  const int nr = n - k;
   double *T = B.T;
-  for (int64_t e = threadIdx.x; e < (int64_t)k * nr; e += kThreads) {
-    const int i = (int)(e % k), c = (int)(e / k) + k;
-    T[rk[i] + (int64_t)k * rk[c]] = M[(int64_t)c * m + i];
+  for (int c = k + wave; c < n; c += NW) {
+    const double *col = M + (int64_t)c * m;
+    double *Tc = T + (int64_t)k * rk[c];
+    for (int i = lane; i < k; i += 64) Tc[rk[i]] = col[i];
   }
   if (threadIdx.x == 0) ranks[B.kslot] = k;
+
 }
 
 // --------------------------------------------------------------------------
@@ -337,16 +416,22 @@ __global__ __launch_bounds__(kThreads) void k_cpqr_id(const CompBox *__restrict_
 // and Lambda = (R D^{-1} L)^{-1} is the box's block of the next level's matrix.
 // D is A(J, J) at a leaf; above, Lambda of each child on its diagonal block and
 // A between siblings.  The root (force_k0) eliminates everything: G = D^{-1}.
-__global__ __launch_bounds__(kThreads) void k_diag_factor(const FacBox *__restrict__ boxes,
-                                                          int first,
-                                                          const ProbDev *__restrict__ probs,
-                                                          const int32_t *__restrict__ pool,
-                                                          const int32_t *__restrict__ order_pool,
-                                                          const int32_t *__restrict__ ranks,
-                                                          double *__restrict__ workbase,
-                                                          int32_t *__restrict__ err) {
-  extern __shared__ double fac[];           // r doubles: elimination factors
-  __shared__ double s_piv;
+// X_rr is inverted in place by Gauss-Jordan elimination with partial pivoting (row
+// interchanges, undone as column interchanges at the end).  INLDS: the whole n x n
+// block lives in LDS (small boxes); otherwise in the global workspace.
+// Index loops are two-level (waves over columns, lanes over rows): no integer division.
+template <int NTH, bool INLDS>
+__global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ boxes, int first,
+                                                     const ProbDev *__restrict__ probs,
+                                                     const int32_t *__restrict__ pool,
+                                                     const int32_t *__restrict__ order_pool,
+                                                     const int32_t *__restrict__ ranks,
+                                                     double *__restrict__ workbase,
+                                                     int32_t *__restrict__ err) {
+  constexpr int NW = NTH / 64;
+  constexpr int CB = 4;
+  extern __shared__ double sh[];
+  __shared__ double s_inv;
   __shared__ int s_prow, s_bad;
   const FacBox &B = boxes[first + blockIdx.x];
   const ProbDev &P = probs[B.prob];
@@ -358,64 +443,72 @@ __global__ __launch_bounds__(kThreads) void k_diag_factor(const FacBox *__restri
   const int32_t *ord = B.force_k0 ? nullptr : order_pool + B.order_off;
   double *slot = B.slot;
   const double *T = slot + slot_T(k, r);
-  double *X = workbase + B.work_off;                 // n x n, (s, r) order
-  double *aug = X + (int64_t)n * n;                  // r x 2r
+  double *X = INLDS ? sh : workbase + B.work_off;            // n x n, (s, r) order
+  double *fac = INLDS ? sh + (int64_t)n * n : sh;            // r
+  int *ipiv = reinterpret_cast<int *>(fac + r);              // r
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   // D in (s, r) order.
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kThreads) {
-    const int b = (int)(e / n), a = (int)(e - (int64_t)b * n);
-    const int li = ord ? ord[a] : a, lj = ord ? ord[b] : b;
-    double v;
-    if (B.leaf) {
-      v = entry(P, J[li], J[lj]);
-    } else {
-      int ca = 0, cb = 0;
-      for (int c = 1; c < B.nchild; ++c) {
-        ca += li >= B.child_lo[c];
-        cb += lj >= B.child_lo[c];
-      }
-      if (ca == cb) {
-        v = B.child_lam[ca][(li - B.child_lo[ca]) + (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
-      } else {
+  for (int b = wave; b < n; b += NW) {
+    const int lj = ord ? ord[b] : b;
+    int cb = 0;
+    if (!B.leaf)
+      for (int c = 1; c < B.nchild; ++c) cb += lj >= B.child_lo[c];
+    double *Xb = X + (int64_t)b * n;
+    for (int a = lane; a < n; a += 64) {
+      const int li = ord ? ord[a] : a;
+      double v;
+      if (B.leaf) {
         v = entry(P, J[li], J[lj]);
+      } else {
+        int ca = 0;
+        for (int c = 1; c < B.nchild; ++c) ca += li >= B.child_lo[c];
+        if (ca == cb) {
+          v = B.child_lam[ca][(li - B.child_lo[ca]) +
+                              (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
+        } else {
+          v = entry(P, J[li], J[lj]);
+        }
       }
+      Xb[a] = v;
     }
-    X[(int64_t)b * n + a] = v;
   }
   __syncthreads();
   if (k > 0 && r > 0) {
     // Y = D Q: redundant columns minus the skeleton columns times T.
-    for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kThreads) {
-      const int jr = (int)(e / n), a = (int)(e - (int64_t)jr * n);
-      double s = X[(int64_t)(k + jr) * n + a];
-      for (int i = 0; i < k; ++i) s -= X[(int64_t)i * n + a] * T[i + (int64_t)k * jr];
-      X[(int64_t)(k + jr) * n + a] = s;
+    for (int jr = wave; jr < r; jr += NW) {
+      const double *Tj = T + (int64_t)k * jr;
+      double *Xc = X + (int64_t)(k + jr) * n;
+      for (int a = lane; a < n; a += 64) {
+        double s = Xc[a];
+        for (int i = 0; i < k; ++i) s -= X[(int64_t)i * n + a] * Tj[i];
+        Xc[a] = s;
+      }
     }
     __syncthreads();
     // X = P Y: redundant rows minus T^T times the skeleton rows.
-    for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kThreads) {
-      const int b = (int)(e / r), jr = (int)(e - (int64_t)b * r);
-      double s = X[(int64_t)b * n + k + jr];
-      for (int i = 0; i < k; ++i) s -= T[i + (int64_t)k * jr] * X[(int64_t)b * n + i];
-      X[(int64_t)b * n + k + jr] = s;
+    for (int b = wave; b < n; b += NW) {
+      double *Xb = X + (int64_t)b * n;
+      for (int jr = lane; jr < r; jr += 64) {
+        const double *Tj = T + (int64_t)k * jr;
+        double s = Xb[k + jr];
+        for (int i = 0; i < k; ++i) s -= Tj[i] * Xb[i];
+        Xb[k + jr] = s;
+      }
     }
     __syncthreads();
   }
-  // Gauss-Jordan with partial pivoting on [X_rr | I] (r x 2r, column-major).
-  const int r2 = 2 * r;
-  for (int64_t e = threadIdx.x; e < (int64_t)r * r2; e += kThreads) {
-    const int c = (int)(e / r), a = (int)(e - (int64_t)c * r);
-    aug[e] = c < r ? X[(int64_t)(k + c) * n + k + a] : (c - r == a ? 1.0 : 0.0);
-  }
+  // In-place Gauss-Jordan inversion of A = X_rr, A(i, c) = X[(k + c) n + k + i].
+  double *A = X + (int64_t)k * n + k;
   if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
+  __syncthreads();      // every thread reads s_bad below, also when r == 0
   for (int j = 0; j < r; ++j) {
     if (wave == 0) {
       double best = -1.0;
       int brow = INT_MAX;
+      const double *Aj = A + (int64_t)j * n;
       for (int i = j + lane; i < r; i += 64) {
-        const double v = fabs(aug[(int64_t)j * r + i]);
+        const double v = fabs(Aj[i]);
         if (v > best || (v == best && i < brow)) { best = v; brow = i; }
       }
 #pragma unroll
@@ -426,6 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_diag_factor(const FacBox *__restri
       }
       if (lane == 0) {
         s_prow = brow;
+        ipiv[j] = brow;
         if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
       }
     }
@@ -433,26 +527,41 @@ __global__ __launch_bounds__(kThreads) void k_diag_factor(const FacBox *__restri
     if (s_bad) break;
     const int pr = s_prow;
     if (pr != j) {
-      for (int c = j + threadIdx.x; c < r2; c += kThreads) {
-        const double a = aug[(int64_t)c * r + j];
-        aug[(int64_t)c * r + j] = aug[(int64_t)c * r + pr];
-        aug[(int64_t)c * r + pr] = a;
+      for (int c = threadIdx.x; c < r; c += NTH) {
+        double *Ac = A + (int64_t)c * n;
+        const double a = Ac[j];
+        Ac[j] = Ac[pr];
+        Ac[pr] = a;
       }
+      __syncthreads();
+    }
+    {
+      const double *Aj = A + (int64_t)j * n;
+      for (int i = threadIdx.x; i < r; i += NTH) fac[i] = Aj[i];
+      if (threadIdx.x == 0) s_inv = 1.0 / Aj[j];
     }
     __syncthreads();
-    if (threadIdx.x == 0) s_piv = 1.0 / aug[(int64_t)j * r + j];
-    for (int i = threadIdx.x; i < r; i += kThreads) fac[i] = aug[(int64_t)j * r + i];
+    const double inv = s_inv;
+    for (int c = threadIdx.x; c < r; c += NTH) {
+      double *Ac = A + (int64_t)c * n;
+      Ac[j] = c == j ? inv : Ac[j] * inv;
+    }
     __syncthreads();
-    const double inv = s_piv;
-    for (int c = j + threadIdx.x; c < r2; c += kThreads) aug[(int64_t)c * r + j] *= inv;
-    __syncthreads();
-    const int64_t ncols = r2 - j;
-    for (int64_t e = threadIdx.x; e < ncols * r; e += kThreads) {
-      const int c = j + (int)(e / r), i = (int)(e % r);
-      if (i == j) continue;
-      const double f = fac[i];
-      if (c == j) aug[(int64_t)c * r + i] = 0.0;
-      else aug[(int64_t)c * r + i] -= f * aug[(int64_t)c * r + j];
+    for (int c0 = wave * CB; c0 < r; c0 += NW * CB) {
+      double aj[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) aj[cb] = c0 + cb < r ? A[(int64_t)(c0 + cb) * n + j] : 0.0;
+      for (int i = lane; i < r; i += 64) {
+        if (i == j) continue;
+        const double f = fac[i];
+        double v[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          v[cb] = (c0 + cb < r && c0 + cb != j) ? A[(int64_t)(c0 + cb) * n + i] : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          if (c0 + cb < r) A[(int64_t)(c0 + cb) * n + i] = v[cb] - f * aj[cb];
+      }
     }
     __syncthreads();
   }
@@ -460,34 +569,52 @@ __global__ __launch_bounds__(kThreads) void k_diag_factor(const FacBox *__restri
     if (threadIdx.x == 0) atomicCAS(err, -1, first + (int)blockIdx.x);
     return;
   }
+  for (int j = r - 1; j >= 0; --j) {      // undo the row interchanges on the columns
+    const int pr = ipiv[j];
+    if (pr != j) {
+      double *Aj = A + (int64_t)j * n, *Ap = A + (int64_t)pr * n;
+      for (int i = threadIdx.x; i < r; i += NTH) {
+        const double a = Aj[i];
+        Aj[i] = Ap[i];
+        Ap[i] = a;
+      }
+      __syncthreads();
+    }
+  }
   double *G = slot + slot_G(k, r);
-  const double *Gs = aug + (int64_t)r * r;
-  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += kThreads) G[e] = Gs[e];
+  for (int c = wave; c < r; c += NW)
+    for (int a = lane; a < r; a += 64) G[(int64_t)c * r + a] = A[(int64_t)c * n + a];
   if (k == 0) return;
   double *E = slot + slot_E(k, r);
   double *F = slot + slot_F(k, r);
   double *L = slot + slot_L(k, r);
-  // F = G X_rs (r x k)
-  for (int64_t e = threadIdx.x; e < (int64_t)r * k; e += kThreads) {
-    const int i = (int)(e / r), a = (int)(e - (int64_t)i * r);
-    double s = 0.0;
-    for (int l = 0; l < r; ++l) s += Gs[(int64_t)l * r + a] * X[(int64_t)i * n + k + l];
-    F[e] = s;
+  // F = G X_rs (r x k); X_rs(l, i) = X[i n + k + l]
+  for (int i = wave; i < k; i += NW) {
+    const double *Xi = X + (int64_t)i * n + k;
+    for (int a = lane; a < r; a += 64) {
+      double s = 0.0;
+      for (int l = 0; l < r; ++l) s += A[(int64_t)l * n + a] * Xi[l];
+      F[(int64_t)i * r + a] = s;
+    }
   }
-  // E = X_sr G (k x r)
-  for (int64_t e = threadIdx.x; e < (int64_t)k * r; e += kThreads) {
-    const int a = (int)(e / k), i = (int)(e - (int64_t)a * k);
-    double s = 0.0;
-    for (int l = 0; l < r; ++l) s += X[(int64_t)(k + l) * n + i] * Gs[(int64_t)a * r + l];
-    E[e] = s;
+  // E = X_sr G (k x r); X_sr(i, l) = X[(k + l) n + i]
+  for (int a = wave; a < r; a += NW) {
+    const double *Ga = A + (int64_t)a * n;
+    for (int i = lane; i < k; i += 64) {
+      double s = 0.0;
+      for (int l = 0; l < r; ++l) s += X[(int64_t)(k + l) * n + i] * Ga[l];
+      E[(int64_t)a * k + i] = s;
+    }
   }
   __syncthreads();
   // Lambda = X_ss - X_sr F (k x k)
-  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += kThreads) {
-    const int i2 = (int)(e / k), i = (int)(e - (int64_t)i2 * k);
-    double s = X[(int64_t)i2 * n + i];
-    for (int a = 0; a < r; ++a) s -= X[(int64_t)(k + a) * n + i] * F[(int64_t)i2 * r + a];
-    L[e] = s;
+  for (int i2 = wave; i2 < k; i2 += NW) {
+    const double *Fi = F + (int64_t)i2 * r;
+    for (int i = lane; i < k; i += 64) {
+      double s = X[(int64_t)i2 * n + i];
+      for (int a = 0; a < r; ++a) s -= X[(int64_t)(k + a) * n + i] * Fi[a];
+      L[(int64_t)i2 * k + i] = s;
+    }
   }
 }
 
@@ -625,6 +752,8 @@ int pick_nt(int nrhs, int max_n) {
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
+// Dynamic LDS requested per workgroup.
+constexpr size_t kLdsLimit = 64 * 1024;
 
 }  // namespace
 
@@ -636,37 +765,90 @@ void launch_assemble(const CompBox *boxes, int first, int count, const ProbDev *
   check_launch("k_assemble");
 }
 
-size_t cpqr_lds_bytes(int max_n) {
-  return (size_t)max_n * sizeof(double) + (size_t)(3 * max_n + 2) * sizeof(int) +
-         (size_t)kWaves * max_n * sizeof(double);
+constexpr int kCpqrThreads = 512;
+constexpr int kVldsMaxRows = 8192;
+
+size_t cpqr_lds_bytes(int max_n, int max_m) {
+  const int nw = kCpqrThreads / 64;
+  size_t b = (size_t)max_n * sizeof(double) + (size_t)2 * max_n * sizeof(int) +
+             (size_t)nw * max_n * sizeof(double);
+  if (max_m <= kVldsMaxRows) b += (size_t)max_m * sizeof(double);
+  return b;
+}
+
+template <int RT, int CB, bool VLDS>
+void cpqr_variant(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                  double *Marena, int32_t *order_pool, int32_t *ranks, size_t lds,
+                  hipStream_t st) {
+  auto kern = k_cpqr_id<kCpqrThreads, RT, CB, VLDS>;
+  if (lds > 64 * 1024)
+    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kern, dim3(count), dim3(kCpqrThreads), lds, st, boxes, first, probs, Marena,
+                     order_pool, ranks);
+  check_launch("k_cpqr_id");
 }
 
 void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *probs,
-                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n,
+                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                     hipStream_t st) {
   if (count <= 0) return;
-  const size_t lds = cpqr_lds_bytes(max_n);
-  if (lds > kMaxLds) throw DeviceError("k_cpqr_id: box too large for LDS", hipErrorInvalidValue);
-  if (lds > 64 * 1024)
-    RS_HIP_CHECK(hipFuncSetAttribute((const void *)k_cpqr_id,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_cpqr_id, dim3(count), dim3(kThreads), lds, st, boxes, first, probs,
-                     Marena, order_pool, ranks);
-  check_launch("k_cpqr_id");
+  const size_t lds = cpqr_lds_bytes(max_n, max_m);
+  if (cpqr_lds_bytes(max_n, kVldsMaxRows + 1) > kLdsLimit)
+    throw DeviceError("k_cpqr_id: box too large for LDS", hipErrorInvalidValue);
+  // size buckets: rows held per lane (RT) and columns per wave (CB)
+  if (max_m <= 256 && lds <= kLdsLimit)
+    cpqr_variant<4, 4, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
+  else if (max_m <= 512 && lds <= kLdsLimit)
+    cpqr_variant<8, 4, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
+  else if (max_m <= 1024 && lds <= kLdsLimit)
+    cpqr_variant<16, 2, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
+  else if (lds <= kLdsLimit)
+    cpqr_variant<16, 2, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
+  else
+    cpqr_variant<16, 2, false>(boxes, first, count, probs, Marena, order_pool, ranks,
+                               cpqr_lds_bytes(max_n, kVldsMaxRows + 1), st);
 }
+
+// Dynamic LDS per workgroup is kept within 64 KiB: n^2 doubles + 12n bytes <= 64 KiB.
+constexpr int kDiagLdsMaxN = 88;
+
+template <int NTH, bool INLDS>
+void diag_factor_nt(const FacBox *boxes, int first, int count, const ProbDev *probs,
+                    const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
+                    double *work, int32_t *err, size_t lds, hipStream_t st) {
+  auto kern = k_diag_factor<NTH, INLDS>;
+  if (lds > 64 * 1024)
+    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool,
+                     order_pool, ranks, work, err);
+  check_launch("k_diag_factor");
+}
+
+// Every box gets its own n x n workspace: the variant (LDS or global) is chosen per
+// launch from the largest box, so the smaller boxes of a launch need one too.
+size_t diag_work_doubles(int n) { return (size_t)n * n; }
 
 void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
                         const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
                         double *work, int32_t *err, int max_n, hipStream_t st) {
   if (count <= 0) return;
-  const size_t lds = (size_t)max_n * sizeof(double);
-  if (lds > kMaxLds) throw DeviceError("k_diag_factor: box too large for LDS", hipErrorInvalidValue);
-  if (lds > 64 * 1024)
-    RS_HIP_CHECK(hipFuncSetAttribute((const void *)k_diag_factor,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_diag_factor, dim3(count), dim3(kThreads), lds, st, boxes, first, probs,
-                     pool, order_pool, ranks, work, err);
-  check_launch("k_diag_factor");
+  if (max_n <= kDiagLdsMaxN) {
+    const size_t lds = (size_t)max_n * max_n * sizeof(double) + (size_t)max_n * 12;
+    diag_factor_nt<256, true>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
+                              lds, st);
+    return;
+  }
+  const size_t lds = (size_t)max_n * 12;
+  if (lds > kLdsLimit) throw DeviceError("k_diag_factor: box too large", hipErrorInvalidValue);
+  // Few large boxes (the root): one 1024-thread workgroup each; otherwise 256 threads.
+  if (count <= 64)
+    diag_factor_nt<1024, false>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
+                                lds, st);
+  else
+    diag_factor_nt<256, false>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
+                               lds, st);
 }
 
 void launch_permute_in(const double *B, int64_t ldb, double *W, const int64_t *perm, int64_t n,

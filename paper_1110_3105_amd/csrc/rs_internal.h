@@ -90,12 +90,14 @@ __host__ __device__ inline int64_t slot_bound(int n) { return (5 * (int64_t)n * 
 void launch_assemble(const CompBox *boxes, int first, int count, const ProbDev *probs,
                      const int32_t *pool, double *Marena, int max_npx, hipStream_t st);
 void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *probs,
-                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n,
+                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                     hipStream_t st);
 void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
                         const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
                         double *work, int32_t *err, int max_n, hipStream_t st);
-size_t cpqr_lds_bytes(int max_n);
+size_t cpqr_lds_bytes(int max_n, int max_m);
+// Global workspace doubles reserved for a box of n DOFs in k_diag_factor.
+size_t diag_work_doubles(int n);
 void launch_permute_in(const double *B, int64_t ldb, double *W, const int64_t *perm, int64_t n,
                        int nrhs, hipStream_t st);
 void launch_permute_out(double *B, int64_t ldb, const double *W, const int64_t *perm,

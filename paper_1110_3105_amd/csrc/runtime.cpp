@@ -243,10 +243,18 @@ void check_err(DevBuf &err, hipStream_t st, const std::vector<StepBox> &items, c
 
 }  // namespace
 
+namespace {
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point a) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - a).count();
+}
+}  // namespace
+
 void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
                  std::vector<rs_factor_s *> &out) {
   std::lock_guard<std::mutex> lock(g_factor_mutex);
   auto t0 = std::chrono::steady_clock::now();
+  double plan_ms = 0.0, wait_ms = 0.0;
   const int np = (int)reqs.size();
   std::vector<std::unique_ptr<rs_factor_s>> handles(np);
   std::vector<ProbState> ps(np);
@@ -280,6 +288,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     }
     if (items.empty()) continue;
     const int cnt = (int)items.size();
+    auto tp = Clock::now();
     // plan: active sets and near lists
     std::vector<std::vector<int32_t>> near_all(cnt);
     {
@@ -296,7 +305,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     std::vector<int32_t> pool;
     std::vector<CompBox> comp(cnt);
     int64_t M_total = 0, order_total = 0, work_total = 0;
-    int max_n = 0;
+    int max_n = 0, max_m_step = 0;
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
@@ -321,11 +330,13 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       double *slot = P.h->arena.alloc_n<double>(slot_bound(cb.n));
       cb.T = slot;
       P.h->box_slot[b] = slot;
-      work_total += 3 * (int64_t)cb.n * cb.n;
+      work_total += (int64_t)diag_work_doubles(cb.n);
       max_n = std::max(max_n, cb.n);
+      max_m_step = std::max(max_m_step, cb.m);
       max_m_seen = std::max<int64_t>(max_m_seen, cb.m);
     }
-    if (cpqr_lds_bytes(max_n) > 160 * 1024)
+    plan_ms += ms_since(tp);
+    if (cpqr_lds_bytes(max_n, 1 << 30) > 64 * 1024)
       throw UserError{RS_ENOTSUP, "a box's active set exceeds the on-chip ID limit"};
     upload(S.pool, pool, st);
     upload(S.comp, comp, st);
@@ -343,7 +354,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
         }
         ProfScope ps_(RS_K_ID, st);
         launch_cpqr_id(d_comp, i, 1, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
-                       S.ranks.as<int32_t>(), comp[i].n, st);
+                       S.ranks.as<int32_t>(), comp[i].n, comp[i].m, st);
       }
     } else {
       {
@@ -353,7 +364,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       }
       ProfScope ps_(RS_K_ID, st);
       launch_cpqr_id(d_comp, 0, cnt, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
-                     S.ranks.as<int32_t>(), max_n, st);
+                     S.ranks.as<int32_t>(), max_n, max_m_step, st);
     }
     std::vector<int32_t> ranks(cnt), order(order_total);
     RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), S.ranks.p, cnt * sizeof(int32_t),
@@ -361,7 +372,12 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     if (order_total)
       RS_HIP_CHECK(hipMemcpyAsync(order.data(), S.order.p, order_total * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, st));
-    RS_HIP_CHECK(hipStreamSynchronize(st));
+    {
+      auto tw = Clock::now();
+      RS_HIP_CHECK(hipStreamSynchronize(st));
+      wait_ms += ms_since(tw);
+    }
+    auto tp2 = Clock::now();
     // record skeletons; build the factor descriptors
     std::vector<FacBox> fac(cnt);
     int64_t woff = 0;
@@ -393,9 +409,10 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       fb.order_off = cb.order_off;
       fb.slot = cb.T;
       fb.work_off = woff;
-      woff += 3 * (int64_t)cb.n * cb.n;
+      woff += (int64_t)diag_work_doubles(cb.n);
       fill_children(P, b, fb);
     }
+    plan_ms += ms_since(tp2);
     upload(S.fac, fac, st);
     RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
     const FacBox *d_fac = S.fac.as<FacBox>();
@@ -415,21 +432,32 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
                          S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(), max_n,
                          st);
     }
-    check_err(S.err, st, items, "box factorization");
-    // persistent solve data: index lists (skeletons then redundant, tree positions)
-    std::vector<std::vector<int32_t>> idx_keep(cnt);   // alive until the step's final sync
+    {
+      auto tw = Clock::now();
+      check_err(S.err, st, items, "box factorization");
+      wait_ms += ms_since(tw);
+    }
+    // persistent solve data: index lists (skeletons then redundant, tree positions),
+    // one contiguous block and one upload per problem and level
+    std::vector<std::vector<int32_t>> idx_keep(np);   // alive until the step's final sync
+    std::vector<int32_t *> d_idx_base(np, nullptr);
+    std::vector<int64_t> idx_fill(np, 0);
+    for (int i = 0; i < cnt; ++i) idx_fill[items[i].ps->pidx] += comp[i].n;
+    for (int p = 0; p < np; ++p) {
+      if (idx_fill[p] == 0) continue;
+      d_idx_base[p] = ps[p].h->arena.alloc_n<int32_t>(idx_fill[p]);
+      idx_keep[p].resize(idx_fill[p]);
+      idx_fill[p] = 0;
+    }
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
       const int k = ranks[i], n = comp[i].n;
       const int32_t *ord = order.data() + comp[i].order_off;
-      std::vector<int32_t> &idx = idx_keep[i];
-      idx.resize(n);
+      int32_t *idx = idx_keep[P.pidx].data() + idx_fill[P.pidx];
       for (int a = 0; a < n; ++a) idx[a] = P.J[b][ord[a]];
-      int32_t *d_idx = P.h->arena.alloc_n<int32_t>(std::max(n, 1));
-      if (n)
-        RS_HIP_CHECK(hipMemcpyAsync(d_idx, idx.data(), n * sizeof(int32_t),
-                                    hipMemcpyHostToDevice, st));
+      int32_t *d_idx = d_idx_base[P.pidx] + idx_fill[P.pidx];
+      idx_fill[P.pidx] += n;
       SweepBox sb;
       sb.k = k;
       sb.r = n - k;
@@ -454,6 +482,11 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       h->stats.max_box_n = std::max<int64_t>(h->stats.max_box_n, n);
       h->stats.max_box_m = std::max<int64_t>(h->stats.max_box_m, comp[i].m);
     }
+    for (int p = 0; p < np; ++p)
+      if (!idx_keep[p].empty())
+        RS_HIP_CHECK(hipMemcpyAsync(d_idx_base[p], idx_keep[p].data(),
+                                    idx_keep[p].size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    st));
     // keep host staging vectors alive until the copies are done
     RS_HIP_CHECK(hipStreamSynchronize(st));
   }
@@ -480,7 +513,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       pool.insert(pool.end(), J.begin(), J.end());
       fb.slot = P.h->arena.alloc_n<double>(std::max<int64_t>((int64_t)fb.n * fb.n, 1));
       fb.work_off = woff;
-      woff += 3 * (int64_t)fb.n * fb.n;
+      woff += (int64_t)diag_work_doubles(fb.n);
       fill_children(P, b, fb);
       fac.push_back(fb);
       items.push_back({&P, b});
@@ -556,6 +589,8 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     h->stats.maxdepth = ps[p].t->maxdepth;
     h->stats.dim = h->dim;
     h->stats.factor_ms = ms;
+    h->stats.plan_ms = plan_ms;
+    h->stats.wait_ms = wait_ms;
     out[p] = handles[p].release();
   }
 }
