@@ -137,6 +137,26 @@ rs_status rs_solve(rs_handle h, double *B, int64_t ldb, int32_t nrhs, void *stre
 rs_status rs_solve_ex(rs_handle h, double *B, int64_t ldb, int32_t nrhs,
                       const rs_options *opts);
 
+/* ------------------------------------------------- batched (many problems) ---- */
+
+/* Factors `count` independent problems together (arrays of length count): every
+ * launch covers one tree level of all problems, aligned at each problem's finest
+ * depth, and all roots share one launch.  Each problem's result is bitwise identical
+ * to rs_factor on it alone (same per-box kernels and reduction order).  On success
+ * out[i] receives problem i's handle; on error no handle is returned.  Errors as
+ * rs_factor. */
+rs_status rs_factor_batched(int32_t count, const rs_kernel *kernels, const rs_tree *trees,
+                            const double *const *points, const double *const *weights,
+                            const double *eps, const rs_options *opts, rs_handle *out);
+
+/* Solves request i (handle h[i], device block B[i] of nrhs[i] columns, leading
+ * dimension ldb[i]) for i < count in place, with shared per-level sweep launches
+ * across the handles; requests may repeat a handle only on disjoint B blocks.
+ * Asynchronous on opts->stream; per-request results are bitwise identical to
+ * rs_solve.  launch_mode must be RS_LAUNCH_LEVEL.  Errors: RS_EINVAL, RS_EDEVICE. */
+rs_status rs_solve_batched(int32_t count, const rs_handle *h, double *const *B,
+                           const int64_t *ldb, const int32_t *nrhs, const rs_options *opts);
+
 /* Releases a handle.  Waits for the library's own queued work on it; returns
  * RS_OK for NULL. */
 rs_status rs_free(rs_handle h);

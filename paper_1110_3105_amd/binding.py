@@ -34,7 +34,8 @@ LAUNCH = {"level": 0, "per_box": 1}
 EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "rs_factor",
             "rs_factor_ex", "rs_solve", "rs_solve_ex", "rs_free", "rs_last_error",
             "rs_device_count", "rs_query", "rs_box_skeletons", "rs_box_export",
-            "rs_profile_enable", "rs_profile_reset", "rs_profile_read"]
+            "rs_profile_enable", "rs_profile_reset", "rs_profile_read", "rs_factor_batched",
+            "rs_solve_batched"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -78,6 +79,11 @@ _sig = {
     "rs_query": (C.c_int, [_P, C.POINTER(rs_stats)]),
     "rs_box_skeletons": (C.c_int, [_P, _PI32, _PI64, C.c_int64, _PI64]),
     "rs_box_export": (C.c_int, [_P, C.c_int64, _PI32, _PI32, _PI64, _PD]),
+    "rs_factor_batched": (C.c_int, [C.c_int32, C.POINTER(rs_kernel), C.POINTER(_P),
+                                    C.POINTER(_PD), C.POINTER(_PD), _PD, C.POINTER(rs_options),
+                                    C.POINTER(_P)]),
+    "rs_solve_batched": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(C.c_void_p), _PI64,
+                                   _PI32, C.POINTER(rs_options)]),
     "rs_profile_enable": (C.c_int, [C.c_int32]),
     "rs_profile_reset": (C.c_int, []),
     "rs_profile_read": (C.c_int, [C.c_int32, _PI64, _PD, _PD, _PD, _PD]),
@@ -280,3 +286,70 @@ def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: 
     _check(_lib.rs_factor_ex(C.byref(k), tree.handle, _dptr(pts), _dptr(w), float(eps),
                              C.byref(o), C.byref(h)))
     return Handle(h, pts.shape[0], keep=(tree,))
+
+
+def _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio):
+    return rs_kernel(KINDS[kind], pts.shape[1], float(identity), 0.0, 0.0, _dptr(nrm),
+                     _dptr(kap), int(proxy_points), float(proxy_ratio))
+
+
+def factor_batched(problems, launch_mode: str = "level", stream=None):
+    """Factors several problems with shared per-level launches.
+
+    ``problems`` is a list of dicts with keys kind, tree, points, weights, eps and
+    optionally normals, curvature, identity, proxy_points, proxy_ratio.
+    Returns one Handle per problem.
+    """
+    count = len(problems)
+    keep, ks, trees, pts_p, w_p, eps = [], [], [], [], [], []
+    for q in problems:
+        pts = np.ascontiguousarray(q["points"], dtype=np.float64)
+        w = np.ascontiguousarray(q["weights"], dtype=np.float64)
+        nrm = q.get("normals")
+        kap = q.get("curvature")
+        nrm = None if nrm is None else np.ascontiguousarray(nrm, dtype=np.float64)
+        kap = None if kap is None else np.ascontiguousarray(kap, dtype=np.float64)
+        keep += [pts, w, nrm, kap]
+        ks.append(_kernel_struct(q["kind"], pts, nrm, kap, q.get("identity", 0.0),
+                                 q.get("proxy_points", 64), q.get("proxy_ratio", 1.5)))
+        trees.append(q["tree"].handle)
+        pts_p.append(_dptr(pts))
+        w_p.append(_dptr(w))
+        eps.append(float(q["eps"]))
+    K = (rs_kernel * count)(*ks)
+    T = (_P * count)(*trees)
+    PP = (_PD * count)(*pts_p)
+    WW = (_PD * count)(*w_p)
+    E = (C.c_double * count)(*eps)
+    out = (_P * count)()
+    o = rs_options(LAUNCH[launch_mode], _stream_ptr(stream))
+    _check(_lib.rs_factor_batched(count, K, T, PP, WW, E, C.byref(o), out))
+    return [Handle(_P(out[i]), problems[i]["points"].shape[0], keep=(problems[i]["tree"],))
+            for i in range(count)]
+
+
+def solve_batched(handles, blocks, stream=None):
+    """In place B_i := A_i^{-1} B_i for float64 CUDA tensors (n_i,) or (n_i, nrhs_i) that are
+    column-major (stride (1, ldb)); all requests share the per-level sweep launches."""
+    import torch
+    count = len(handles)
+    if len(blocks) != count:
+        raise ValueError("one block per handle")
+    ptrs, ldbs, nrhs = [], [], []
+    for h, B in zip(handles, blocks):
+        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.float64):
+            raise TypeError("blocks must be float64 tensors on the HIP device")
+        X = B.unsqueeze(1) if B.dim() == 1 else B
+        if X.shape[0] != h.n or X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) < h.n):
+            raise ValueError("each block must be column-major with n rows")
+        ptrs.append(X.data_ptr())
+        ldbs.append(X.stride(1) if X.shape[1] > 1 else h.n)
+        nrhs.append(X.shape[1])
+    H = (_P * count)(*[h.handle for h in handles])
+    Bp = (C.c_void_p * count)(*ptrs)
+    L = (C.c_int64 * count)(*ldbs)
+    R = (C.c_int32 * count)(*nrhs)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o = rs_options(LAUNCH["level"], _stream_ptr(stream))
+    _check(_lib.rs_solve_batched(count, H, Bp, L, R, C.byref(o)))

@@ -169,6 +169,57 @@ rs_status rs_factor(const rs_kernel *k, rs_tree t, const double *points, const d
   return rs_factor_ex(k, t, points, weights, eps, nullptr, out);
 }
 
+rs_status rs_factor_batched(int32_t count, const rs_kernel *kernels, const rs_tree *trees,
+                            const double *const *points, const double *const *weights,
+                            const double *eps, const rs_options *opts, rs_handle *out) {
+  return guarded([&]() -> rs_status {
+    if (count < 0) fail(RS_EINVAL, "count must be >= 0");
+    if (count == 0) return RS_OK;
+    if (!kernels || !trees || !points || !weights || !eps || !out) fail(RS_EINVAL, "NULL argument");
+    std::vector<FactorRequest> reqs(count);
+    for (int i = 0; i < count; ++i) {
+      if (!trees[i]) fail(RS_EINVAL, "NULL tree");
+      validate_kernel(&kernels[i], trees[i]->t, points[i], weights[i], eps[i]);
+      reqs[i] = FactorRequest{&kernels[i], &trees[i]->t, points[i], weights[i], eps[i]};
+    }
+    const int mode = mode_of(opts);
+    require_device();
+    std::vector<rs_factor_s *> hs;
+    factor_many(reqs, mode, stream_of(opts), hs);
+    for (int i = 0; i < count; ++i) out[i] = hs[i];
+    return RS_OK;
+  });
+}
+
+rs_status rs_solve_batched(int32_t count, const rs_handle *h, double *const *B,
+                           const int64_t *ldb, const int32_t *nrhs, const rs_options *opts) {
+  return guarded([&]() -> rs_status {
+    if (count < 0) fail(RS_EINVAL, "count must be >= 0");
+    if (count == 0) return RS_OK;
+    if (!h || !B || !ldb || !nrhs) fail(RS_EINVAL, "NULL argument");
+    std::vector<SolveRequest> reqs(count);
+    for (int i = 0; i < count; ++i) {
+      if (!h[i]) fail(RS_EINVAL, "NULL handle");
+      if (nrhs[i] < 0) fail(RS_EINVAL, "nrhs must be >= 0");
+      if (nrhs[i] > 0 && !B[i]) fail(RS_EINVAL, "NULL right-hand side");
+      if (ldb[i] < h[i]->n) fail(RS_EINVAL, "ldb < n");
+      reqs[i] = SolveRequest{h[i], B[i], ldb[i], nrhs[i]};
+    }
+    if (opts && opts->launch_mode != RS_LAUNCH_LEVEL)
+      fail(RS_EINVAL, "batched solves use per-level launches");
+    for (int i = 0; i < count; ++i) h[i]->busy.fetch_add(1);
+    struct Dec {
+      const rs_handle *h;
+      int n;
+      ~Dec() {
+        for (int i = 0; i < n; ++i) h[i]->busy.fetch_sub(1);
+      }
+    } dec{h, count};
+    solve_many(reqs, stream_of(opts));
+    return RS_OK;
+  });
+}
+
 rs_status rs_solve_ex(rs_handle h, double *B, int64_t ldb, int32_t nrhs,
                       const rs_options *opts) {
   return guarded([&]() -> rs_status {

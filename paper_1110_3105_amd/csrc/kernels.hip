@@ -626,14 +626,9 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
 // Up (finest level first):  t = b_r - T^T b_s;  b_r <- G t;  b_s <- b_s - E t.
 // Down (root side first):   u = y_r - F z_s;   b_r <- u;     b_s <- z_s - T u.
 template <int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_up(const SweepBox *__restrict__ boxes,
-                                                       int first, double *__restrict__ W,
-                                                       int nrhs) {
-  extern __shared__ double sh[];
-  const SweepBox &B = boxes[first + blockIdx.x];
+__device__ __forceinline__ void sweep_up_box(const SweepBox &B, double *__restrict__ W, int nrhs,
+                                             int col0, double *sh) {
   const int k = B.k, r = B.r;
-  if (r == 0) return;
-  const int col0 = blockIdx.y * NT;
   const int nt = min(NT, nrhs - col0);
   double *bs = sh;              // k x NT
   double *t = sh + k * NT;      // r x NT
@@ -666,14 +661,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_up(const SweepBox *__restric
 }
 
 template <int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restrict__ boxes,
-                                                         int first, double *__restrict__ W,
-                                                         int nrhs) {
-  extern __shared__ double sh[];
-  const SweepBox &B = boxes[first + blockIdx.x];
+__device__ __forceinline__ void sweep_down_box(const SweepBox &B, double *__restrict__ W,
+                                               int nrhs, int col0, double *sh) {
   const int k = B.k, r = B.r;
-  if (r == 0 || k == 0) return;
-  const int col0 = blockIdx.y * NT;
   const int nt = min(NT, nrhs - col0);
   double *z = sh;              // k x NT
   double *u = sh + k * NT;     // r x NT
@@ -696,6 +686,73 @@ __global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restr
     double s = z[e];
     for (int j = 0; j < r; ++j) s -= B.T[i + (int64_t)k * j] * u[j * NT + c];
     if (c < nt) W[(int64_t)idx[i] * nrhs + col0 + c] = s;
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_up(const SweepBox *__restrict__ boxes,
+                                                       int first, double *__restrict__ W,
+                                                       int nrhs) {
+  extern __shared__ double sh[];
+  const SweepBox &B = boxes[first + blockIdx.x];
+  if (B.r == 0) return;
+  sweep_up_box<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restrict__ boxes,
+                                                         int first, double *__restrict__ W,
+                                                         int nrhs) {
+  extern __shared__ double sh[];
+  const SweepBox &B = boxes[first + blockIdx.x];
+  if (B.r == 0 || B.k == 0) return;
+  sweep_down_box<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+}
+
+// Segment lookup for launches that cover the boxes of several handles: the last
+// segment whose first block is <= blockIdx.x.
+__device__ __forceinline__ int find_seg(const SweepSeg *segs, int nseg) {
+  int lo = 0, hi = nseg - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].block0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_up_seg(const SweepSeg *__restrict__ segs,
+                                                           int nseg) {
+  extern __shared__ double sh[];
+  const SweepSeg &S = segs[find_seg(segs, nseg)];
+  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
+  const int col0 = blockIdx.y * NT;
+  if (B.r == 0 || col0 >= S.nrhs) return;
+  sweep_up_box<NT>(B, S.W, S.nrhs, col0, sh);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_down_seg(const SweepSeg *__restrict__ segs,
+                                                             int nseg) {
+  extern __shared__ double sh[];
+  const SweepSeg &S = segs[find_seg(segs, nseg)];
+  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
+  const int col0 = blockIdx.y * NT;
+  if (B.r == 0 || B.k == 0 || col0 >= S.nrhs) return;
+  sweep_down_box<NT>(B, S.W, S.nrhs, col0, sh);
+}
+
+// Caller order <-> tree order for several right-hand-side blocks (grid.y = block).
+__global__ void k_permute_seg(const PermSeg *__restrict__ segs, int to_tree) {
+  const PermSeg &S = segs[blockIdx.y];
+  const int64_t total = S.n * S.nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / S.nrhs;
+    const int c = (int)(e - i * S.nrhs);
+    if (to_tree) S.W[e] = S.B[S.perm[i] + S.ldb * c];
+    else S.B[S.perm[i] + S.ldb * c] = S.W[e];
   }
 }
 
@@ -867,6 +924,37 @@ void launch_permute_out(double *B, int64_t ldb, const double *W, const int64_t *
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   hipLaunchKernelGGL(k_permute_out, dim3(blocks), dim3(256), 0, st, B, ldb, W, perm, n, nrhs);
   check_launch("k_permute_out");
+}
+
+template <int NT>
+void sweep_seg_nt(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs, int max_n,
+                  hipStream_t st) {
+  dim3 grid(nblocks, (max_nrhs + NT - 1) / NT);
+  const size_t lds = (size_t)max_n * NT * sizeof(double);
+  if (up)
+    hipLaunchKernelGGL(k_sweep_up_seg<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
+  else
+    hipLaunchKernelGGL(k_sweep_down_seg<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
+  check_launch("k_sweep_seg");
+}
+
+void launch_sweep_seg(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
+                      int max_n, hipStream_t st) {
+  if (nseg <= 0 || nblocks <= 0 || max_nrhs <= 0) return;
+  switch (pick_nt(max_nrhs, max_n)) {
+    case 1: sweep_seg_nt<1>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+    case 4: sweep_seg_nt<4>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+    case 16: sweep_seg_nt<16>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+    default: sweep_seg_nt<32>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+  }
+}
+
+void launch_permute_seg(const PermSeg *segs, int nseg, int64_t max_elems, bool to_tree,
+                        hipStream_t st) {
+  if (nseg <= 0 || max_elems <= 0) return;
+  const int blocks = (int)std::min<int64_t>((max_elems + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_permute_seg, dim3(blocks, nseg), dim3(256), 0, st, segs, to_tree ? 1 : 0);
+  check_launch("k_permute_seg");
 }
 
 void launch_sweep_up(const SweepBox *boxes, int first, int count, double *W, int nrhs,

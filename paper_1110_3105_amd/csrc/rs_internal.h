@@ -72,6 +72,28 @@ struct SweepBox {
   const double *F;         // r x k  (G X_rs)
 };
 
+// A run of consecutive blocks of a multi-handle sweep launch: boxes[0..count) of one
+// handle's level, applied to that handle's workspace W (nrhs columns).
+struct SweepSeg {
+  const SweepBox *boxes;
+  double *W;
+  int32_t count;
+  int32_t nrhs;
+  int32_t block0;          // first block of the launch that belongs to this segment
+  int32_t pad;
+};
+
+// One right-hand-side block of a multi-handle permutation launch.
+struct PermSeg {
+  double *B;               // caller order, column-major, leading dimension ldb
+  int64_t ldb;
+  double *W;               // tree order, row-major n x nrhs
+  const int64_t *perm;
+  int64_t n;
+  int32_t nrhs;
+  int32_t pad;
+};
+
 // Slot layout of a factored box with n = k + r.
 __host__ __device__ inline int64_t slot_T(int k, int r) { (void)k; (void)r; return 0; }
 __host__ __device__ inline int64_t slot_G(int k, int r) { return (int64_t)k * r; }
@@ -106,6 +128,10 @@ void launch_sweep_up(const SweepBox *boxes, int first, int count, double *W, int
                      int max_n, hipStream_t st);
 void launch_sweep_down(const SweepBox *boxes, int first, int count, double *W, int nrhs,
                        int max_n, hipStream_t st);
+void launch_sweep_seg(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
+                      int max_n, hipStream_t st);
+void launch_permute_seg(const PermSeg *segs, int nseg, int64_t max_elems, bool to_tree,
+                        hipStream_t st);
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string &msg);

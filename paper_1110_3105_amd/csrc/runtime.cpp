@@ -25,7 +25,7 @@ void *Arena::alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (chunks.empty() || used + bytes > chunks.back()->bytes) {
     auto c = std::make_unique<DevBuf>();
-    c->ensure(std::max<size_t>(bytes, size_t(32) << 20));
+    c->ensure(std::max<size_t>(bytes, size_t(8) << 20));
     chunks.push_back(std::move(c));
     used = 0;
   }
@@ -657,6 +657,109 @@ void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode
     ProfScope ps_(RS_K_PERMUTE, st);
     launch_permute_out(B, ldb, W, h->d_perm, n, nrhs, st);
   }
+}
+
+}  // namespace rs
+
+namespace rs {
+
+namespace {
+struct LaunchRec {
+  int64_t seg_off;
+  int nseg, nblocks, max_nrhs, max_n;
+  bool up;
+};
+void release_host_vector(void *p) { delete static_cast<std::vector<char> *>(p); }
+}  // namespace
+
+void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
+  std::vector<SolveRequest> rq;
+  for (const SolveRequest &q : reqs)
+    if (q.nrhs > 0) rq.push_back(q);
+  if (rq.empty()) return;
+  const int nq = (int)rq.size();
+  // workspace offsets
+  std::vector<int64_t> woff(nq);
+  int64_t wtot = 0;
+  int max_levels = 0;
+  for (int i = 0; i < nq; ++i) {
+    woff[i] = wtot;
+    wtot += rq[i].h->n * (int64_t)rq[i].nrhs;
+    max_levels = std::max(max_levels, (int)rq[i].h->levels.size());
+  }
+  double *W = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)wtot * sizeof(double), st));
+  // segment tables: permutations, then upward steps (finest level first), the roots,
+  // then downward steps; each launch's segments are contiguous.
+  std::vector<PermSeg> perm(nq);
+  int64_t max_elems = 0;
+  for (int i = 0; i < nq; ++i) {
+    perm[i].B = rq[i].B;
+    perm[i].ldb = rq[i].ldb;
+    perm[i].W = W + woff[i];
+    perm[i].perm = rq[i].h->d_perm;
+    perm[i].n = rq[i].h->n;
+    perm[i].nrhs = rq[i].nrhs;
+    perm[i].pad = 0;
+    max_elems = std::max<int64_t>(max_elems, rq[i].h->n * (int64_t)rq[i].nrhs);
+  }
+  std::vector<SweepSeg> segs;
+  std::vector<LaunchRec> launches;
+  auto add_step = [&](bool up, auto level_of) {
+    LaunchRec L{(int64_t)segs.size(), 0, 0, 0, 0, up};
+    for (int i = 0; i < nq; ++i) {
+      const LevelRec *lv = level_of(rq[i].h);
+      if (!lv || lv->sweep.empty()) continue;
+      SweepSeg s;
+      s.boxes = lv->d_sweep;
+      s.W = W + woff[i];
+      s.count = (int)lv->sweep.size();
+      s.nrhs = rq[i].nrhs;
+      s.block0 = L.nblocks;
+      s.pad = 0;
+      segs.push_back(s);
+      L.nseg++;
+      L.nblocks += s.count;
+      L.max_nrhs = std::max(L.max_nrhs, s.nrhs);
+      L.max_n = std::max(L.max_n, lv->max_n);
+    }
+    if (L.nseg) launches.push_back(L);
+  };
+  for (int t = 0; t < max_levels; ++t)
+    add_step(true, [t](rs_factor_s *h) -> const LevelRec * {
+      return t < (int)h->levels.size() ? &h->levels[t] : nullptr;
+    });
+  add_step(true, [](rs_factor_s *h) -> const LevelRec * { return &h->root; });
+  for (int t = max_levels - 1; t >= 0; --t)
+    add_step(false, [t](rs_factor_s *h) -> const LevelRec * {
+      return t < (int)h->levels.size() ? &h->levels[t] : nullptr;
+    });
+  // one upload of all tables; the host copy is released by a stream callback
+  const size_t perm_bytes = perm.size() * sizeof(PermSeg);
+  const size_t seg_bytes = segs.size() * sizeof(SweepSeg);
+  auto *host = new std::vector<char>(perm_bytes + seg_bytes);
+  std::memcpy(host->data(), perm.data(), perm_bytes);
+  if (seg_bytes) std::memcpy(host->data() + perm_bytes, segs.data(), seg_bytes);
+  char *dtab = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&dtab, host->size(), st));
+  RS_HIP_CHECK(hipMemcpyAsync(dtab, host->data(), host->size(), hipMemcpyHostToDevice, st));
+  RS_HIP_CHECK(hipLaunchHostFunc(st, release_host_vector, host));
+  const PermSeg *d_perm = reinterpret_cast<const PermSeg *>(dtab);
+  const SweepSeg *d_segs = reinterpret_cast<const SweepSeg *>(dtab + perm_bytes);
+  {
+    ProfScope ps_(RS_K_PERMUTE, st);
+    launch_permute_seg(d_perm, nq, max_elems, true, st);
+  }
+  for (const LaunchRec &L : launches) {
+    ProfScope ps_(L.up ? RS_K_SWEEP_UP : RS_K_SWEEP_DOWN, st);
+    launch_sweep_seg(L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs, L.max_n, st);
+  }
+  {
+    ProfScope ps_(RS_K_PERMUTE, st);
+    launch_permute_seg(d_perm, nq, max_elems, false, st);
+  }
+  RS_HIP_CHECK(hipFreeAsync(dtab, st));
+  RS_HIP_CHECK(hipFreeAsync(W, st));
 }
 
 }  // namespace rs

@@ -89,6 +89,16 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
 void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode,
                hipStream_t st);
 
+struct SolveRequest {
+  rs_factor_s *h;
+  double *B;
+  int64_t ldb;
+  int nrhs;
+};
+// Solves every request with shared per-level launches (levels aligned at the finest
+// depth of each handle; all roots in one launch).  Enqueued on st; asynchronous.
+void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st);
+
 struct UserError {
   rs_status code;
   std::string what;
