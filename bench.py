@@ -75,6 +75,66 @@ def cpu_baseline(g, b_host):
             "host_cpus": os.cpu_count()}
 
 
+def many_problems(rs, torch, stream, count=256):
+    """Independent problems factored and solved in shared launches vs one at a time.
+
+    Workload: `count` random smooth curves r = 1 + sum_{k<=8} a_k cos(k t + phi_k),
+    a_k ~ U(0, 0.04), N ~ U{1024..16384} (member p seeded with 1000 + p), interior
+    double layer, eps = 1e-9, leaf 64, 64 proxies, one Gaussian right-hand side each.
+    """
+    import numpy as np
+    import workloads as W
+    probs = [W.random_curve_problem(p) for p in range(count)]
+    specs = []
+    for g, _ in probs:
+        specs.append(dict(kind="lap2d_dl", tree=rs.build_tree(g.points, LEAF), points=g.points,
+                          weights=g.weights, normals=g.normals, curvature=g.curvature,
+                          identity=-0.5, eps=EPS, proxy_points=NPX))
+    for h in rs.factor_batched(specs[:8], stream=stream):         # warm-up
+        h.free()
+    fb = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        hb = rs.factor_batched(specs, stream=stream)
+        torch.cuda.synchronize()
+        fb.append((time.perf_counter() - a) * 1e3)
+        if _ == 0:
+            for h in hb:
+                h.free()
+    blocks = [torch.tensor(b.T.copy(), device="cuda").t() for _, b in probs]
+    rs.solve_batched(hb, blocks, stream=stream)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(5):
+        rs.solve_batched(hb, blocks, stream=stream)
+    torch.cuda.synchronize()
+    sb = (time.perf_counter() - a) * 1e3 / 5
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    hs = [rs.factor(q["kind"], q["tree"], q["points"], q["weights"], EPS, normals=q["normals"],
+                    curvature=q["curvature"], identity=-0.5, proxy_points=NPX, stream=stream)
+          for q in specs]
+    torch.cuda.synchronize()
+    fs = (time.perf_counter() - a) * 1e3
+    a = time.perf_counter()
+    for _ in range(2):
+        for h, blk in zip(hs, blocks):
+            h.solve(blk, stream=stream)
+    torch.cuda.synchronize()
+    ss = (time.perf_counter() - a) * 1e3 / 2
+    for h in hb + hs:
+        h.free()
+    nsum = int(sum(g.n for g, _ in probs))
+    return {"workload": f"{count} random curves, N~U[1024,16384] (sum {nsum}), double layer, "
+                        "eps=1e-9, 1 RHS each",
+            "problems": count, "unknowns": nsum,
+            "factor_ms_batched": float(np.median(fb)), "factor_ms_one_at_a_time": fs,
+            "solve_ms_batched": sb, "solve_ms_one_at_a_time": ss,
+            "rhs_per_s_batched": count / (sb * 1e-3), "rhs_per_s_one_at_a_time": count / (ss * 1e-3),
+            "factor_speedup": fs / float(np.median(fb)), "solve_speedup": ss / sb}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -205,6 +265,7 @@ def main():
             "solve_speedup_512": extras["per_box"]["solve"]["512"]["ms"]
             / extras["level"]["solve"]["512"]["ms"]}
         out["latency_ms"] = extras["level"]["latency"]
+        out["many_problems"] = many_problems(rs, torch, stream)
         out["paper_context"] = {"hardware": "2.66 GHz single CPU core, Fortran (Section 6)",
                                 "table5_N65536_ellipse_dl": {"T_cm_s": 2.3, "T_lu_s": 1.8,
                                                              "T_sv_s": 0.038}}

@@ -202,6 +202,67 @@ rs_status rs_box_skeletons(rs_handle h, int32_t *k_out, int64_t *skel_out, int64
 rs_status rs_box_export(rs_handle h, int64_t b, int32_t *n_out, int32_t *k_out,
                         int64_t *J_out, double *T_out);
 
+/* -------------------------------------------------------------- serving ---- */
+
+/* A request server: factorizations stay resident in device memory; solve requests
+ * (any handle, any nrhs) are batched continuously into shared per-level sweeps, with
+ * up to two batches on the device at once on separate streams, so requests that
+ * arrive while a batch runs join the next one; factor requests are admitted in
+ * arrival order when their estimated device footprint fits the free budget, and run
+ * on their own stream concurrently with the solves.  Per-request results are
+ * bitwise identical to rs_solve / rs_factor on the same inputs.
+ * For callers that keep many factors resident and serve streams of right-hand sides
+ * (the regime the paper's fast solve phase targets). */
+typedef struct rs_server_s *rs_server;
+
+typedef struct {
+  size_t hbm_budget;            /* bytes the server's own factorizations may occupy */
+  int32_t max_batch_requests;   /* solve requests per batch (<= 0: 64) */
+  int32_t max_batch_rhs;        /* right-hand-side columns per batch (<= 0: 4096) */
+} rs_server_opts;
+
+typedef struct {
+  int64_t solves_done, rhs_done, factors_done, rejected, batches;
+  int64_t resident_bytes;       /* device bytes held by the server's factorizations */
+  int64_t queued_solves, queued_factors;
+  double p50_ms, p99_ms, mean_ms;  /* solve latency: submission -> completion event */
+  double window_ms;             /* first submission -> last completion */
+} rs_server_stats;
+
+/* Creates a server on the current device.  Errors: RS_EINVAL, RS_EDEVICE. */
+rs_status rs_server_create(const rs_server_opts *opts, rs_server *out);
+
+/* Queues a factorization (arguments as rs_factor; inputs are copied, so they may be
+ * freed on return).  A request whose estimated footprint exceeds the whole budget
+ * completes at once with RS_ENOMEM.  *ticket identifies the request. */
+rs_status rs_server_submit_factor(rs_server s, const rs_kernel *k, rs_tree t,
+                                  const double *points, const double *weights, double eps,
+                                  uint64_t *ticket);
+
+/* Queues B := A^{-1} B (device memory, column-major, ldb >= n, nrhs >= 1).  B must
+ * not be touched until the ticket completes; concurrent requests need disjoint B. */
+rs_status rs_server_submit_solve(rs_server s, rs_handle h, double *B, int64_t ldb,
+                                 int32_t nrhs, uint64_t *ticket);
+
+/* Waits up to timeout_ms (0: no wait, < 0: forever) for a ticket.  *done = 1 when it
+ * completed; then *status holds its outcome, *factor_out the new handle of a factor
+ * request, and the ticket is forgotten.  Handles created by the server are owned by
+ * it: release them with rs_server_release (not rs_free); the rest are freed by
+ * rs_server_destroy. */
+rs_status rs_server_poll(rs_server s, uint64_t ticket, int32_t timeout_ms, int32_t *done,
+                         rs_status *status, rs_handle *factor_out);
+
+/* Frees a server-created handle and returns its memory to the budget.  RS_EBUSY if
+ * solves on it are queued or running. */
+rs_status rs_server_release(rs_server s, rs_handle h);
+
+rs_status rs_server_query(rs_server s, rs_server_stats *out);
+rs_status rs_server_reset_stats(rs_server s);
+
+/* Waits for queued and running solves, drops queued factor requests, stops the
+ * threads and frees the server's handles. */
+void rs_server_destroy(rs_server s);
+
 /* ------------------------------------------------------------ profiling ---- */
 
 /* Kernel families of the library, for rs_profile_read. */

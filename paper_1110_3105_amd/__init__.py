@@ -9,7 +9,9 @@ from .binding import (  # noqa: F401
     rs_free, rs_last_error, rs_query, rs_solve, rs_solve_ex, rs_tree_export, rs_tree_free,
     rs_tree_info, LIB_PATH, FAMILIES, profile_enable, profile_read, profile_reset,
     rs_profile_enable, rs_profile_read, rs_profile_reset, factor_batched, solve_batched,
-    rs_factor_batched, rs_solve_batched,
+    rs_factor_batched, rs_solve_batched, Server, rs_server_create, rs_server_destroy,
+    rs_server_poll, rs_server_query, rs_server_release, rs_server_reset_stats,
+    rs_server_submit_factor, rs_server_submit_solve,
 )
 
 

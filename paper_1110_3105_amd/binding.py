@@ -35,7 +35,9 @@ EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "
             "rs_factor_ex", "rs_solve", "rs_solve_ex", "rs_free", "rs_last_error",
             "rs_device_count", "rs_query", "rs_box_skeletons", "rs_box_export",
             "rs_profile_enable", "rs_profile_reset", "rs_profile_read", "rs_factor_batched",
-            "rs_solve_batched"]
+            "rs_solve_batched", "rs_server_create", "rs_server_submit_factor",
+            "rs_server_submit_solve", "rs_server_poll", "rs_server_release", "rs_server_query",
+            "rs_server_reset_stats", "rs_server_destroy"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -56,6 +58,19 @@ class rs_stats(C.Structure):
                 ("factor_doubles", C.c_int64), ("max_box_n", C.c_int64),
                 ("max_box_m", C.c_int64), ("factor_ms", C.c_double), ("plan_ms", C.c_double),
                 ("wait_ms", C.c_double)]
+
+
+class rs_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_batch_requests", C.c_int32),
+                ("max_batch_rhs", C.c_int32)]
+
+
+class rs_server_stats(C.Structure):
+    _fields_ = [("solves_done", C.c_int64), ("rhs_done", C.c_int64), ("factors_done", C.c_int64),
+                ("rejected", C.c_int64), ("batches", C.c_int64), ("resident_bytes", C.c_int64),
+                ("queued_solves", C.c_int64), ("queued_factors", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("window_ms", C.c_double)]
 
 
 _P = C.c_void_p
@@ -84,6 +99,16 @@ _sig = {
                                     C.POINTER(_P)]),
     "rs_solve_batched": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(C.c_void_p), _PI64,
                                    _PI32, C.POINTER(rs_options)]),
+    "rs_server_create": (C.c_int, [C.POINTER(rs_server_opts), C.POINTER(_P)]),
+    "rs_server_submit_factor": (C.c_int, [_P, C.POINTER(rs_kernel), _P, _PD, _PD, C.c_double,
+                                          C.POINTER(C.c_uint64)]),
+    "rs_server_submit_solve": (C.c_int, [_P, _P, C.c_void_p, C.c_int64, C.c_int32,
+                                         C.POINTER(C.c_uint64)]),
+    "rs_server_poll": (C.c_int, [_P, C.c_uint64, C.c_int32, _PI32, _PI32, C.POINTER(_P)]),
+    "rs_server_release": (C.c_int, [_P, _P]),
+    "rs_server_query": (C.c_int, [_P, C.POINTER(rs_server_stats)]),
+    "rs_server_reset_stats": (C.c_int, [_P]),
+    "rs_server_destroy": (None, [_P]),
     "rs_profile_enable": (C.c_int, [C.c_int32]),
     "rs_profile_reset": (C.c_int, []),
     "rs_profile_read": (C.c_int, [C.c_int32, _PI64, _PD, _PD, _PD, _PD]),
@@ -196,17 +221,25 @@ def _stream_ptr(stream) -> Optional[int]:
 class Handle:
     """Owning wrapper of an rs_handle (compressed inverse resident in device memory)."""
 
-    def __init__(self, h, n: int, keep):
+    def __init__(self, h, n: int, keep, server=None):
         self._h = h
         self.n = n
         self._keep = keep
+        self._server = server
 
     def __del__(self):
-        self.free()
+        try:
+            self.free()
+        except Exception:
+            pass
 
     def free(self):
         if getattr(self, "_h", None):
-            _check(_lib.rs_free(self._h))
+            if self._server is not None:
+                if self._server._s is not None:
+                    _check(_lib.rs_server_release(self._server._s, self._h))
+            else:
+                _check(_lib.rs_free(self._h))
             self._h = None
 
     @property
@@ -353,3 +386,75 @@ def solve_batched(handles, blocks, stream=None):
         stream = torch.cuda.current_stream()
     o = rs_options(LAUNCH["level"], _stream_ptr(stream))
     _check(_lib.rs_solve_batched(count, H, Bp, L, R, C.byref(o)))
+
+
+class Server:
+    """Request server (rs_server_*): resident factorizations, continuous batching of
+    solve requests, factor requests admitted against a device-memory budget."""
+
+    def __init__(self, hbm_budget: int, max_batch_requests: int = 64, max_batch_rhs: int = 4096):
+        o = rs_server_opts(int(hbm_budget), int(max_batch_requests), int(max_batch_rhs))
+        h = _P()
+        _check(_lib.rs_server_create(C.byref(o), C.byref(h)))
+        self._s = h
+        self._pending = {}          # ticket -> objects kept alive until completion
+
+    def close(self):
+        if getattr(self, "_s", None):
+            _lib.rs_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        self.close()
+
+    def submit_factor(self, kind: str, tree: Tree, points, weights, eps: float, normals=None,
+                      curvature=None, identity: float = 0.0, proxy_points: int = 64,
+                      proxy_ratio: float = 1.5) -> int:
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64)
+        kap = None if curvature is None else np.ascontiguousarray(curvature, dtype=np.float64)
+        k = _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio)
+        t = C.c_uint64()
+        _check(_lib.rs_server_submit_factor(self._s, C.byref(k), tree.handle, _dptr(pts), _dptr(w),
+                                            float(eps), C.byref(t)))
+        self._pending[t.value] = ("factor", pts.shape[0], tree)
+        return t.value
+
+    def submit_solve(self, handle: Handle, B) -> int:
+        X = B.unsqueeze(1) if B.dim() == 1 else B
+        if X.shape[0] != handle.n or X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) < handle.n):
+            raise ValueError("B must be column-major with n rows")
+        ldb = X.stride(1) if X.shape[1] > 1 else handle.n
+        t = C.c_uint64()
+        _check(_lib.rs_server_submit_solve(self._s, handle.handle, C.c_void_p(X.data_ptr()),
+                                           int(ldb), int(X.shape[1]), C.byref(t)))
+        self._pending[t.value] = ("solve", B, handle)
+        return t.value
+
+    def poll(self, ticket: int, timeout_ms: int = 0):
+        """(done, status, Handle-or-None); a completed ticket is forgotten."""
+        done, st, h = C.c_int32(), C.c_int32(), _P()
+        _check(_lib.rs_server_poll(self._s, C.c_uint64(ticket), int(timeout_ms), C.byref(done),
+                                   C.byref(st), C.byref(h)))
+        if not done.value:
+            return False, None, None
+        kind = self._pending.pop(ticket, (None,))
+        handle = None
+        if kind[0] == "factor" and st.value == RS_OK and h.value:
+            handle = Handle(_P(h.value), kind[1], keep=(kind[2],), server=self)
+        return True, st.value, handle
+
+    def wait(self, ticket: int):
+        done, st, h = self.poll(ticket, -1)
+        if st != RS_OK:
+            raise RSError(st, _lib.rs_last_error().decode())
+        return h
+
+    def stats(self) -> dict:
+        s = rs_server_stats()
+        _check(_lib.rs_server_query(self._s, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in rs_server_stats._fields_}
+
+    def reset_stats(self):
+        _check(_lib.rs_server_reset_stats(self._s))

@@ -104,6 +104,10 @@ struct UserError {
   std::string what;
 };
 
+// Argument checks shared by rs_factor and the server (throws UserError).
+void validate_kernel(const rs_kernel *k, const Tree &t, const double *points,
+                     const double *weights, double eps);
+
 // ---- launch profiler (see rs_profile_enable)
 struct Work {
   double flops = 0, bytes = 0, entries = 0;

@@ -1,0 +1,129 @@
+"""The request server on the MI355X: continuous batching, admission by memory.
+
+Requests arrive from several threads at random times while others are on the device;
+each request's result must be bitwise identical to solving it alone, factor requests
+must be admitted only when their footprint fits the budget, and latency statistics are
+reported.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GiB = 1 << 30
+
+
+def _factor_direct(rs, g, kind="lap2d_sl", leaf=64):
+    t = rs.build_tree(g.points, leaf)
+    kw = {}
+    if kind == "lap2d_dl":
+        kw = dict(normals=g.normals, curvature=g.curvature, identity=-0.5)
+    return rs.factor(kind, t, g.points, g.weights, 1e-9, **kw)
+
+
+def _solve_alone(h, b):
+    import torch
+    B = torch.tensor(b.T.copy(), device="cuda").t()
+    h.solve(B)
+    torch.cuda.synchronize()
+    return B.cpu().numpy()
+
+
+def test_mixed_requests_equal_alone(gpu_lib):
+    import torch
+    rs = gpu_lib
+    geoms = [W.star_curve(4096), W.star_curve(2500),
+             W.random_curve(3000, [0.03, 0.02, 0.01], [0.3, 1.0, 2.0])]
+    kinds = ["lap2d_sl", "lap2d_sl", "lap2d_dl"]
+    handles = [_factor_direct(rs, g, k) for g, k in zip(geoms, kinds)]
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(48):
+        j = int(rng.integers(0, 3))
+        nrhs = int(rng.integers(1, 41))
+        reqs.append((j, W.gaussian_rhs(geoms[j].n, nrhs, 200 + i)))
+    srv = rs.Server(8 * GiB, max_batch_requests=16, max_batch_rhs=256)
+    blocks = [torch.tensor(b.T.copy(), device="cuda").t() for _, b in reqs]
+    torch.cuda.synchronize()
+    tickets = [None] * len(reqs)
+
+    def worker(ids):
+        r = np.random.default_rng(ids[0])
+        for i in ids:
+            time.sleep(float(r.uniform(0, 0.002)))
+            tickets[i] = srv.submit_solve(handles[reqs[i][0]], blocks[i])
+
+    threads = [threading.Thread(target=worker, args=(list(range(w, len(reqs), 4)),))
+               for w in range(4)]
+    for th in threads:
+        th.start()
+    # a factor request arrives while solves are running and overlaps them
+    g4 = W.star_curve(8192)
+    t4 = rs.build_tree(g4.points, 64)
+    ft = srv.submit_factor("lap2d_sl", t4, g4.points, g4.weights, 1e-9)
+    for th in threads:
+        th.join()
+    for t in tickets:
+        done, st, _ = srv.poll(t, -1)
+        assert done and st == 0
+    h4 = srv.wait(ft)
+    for (j, b), blk in zip(reqs, blocks):
+        assert np.array_equal(blk.cpu().numpy(), _solve_alone(handles[j], b))
+    # the server-made factor is identical to a direct one
+    d4 = _factor_direct(rs, g4)
+    b4 = W.gaussian_rhs(g4.n, 3, 1)
+    B4 = torch.tensor(b4.T.copy(), device="cuda").t()
+    srv.wait(srv.submit_solve(h4, B4))
+    assert np.array_equal(B4.cpu().numpy(), _solve_alone(d4, b4))
+    st = srv.stats()
+    assert st["solves_done"] == len(reqs) + 1 and st["factors_done"] == 1
+    assert st["batches"] >= 2
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    h4.free()
+    srv.close()
+
+
+def test_admission_by_memory(gpu_lib):
+    rs = gpu_lib
+    g = W.star_curve(16384)
+    t = rs.build_tree(g.points, 64)
+    # footprint estimate of this request: 6 KiB * N + 64 MiB = 160 MiB; the factor it
+    # leaves resident holds > 10 MiB, so a second one does not fit in 170 MiB
+    srv = rs.Server(170 << 20)
+    big = W.star_curve(65536)
+    tb = rs.build_tree(big.points, 64)
+    tk_big = srv.submit_factor("lap2d_sl", tb, big.points, big.weights, 1e-9)
+    done, st, _ = srv.poll(tk_big, -1)
+    assert done and st == rs.binding.RS_ENOMEM          # larger than the whole budget
+    t1 = srv.submit_factor("lap2d_sl", t, g.points, g.weights, 1e-9)
+    h1 = srv.wait(t1)
+    # the next request does not fit while h1 is resident ...
+    t2 = srv.submit_factor("lap2d_sl", t, g.points, g.weights, 1e-9)
+    time.sleep(0.5)
+    done, _, _ = srv.poll(t2, 0)
+    assert not done
+    assert srv.stats()["queued_factors"] == 1
+    # ... and is admitted once h1 is released
+    h1.free()
+    h2 = srv.wait(t2)
+    assert h2 is not None
+    h2.free()
+    srv.close()
+
+
+def test_server_rejects_bad_requests(gpu_lib):
+    import torch
+    rs = gpu_lib
+    g = W.star_curve(512)
+    h = _factor_direct(rs, g)
+    srv = rs.Server(1 * GiB)
+    with pytest.raises(ValueError):
+        srv.submit_solve(h, torch.zeros(511, 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(rs.RSError):
+        srv.submit_factor("lap2d_sl", rs.build_tree(g.points, 64), g.points, g.weights, -1.0)
+    srv.close()
