@@ -427,9 +427,10 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
                                                      const int32_t *__restrict__ order_pool,
                                                      const int32_t *__restrict__ ranks,
                                                      double *__restrict__ workbase,
-                                                     int32_t *__restrict__ err) {
+                                                     int32_t *__restrict__ err, int err_base) {
   constexpr int NW = NTH / 64;
-  constexpr int CB = 4;
+  constexpr int CB = 4;    // columns per wave in the elimination
+  constexpr int RB = 4;    // rows per lane per chunk in the elimination
   extern __shared__ double sh[];
   __shared__ double s_inv;
   __shared__ int s_prow, s_bad;
@@ -547,26 +548,39 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
       Ac[j] = c == j ? inv : Ac[j] * inv;
     }
     __syncthreads();
+    // A(i, c) <- [c != j] A(i, c) - fac[i] A(j, c) for i != j.  All loads of a chunk of
+    // RB rows x CB columns are issued before its stores, so they overlap in flight.
     for (int c0 = wave * CB; c0 < r; c0 += NW * CB) {
       double aj[CB];
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) aj[cb] = c0 + cb < r ? A[(int64_t)(c0 + cb) * n + j] : 0.0;
-      for (int i = lane; i < r; i += 64) {
-        if (i == j) continue;
-        const double f = fac[i];
-        double v[CB];
+      for (int i0 = 0; i0 < r; i0 += 64 * RB) {
+        double v[RB][CB], f[RB];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-          v[cb] = (c0 + cb < r && c0 + cb != j) ? A[(int64_t)(c0 + cb) * n + i] : 0.0;
+        for (int rb = 0; rb < RB; ++rb) {
+          const int i = i0 + lane + 64 * rb;
+          const bool ok = i < r && i != j;
+          f[rb] = ok ? fac[i] : 0.0;
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-          if (c0 + cb < r) A[(int64_t)(c0 + cb) * n + i] = v[cb] - f * aj[cb];
+          for (int cb = 0; cb < CB; ++cb)
+            v[rb][cb] = (ok && c0 + cb < r && c0 + cb != j) ? A[(int64_t)(c0 + cb) * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int i = i0 + lane + 64 * rb;
+          if (i < r && i != j) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+              if (c0 + cb < r) A[(int64_t)(c0 + cb) * n + i] = v[rb][cb] - f[rb] * aj[cb];
+          }
+        }
       }
     }
     __syncthreads();
   }
   if (s_bad) {
-    if (threadIdx.x == 0) atomicCAS(err, -1, first + (int)blockIdx.x);
+    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned int *>(err),
+                                    (unsigned int)(err_base + first + (int)blockIdx.x));
     return;
   }
   for (int j = r - 1; j >= 0; --j) {      // undo the row interchanges on the columns
@@ -822,49 +836,70 @@ void launch_assemble(const CompBox *boxes, int first, int count, const ProbDev *
   check_launch("k_assemble");
 }
 
-constexpr int kCpqrThreads = 512;
 constexpr int kVldsMaxRows = 8192;
 
-size_t cpqr_lds_bytes(int max_n, int max_m) {
-  const int nw = kCpqrThreads / 64;
+size_t cpqr_lds_bytes_nt(int nth, int max_n, int max_m) {
+  const int nw = nth / 64;
   size_t b = (size_t)max_n * sizeof(double) + (size_t)2 * max_n * sizeof(int) +
              (size_t)nw * max_n * sizeof(double);
   if (max_m <= kVldsMaxRows) b += (size_t)max_m * sizeof(double);
   return b;
 }
 
-template <int RT, int CB, bool VLDS>
+size_t cpqr_lds_bytes(int max_n, int max_m) { return cpqr_lds_bytes_nt(256, max_n, max_m); }
+
+template <int NTH, int RT, int CB, bool VLDS>
 void cpqr_variant(const CompBox *boxes, int first, int count, const ProbDev *probs,
                   double *Marena, int32_t *order_pool, int32_t *ranks, size_t lds,
                   hipStream_t st) {
-  auto kern = k_cpqr_id<kCpqrThreads, RT, CB, VLDS>;
+  auto kern = k_cpqr_id<NTH, RT, CB, VLDS>;
   if (lds > 64 * 1024)
     RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kern, dim3(count), dim3(kCpqrThreads), lds, st, boxes, first, probs, Marena,
+  hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, Marena,
                      order_pool, ranks);
   check_launch("k_cpqr_id");
+}
+
+template <int NTH>
+void cpqr_bucket(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                 double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
+                 hipStream_t st) {
+  const size_t lds = cpqr_lds_bytes_nt(NTH, max_n, max_m);
+  const size_t lds_nov = cpqr_lds_bytes_nt(NTH, max_n, kVldsMaxRows + 1);
+  if (lds_nov > kLdsLimit)
+    throw DeviceError("k_cpqr_id: box too large for LDS", hipErrorInvalidValue);
+  // size buckets: rows held per lane (RT) and columns per wave (CB); 1024-thread
+  // workgroups have half the registers per lane, so they hold fewer columns
+  constexpr int CB4 = NTH >= 1024 ? 2 : 4;
+  constexpr int CB16 = NTH >= 1024 ? 1 : 2;
+  if (max_m <= 256 && lds <= kLdsLimit)
+    cpqr_variant<NTH, 4, CB4, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds,
+                                    st);
+  else if (max_m <= 512 && lds <= kLdsLimit)
+    cpqr_variant<NTH, 8, CB4 / 2 * (NTH >= 1024 ? 1 : 2), true>(
+        boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
+  else if (lds <= kLdsLimit)
+    cpqr_variant<NTH, 16, CB16, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds,
+                                      st);
+  else
+    cpqr_variant<NTH, 16, CB16, false>(boxes, first, count, probs, Marena, order_pool, ranks,
+                                       lds_nov, st);
 }
 
 void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *probs,
                     double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                     hipStream_t st) {
   if (count <= 0) return;
-  const size_t lds = cpqr_lds_bytes(max_n, max_m);
-  if (cpqr_lds_bytes(max_n, kVldsMaxRows + 1) > kLdsLimit)
-    throw DeviceError("k_cpqr_id: box too large for LDS", hipErrorInvalidValue);
-  // size buckets: rows held per lane (RT) and columns per wave (CB)
-  if (max_m <= 256 && lds <= kLdsLimit)
-    cpqr_variant<4, 4, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
-  else if (max_m <= 512 && lds <= kLdsLimit)
-    cpqr_variant<8, 4, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
-  else if (max_m <= 1024 && lds <= kLdsLimit)
-    cpqr_variant<16, 2, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
-  else if (lds <= kLdsLimit)
-    cpqr_variant<16, 2, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
+  // Wide levels of small boxes: 256 threads, so several boxes share a CU; a few large
+  // boxes: 1024 threads, so more trailing columns are updated at once.
+  if (count >= 512 && max_n <= 96)
+    cpqr_bucket<256>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m, st);
+  else if (count <= 64 && max_m <= 512 &&
+           cpqr_lds_bytes_nt(1024, max_n, kVldsMaxRows + 1) <= kLdsLimit)
+    cpqr_bucket<1024>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m, st);
   else
-    cpqr_variant<16, 2, false>(boxes, first, count, probs, Marena, order_pool, ranks,
-                               cpqr_lds_bytes(max_n, kVldsMaxRows + 1), st);
+    cpqr_bucket<512>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m, st);
 }
 
 // Dynamic LDS per workgroup is kept within 64 KiB: n^2 doubles + 12n bytes <= 64 KiB.
@@ -873,13 +908,13 @@ constexpr int kDiagLdsMaxN = 88;
 template <int NTH, bool INLDS>
 void diag_factor_nt(const FacBox *boxes, int first, int count, const ProbDev *probs,
                     const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
-                    double *work, int32_t *err, size_t lds, hipStream_t st) {
+                    double *work, int32_t *err, int err_base, size_t lds, hipStream_t st) {
   auto kern = k_diag_factor<NTH, INLDS>;
   if (lds > 64 * 1024)
     RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool,
-                     order_pool, ranks, work, err);
+                     order_pool, ranks, work, err, err_base);
   check_launch("k_diag_factor");
 }
 
@@ -889,12 +924,12 @@ size_t diag_work_doubles(int n) { return (size_t)n * n; }
 
 void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
                         const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
-                        double *work, int32_t *err, int max_n, hipStream_t st) {
+                        double *work, int32_t *err, int err_base, int max_n, hipStream_t st) {
   if (count <= 0) return;
   if (max_n <= kDiagLdsMaxN) {
     const size_t lds = (size_t)max_n * max_n * sizeof(double) + (size_t)max_n * 12;
     diag_factor_nt<256, true>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
-                              lds, st);
+                              err_base, lds, st);
     return;
   }
   const size_t lds = (size_t)max_n * 12;
@@ -902,10 +937,10 @@ void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev
   // Few large boxes (the root): one 1024-thread workgroup each; otherwise 256 threads.
   if (count <= 64)
     diag_factor_nt<1024, false>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
-                                lds, st);
+                                err_base, lds, st);
   else
     diag_factor_nt<256, false>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
-                               lds, st);
+                               err_base, lds, st);
 }
 
 void launch_permute_in(const double *B, int64_t ldb, double *W, const int64_t *perm, int64_t n,

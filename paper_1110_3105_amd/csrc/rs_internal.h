@@ -116,7 +116,7 @@ void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *p
                     hipStream_t st);
 void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
                         const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
-                        double *work, int32_t *err, int max_n, hipStream_t st);
+                        double *work, int32_t *err, int err_base, int max_n, hipStream_t st);
 size_t cpqr_lds_bytes(int max_n, int max_m);
 // Global workspace doubles reserved for a box of n DOFs in k_diag_factor.
 size_t diag_work_doubles(int n);

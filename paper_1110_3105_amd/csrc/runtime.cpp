@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <unordered_map>
 
 namespace rs {
@@ -62,72 +63,93 @@ struct ProbState {
   int pidx = 0;
   std::vector<std::vector<int32_t>> J, skel;
   std::vector<int> leaves_by_depth;   // leaves sorted by depth
-  std::vector<char> mark;
+  std::vector<std::unordered_map<uint64_t, int>> leaf_map;   // per depth: cell -> leaf
   int npx = 0;
   bool log_kernel = false;
 };
 
+// Runs f(i) for i in [0, n) on up to kPlanThreads host threads.
+constexpr int kPlanThreads = 16;
+template <class F>
+void parallel_for(int n, F &&f) {
+  int nt = (int)std::min<unsigned>(std::thread::hardware_concurrency(), kPlanThreads);
+  nt = std::max(1, std::min(nt, n / 32));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 1; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int i = t * chunk; i < std::min(n, (t + 1) * chunk); ++i) f(i);
+    });
+  for (int i = 0; i < std::min(n, chunk); ++i) f(i);
+  for (auto &x : th) x.join();
+}
+
+uint64_t cell_key(int64_t x, int64_t y, int64_t z) {
+  return ((uint64_t)(x + (1 << 20)) << 42) | ((uint64_t)(y + (1 << 20)) << 21) |
+         (uint64_t)(z + (1 << 20));
+}
+
 // Near DOFs of every box of depth d: active DOFs outside the box's own active set,
-// strictly inside the proxy radius (Section 3.2).
+// strictly inside the proxy radius (Section 3.2).  Candidates come from the boxes of
+// the same depth in the surrounding cells and from coarser leaves around the box's
+// ancestors (exact integer box coordinates); each candidate is then tested with
+// |x - c|^2 < rho^2.
 void plan_near(ProbState &ps, int d, std::vector<std::vector<int32_t>> &near) {
   const Tree &t = *ps.t;
   const std::vector<int> &boxes = t.levels[d];
   const int dim = t.dim;
   const double ratio = ps.req->k->proxy_ratio;
-  const double side_d = t.side[boxes[0]];
-  double origin[3] = {0, 0, 0};
-  for (int a = 0; a < dim; ++a) origin[a] = t.center[a] - t.side[0] * 0.5;
-  std::unordered_map<uint64_t, std::vector<int32_t>> cells;
-  cells.reserve(boxes.size() * 4 + 16);
-  auto cell_of = [&](double x, int a) -> int64_t {
-    return (int64_t)std::floor((x - origin[a]) / side_d);
-  };
-  auto key_of = [](const int64_t *c) -> uint64_t {
-    return ((uint64_t)(c[0] + (1 << 20)) << 42) | ((uint64_t)(c[1] + (1 << 20)) << 21) |
-           (uint64_t)(c[2] + (1 << 20));
-  };
-  auto add_dof = [&](int32_t g) {
-    int64_t c[3] = {0, 0, 0};
-    for (int a = 0; a < dim; ++a) c[a] = cell_of(t.coords[(size_t)a * t.n + g], a);
-    cells[key_of(c)].push_back(g);
-  };
-  for (int b : boxes)
-    for (int32_t g : ps.J[b]) add_dof(g);
-  for (int lb : ps.leaves_by_depth) {
-    if (t.depth[lb] >= d) break;
-    for (int64_t g = t.begin[lb]; g < t.end[lb]; ++g) add_dof((int32_t)g);
-  }
-  const int R = (int)std::ceil(ratio - 0.5) + 1;
+  std::unordered_map<uint64_t, int> same;
+  same.reserve(boxes.size() * 2 + 8);
+  for (int b : boxes) same[cell_key(t.icoord[3 * b], t.icoord[3 * b + 1], t.icoord[3 * b + 2])] = b;
+  const int R = (int)std::ceil(ratio - 0.5) + 1;                // same-depth cell radius
+  const int Rc = (int)std::ceil((ratio - 0.5) * 0.5) + 1;      // coarser-depth cell radius
   near.assign(boxes.size(), {});
-  for (size_t bi = 0; bi < boxes.size(); ++bi) {
+  parallel_for((int)boxes.size(), [&](int bi) {
     const int b = boxes[bi];
-    for (int32_t g : ps.J[b]) ps.mark[g] = 1;
     const double *c = &t.center[3 * b];
     const double rho = ratio * t.side[b];
     const double rho2 = rho * rho;
-    int64_t cb[3] = {0, 0, 0};
-    for (int a = 0; a < dim; ++a) cb[a] = cell_of(c[a], a);
     std::vector<int32_t> &out = near[bi];
-    const int R2 = dim == 3 ? R : 0;
+    auto test = [&](int32_t g) {
+      double d2 = 0.0;
+      for (int a = 0; a < dim; ++a) {
+        const double df = t.coords[(size_t)a * t.n + g] - c[a];
+        d2 += df * df;
+      }
+      if (d2 < rho2) out.push_back(g);
+    };
+    const int64_t *ic = &t.icoord[3 * b];
+    const int Rz = dim == 3 ? R : 0;
     for (int64_t o0 = -R; o0 <= R; ++o0)
       for (int64_t o1 = -R; o1 <= R; ++o1)
-        for (int64_t o2 = -R2; o2 <= R2; ++o2) {
-          int64_t cc[3] = {cb[0] + o0, cb[1] + o1, dim == 3 ? cb[2] + o2 : 0};
-          auto it = cells.find(key_of(cc));
-          if (it == cells.end()) continue;
-          for (int32_t g : it->second) {
-            if (ps.mark[g]) continue;
-            double d2 = 0.0;
-            for (int a = 0; a < dim; ++a) {
-              const double df = t.coords[(size_t)a * t.n + g] - c[a];
-              d2 += df * df;
-            }
-            if (d2 < rho2) out.push_back(g);
-          }
+        for (int64_t o2 = -Rz; o2 <= Rz; ++o2) {
+          if (o0 == 0 && o1 == 0 && o2 == 0) continue;
+          auto it = same.find(cell_key(ic[0] + o0, ic[1] + o1, ic[2] + o2));
+          if (it == same.end()) continue;
+          for (int32_t g : ps.J[it->second]) test(g);
         }
+    const int Rcz = dim == 3 ? Rc : 0;
+    for (int dc = 0; dc < d; ++dc) {
+      const auto &lm = ps.leaf_map[dc];
+      if (lm.empty()) continue;
+      const int sh = d - dc;
+      const int64_t a0 = ic[0] >> sh, a1 = ic[1] >> sh, a2 = ic[2] >> sh;
+      for (int64_t o0 = -Rc; o0 <= Rc; ++o0)
+        for (int64_t o1 = -Rc; o1 <= Rc; ++o1)
+          for (int64_t o2 = -Rcz; o2 <= Rcz; ++o2) {
+            auto it = lm.find(cell_key(a0 + o0, a1 + o1, a2 + o2));
+            if (it == lm.end()) continue;
+            const int L = it->second;
+            for (int64_t g = t.begin[L]; g < t.end[L]; ++g) test((int32_t)g);
+          }
+    }
     std::sort(out.begin(), out.end());
-    for (int32_t g : ps.J[b]) ps.mark[g] = 0;
-  }
+  });
 }
 
 // Copies the geometry of one request to device memory in tree order.
@@ -181,7 +203,10 @@ void setup_problem(ProbState &ps, hipStream_t st) {
   const int nb = t.nbox();
   ps.J.assign(nb, {});
   ps.skel.assign(nb, {});
-  ps.mark.assign(n, 0);
+  ps.leaf_map.assign(t.maxdepth + 1, {});
+  for (int b = 0; b < t.nbox(); ++b)
+    if (t.is_leaf(b))
+      ps.leaf_map[t.depth[b]][cell_key(t.icoord[3 * b], t.icoord[3 * b + 1], t.icoord[3 * b + 2])] = b;
   ps.leaves_by_depth.clear();
   for (int b = 0; b < nb; ++b)
     if (t.is_leaf(b)) ps.leaves_by_depth.push_back(b);
@@ -235,8 +260,8 @@ void check_err(DevBuf &err, hipStream_t st, const std::vector<StepBox> &items, c
   if (e >= 0) {
     const StepBox &sb = items[e];
     char buf[256];
-    snprintf(buf, sizeof buf, "%s: zero or non-finite pivot at depth %d, box %d", what,
-             sb.ps->t->depth[sb.box], sb.box);
+    snprintf(buf, sizeof buf, "%s: zero or non-finite pivot at depth %d, box %d%s", what,
+             sb.ps->t->depth[sb.box], sb.box, sb.box == 0 ? " (root)" : "");
     throw UserError{RS_ESINGULAR, buf};
   }
 }
@@ -275,8 +300,19 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
   upload(S.probs, probs, st);
   const ProbDev *d_probs = S.probs.as<ProbDev>();
   S.err.ensure(sizeof(int32_t));
+  RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
   int64_t max_m_seen = 0;
+  // Every factored box gets a global index; a singular pivot reports the first one,
+  // checked once after the root (no host wait per level).
+  std::vector<StepBox> all_items;
+  // Host staging of the uploads enqueued after a level's rank readback: kept until the
+  // next synchronization, so the asynchronous copies never read released memory.
+  struct Staging {
+    std::vector<FacBox> fac;
+    std::vector<std::vector<int32_t>> idx;
+  };
+  Staging prev_stage, cur_stage;
 
   // ---- compressed levels, aligned at the finest depth of every problem
   for (int step = 0; step < max_depth; ++step) {
@@ -377,9 +413,13 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       RS_HIP_CHECK(hipStreamSynchronize(st));
       wait_ms += ms_since(tw);
     }
+    prev_stage = Staging();        // the previous level's uploads have completed
     auto tp2 = Clock::now();
     // record skeletons; build the factor descriptors
-    std::vector<FacBox> fac(cnt);
+    const int err_base = (int)all_items.size();
+    all_items.insert(all_items.end(), items.begin(), items.end());
+    std::vector<FacBox> &fac = cur_stage.fac;
+    fac.assign(cnt, FacBox{});
     int64_t woff = 0;
     Work w_asm, w_id, w_fac;
     for (int i = 0; i < cnt; ++i) {
@@ -414,7 +454,6 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     }
     plan_ms += ms_since(tp2);
     upload(S.fac, fac, st);
-    RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
     const FacBox *d_fac = S.fac.as<FacBox>();
     prof_add_work(RS_K_ASSEMBLE, w_asm);
     prof_add_work(RS_K_ID, w_id);
@@ -424,22 +463,18 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
         ProfScope ps_(RS_K_FACTOR, st);
         launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
                            S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
-                           comp[i].n, st);
+                           err_base, comp[i].n, st);
       }
     } else {
       ProfScope ps_(RS_K_FACTOR, st);
       launch_diag_factor(d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
-                         S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(), max_n,
-                         st);
-    }
-    {
-      auto tw = Clock::now();
-      check_err(S.err, st, items, "box factorization");
-      wait_ms += ms_since(tw);
+                         S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
+                         err_base, max_n, st);
     }
     // persistent solve data: index lists (skeletons then redundant, tree positions),
     // one contiguous block and one upload per problem and level
-    std::vector<std::vector<int32_t>> idx_keep(np);   // alive until the step's final sync
+    std::vector<std::vector<int32_t>> &idx_keep = cur_stage.idx;
+    idx_keep.assign(np, {});
     std::vector<int32_t *> d_idx_base(np, nullptr);
     std::vector<int64_t> idx_fill(np, 0);
     for (int i = 0; i < cnt; ++i) idx_fill[items[i].ps->pidx] += comp[i].n;
@@ -487,8 +522,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
         RS_HIP_CHECK(hipMemcpyAsync(d_idx_base[p], idx_keep[p].data(),
                                     idx_keep[p].size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                     st));
-    // keep host staging vectors alive until the copies are done
-    RS_HIP_CHECK(hipStreamSynchronize(st));
+    std::swap(prev_stage, cur_stage);   // released after the next level's readback
   }
 
   // ---- roots: the dense block of the surviving skeletons, fully eliminated
@@ -525,8 +559,9 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     upload(S.pool, pool, st);
     upload(S.fac, fac, st);
     S.work.ensure(std::max<int64_t>(woff, 1) * sizeof(double));
-    RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
     const FacBox *d_fac = S.fac.as<FacBox>();
+    const int err_base = (int)all_items.size();
+    all_items.insert(all_items.end(), items.begin(), items.end());
     {
       Work w;
       for (const FacBox &f : fac) w += work_factor(f.n, 0);
@@ -536,14 +571,19 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       for (int i = 0; i < np; ++i) {
         ProfScope ps_(RS_K_FACTOR, st);
         launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
-                           S.work.as<double>(), S.err.as<int32_t>(), fac[i].n, st);
+                           S.work.as<double>(), S.err.as<int32_t>(), err_base, fac[i].n, st);
       }
     } else {
       ProfScope ps_(RS_K_FACTOR, st);
       launch_diag_factor(d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
-                         S.work.as<double>(), S.err.as<int32_t>(), max_n, st);
+                         S.work.as<double>(), S.err.as<int32_t>(), err_base, max_n, st);
     }
-    check_err(S.err, st, items, "root factorization");
+    {
+      auto tw = Clock::now();
+      check_err(S.err, st, all_items, "factorization");
+      wait_ms += ms_since(tw);
+    }
+    prev_stage = Staging();
     for (int p = 0; p < np; ++p) {
       ProbState &P = ps[p];
       const std::vector<int32_t> &J = P.J[0];

@@ -23,9 +23,11 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
   }
-  // Grow-only; contents are not preserved when it grows.
+  // Grow-only; contents are not preserved when it grows.  Waits for the device first:
+  // queued kernels may still read the old buffer.
   void ensure(size_t b) {
     if (b <= bytes) return;
+    if (p) RS_HIP_CHECK(hipDeviceSynchronize());
     release();
     RS_HIP_CHECK(hipMalloc(&p, b < 256 ? 256 : b));
     bytes = b < 256 ? 256 : b;

@@ -36,9 +36,11 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   perm.resize(n);
   for (int64_t i = 0; i < n; ++i) perm[i] = i;
   center.clear(); side.clear(); depth.clear(); parent.clear(); begin.clear(); end.clear();
-  first_child.clear(); nchild.clear();
+  first_child.clear(); nchild.clear(); icoord.clear();
 
-  auto add = [&](const double *c, double s, int d, int p, int64_t b, int64_t e) {
+  auto add = [&](const double *c, double s, int d, int p, int64_t b, int64_t e, int code) {
+    for (int a = 0; a < 3; ++a)
+      icoord.push_back(p < 0 ? 0 : 2 * icoord[3 * p + a] + ((code >> a) & 1));
     for (int a = 0; a < 3; ++a) center.push_back(a < dim ? c[a] : 0.0);
     side.push_back(s);
     depth.push_back(d);
@@ -48,7 +50,7 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
     first_child.push_back(-1);
     nchild.push_back(0);
   };
-  add(c0, s0, 0, -1, 0, n);
+  add(c0, s0, 0, -1, 0, n, 0);
   const int ncode = 1 << dim;
   std::vector<int64_t> tmp;
   std::vector<int> code;
@@ -85,7 +87,7 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
       const int id = (int)side.size();
       if (first_child[q] < 0) first_child[q] = id;
       nchild[q]++;
-      add(cch, s * 0.5, depth[q] + 1, (int)q, b + off[cc], b + off[cc] + count[cc]);
+      add(cch, s * 0.5, depth[q] + 1, (int)q, b + off[cc], b + off[cc] + count[cc], cc);
     }
   }
   maxdepth = 0;

@@ -18,6 +18,7 @@ struct Tree {
   std::vector<int> depth, parent;
   std::vector<int64_t> begin, end;
   std::vector<int> first_child, nchild;   // children are consecutive (breadth-first ids)
+  std::vector<int64_t> icoord;            // 3 per box: integer cell of the box at its depth
   std::vector<std::vector<int>> levels;   // box ids per depth, in tree order
   std::vector<double> coords;             // dim x n, tree order (structure of arrays)
 
