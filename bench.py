@@ -34,6 +34,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # families whose dominant resource is HBM traffic rather than FP64 arithmetic
 HBM_FAMILIES = {"assemble", "permute"}
+# families whose flops run on FP64 MFMA (dense 78.6 TFLOP/s) rather than the FP64 VALU
+MFMA_FAMILIES = {"sweep_up", "sweep_down"}
 
 
 def parse():
@@ -327,7 +329,8 @@ def main():
             peak, unit, bound = PEAK_HBM_GBS, "GB/s", "hbm"
         else:
             achieved = d["flops"] / (d["total_ms"] * 1e-3) / 1e12
-            peak, unit, bound = PEAK_FP64_VECTOR_TFLOPS, "TFLOP/s", "alu"
+            peak, unit = PEAK_FP64_VECTOR_TFLOPS, "TFLOP/s"
+            bound = "mfma" if name in MFMA_FAMILIES else "alu"
         fams[name] = {"launches_per_step": d["launches"] / args.steps,
                       "ms_per_step": d["total_ms"] / args.steps, "avg_launch_ms": avg_ms,
                       "flops_per_launch": d["flops"] / d["launches"],

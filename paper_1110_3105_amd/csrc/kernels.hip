@@ -723,6 +723,154 @@ __global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restr
   sweep_down_box<NT>(B, W, nrhs, blockIdx.y * NT, sh);
 }
 
+// ---- FP64 MFMA variants of the sweeps (boxes with n <= kMfmaMaxN) -----------------
+// v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l & 15][l >> 4] and
+// B[l >> 4][l & 15]; element v of its result holds D[(l >> 4) + 4 v][l & 15].
+// Every 16 x 16 output tile is produced by one wave with the full K loop, so the
+// arithmetic of a column does not depend on how many columns share the launch.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// acc += A(r0 + i, kk) * Bs(kk, c0 + j) over kk in [0, K); A(i, kk) = a(i, kk) for
+// i < M (zero beyond), Bs row-major with leading dimension ldb (LDS).
+template <class AF>
+__device__ __forceinline__ dbl4 tile_gemm(AF a, const double *Bs, int ldb, int K, int M, int r0,
+                                          int c0) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  const bool rowok = r0 + i < M;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int kk = k0 + kq;
+    const bool kok = kk < K;
+    const double av = (rowok && kok) ? a(r0 + i, kk) : 0.0;
+    const double bv = kok ? Bs[kk * ldb + c0 + i] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int NT>
+__device__ __forceinline__ void sweep_up_box_mfma(const SweepBox &B, double *__restrict__ W,
+                                                  int nrhs, int col0, double *sh) {
+  constexpr int TN = NT / 16;
+  const int k = B.k, r = B.r;
+  const int nt = min(NT, nrhs - col0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4, cj = lane & 15;
+  double *bs = sh;              // k x NT
+  double *t = sh + k * NT;      // r x NT
+  const int32_t *idx = B.idx;
+  for (int e = threadIdx.x; e < (k + r) * NT; e += kThreads) {
+    const int i = e / NT, c = e - i * NT;
+    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+  }
+  __syncthreads();
+  const double *T = B.T;
+  const int tm_r = (r + 15) >> 4, tm_k = (k + 15) >> 4;
+  if (k > 0) {   // t = b_r - T^T b_s
+    for (int tile = wave; tile < tm_r * TN; tile += kWaves) {
+      const int tm = tile / TN, tn = tile - tm * TN;
+      const dbl4 acc = tile_gemm([&](int i, int kk) { return T[kk + (int64_t)k * i]; }, bs, NT,
+                                 k, r, tm * 16, tn * 16);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = tm * 16 + kq + 4 * v;
+        if (row < r) t[row * NT + tn * 16 + cj] -= acc[v];
+      }
+    }
+    __syncthreads();
+  }
+  const double *G = B.G;
+  for (int tile = wave; tile < tm_r * TN; tile += kWaves) {   // b_r <- G t
+    const int tm = tile / TN, tn = tile - tm * TN;
+    const dbl4 acc = tile_gemm([&](int i, int l) { return G[i + (int64_t)r * l]; }, t, NT, r, r,
+                               tm * 16, tn * 16);
+    const int c = tn * 16 + cj;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = tm * 16 + kq + 4 * v;
+      if (row < r && c < nt) W[(int64_t)idx[k + row] * nrhs + col0 + c] = acc[v];
+    }
+  }
+  const double *E = B.E;
+  for (int tile = wave; tile < tm_k * TN; tile += kWaves) {   // b_s <- b_s - E t
+    const int tm = tile / TN, tn = tile - tm * TN;
+    const dbl4 acc = tile_gemm([&](int i, int l) { return E[i + (int64_t)k * l]; }, t, NT, r, k,
+                               tm * 16, tn * 16);
+    const int c = tn * 16 + cj;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = tm * 16 + kq + 4 * v;
+      if (row < k && c < nt) W[(int64_t)idx[row] * nrhs + col0 + c] = bs[row * NT + c] - acc[v];
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void sweep_down_box_mfma(const SweepBox &B, double *__restrict__ W,
+                                                    int nrhs, int col0, double *sh) {
+  constexpr int TN = NT / 16;
+  const int k = B.k, r = B.r;
+  const int nt = min(NT, nrhs - col0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4, cj = lane & 15;
+  double *z = sh;              // k x NT
+  double *u = sh + k * NT;     // r x NT
+  const int32_t *idx = B.idx;
+  for (int e = threadIdx.x; e < (k + r) * NT; e += kThreads) {
+    const int i = e / NT, c = e - i * NT;
+    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int tm_r = (r + 15) >> 4, tm_k = (k + 15) >> 4;
+  const double *F = B.F;
+  for (int tile = wave; tile < tm_r * TN; tile += kWaves) {   // u = y_r - F z
+    const int tm = tile / TN, tn = tile - tm * TN;
+    const dbl4 acc = tile_gemm([&](int j, int i) { return F[j + (int64_t)r * i]; }, z, NT, k, r,
+                               tm * 16, tn * 16);
+    const int c = tn * 16 + cj;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = tm * 16 + kq + 4 * v;
+      if (row < r) {
+        const double val = u[row * NT + c] - acc[v];
+        u[row * NT + c] = val;
+        if (c < nt) W[(int64_t)idx[k + row] * nrhs + col0 + c] = val;
+      }
+    }
+  }
+  __syncthreads();
+  const double *T = B.T;
+  for (int tile = wave; tile < tm_k * TN; tile += kWaves) {   // x_s = z - T u
+    const int tm = tile / TN, tn = tile - tm * TN;
+    const dbl4 acc = tile_gemm([&](int i, int j) { return T[i + (int64_t)k * j]; }, u, NT, r, k,
+                               tm * 16, tn * 16);
+    const int c = tn * 16 + cj;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = tm * 16 + kq + 4 * v;
+      if (row < k && c < nt) W[(int64_t)idx[row] * nrhs + col0 + c] = z[row * NT + c] - acc[v];
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_up_mfma(const SweepBox *__restrict__ boxes,
+                                                            int first, double *__restrict__ W,
+                                                            int nrhs) {
+  extern __shared__ double sh[];
+  const SweepBox &B = boxes[first + blockIdx.x];
+  if (B.r == 0) return;
+  sweep_up_box_mfma<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_down_mfma(const SweepBox *__restrict__ boxes,
+                                                              int first, double *__restrict__ W,
+                                                              int nrhs) {
+  extern __shared__ double sh[];
+  const SweepBox &B = boxes[first + blockIdx.x];
+  if (B.r == 0 || B.k == 0) return;
+  sweep_down_box_mfma<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+}
+
 // Segment lookup for launches that cover the boxes of several handles: the last
 // segment whose first block is <= blockIdx.x.
 __device__ __forceinline__ int find_seg(const SweepSeg *segs, int nseg) {
@@ -755,6 +903,28 @@ __global__ __launch_bounds__(kThreads) void k_sweep_down_seg(const SweepSeg *__r
   const int col0 = blockIdx.y * NT;
   if (B.r == 0 || B.k == 0 || col0 >= S.nrhs) return;
   sweep_down_box<NT>(B, S.W, S.nrhs, col0, sh);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_up_seg_mfma(const SweepSeg *__restrict__ segs,
+                                                                int nseg) {
+  extern __shared__ double sh[];
+  const SweepSeg &S = segs[find_seg(segs, nseg)];
+  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
+  const int col0 = blockIdx.y * NT;
+  if (B.r == 0 || col0 >= S.nrhs) return;
+  sweep_up_box_mfma<NT>(B, S.W, S.nrhs, col0, sh);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_down_seg_mfma(
+    const SweepSeg *__restrict__ segs, int nseg) {
+  extern __shared__ double sh[];
+  const SweepSeg &S = segs[find_seg(segs, nseg)];
+  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
+  const int col0 = blockIdx.y * NT;
+  if (B.r == 0 || B.k == 0 || col0 >= S.nrhs) return;
+  sweep_down_box_mfma<NT>(B, S.W, S.nrhs, col0, sh);
 }
 
 // Caller order <-> tree order for several right-hand-side blocks (grid.y = block).
@@ -867,7 +1037,7 @@ void cpqr_bucket(const CompBox *boxes, int first, int count, const ProbDev *prob
                  hipStream_t st) {
   const size_t lds = cpqr_lds_bytes_nt(NTH, max_n, max_m);
   const size_t lds_nov = cpqr_lds_bytes_nt(NTH, max_n, kVldsMaxRows + 1);
-  if (lds_nov > kLdsLimit)
+  if (lds_nov > kMaxLds)
     throw DeviceError("k_cpqr_id: box too large for LDS", hipErrorInvalidValue);
   // size buckets: rows held per lane (RT) and columns per wave (CB); 1024-thread
   // workgroups have half the registers per lane, so they hold fewer columns
@@ -990,6 +1160,59 @@ void launch_permute_seg(const PermSeg *segs, int nseg, int64_t max_elems, bool t
   const int blocks = (int)std::min<int64_t>((max_elems + 255) / 256, 2048);
   hipLaunchKernelGGL(k_permute_seg, dim3(blocks, nseg), dim3(256), 0, st, segs, to_tree ? 1 : 0);
   check_launch("k_permute_seg");
+}
+
+int pick_nt_mfma(int nrhs, int max_n) {
+  int nt = nrhs <= 16 ? 16 : nrhs <= 32 ? 32 : 64;
+  while (nt > 16 && (int64_t)max_n * nt * 8 > 65536) nt /= 2;
+  return nt;
+}
+
+template <int NT>
+void sweep_mfma_nt(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                   int max_n, hipStream_t st) {
+  dim3 grid(count, (nrhs + NT - 1) / NT);
+  const size_t lds = (size_t)max_n * NT * sizeof(double);
+  if (up)
+    hipLaunchKernelGGL(k_sweep_up_mfma<NT>, grid, dim3(kThreads), lds, st, boxes, first, W, nrhs);
+  else
+    hipLaunchKernelGGL(k_sweep_down_mfma<NT>, grid, dim3(kThreads), lds, st, boxes, first, W,
+                       nrhs);
+  check_launch("k_sweep_mfma");
+}
+
+void launch_sweep_mfma(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                       int max_n, hipStream_t st) {
+  if (count <= 0 || nrhs <= 0) return;
+  if (max_n > kMfmaMaxN) throw DeviceError("k_sweep_mfma: box too large", hipErrorInvalidValue);
+  switch (pick_nt_mfma(nrhs, max_n)) {
+    case 16: sweep_mfma_nt<16>(up, boxes, first, count, W, nrhs, max_n, st); break;
+    case 32: sweep_mfma_nt<32>(up, boxes, first, count, W, nrhs, max_n, st); break;
+    default: sweep_mfma_nt<64>(up, boxes, first, count, W, nrhs, max_n, st); break;
+  }
+}
+
+template <int NT>
+void sweep_seg_mfma_nt(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
+                       int max_n, hipStream_t st) {
+  dim3 grid(nblocks, (max_nrhs + NT - 1) / NT);
+  const size_t lds = (size_t)max_n * NT * sizeof(double);
+  if (up)
+    hipLaunchKernelGGL(k_sweep_up_seg_mfma<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
+  else
+    hipLaunchKernelGGL(k_sweep_down_seg_mfma<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
+  check_launch("k_sweep_seg_mfma");
+}
+
+void launch_sweep_seg_mfma(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
+                           int max_n, hipStream_t st) {
+  if (nseg <= 0 || nblocks <= 0 || max_nrhs <= 0) return;
+  if (max_n > kMfmaMaxN) throw DeviceError("k_sweep_seg_mfma: box too large", hipErrorInvalidValue);
+  switch (pick_nt_mfma(max_nrhs, max_n)) {
+    case 16: sweep_seg_mfma_nt<16>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+    case 32: sweep_seg_mfma_nt<32>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+    default: sweep_seg_mfma_nt<64>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+  }
 }
 
 void launch_sweep_up(const SweepBox *boxes, int first, int count, double *W, int nrhs,

@@ -130,6 +130,13 @@ void launch_sweep_down(const SweepBox *boxes, int first, int count, double *W, i
                        int max_n, hipStream_t st);
 void launch_sweep_seg(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
                       int max_n, hipStream_t st);
+// Boxes with n = k + r <= kMfmaMaxN are swept with FP64 MFMA tiles (any nrhs); larger
+// boxes with the FP64 VALU kernels.  The class of a box never depends on the launch.
+constexpr int kMfmaMaxN = 512;
+void launch_sweep_mfma(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                       int max_n, hipStream_t st);
+void launch_sweep_seg_mfma(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
+                           int max_n, hipStream_t st);
 void launch_permute_seg(const PermSeg *segs, int nseg, int64_t max_elems, bool to_tree,
                         hipStream_t st);
 

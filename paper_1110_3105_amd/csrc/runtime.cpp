@@ -21,6 +21,30 @@
 
 namespace rs {
 
+void LevelRec::partition_classes() {
+  std::vector<int> order(sweep.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  auto small = [&](int i) { return sweep[i].k + sweep[i].r <= kMfmaMaxN; };
+  std::stable_partition(order.begin(), order.end(), small);
+  std::vector<SweepBox> s2;
+  std::vector<int> b2;
+  n_small = 0;
+  max_n_small = max_n_large = 0;
+  for (int i : order) {
+    s2.push_back(sweep[i]);
+    if (!boxes.empty()) b2.push_back(boxes[i]);
+    const int n = sweep[i].k + sweep[i].r;
+    if (small(i)) {
+      n_small++;
+      max_n_small = std::max(max_n_small, n);
+    } else {
+      max_n_large = std::max(max_n_large, n);
+    }
+  }
+  sweep.swap(s2);
+  if (!boxes.empty()) boxes.swap(b2);
+}
+
 void *Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
@@ -372,7 +396,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       max_m_seen = std::max<int64_t>(max_m_seen, cb.m);
     }
     plan_ms += ms_since(tp);
-    if (cpqr_lds_bytes(max_n, 1 << 30) > 64 * 1024)
+    if (cpqr_lds_bytes(max_n, 1 << 30) > 160 * 1024)
       throw UserError{RS_ENOTSUP, "a box's active set exceeds the on-chip ID limit"};
     upload(S.pool, pool, st);
     upload(S.comp, comp, st);
@@ -610,10 +634,12 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
   for (int p = 0; p < np; ++p) {
     rs_factor_s *h = handles[p].get();
     for (LevelRec &lv : h->levels) {
+      lv.partition_classes();
       lv.d_sweep = h->arena.alloc_n<SweepBox>((int64_t)lv.sweep.size());
       RS_HIP_CHECK(hipMemcpyAsync(lv.d_sweep, lv.sweep.data(), lv.sweep.size() * sizeof(SweepBox),
                                   hipMemcpyHostToDevice, st));
     }
+    h->root.partition_classes();
     h->root.d_sweep = h->arena.alloc_n<SweepBox>(1);
     RS_HIP_CHECK(hipMemcpyAsync(h->root.d_sweep, h->root.sweep.data(), sizeof(SweepBox),
                                 hipMemcpyHostToDevice, st));
@@ -665,11 +691,14 @@ void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         ProfScope ps_(RS_K_SWEEP_UP, st);
-        launch_sweep_up(lv.d_sweep, i, 1, W, nrhs, lv.sweep[i].k + lv.sweep[i].r, st);
+        const int n = lv.sweep[i].k + lv.sweep[i].r;
+        if (i < lv.n_small) launch_sweep_mfma(true, lv.d_sweep, i, 1, W, nrhs, n, st);
+        else launch_sweep_up(lv.d_sweep, i, 1, W, nrhs, n, st);
       }
     } else {
       ProfScope ps_(RS_K_SWEEP_UP, st);
-      launch_sweep_up(lv.d_sweep, 0, cnt, W, nrhs, lv.max_n, st);
+      launch_sweep_mfma(true, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
+      launch_sweep_up(lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs, lv.max_n_large, st);
     }
   };
   auto down = [&](const LevelRec &lv) {
@@ -682,11 +711,14 @@ void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         ProfScope ps_(RS_K_SWEEP_DOWN, st);
-        launch_sweep_down(lv.d_sweep, i, 1, W, nrhs, lv.sweep[i].k + lv.sweep[i].r, st);
+        const int n = lv.sweep[i].k + lv.sweep[i].r;
+        if (i < lv.n_small) launch_sweep_mfma(false, lv.d_sweep, i, 1, W, nrhs, n, st);
+        else launch_sweep_down(lv.d_sweep, i, 1, W, nrhs, n, st);
       }
     } else {
       ProfScope ps_(RS_K_SWEEP_DOWN, st);
-      launch_sweep_down(lv.d_sweep, 0, cnt, W, nrhs, lv.max_n, st);
+      launch_sweep_mfma(false, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
+      launch_sweep_down(lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs, lv.max_n_large, st);
     }
   };
   for (const LevelRec &lv : h->levels) up(lv);
@@ -707,7 +739,7 @@ namespace {
 struct LaunchRec {
   int64_t seg_off;
   int nseg, nblocks, max_nrhs, max_n;
-  bool up;
+  bool up, mfma;
 };
 void release_host_vector(void *p) { delete static_cast<std::vector<char> *>(p); }
 }  // namespace
@@ -746,24 +778,29 @@ void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
   std::vector<SweepSeg> segs;
   std::vector<LaunchRec> launches;
   auto add_step = [&](bool up, auto level_of) {
-    LaunchRec L{(int64_t)segs.size(), 0, 0, 0, 0, up};
-    for (int i = 0; i < nq; ++i) {
-      const LevelRec *lv = level_of(rq[i].h);
-      if (!lv || lv->sweep.empty()) continue;
-      SweepSeg s;
-      s.boxes = lv->d_sweep;
-      s.W = W + woff[i];
-      s.count = (int)lv->sweep.size();
-      s.nrhs = rq[i].nrhs;
-      s.block0 = L.nblocks;
-      s.pad = 0;
-      segs.push_back(s);
-      L.nseg++;
-      L.nblocks += s.count;
-      L.max_nrhs = std::max(L.max_nrhs, s.nrhs);
-      L.max_n = std::max(L.max_n, lv->max_n);
+    for (int mfma = 1; mfma >= 0; --mfma) {
+      LaunchRec L{(int64_t)segs.size(), 0, 0, 0, 0, up, mfma == 1};
+      for (int i = 0; i < nq; ++i) {
+        const LevelRec *lv = level_of(rq[i].h);
+        if (!lv || lv->sweep.empty()) continue;
+        const int lo = mfma ? 0 : lv->n_small;
+        const int cnt = mfma ? lv->n_small : (int)lv->sweep.size() - lv->n_small;
+        if (cnt <= 0) continue;
+        SweepSeg s;
+        s.boxes = lv->d_sweep + lo;
+        s.W = W + woff[i];
+        s.count = cnt;
+        s.nrhs = rq[i].nrhs;
+        s.block0 = L.nblocks;
+        s.pad = 0;
+        segs.push_back(s);
+        L.nseg++;
+        L.nblocks += s.count;
+        L.max_nrhs = std::max(L.max_nrhs, s.nrhs);
+        L.max_n = std::max(L.max_n, mfma ? lv->max_n_small : lv->max_n_large);
+      }
+      if (L.nseg) launches.push_back(L);
     }
-    if (L.nseg) launches.push_back(L);
   };
   for (int t = 0; t < max_levels; ++t)
     add_step(true, [t](rs_factor_s *h) -> const LevelRec * {
@@ -792,7 +829,10 @@ void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
   }
   for (const LaunchRec &L : launches) {
     ProfScope ps_(L.up ? RS_K_SWEEP_UP : RS_K_SWEEP_DOWN, st);
-    launch_sweep_seg(L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs, L.max_n, st);
+    if (L.mfma)
+      launch_sweep_seg_mfma(L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs, L.max_n, st);
+    else
+      launch_sweep_seg(L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs, L.max_n, st);
   }
   {
     ProfScope ps_(RS_K_PERMUTE, st);

@@ -51,6 +51,10 @@ struct LevelRec {
   std::vector<SweepBox> sweep;     // host copy (device pointers inside)
   SweepBox *d_sweep = nullptr;     // device copy
   int max_n = 0;
+  int n_small = 0;                 // sweep[0, n_small): MFMA class (n <= kMfmaMaxN)
+  int max_n_small = 0, max_n_large = 0;
+  // Orders the boxes MFMA class first and records the class boundary.
+  void partition_classes();
 };
 
 }  // namespace rs
