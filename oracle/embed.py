@@ -134,7 +134,7 @@ def embedding_solve(F: RSFactor, b: np.ndarray) -> np.ndarray:
     pos[V] = np.arange(V.size)
     rhs[:nV] = bt[V]
     sol = splu(E.tocsc()).solve(rhs)
-    xt = np.empty_like(bt)
+    xt = np.empty(bt.shape, dtype=rhs.dtype)      # complex for a complex operator
     xt[V] = sol[:nV]
     x = np.empty_like(xt)
     x[t.perm] = xt

@@ -19,6 +19,11 @@ def _dl2(g, c=-0.5):
     return Problem("lap2d_dl", g.points, g.weights, g.normals, g.curvature, identity=c)
 
 
+def _cfie(g, k, eta, c=0.5):
+    return Problem("helm2d_cfie", g.points, g.weights, g.normals, g.curvature, identity=c,
+                   wavenumber=k, eta=eta)
+
+
 @pytest.mark.parametrize("n", [64, 333, 1024])
 def test_unit_circle_double_layer_closed_form(n):
     # On the unit circle (x-y).nu_y / |x-y|^2 = -1/2 for every pair, so with the
@@ -111,3 +116,47 @@ def test_curve_generators_closed_forms():
     assert abs(area - np.pi * (1 + 0.3 ** 2 / 2)) < 1e-12
     # Total curvature of a simple closed curve is 2 pi.
     assert abs(np.sum(s.curvature * s.weights) - 2 * np.pi) < 1e-10
+
+
+@pytest.mark.parametrize("m", [0, 1, 3, 8])
+def test_unit_circle_cfie_eigenvalues(m):
+    # Graf's addition theorem on the unit circle: the Helmholtz single layer maps
+    # e^{imt} to (i pi/2) J_m(k) H_m(k) e^{imt}, the double layer (principal value, outward
+    # normal) to ((i pi k/2) J_m(k) H_m'(k) + 1/2) e^{imt}.  With A = c I + D - i eta S,
+    # every Fourier mode is an eigenvector; the equispaced rule with the diagonal rule
+    # converges to it at third order (m = 0 exercises the log(k/2) + gamma term).
+    from scipy.special import h1vp, hankel1, jv
+    k, eta, c = 10.0, 10.0, 0.5
+    lam_s = 0.5j * np.pi * jv(m, k) * hankel1(m, k)
+    lam_d = 0.5j * np.pi * k * jv(m, k) * h1vp(m, k) + 0.5
+    lam = c + lam_d - 1j * eta * lam_s
+    errs = []
+    for n in (256, 1024):
+        A = dense.matrix(_cfie(W.circle(n), k, eta, c))
+        t = 2 * np.pi * np.arange(n) / n
+        v = np.exp(1j * m * t)
+        errs.append(np.abs(A @ v - lam * v).max())
+    assert errs[1] < 2e-6
+    assert errs[0] / errs[1] > 30          # ~ 4^3 for a quadrupled N
+
+
+def test_cfie_diagonal_rule_sign_and_coupling():
+    # The eta-part of the operator is -i eta S_k: with eta doubled and c = 0, D fixed,
+    # A(eta2) - A(eta1) = -i (eta2 - eta1) S_k.  S_k's diagonal rule makes the unit
+    # circle's constant mode exact to the quadrature order: S_k[1] = (i pi/2) J_0 H_0.
+    from scipy.special import hankel1, jv
+    k, n = 7.0, 1024
+    g = W.circle(n)
+    A1 = dense.matrix(_cfie(g, k, 1.0, 0.0))
+    A2 = dense.matrix(_cfie(g, k, 3.0, 0.0))
+    S = (A2 - A1) / (-2j)
+    ones = np.ones(n)
+    expect = 0.5j * np.pi * jv(0, k) * hankel1(0, k)
+    assert np.abs(S @ ones - expect).max() < 1e-6
+    # the real-valued Laplace single layer is the k -> 0 limit of S_k minus its constant
+    S0 = dense.matrix(_sl2(g))
+    ks = 1e-4
+    Sk = (dense.matrix(_cfie(g, ks, 3.0, 0.0)) - dense.matrix(_cfie(g, ks, 1.0, 0.0))) / (-2j)
+    const = 0.25j - (np.log(ks / 2) + 0.57721566490153286) / (2 * np.pi)
+    W_ = np.tile(g.weights, (n, 1))
+    assert np.abs(Sk - const * W_ - S0).max() < 1e-7

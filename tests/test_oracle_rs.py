@@ -32,6 +32,15 @@ def sph_prob(g):
     return Problem("lap3d_sl", g.points, g.weights)
 
 
+def helm_prob(g, wavelengths=5.0):
+    # exterior combined-field equation (1/2 I + D - i k S) sigma = f, k giving the stated
+    # number of wavelengths across the curve
+    diam = np.ptp(g.points[:, 0])
+    k = 2 * np.pi * wavelengths / diam
+    return Problem("helm2d_cfie", g.points, g.weights, g.normals, g.curvature, identity=0.5,
+                   wavenumber=k, eta=k)
+
+
 @pytest.mark.parametrize("mk,leaf", [(lambda: dl_prob(W.star_curve(700)), 32),
                                      (lambda: sl_prob(W.star_curve(500)), 24),
                                      (lambda: sph_prob(W.fibonacci_sphere(600)), 40)])
@@ -69,6 +78,7 @@ def test_brute_force_error_bounds(kind, n, eps, leaf):
 
 @pytest.mark.parametrize("mk,eps,leaf", [(lambda: dl_prob(W.star_curve(1024)), 1e-9, 64),
                                          (lambda: sl_prob(W.star_curve(700)), 1e-6, 32),
+                                         (lambda: helm_prob(W.star_curve(800)), 1e-9, 64),
                                          (lambda: sph_prob(W.fibonacci_sphere(900)), 1e-4, 48)])
 def test_sparse_embedding_equals_telescoping_inverse(mk, eps, leaf):
     p = mk()
@@ -93,9 +103,10 @@ def test_compressed_operator_close_to_A():
         assert np.linalg.norm(y - A @ v) / np.linalg.norm(A @ v) < 1e-8
 
 
-def test_lambda_equals_schur_complement():
+@pytest.mark.parametrize("mk", [lambda g: sl_prob(g), lambda g: helm_prob(g)])
+def test_lambda_equals_schur_complement(mk):
     g = W.star_curve(1024)
-    F = factor(sl_prob(g), 1e-9, 64, 64)
+    F = factor(mk(g), 1e-9, 64, 64)
     checked = 0
     for r in F.records.values():
         k, n = r.k, r.n
@@ -112,8 +123,7 @@ def test_lambda_equals_schur_complement():
         assert np.linalg.norm(schur - r.Lam) <= 1e-9 * np.linalg.norm(r.Lam)
         # cD = [I; -T] X_rr^-1 [I, -T^T] in (r, s) coordinates
         G = np.linalg.inv(Xrr)
-        cD = np.zeros((n, n))
-        Pr = np.zeros((n, rr.size))
+        Pr = np.zeros((n, rr.size), dtype=D.dtype)
         Pr[rr, np.arange(rr.size)] = 1.0
         Pr[np.ix_(s, np.arange(rr.size))] = -T
         cD = Pr @ G @ Pr.T
@@ -187,3 +197,19 @@ def test_ranks_consistent_with_paper_scale():
         sizes.append(F.root_size)
     assert all(40 <= s <= 260 for s in sizes)
     assert sizes[1] <= 1.3 * sizes[0]
+
+
+def test_helmholtz_cfie_brute_force():
+    # complex128 path: RS solution of the combined-field system against dense LU, and
+    # the second-kind bound (relative error and residual O(eps)).
+    g = W.star_curve(1024)
+    p = helm_prob(g, 5.0)
+    eps = 1e-9
+    F = factor(p, eps, 64, 64)
+    A = dense.matrix(p)
+    b = W.gaussian_rhs(p.n, 2, 3, complex_valued=True)
+    x = F.solve(b)
+    xd = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 10 * eps
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 10 * eps
+    assert any(0 < r.k < r.n for r in F.records.values())
