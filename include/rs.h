@@ -8,7 +8,9 @@
  * compresses it level by level over a quadtree/octree with proxy surfaces and
  * interpolative decompositions (Sections 2.2, 3.1, 3.2), factors the compressed
  * inverse (Section 3.4, eq. (multilevel-inverse)), and applies it to right-hand
- * sides (the solution phase of Section 3.4).  All arithmetic is IEEE binary64.
+ * sides (the solution phase of Section 3.4).  All arithmetic is IEEE binary64: real
+ * for the Laplace kernels, complex (complex128, re/im pairs of binary64) for the
+ * Helmholtz kernel.
  *
  * Conventions shared by every entry point
  *   - Indices are 0-based.  Point arrays are point-major: x0,y0[,z0],x1,... in the
@@ -48,21 +50,27 @@ typedef enum {
   RS_LAP2D_SL = 1,   /* -(1/2pi) log|x-y|,  dim 2 */
   RS_LAP2D_DL = 2,   /* (x-y).nu_y / (2pi |x-y|^2), dim 2, needs normals + curvature */
   RS_LAP3D_SL = 3,   /* 1/(4pi |x-y|), dim 3 */
-  RS_HELM2D_CFIE = 4 /* combined field, complex128: reserved, returns RS_ENOTSUP */
+  RS_HELM2D_CFIE = 4 /* combined field dG_k/dnu_y - i eta G_k, G_k = (i/4) H0(k|x-y|),
+                        dim 2, complex128; needs normals + curvature (Section 6.1
+                        eq. (2d-helmholtz), combined layer of Section 3.2) */
 } rs_kernel_kind;
 
 /* Kernel description.  The diagonal entries A_ii follow a per-kernel rule:
  *   LAP2D_SL: c - (w_i/2pi) log(w_i/2pi);   LAP2D_DL: c - kappa_i w_i/(4pi);
- *   LAP3D_SL: c + sqrt(w_i/pi)/2. */
+ *   LAP3D_SL: c + sqrt(w_i/pi)/2;
+ *   HELM2D_CFIE: c - kappa_i w_i/(4pi) - i eta s_i with the single-layer self term
+ *     s_i = w_i (i/4 - (log(k/2) + gamma)/(2pi)) - (w_i/2pi) log(w_i/2pi)
+ *     (gamma = Euler's constant; the smooth part of G_k at coincidence plus the
+ *     LAP2D_SL rule for its logarithm). */
 typedef struct {
   int32_t kind;             /* rs_kernel_kind */
   int32_t dim;              /* 2 or 3, must match kind */
   double identity;          /* c: -0.5 for the interior double-layer equation
                                (eq. (2k-integral-eqn)), 0 for first kind */
-  double wavenumber;        /* Helmholtz only (unused otherwise) */
-  double eta;               /* Helmholtz only (unused otherwise) */
-  const double *normals;    /* host, N x dim, caller order; DL kinds, else NULL */
-  const double *curvature;  /* host, N, caller order; LAP2D_DL, else NULL */
+  double wavenumber;        /* Helmholtz: k > 0 (unused otherwise) */
+  double eta;               /* Helmholtz: combined-field coupling, e.g. k (unused otherwise) */
+  const double *normals;    /* host, N x dim, caller order; LAP2D_DL and HELM2D_CFIE */
+  const double *curvature;  /* host, N, caller order; LAP2D_DL and HELM2D_CFIE */
   int32_t proxy_points;     /* proxy-surface points per box (Section 3.2), >= 8 */
   double proxy_ratio;       /* proxy radius / box side; > 0.5*sqrt(dim), e.g. 1.5 */
 } rs_kernel;
@@ -126,22 +134,25 @@ rs_status rs_factor_ex(const rs_kernel *k, rs_tree t, const double *points,
 /* ---------------------------------------------------------------- solve ---- */
 
 /* B := A_eps^{-1} B in place (the solution phase, Section 3.4).  B is device
- * memory, column-major n x nrhs with leading dimension ldb >= n, caller order.
+ * memory, column-major n x nrhs with leading dimension ldb >= n (in entries), caller
+ * order; entries are doubles for the Laplace kernels and complex128 (re, im pairs of
+ * doubles) for HELM2D_CFIE.
  * Work is enqueued on stream (hipStream_t, NULL = default stream); the result is
  * valid once the stream has reached this point.  nrhs = 0 is a no-op.
  * Concurrent calls on one handle from different streams are allowed; each call
  * takes its own workspace.  Errors: RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
-rs_status rs_solve(rs_handle h, double *B, int64_t ldb, int32_t nrhs, void *stream);
+rs_status rs_solve(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream);
 
 /* rs_solve with a launch mode (RS_LAUNCH_LEVEL or RS_LAUNCH_PER_BOX). */
-rs_status rs_solve_ex(rs_handle h, double *B, int64_t ldb, int32_t nrhs,
+rs_status rs_solve_ex(rs_handle h, void *B, int64_t ldb, int32_t nrhs,
                       const rs_options *opts);
 
 /* ------------------------------------------------- batched (many problems) ---- */
 
 /* Factors `count` independent problems together (arrays of length count): every
  * launch covers one tree level of all problems, aligned at each problem's finest
- * depth, and all roots share one launch.  Each problem's result is bitwise identical
+ * depth, and all roots share one launch (real and complex problems in separate
+ * launch groups).  Each problem's result is bitwise identical
  * to rs_factor on it alone (same per-box kernels and reduction order).  On success
  * out[i] receives problem i's handle; on error no handle is returned.  Errors as
  * rs_factor. */
@@ -154,7 +165,7 @@ rs_status rs_factor_batched(int32_t count, const rs_kernel *kernels, const rs_tr
  * across the handles; requests may repeat a handle only on disjoint B blocks.
  * Asynchronous on opts->stream; per-request results are bitwise identical to
  * rs_solve.  launch_mode must be RS_LAUNCH_LEVEL.  Errors: RS_EINVAL, RS_EDEVICE. */
-rs_status rs_solve_batched(int32_t count, const rs_handle *h, double *const *B,
+rs_status rs_solve_batched(int32_t count, const rs_handle *h, void *const *B,
                            const int64_t *ldb, const int32_t *nrhs, const rs_options *opts);
 
 /* Releases a handle.  Waits for the library's own queued work on it; returns
@@ -176,12 +187,14 @@ typedef struct {
   int32_t dim;
   int64_t root_size;        /* unknowns left at the root (dense block) */
   int64_t total_skeletons;  /* sum of k over all compressed boxes */
-  int64_t factor_doubles;   /* doubles stored for the compressed inverse */
+  int64_t factor_doubles;   /* doubles stored for the compressed inverse (2 per complex) */
   int64_t max_box_n;        /* largest active set of a box */
   int64_t max_box_m;        /* largest compression block row count */
   double factor_ms;         /* host wall time of the factor call */
   double plan_ms;           /* of which: host planning (active sets, near lists, descriptors) */
   double wait_ms;           /* of which: host blocked waiting for the device */
+  int32_t complex_values;   /* 1: complex128 operator and right-hand sides (HELM2D_CFIE) */
+  int32_t pad;
 } rs_stats;
 
 rs_status rs_query(rs_handle h, rs_stats *out);
@@ -198,7 +211,7 @@ rs_status rs_box_skeletons(rs_handle h, int32_t *k_out, int64_t *skel_out, int64
  * matrix T (k x (n-k), column-major; rows follow the sorted skeletons, columns the
  * sorted redundant DOFs) to host arrays.  Either output may be NULL.  n_out/k_out
  * receive the sizes.  The root (b = 0 unless the tree is a single box) reports
- * k = 0 and no T. */
+ * k = 0 and no T.  For HELM2D_CFIE, T_out receives complex128 entries (2 doubles each). */
 rs_status rs_box_export(rs_handle h, int64_t b, int32_t *n_out, int32_t *k_out,
                         int64_t *J_out, double *T_out);
 
@@ -241,7 +254,7 @@ rs_status rs_server_submit_factor(rs_server s, const rs_kernel *k, rs_tree t,
 
 /* Queues B := A^{-1} B (device memory, column-major, ldb >= n, nrhs >= 1).  B must
  * not be touched until the ticket completes; concurrent requests need disjoint B. */
-rs_status rs_server_submit_solve(rs_server s, rs_handle h, double *B, int64_t ldb,
+rs_status rs_server_submit_solve(rs_server s, rs_handle h, void *B, int64_t ldb,
                                  int32_t nrhs, uint64_t *ticket);
 
 /* Waits up to timeout_ms (0: no wait, < 0: forever) for a ticket.  *done = 1 when it

@@ -57,7 +57,7 @@ class rs_stats(C.Structure):
                 ("dim", C.c_int32), ("root_size", C.c_int64), ("total_skeletons", C.c_int64),
                 ("factor_doubles", C.c_int64), ("max_box_n", C.c_int64),
                 ("max_box_m", C.c_int64), ("factor_ms", C.c_double), ("plan_ms", C.c_double),
-                ("wait_ms", C.c_double)]
+                ("wait_ms", C.c_double), ("complex_values", C.c_int32), ("pad", C.c_int32)]
 
 
 class rs_server_opts(C.Structure):
@@ -218,6 +218,11 @@ def _stream_ptr(stream) -> Optional[int]:
     return int(stream.cuda_stream)      # torch.cuda.Stream
 
 
+def _rhs_dtype(complex_values: bool):
+    import torch
+    return torch.complex128 if complex_values else torch.float64
+
+
 class Handle:
     """Owning wrapper of an rs_handle (compressed inverse resident in device memory)."""
 
@@ -226,6 +231,12 @@ class Handle:
         self.n = n
         self._keep = keep
         self._server = server
+        self.is_complex = bool(self.stats()["complex_values"])
+
+    @property
+    def dtype(self):
+        """torch dtype of right-hand sides: float64, or complex128 for Helmholtz."""
+        return _rhs_dtype(self.is_complex)
 
     def __del__(self):
         try:
@@ -256,10 +267,11 @@ class Handle:
         _check(_lib.rs_solve_ex(self._h, C.c_void_p(ptr), int(ldb), int(nrhs), C.byref(o)))
 
     def solve(self, B, stream=None, launch_mode: str = "level"):
-        """In-place B := A_eps^{-1} B for a float64 CUDA tensor of shape (n,) or (n, nrhs)."""
+        """In-place B := A_eps^{-1} B for a CUDA tensor of shape (n,) or (n, nrhs), float64
+        (complex128 for a Helmholtz handle)."""
         import torch
-        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.float64):
-            raise TypeError("B must be a float64 tensor on the HIP device")
+        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == self.dtype):
+            raise TypeError(f"B must be a {self.dtype} tensor on the HIP device")
         vec = B.dim() == 1
         X = B.unsqueeze(1) if vec else B
         if X.shape[0] != self.n:
@@ -294,7 +306,8 @@ class Handle:
         n, k = C.c_int32(), C.c_int32()
         _check(_lib.rs_box_export(self._h, int(b), C.byref(n), C.byref(k), None, None))
         J = np.empty(max(n.value, 1), dtype=np.int64)
-        T = np.empty(max(k.value * (n.value - k.value), 1), dtype=np.float64)
+        T = np.empty(max(k.value * (n.value - k.value), 1),
+                     dtype=np.complex128 if self.is_complex else np.float64)
         _check(_lib.rs_box_export(self._h, int(b), C.byref(n), C.byref(k),
                                   J.ctypes.data_as(_PI64), T.ctypes.data_as(_PD)))
         kk, nn = k.value, n.value
@@ -305,15 +318,15 @@ class Handle:
 def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: float,
            normals: Optional[np.ndarray] = None, curvature: Optional[np.ndarray] = None,
            identity: float = 0.0, proxy_points: int = 64, proxy_ratio: float = 1.5,
-           launch_mode: str = "level", stream=None) -> Handle:
+           launch_mode: str = "level", stream=None, wavenumber: float = 0.0,
+           eta: float = 0.0) -> Handle:
     pts = np.ascontiguousarray(points, dtype=np.float64)
     w = np.ascontiguousarray(weights, dtype=np.float64)
     nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64)
     kap = None if curvature is None else np.ascontiguousarray(curvature, dtype=np.float64)
     if pts.shape[0] != w.shape[0]:
         raise ValueError("points and weights differ in length")
-    k = rs_kernel(KINDS[kind], pts.shape[1], float(identity), 0.0, 0.0, _dptr(nrm), _dptr(kap),
-                  int(proxy_points), float(proxy_ratio))
+    k = _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber, eta)
     o = rs_options(LAUNCH[launch_mode], _stream_ptr(stream))
     h = _P()
     _check(_lib.rs_factor_ex(C.byref(k), tree.handle, _dptr(pts), _dptr(w), float(eps),
@@ -321,16 +334,17 @@ def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: 
     return Handle(h, pts.shape[0], keep=(tree,))
 
 
-def _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio):
-    return rs_kernel(KINDS[kind], pts.shape[1], float(identity), 0.0, 0.0, _dptr(nrm),
-                     _dptr(kap), int(proxy_points), float(proxy_ratio))
+def _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber=0.0,
+                   eta=0.0):
+    return rs_kernel(KINDS[kind], pts.shape[1], float(identity), float(wavenumber), float(eta),
+                     _dptr(nrm), _dptr(kap), int(proxy_points), float(proxy_ratio))
 
 
 def factor_batched(problems, launch_mode: str = "level", stream=None):
     """Factors several problems with shared per-level launches.
 
     ``problems`` is a list of dicts with keys kind, tree, points, weights, eps and
-    optionally normals, curvature, identity, proxy_points, proxy_ratio.
+    optionally normals, curvature, identity, proxy_points, proxy_ratio, wavenumber, eta.
     Returns one Handle per problem.
     """
     count = len(problems)
@@ -344,7 +358,8 @@ def factor_batched(problems, launch_mode: str = "level", stream=None):
         kap = None if kap is None else np.ascontiguousarray(kap, dtype=np.float64)
         keep += [pts, w, nrm, kap]
         ks.append(_kernel_struct(q["kind"], pts, nrm, kap, q.get("identity", 0.0),
-                                 q.get("proxy_points", 64), q.get("proxy_ratio", 1.5)))
+                                 q.get("proxy_points", 64), q.get("proxy_ratio", 1.5),
+                                 q.get("wavenumber", 0.0), q.get("eta", 0.0)))
         trees.append(q["tree"].handle)
         pts_p.append(_dptr(pts))
         w_p.append(_dptr(w))
@@ -362,16 +377,17 @@ def factor_batched(problems, launch_mode: str = "level", stream=None):
 
 
 def solve_batched(handles, blocks, stream=None):
-    """In place B_i := A_i^{-1} B_i for float64 CUDA tensors (n_i,) or (n_i, nrhs_i) that are
-    column-major (stride (1, ldb)); all requests share the per-level sweep launches."""
+    """In place B_i := A_i^{-1} B_i for CUDA tensors (n_i,) or (n_i, nrhs_i) that are
+    column-major (stride (1, ldb)), float64 (complex128 for Helmholtz handles); all
+    requests share the per-level sweep launches."""
     import torch
     count = len(handles)
     if len(blocks) != count:
         raise ValueError("one block per handle")
     ptrs, ldbs, nrhs = [], [], []
     for h, B in zip(handles, blocks):
-        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.float64):
-            raise TypeError("blocks must be float64 tensors on the HIP device")
+        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == h.dtype):
+            raise TypeError("each block must be a tensor of its handle's dtype on the device")
         X = B.unsqueeze(1) if B.dim() == 1 else B
         if X.shape[0] != h.n or X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) < h.n):
             raise ValueError("each block must be column-major with n rows")
@@ -409,12 +425,13 @@ class Server:
 
     def submit_factor(self, kind: str, tree: Tree, points, weights, eps: float, normals=None,
                       curvature=None, identity: float = 0.0, proxy_points: int = 64,
-                      proxy_ratio: float = 1.5) -> int:
+                      proxy_ratio: float = 1.5, wavenumber: float = 0.0, eta: float = 0.0) -> int:
         pts = np.ascontiguousarray(points, dtype=np.float64)
         w = np.ascontiguousarray(weights, dtype=np.float64)
         nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64)
         kap = None if curvature is None else np.ascontiguousarray(curvature, dtype=np.float64)
-        k = _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio)
+        k = _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber,
+                           eta)
         t = C.c_uint64()
         _check(_lib.rs_server_submit_factor(self._s, C.byref(k), tree.handle, _dptr(pts), _dptr(w),
                                             float(eps), C.byref(t)))
@@ -422,6 +439,8 @@ class Server:
         return t.value
 
     def submit_solve(self, handle: Handle, B) -> int:
+        if B.dtype != handle.dtype:
+            raise TypeError(f"B must be {handle.dtype} for this handle")
         X = B.unsqueeze(1) if B.dim() == 1 else B
         if X.shape[0] != handle.n or X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) < handle.n):
             raise ValueError("B must be column-major with n rows")

@@ -45,13 +45,16 @@ bool all_finite(const double *p, int64_t n) {
 void validate_kernel(const rs_kernel *k, const Tree &t, const double *points,
                      const double *weights, double eps) {
   if (!k || !points || !weights) fail(RS_EINVAL, "NULL kernel, points or weights");
-  if (k->kind == RS_HELM2D_CFIE) fail(RS_ENOTSUP, "complex Helmholtz kernel is not built");
-  if (k->kind != RS_LAP2D_SL && k->kind != RS_LAP2D_DL && k->kind != RS_LAP3D_SL)
+  if (k->kind != RS_LAP2D_SL && k->kind != RS_LAP2D_DL && k->kind != RS_LAP3D_SL &&
+      k->kind != RS_HELM2D_CFIE)
     fail(RS_EINVAL, "unknown kernel kind");
   const int want_dim = k->kind == RS_LAP3D_SL ? 3 : 2;
   if (k->dim != want_dim || t.dim != want_dim) fail(RS_EINVAL, "kernel dimension mismatch");
-  if (k->kind == RS_LAP2D_DL && (!k->normals || !k->curvature))
+  if ((k->kind == RS_LAP2D_DL || k->kind == RS_HELM2D_CFIE) && (!k->normals || !k->curvature))
     fail(RS_EINVAL, "double-layer kernel needs normals and curvature");
+  if (k->kind == RS_HELM2D_CFIE &&
+      (!(k->wavenumber > 0.0) || !std::isfinite(k->wavenumber) || !std::isfinite(k->eta)))
+    fail(RS_EINVAL, "Helmholtz kernel needs a finite wavenumber > 0 and a finite eta");
   if (k->proxy_points < 8 || k->proxy_points > 4096) fail(RS_EINVAL, "proxy_points out of range");
   if (!(k->proxy_ratio > 0.5 * std::sqrt((double)want_dim)) || !(k->proxy_ratio < 16.0))
     fail(RS_EINVAL, "proxy_ratio must exceed half the box diagonal");
@@ -191,7 +194,7 @@ rs_status rs_factor_batched(int32_t count, const rs_kernel *kernels, const rs_tr
   });
 }
 
-rs_status rs_solve_batched(int32_t count, const rs_handle *h, double *const *B,
+rs_status rs_solve_batched(int32_t count, const rs_handle *h, void *const *B,
                            const int64_t *ldb, const int32_t *nrhs, const rs_options *opts) {
   return guarded([&]() -> rs_status {
     if (count < 0) fail(RS_EINVAL, "count must be >= 0");
@@ -220,7 +223,7 @@ rs_status rs_solve_batched(int32_t count, const rs_handle *h, double *const *B,
   });
 }
 
-rs_status rs_solve_ex(rs_handle h, double *B, int64_t ldb, int32_t nrhs,
+rs_status rs_solve_ex(rs_handle h, void *B, int64_t ldb, int32_t nrhs,
                       const rs_options *opts) {
   return guarded([&]() -> rs_status {
     if (!h) fail(RS_EINVAL, "NULL handle");
@@ -239,7 +242,7 @@ rs_status rs_solve_ex(rs_handle h, double *B, int64_t ldb, int32_t nrhs,
   });
 }
 
-rs_status rs_solve(rs_handle h, double *B, int64_t ldb, int32_t nrhs, void *stream) {
+rs_status rs_solve(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream) {
   rs_options o{RS_LAUNCH_LEVEL, stream};
   return rs_solve_ex(h, B, ldb, nrhs, &o);
 }
@@ -294,7 +297,8 @@ rs_status rs_box_export(rs_handle h, int64_t b, int32_t *n_out, int32_t *k_out, 
       for (int i = 0; i < n; ++i) J_out[i] = J[i];
     if (T_out && k > 0 && n - k > 0)
       RS_HIP_CHECK(hipMemcpy(T_out, h->box_slot[b] + slot_T(k, n - k),
-                             (size_t)k * (n - k) * sizeof(double), hipMemcpyDeviceToHost));
+                             (size_t)k * (n - k) * sizeof(double) * (h->cplx ? 2 : 1),
+                             hipMemcpyDeviceToHost));
     return RS_OK;
   });
 }

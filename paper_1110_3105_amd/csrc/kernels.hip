@@ -1,8 +1,10 @@
 // HIP kernels of the recursive-skeletonization factor and solve passes (gfx950).
 //
-// Every kernel processes one box per workgroup (256 threads = 4 wave64s); a launch
-// covers all boxes of one tree level (of every problem of a batch), or a single box
-// in the per-box reference mode.  All arithmetic is binary64.
+// Every kernel processes one box per workgroup; a launch covers all boxes of one tree
+// level (of every problem of a batch), or a single box in the per-box reference mode.
+// Every kernel is a template over the scalar type S: binary64 (`double`) for the
+// Laplace kernels, complex128 (`Cplx`, stored as re/im pairs of binary64) for the
+// Helmholtz combined-field kernel.
 #include <float.h>
 #include <limits.h>
 
@@ -17,10 +19,55 @@ constexpr int kWaves = kThreads / 64;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kInv2Pi = 0.15915494309189533577;   // 1 / (2 pi)
 constexpr double kInv4Pi = 0.07957747154594766788;   // 1 / (4 pi)
+constexpr double kEulerGamma = 0.57721566490153286061;
 
-__device__ __forceinline__ double wave_sum(double v) {
+// ---------------------------------------------------------------- scalar types
+struct Cplx {
+  double re, im;
+  Cplx() = default;
+  __host__ __device__ constexpr Cplx(double r, double i = 0.0) : re(r), im(i) {}
+};
+__device__ __forceinline__ Cplx operator+(Cplx a, Cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ Cplx operator-(Cplx a, Cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ Cplx operator-(Cplx a) { return {-a.re, -a.im}; }
+__device__ __forceinline__ Cplx operator*(Cplx a, Cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ Cplx operator*(double a, Cplx b) { return {a * b.re, a * b.im}; }
+__device__ __forceinline__ Cplx operator*(Cplx a, double b) { return {a.re * b, a.im * b}; }
+__device__ __forceinline__ Cplx &operator+=(Cplx &a, Cplx b) { return a = a + b; }
+__device__ __forceinline__ Cplx &operator-=(Cplx &a, Cplx b) { return a = a - b; }
+__device__ __forceinline__ double abs2(double a) { return a * a; }
+__device__ __forceinline__ double abs2(Cplx a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ double mag(double a) { return fabs(a); }
+__device__ __forceinline__ double mag(Cplx a) { return hypot(a.re, a.im); }
+__device__ __forceinline__ double conjg(double a) { return a; }
+__device__ __forceinline__ Cplx conjg(Cplx a) { return {a.re, -a.im}; }
+__device__ __forceinline__ double re_part(double a) { return a; }
+__device__ __forceinline__ double re_part(Cplx a) { return a.re; }
+__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
+// 1 / (a + ib) by Smith's scaling (R. L. Smith, CACM 5 (1962)), no intermediate overflow.
+__device__ __forceinline__ Cplx recip(Cplx a) {
+  if (fabs(a.re) >= fabs(a.im)) {
+    const double q = a.im / a.re, d = a.re + a.im * q;
+    return {1.0 / d, -q / d};
+  }
+  const double q = a.re / a.im, d = a.re * q + a.im;
+  return {q / d, -1.0 / d};
+}
+__device__ __forceinline__ double sdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ Cplx sdiv(Cplx a, double b) { return {a.re / b, a.im / b}; }
+__device__ __forceinline__ Cplx sdiv(Cplx a, Cplx b) { return a * recip(b); }
+
+__device__ __forceinline__ double shfl_xor(double v, int off) { return __shfl_xor(v, off, 64); }
+__device__ __forceinline__ Cplx shfl_xor(Cplx v, int off) {
+  return {__shfl_xor(v.re, off, 64), __shfl_xor(v.im, off, 64)};
+}
+
+template <class S>
+__device__ __forceinline__ S wave_sum(S v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int off = 32; off > 0; off >>= 1) v += shfl_xor(v, off);
   return v;
 }
 
@@ -30,8 +77,9 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Green's function K(t, s) with the unit normal ns at the source (double layer):
-// eqs. (2d-laplace), (3d-laplace) and the double-layer kernel of eq. (double-layer).
+// ---------------------------------------------------------------- kernels K(t, s)
+// Laplace: eqs. (2d-laplace), (3d-laplace) and the double-layer kernel of eq.
+// (double-layer), with the unit normal ns at the source.
 __device__ __forceinline__ double green(int kind, const double *t, const double *s,
                                         const double *ns) {
   const double dx = t[0] - s[0], dy = t[1] - s[1];
@@ -43,6 +91,33 @@ __device__ __forceinline__ double green(int kind, const double *t, const double 
     const double dz = t[2] - s[2];
     return kInv4Pi / sqrt(dx * dx + dy * dy + dz * dz);
   }
+}
+
+// Helmholtz combined field (eq. (2d-helmholtz) with the combined layer of Section 3.2):
+// K = dG/dnu_s - i eta G with G = (i/4) H0(kr).  With H_n = J_n + i Y_n,
+//   dG/dnu_s = (k (d.nu)/(4 r)) (-Y1 + i J1),   -i eta G = (eta/4) (J0 + i Y0).
+__device__ __noinline__ Cplx green_cfie(double kw, double eta, const double *t,
+                                     const double *s, const double *ns) {
+  const double dx = t[0] - s[0], dy = t[1] - s[1];
+  const double r = sqrt(dx * dx + dy * dy);
+  const double z = kw * r;
+  const double j0v = j0(z), y0v = y0(z), j1v = j1(z), y1v = y1(z);
+  const double dl = 0.25 * kw * (dx * ns[0] + dy * ns[1]) / r;
+  return {-dl * y1v + 0.25 * eta * j0v, dl * j1v + 0.25 * eta * y0v};
+}
+
+template <class S>
+__device__ __forceinline__ S kernel_val(const ProbDev &P, const double *t, const double *s,
+                                        const double *ns);
+template <>
+__device__ __forceinline__ double kernel_val<double>(const ProbDev &P, const double *t,
+                                                     const double *s, const double *ns) {
+  return green(P.kind, t, s, ns);
+}
+template <>
+__device__ __forceinline__ Cplx kernel_val<Cplx>(const ProbDev &P, const double *t,
+                                                 const double *s, const double *ns) {
+  return green_cfie(P.kwave, P.eta, t, s, ns);
 }
 
 __device__ __forceinline__ void load_pt(const ProbDev &P, int g, double *x) {
@@ -62,7 +137,10 @@ __device__ __forceinline__ void load_nrm(const ProbDev &P, int g, double *nv) {
 }
 
 // Diagonal entry A_ii: identity coefficient plus the kernel's diagonal rule.
-__device__ __forceinline__ double diag_entry(const ProbDev &P, int g) {
+template <class S>
+__device__ __forceinline__ S diag_entry(const ProbDev &P, int g);
+template <>
+__device__ __forceinline__ double diag_entry<double>(const ProbDev &P, int g) {
   const double w = P.w[g];
   double d;
   if (P.kind == RS_LAP2D_SL) {
@@ -74,15 +152,28 @@ __device__ __forceinline__ double diag_entry(const ProbDev &P, int g) {
   }
   return P.c + d;
 }
+// Combined field: double-layer limit -kappa w / (4 pi) minus i eta times the
+// single-layer self term w (i/4 - (log(k/2) + gamma)/(2 pi)) - (w/2pi) log(w/2pi).
+template <>
+__device__ __forceinline__ Cplx diag_entry<Cplx>(const ProbDev &P, int g) {
+  const double w = P.w[g];
+  const double dl = -P.kappa[g] * w * (0.25 / kPi);
+  const double sl_re = -w * (log(0.5 * P.kwave) + kEulerGamma) * kInv2Pi -
+                       (w * kInv2Pi) * log(w * kInv2Pi);
+  const double sl_im = 0.25 * w;
+  // -i eta (sl_re + i sl_im) = eta sl_im - i eta sl_re
+  return {P.c + dl + P.eta * sl_im, -P.eta * sl_re};
+}
 
 // A(gi, gj) = c delta + K(x_gi, x_gj) w_gj.
-__device__ __forceinline__ double entry(const ProbDev &P, int gi, int gj) {
-  if (gi == gj) return diag_entry(P, gi);
+template <class S>
+__device__ __forceinline__ S entry(const ProbDev &P, int gi, int gj) {
+  if (gi == gj) return diag_entry<S>(P, gi);
   double t[3], s[3], ns[3];
   load_pt(P, gi, t);
   load_pt(P, gj, s);
   load_nrm(P, gj, ns);
-  return green(P.kind, t, s, ns) * P.w[gj];
+  return kernel_val<S>(P, t, s, ns) * P.w[gj];
 }
 
 __device__ __forceinline__ void proxy_unit(int dim, int p, int npx, double *u) {
@@ -120,13 +211,14 @@ __device__ double block_max(double v, double *red) {
 //   rows [nn, 2nn)          near DOFs as sources      A(J, N)^T
 //   rows [2nn, 2nn+np)      proxies as targets        K(Gamma, J) W_J
 //   rows [2nn+np, 2nn+2np)  proxies as sources        (K(J, Gamma) W_Gamma)^T
-//   rows m-2, m-1 (log kernels): total charge and constant field, scaled to the
-//                           largest proxy entry.
+//   rows m-2, m-1 (kernels with a logarithmic part): total charge and constant field,
+//                           scaled to the largest proxy entry.
+template <class S>
 __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict__ boxes,
                                                        int first,
                                                        const ProbDev *__restrict__ probs,
                                                        const int32_t *__restrict__ pool,
-                                                       double *__restrict__ Marena) {
+                                                       S *__restrict__ Marena) {
   extern __shared__ double sh_u[];   // npx * 3 proxy unit vectors
   __shared__ double red[kWaves];
   const CompBox &B = boxes[first + blockIdx.x];
@@ -135,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict
   if (n == 0) return;
   const int32_t *J = pool + B.J_off;
   const int32_t *N = pool + B.N_off;
-  double *M = Marena + B.M_off;
+  S *M = Marena + B.M_off;
   for (int p = threadIdx.x; p < npx; p += kThreads) proxy_unit(dim, p, npx, sh_u + 3 * p);
   double wmax = 0.0;
   for (int j = threadIdx.x; j < n; j += kThreads) wmax = fmax(wmax, P.w[J[j]]);
@@ -147,38 +239,39 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict
   for (int64_t e = threadIdx.x; e < total; e += kThreads) {
     const int j = (int)(e / rows), i = (int)(e - (int64_t)j * rows);
     const int g = J[j];
-    double xs[3], ns[3], v;
+    double xs[3], ns[3];
+    S v;
     load_pt(P, g, xs);
     if (i < nn) {
       double xq[3];
       load_nrm(P, g, ns);
       load_pt(P, N[i], xq);
-      v = green(P.kind, xq, xs, ns) * P.w[g];
+      v = kernel_val<S>(P, xq, xs, ns) * P.w[g];
     } else if (i < 2 * nn) {
       const int q = N[i - nn];
       double xq[3], nq[3];
       load_pt(P, q, xq);
       load_nrm(P, q, nq);
-      v = green(P.kind, xs, xq, nq) * P.w[q];
+      v = kernel_val<S>(P, xs, xq, nq) * P.w[q];
     } else if (i < 2 * nn + npx) {
       const double *u = sh_u + 3 * (i - 2 * nn);
       double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
       load_nrm(P, g, ns);
-      v = green(P.kind, y, xs, ns) * P.w[g];
-      pmax = fmax(pmax, fabs(v));
+      v = kernel_val<S>(P, y, xs, ns) * P.w[g];
+      pmax = fmax(pmax, mag(v));
     } else {
       const double *u = sh_u + 3 * (i - 2 * nn - npx);
       double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
-      v = green(P.kind, xs, y, u) * wG;
-      pmax = fmax(pmax, fabs(v));
+      v = kernel_val<S>(P, xs, y, u) * wG;
+      pmax = fmax(pmax, mag(v));
     }
     M[(int64_t)j * m + i] = v;
   }
   if (P.log_kernel) {
     pmax = block_max(pmax, red);
     for (int j = threadIdx.x; j < n; j += kThreads) {
-      M[(int64_t)j * m + rows] = pmax * P.w[J[j]] / wmax;
-      M[(int64_t)j * m + rows + 1] = pmax;
+      M[(int64_t)j * m + rows] = S(pmax * P.w[J[j]] / wmax);
+      M[(int64_t)j * m + rows + 1] = S(pmax);
     }
   }
 }
@@ -190,19 +283,25 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict
 // T = R11^{-1} R12 and the skeleton / redundant sets sorted ascending.
 // Outputs: ranks[kslot] = k, order (n ints: sorted s, then sorted r), T (k x (n-k)).
 //
+// Reflector of column x (rows j..m-1): beta = -sign(Re x_0) |x|, v = x / (x_0 - beta)
+// with v_0 = 1, tau = (beta - x_0) / beta; the trailing columns are multiplied by
+// I - conj(tau) v v^H, which maps x to beta e_0 (beta real; for real data this is the
+// usual Householder reflector).
+//
 // Trailing update: each wave takes CB columns at a time; a lane holds up to RT rows of
 // each of them in registers, so one step reads and writes the trailing matrix once
 // (dot product with the reflector, update, and the recomputed norm in one pass).  The
 // reflector is staged in LDS when VLDS.  Rows beyond 64*RT are streamed in two passes.
-template <int NTH, int RT, int CB, bool VLDS>
+template <class S, int NTH, int RT, int CB, bool VLDS>
 __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ boxes, int first,
                                                  const ProbDev *__restrict__ probs,
-                                                 double *__restrict__ Marena,
+                                                 S *__restrict__ Marena,
                                                  int32_t *__restrict__ order_pool,
                                                  int32_t *__restrict__ ranks) {
   constexpr int NW = NTH / 64;
   extern __shared__ double smem[];
-  __shared__ double s_best, s_tau;
+  __shared__ double s_best;
+  __shared__ S s_ctau;
   __shared__ int s_p;
   const CompBox &B = boxes[first + blockIdx.x];
   const int m = B.m, n = B.n;
@@ -212,19 +311,19 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
     if (threadIdx.x == 0) ranks[B.kslot] = 0;
     return;
   }
-  double *M = Marena + B.M_off;
+  S *M = Marena + B.M_off;
   const int kmax = min(m, n);
   double *norms = smem;                                    // n
   int *perm = reinterpret_cast<int *>(norms + n);          // n
   int *rk = perm + n;                                      // n
-  double *wbuf = reinterpret_cast<double *>(rk + n);       // NW * kmax (16n bytes in)
-  double *sv = wbuf + NW * kmax;                           // m (VLDS only)
+  S *wbuf = reinterpret_cast<S *>(rk + n);                 // NW * kmax (16n bytes in)
+  S *sv = wbuf + NW * kmax;                                // m (VLDS only)
 
   for (int c = threadIdx.x; c < n; c += NTH) perm[c] = c;
   for (int c = wave; c < n; c += NW) {
-    const double *col = M + (int64_t)c * m;
+    const S *col = M + (int64_t)c * m;
     double s = 0.0;
-    for (int i = lane; i < m; i += 64) s += col[i] * col[i];
+    for (int i = lane; i < m; i += 64) s += abs2(col[i]);
     s = wave_sum(s);
     if (lane == 0) norms[c] = sqrt(s);
   }
@@ -256,9 +355,9 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
     if (j == 0) r00 = best;
     if (best == 0.0 || best <= eps * r00) { k = j; break; }
     if (p != j) {
-      double *cj = M + (int64_t)j * m, *cp = M + (int64_t)p * m;
+      S *cj = M + (int64_t)j * m, *cp = M + (int64_t)p * m;
       for (int i = threadIdx.x; i < m; i += NTH) {
-        const double a = cj[i];
+        const S a = cj[i];
         cj[i] = cp[i];
         cp[i] = a;
       }
@@ -269,50 +368,51 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
     }
     __syncthreads();
     if (wave == 0) {   // Householder reflector of column j, rows j..m-1
-      double *cj = M + (int64_t)j * m;
+      S *cj = M + (int64_t)j * m;
       double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) s += cj[i] * cj[i];
+      for (int i = j + lane; i < m; i += 64) s += abs2(cj[i]);
       s = wave_sum(s);
       const double alpha = sqrt(s);
-      const double x0 = cj[j];
-      const double beta = x0 >= 0.0 ? -alpha : alpha;
-      const double scale = 1.0 / (x0 - beta);
+      const S x0 = cj[j];
+      const double beta = re_part(x0) >= 0.0 ? -alpha : alpha;
+      const S scale = recip(x0 - S(beta));
       for (int i = j + 1 + lane; i < m; i += 64) {
-        const double v = cj[i] * scale;
+        const S v = cj[i] * scale;
         cj[i] = v;
         if (VLDS) sv[i] = v;
       }
       if (lane == 0) {
-        s_tau = (beta - x0) / beta;
-        cj[j] = beta;
-        if (VLDS) sv[j] = 1.0;
+        s_ctau = conjg(sdiv(S(beta) - x0, beta));
+        cj[j] = S(beta);
+        if (VLDS) sv[j] = S(1.0);
       }
     }
     __syncthreads();
-    const double tau = s_tau;
-    const double *vg = M + (int64_t)j * m;
-    auto vload = [&](int i) -> double { return i == j ? 1.0 : (VLDS ? sv[i] : vg[i]); };
+    const S ctau = s_ctau;
+    const S *vg = M + (int64_t)j * m;
+    auto vload = [&](int i) -> S { return i == j ? S(1.0) : (VLDS ? sv[i] : vg[i]); };
     const int rows = m - j;
     for (int c0 = j + 1 + wave * CB; c0 < n; c0 += NW * CB) {
-      double dot[CB], nrm[CB];
+      S dot[CB];
+      double nrm[CB];
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) { dot[cb] = 0.0; nrm[cb] = 0.0; }
+      for (int cb = 0; cb < CB; ++cb) { dot[cb] = S(0.0); nrm[cb] = 0.0; }
       if (rows <= 64 * RT) {
-        double val[CB][RT], vi[RT];
+        S val[CB][RT], vi[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
           const int i = j + lane + 64 * t;
           const bool ok = i < m;
-          vi[t] = ok ? vload(i) : 0.0;
+          vi[t] = ok ? vload(i) : S(0.0);
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
             const int c = c0 + cb;
-            val[cb][t] = (ok && c < n) ? M[(int64_t)c * m + i] : 0.0;
-            dot[cb] += vi[t] * val[cb][t];
+            val[cb][t] = (ok && c < n) ? M[(int64_t)c * m + i] : S(0.0);
+            dot[cb] += conjg(vi[t]) * val[cb][t];
           }
         }
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) dot[cb] = wave_sum(dot[cb]) * tau;
+        for (int cb = 0; cb < CB; ++cb) dot[cb] = wave_sum(dot[cb]) * ctau;
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
           const int i = j + lane + 64 * t;
@@ -321,9 +421,9 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
             for (int cb = 0; cb < CB; ++cb) {
               const int c = c0 + cb;
               if (c < n) {
-                const double nv = val[cb][t] - dot[cb] * vi[t];
+                const S nv = val[cb][t] - dot[cb] * vi[t];
                 M[(int64_t)c * m + i] = nv;
-                if (i > j) nrm[cb] += nv * nv;
+                if (i > j) nrm[cb] += abs2(nv);
               }
             }
           }
@@ -334,7 +434,7 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
           for (int t = 0; t < RT; ++t) {
             const int i = base + lane + 64 * t;
             if (i < m) {
-              const double v = vload(i);
+              const S v = conjg(vload(i));
 #pragma unroll
               for (int cb = 0; cb < CB; ++cb) {
                 const int c = c0 + cb;
@@ -344,21 +444,21 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
           }
         }
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) dot[cb] = wave_sum(dot[cb]) * tau;
+        for (int cb = 0; cb < CB; ++cb) dot[cb] = wave_sum(dot[cb]) * ctau;
         for (int base = j; base < m; base += 64 * RT) {
 #pragma unroll
           for (int t = 0; t < RT; ++t) {
             const int i = base + lane + 64 * t;
             if (i < m) {
-              const double v = vload(i);
+              const S v = vload(i);
 #pragma unroll
               for (int cb = 0; cb < CB; ++cb) {
                 const int c = c0 + cb;
                 if (c < n) {
-                  double *pc = M + (int64_t)c * m + i;
-                  const double nv = *pc - dot[cb] * v;
+                  S *pc = M + (int64_t)c * m + i;
+                  const S nv = *pc - dot[cb] * v;
                   *pc = nv;
-                  if (i > j) nrm[cb] += nv * nv;
+                  if (i > j) nrm[cb] += abs2(nv);
                 }
               }
             }
@@ -375,13 +475,13 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
   }
 
   // T = R11^{-1} R12, one column per wave, column held in the wave's LDS buffer.
-  double *buf = wbuf + wave * kmax;
+  S *buf = wbuf + wave * kmax;
   for (int c = k + wave; c < n; c += NW) {
-    double *col = M + (int64_t)c * m;
+    S *col = M + (int64_t)c * m;
     for (int i = lane; i < k; i += 64) buf[i] = col[i];
     for (int i = k - 1; i >= 0; --i) {
-      const double xi = buf[i] / M[(int64_t)i * m + i];
-      const double *ri = M + (int64_t)i * m;
+      const S xi = sdiv(buf[i], M[(int64_t)i * m + i]);
+      const S *ri = M + (int64_t)i * m;
       for (int l = lane; l < i; l += 64) buf[l] -= xi * ri[l];
       if (lane == 0) buf[i] = xi;
     }
@@ -398,14 +498,13 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
     order[lo + r] = pc;
   }
   __syncthreads();
-  double *T = B.T;
+  S *T = reinterpret_cast<S *>(B.T);
   for (int c = k + wave; c < n; c += NW) {
-    const double *col = M + (int64_t)c * m;
-    double *Tc = T + (int64_t)k * rk[c];
+    const S *col = M + (int64_t)c * m;
+    S *Tc = T + (int64_t)k * rk[c];
     for (int i = lane; i < k; i += 64) Tc[rk[i]] = col[i];
   }
   if (threadIdx.x == 0) ranks[B.kslot] = k;
-
 }
 
 // --------------------------------------------------------------------------
@@ -414,25 +513,27 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
 // Q = [[I, -T], [0, I]] remove the skeleton-interpolated part; then
 //   G = X_rr^{-1},  F = G X_rs,  E = X_sr G,  Lambda = X_ss - X_sr F,
 // and Lambda = (R D^{-1} L)^{-1} is the box's block of the next level's matrix.
+// (T^T is the plain transpose also for complex data: the row and column IDs share T.)
 // D is A(J, J) at a leaf; above, Lambda of each child on its diagonal block and
 // A between siblings.  The root (force_k0) eliminates everything: G = D^{-1}.
 // X_rr is inverted in place by Gauss-Jordan elimination with partial pivoting (row
 // interchanges, undone as column interchanges at the end).  INLDS: the whole n x n
 // block lives in LDS (small boxes); otherwise in the global workspace.
 // Index loops are two-level (waves over columns, lanes over rows): no integer division.
-template <int NTH, bool INLDS>
+template <class S, int NTH, bool INLDS>
 __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ boxes, int first,
                                                      const ProbDev *__restrict__ probs,
                                                      const int32_t *__restrict__ pool,
                                                      const int32_t *__restrict__ order_pool,
                                                      const int32_t *__restrict__ ranks,
-                                                     double *__restrict__ workbase,
+                                                     S *__restrict__ workbase,
                                                      int32_t *__restrict__ err, int err_base) {
   constexpr int NW = NTH / 64;
   constexpr int CB = 4;    // columns per wave in the elimination
-  constexpr int RB = 4;    // rows per lane per chunk in the elimination
-  extern __shared__ double sh[];
-  __shared__ double s_inv;
+  constexpr int RB = 4 / (int)(sizeof(S) / sizeof(double));   // rows per lane per chunk
+  extern __shared__ double sh_raw[];
+  S *sh = reinterpret_cast<S *>(sh_raw);
+  __shared__ S s_inv;
   __shared__ int s_prow, s_bad;
   const FacBox &B = boxes[first + blockIdx.x];
   const ProbDev &P = probs[B.prob];
@@ -442,10 +543,10 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   const int r = n - k;
   const int32_t *J = pool + B.J_off;
   const int32_t *ord = B.force_k0 ? nullptr : order_pool + B.order_off;
-  double *slot = B.slot;
-  const double *T = slot + slot_T(k, r);
-  double *X = INLDS ? sh : workbase + B.work_off;            // n x n, (s, r) order
-  double *fac = INLDS ? sh + (int64_t)n * n : sh;            // r
+  S *slot = reinterpret_cast<S *>(B.slot);
+  const S *T = slot + slot_T(k, r);
+  S *X = INLDS ? sh : workbase + B.work_off;                 // n x n, (s, r) order
+  S *fac = INLDS ? sh + (int64_t)n * n : sh;                 // r
   int *ipiv = reinterpret_cast<int *>(fac + r);              // r
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
@@ -455,20 +556,20 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
     int cb = 0;
     if (!B.leaf)
       for (int c = 1; c < B.nchild; ++c) cb += lj >= B.child_lo[c];
-    double *Xb = X + (int64_t)b * n;
+    S *Xb = X + (int64_t)b * n;
     for (int a = lane; a < n; a += 64) {
       const int li = ord ? ord[a] : a;
-      double v;
+      S v;
       if (B.leaf) {
-        v = entry(P, J[li], J[lj]);
+        v = entry<S>(P, J[li], J[lj]);
       } else {
         int ca = 0;
         for (int c = 1; c < B.nchild; ++c) ca += li >= B.child_lo[c];
         if (ca == cb) {
-          v = B.child_lam[ca][(li - B.child_lo[ca]) +
-                              (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
+          v = reinterpret_cast<const S *>(B.child_lam[ca])[(li - B.child_lo[ca]) +
+              (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
         } else {
-          v = entry(P, J[li], J[lj]);
+          v = entry<S>(P, J[li], J[lj]);
         }
       }
       Xb[a] = v;
@@ -478,10 +579,10 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   if (k > 0 && r > 0) {
     // Y = D Q: redundant columns minus the skeleton columns times T.
     for (int jr = wave; jr < r; jr += NW) {
-      const double *Tj = T + (int64_t)k * jr;
-      double *Xc = X + (int64_t)(k + jr) * n;
+      const S *Tj = T + (int64_t)k * jr;
+      S *Xc = X + (int64_t)(k + jr) * n;
       for (int a = lane; a < n; a += 64) {
-        double s = Xc[a];
+        S s = Xc[a];
         for (int i = 0; i < k; ++i) s -= X[(int64_t)i * n + a] * Tj[i];
         Xc[a] = s;
       }
@@ -489,10 +590,10 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
     __syncthreads();
     // X = P Y: redundant rows minus T^T times the skeleton rows.
     for (int b = wave; b < n; b += NW) {
-      double *Xb = X + (int64_t)b * n;
+      S *Xb = X + (int64_t)b * n;
       for (int jr = lane; jr < r; jr += 64) {
-        const double *Tj = T + (int64_t)k * jr;
-        double s = Xb[k + jr];
+        const S *Tj = T + (int64_t)k * jr;
+        S s = Xb[k + jr];
         for (int i = 0; i < k; ++i) s -= Tj[i] * Xb[i];
         Xb[k + jr] = s;
       }
@@ -500,16 +601,16 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
     __syncthreads();
   }
   // In-place Gauss-Jordan inversion of A = X_rr, A(i, c) = X[(k + c) n + k + i].
-  double *A = X + (int64_t)k * n + k;
+  S *A = X + (int64_t)k * n + k;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();      // every thread reads s_bad below, also when r == 0
   for (int j = 0; j < r; ++j) {
     if (wave == 0) {
       double best = -1.0;
       int brow = INT_MAX;
-      const double *Aj = A + (int64_t)j * n;
+      const S *Aj = A + (int64_t)j * n;
       for (int i = j + lane; i < r; i += 64) {
-        const double v = fabs(Aj[i]);
+        const double v = mag(Aj[i]);
         if (v > best || (v == best && i < brow)) { best = v; brow = i; }
       }
 #pragma unroll
@@ -529,41 +630,43 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
     const int pr = s_prow;
     if (pr != j) {
       for (int c = threadIdx.x; c < r; c += NTH) {
-        double *Ac = A + (int64_t)c * n;
-        const double a = Ac[j];
+        S *Ac = A + (int64_t)c * n;
+        const S a = Ac[j];
         Ac[j] = Ac[pr];
         Ac[pr] = a;
       }
       __syncthreads();
     }
     {
-      const double *Aj = A + (int64_t)j * n;
+      const S *Aj = A + (int64_t)j * n;
       for (int i = threadIdx.x; i < r; i += NTH) fac[i] = Aj[i];
-      if (threadIdx.x == 0) s_inv = 1.0 / Aj[j];
+      if (threadIdx.x == 0) s_inv = recip(Aj[j]);
     }
     __syncthreads();
-    const double inv = s_inv;
+    const S inv = s_inv;
     for (int c = threadIdx.x; c < r; c += NTH) {
-      double *Ac = A + (int64_t)c * n;
+      S *Ac = A + (int64_t)c * n;
       Ac[j] = c == j ? inv : Ac[j] * inv;
     }
     __syncthreads();
     // A(i, c) <- [c != j] A(i, c) - fac[i] A(j, c) for i != j.  All loads of a chunk of
     // RB rows x CB columns are issued before its stores, so they overlap in flight.
     for (int c0 = wave * CB; c0 < r; c0 += NW * CB) {
-      double aj[CB];
+      S aj[CB];
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) aj[cb] = c0 + cb < r ? A[(int64_t)(c0 + cb) * n + j] : 0.0;
+      for (int cb = 0; cb < CB; ++cb)
+        aj[cb] = c0 + cb < r ? A[(int64_t)(c0 + cb) * n + j] : S(0.0);
       for (int i0 = 0; i0 < r; i0 += 64 * RB) {
-        double v[RB][CB], f[RB];
+        S v[RB][CB], f[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           const int i = i0 + lane + 64 * rb;
           const bool ok = i < r && i != j;
-          f[rb] = ok ? fac[i] : 0.0;
+          f[rb] = ok ? fac[i] : S(0.0);
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb)
-            v[rb][cb] = (ok && c0 + cb < r && c0 + cb != j) ? A[(int64_t)(c0 + cb) * n + i] : 0.0;
+            v[rb][cb] = (ok && c0 + cb < r && c0 + cb != j) ? A[(int64_t)(c0 + cb) * n + i]
+                                                            : S(0.0);
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -586,36 +689,36 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   for (int j = r - 1; j >= 0; --j) {      // undo the row interchanges on the columns
     const int pr = ipiv[j];
     if (pr != j) {
-      double *Aj = A + (int64_t)j * n, *Ap = A + (int64_t)pr * n;
+      S *Aj = A + (int64_t)j * n, *Ap = A + (int64_t)pr * n;
       for (int i = threadIdx.x; i < r; i += NTH) {
-        const double a = Aj[i];
+        const S a = Aj[i];
         Aj[i] = Ap[i];
         Ap[i] = a;
       }
       __syncthreads();
     }
   }
-  double *G = slot + slot_G(k, r);
+  S *G = slot + slot_G(k, r);
   for (int c = wave; c < r; c += NW)
     for (int a = lane; a < r; a += 64) G[(int64_t)c * r + a] = A[(int64_t)c * n + a];
   if (k == 0) return;
-  double *E = slot + slot_E(k, r);
-  double *F = slot + slot_F(k, r);
-  double *L = slot + slot_L(k, r);
+  S *E = slot + slot_E(k, r);
+  S *F = slot + slot_F(k, r);
+  S *L = slot + slot_L(k, r);
   // F = G X_rs (r x k); X_rs(l, i) = X[i n + k + l]
   for (int i = wave; i < k; i += NW) {
-    const double *Xi = X + (int64_t)i * n + k;
+    const S *Xi = X + (int64_t)i * n + k;
     for (int a = lane; a < r; a += 64) {
-      double s = 0.0;
+      S s = S(0.0);
       for (int l = 0; l < r; ++l) s += A[(int64_t)l * n + a] * Xi[l];
       F[(int64_t)i * r + a] = s;
     }
   }
   // E = X_sr G (k x r); X_sr(i, l) = X[(k + l) n + i]
   for (int a = wave; a < r; a += NW) {
-    const double *Ga = A + (int64_t)a * n;
+    const S *Ga = A + (int64_t)a * n;
     for (int i = lane; i < k; i += 64) {
-      double s = 0.0;
+      S s = S(0.0);
       for (int l = 0; l < r; ++l) s += X[(int64_t)(k + l) * n + i] * Ga[l];
       E[(int64_t)a * k + i] = s;
     }
@@ -623,9 +726,9 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   __syncthreads();
   // Lambda = X_ss - X_sr F (k x k)
   for (int i2 = wave; i2 < k; i2 += NW) {
-    const double *Fi = F + (int64_t)i2 * r;
+    const S *Fi = F + (int64_t)i2 * r;
     for (int i = lane; i < k; i += 64) {
-      double s = X[(int64_t)i2 * n + i];
+      S s = X[(int64_t)i2 * n + i];
       for (int a = 0; a < r; ++a) s -= X[(int64_t)(k + a) * n + i] * Fi[a];
       L[(int64_t)i2 * k + i] = s;
     }
@@ -639,236 +742,272 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
 //
 // Up (finest level first):  t = b_r - T^T b_s;  b_r <- G t;  b_s <- b_s - E t.
 // Down (root side first):   u = y_r - F z_s;   b_r <- u;     b_s <- z_s - T u.
-template <int NT>
-__device__ __forceinline__ void sweep_up_box(const SweepBox &B, double *__restrict__ W, int nrhs,
-                                             int col0, double *sh) {
+template <class S>
+struct SweepOps {
+  const S *T, *G, *E, *F;
+  __device__ __forceinline__ explicit SweepOps(const SweepBox &B)
+      : T(reinterpret_cast<const S *>(B.T)), G(reinterpret_cast<const S *>(B.G)),
+        E(reinterpret_cast<const S *>(B.E)), F(reinterpret_cast<const S *>(B.F)) {}
+};
+
+template <class S, int NT>
+__device__ __forceinline__ void sweep_up_box(const SweepBox &B, S *__restrict__ W, int nrhs,
+                                             int col0, S *sh) {
   const int k = B.k, r = B.r;
   const int nt = min(NT, nrhs - col0);
-  double *bs = sh;              // k x NT
-  double *t = sh + k * NT;      // r x NT
+  const SweepOps<S> O(B);
+  S *bs = sh;              // k x NT
+  S *t = sh + k * NT;      // r x NT
   const int32_t *idx = B.idx;
   for (int e = threadIdx.x; e < k * NT; e += kThreads) {
     const int i = e / NT, c = e - i * NT;
-    bs[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+    bs[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < r * NT; e += kThreads) {
     const int j = e / NT, c = e - j * NT;
-    double s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : 0.0;
-    const double *Tj = B.T + (int64_t)k * j;
+    S s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : S(0.0);
+    const S *Tj = O.T + (int64_t)k * j;
     for (int i = 0; i < k; ++i) s -= Tj[i] * bs[i * NT + c];
     t[e] = s;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < r * NT; e += kThreads) {
     const int j = e / NT, c = e - j * NT;
-    double s = 0.0;
-    for (int l = 0; l < r; ++l) s += B.G[j + (int64_t)r * l] * t[l * NT + c];
+    S s = S(0.0);
+    for (int l = 0; l < r; ++l) s += O.G[j + (int64_t)r * l] * t[l * NT + c];
     if (c < nt) W[(int64_t)idx[k + j] * nrhs + col0 + c] = s;
   }
   for (int e = threadIdx.x; e < k * NT; e += kThreads) {
     const int i = e / NT, c = e - i * NT;
-    double s = bs[e];
-    for (int l = 0; l < r; ++l) s -= B.E[i + (int64_t)k * l] * t[l * NT + c];
+    S s = bs[e];
+    for (int l = 0; l < r; ++l) s -= O.E[i + (int64_t)k * l] * t[l * NT + c];
     if (c < nt) W[(int64_t)idx[i] * nrhs + col0 + c] = s;
   }
 }
 
-template <int NT>
-__device__ __forceinline__ void sweep_down_box(const SweepBox &B, double *__restrict__ W,
-                                               int nrhs, int col0, double *sh) {
+template <class S, int NT>
+__device__ __forceinline__ void sweep_down_box(const SweepBox &B, S *__restrict__ W, int nrhs,
+                                               int col0, S *sh) {
   const int k = B.k, r = B.r;
   const int nt = min(NT, nrhs - col0);
-  double *z = sh;              // k x NT
-  double *u = sh + k * NT;     // r x NT
+  const SweepOps<S> O(B);
+  S *z = sh;              // k x NT
+  S *u = sh + k * NT;     // r x NT
   const int32_t *idx = B.idx;
   for (int e = threadIdx.x; e < k * NT; e += kThreads) {
     const int i = e / NT, c = e - i * NT;
-    z[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+    z[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < r * NT; e += kThreads) {
     const int j = e / NT, c = e - j * NT;
-    double s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : 0.0;
-    for (int i = 0; i < k; ++i) s -= B.F[j + (int64_t)r * i] * z[i * NT + c];
+    S s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : S(0.0);
+    for (int i = 0; i < k; ++i) s -= O.F[j + (int64_t)r * i] * z[i * NT + c];
     u[e] = s;
     if (c < nt) W[(int64_t)idx[k + j] * nrhs + col0 + c] = s;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < k * NT; e += kThreads) {
     const int i = e / NT, c = e - i * NT;
-    double s = z[e];
-    for (int j = 0; j < r; ++j) s -= B.T[i + (int64_t)k * j] * u[j * NT + c];
+    S s = z[e];
+    for (int j = 0; j < r; ++j) s -= O.T[i + (int64_t)k * j] * u[j * NT + c];
     if (c < nt) W[(int64_t)idx[i] * nrhs + col0 + c] = s;
   }
 }
 
-template <int NT>
+template <class S, int NT>
 __global__ __launch_bounds__(kThreads) void k_sweep_up(const SweepBox *__restrict__ boxes,
-                                                       int first, double *__restrict__ W,
-                                                       int nrhs) {
-  extern __shared__ double sh[];
+                                                       int first, S *__restrict__ W, int nrhs) {
+  extern __shared__ double sh_raw[];
   const SweepBox &B = boxes[first + blockIdx.x];
   if (B.r == 0) return;
-  sweep_up_box<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+  sweep_up_box<S, NT>(B, W, nrhs, blockIdx.y * NT, reinterpret_cast<S *>(sh_raw));
 }
 
-template <int NT>
+template <class S, int NT>
 __global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restrict__ boxes,
-                                                         int first, double *__restrict__ W,
+                                                         int first, S *__restrict__ W,
                                                          int nrhs) {
-  extern __shared__ double sh[];
+  extern __shared__ double sh_raw[];
   const SweepBox &B = boxes[first + blockIdx.x];
   if (B.r == 0 || B.k == 0) return;
-  sweep_down_box<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+  sweep_down_box<S, NT>(B, W, nrhs, blockIdx.y * NT, reinterpret_cast<S *>(sh_raw));
 }
 
-// ---- FP64 MFMA variants of the sweeps (boxes with n <= kMfmaMaxN) -----------------
+// ---- FP64 MFMA variants of the sweeps (boxes with n <= the MFMA class limit) --------
 // v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l & 15][l >> 4] and
 // B[l >> 4][l & 15]; element v of its result holds D[(l >> 4) + 4 v][l & 15].
 // Every 16 x 16 output tile is produced by one wave with the full K loop, so the
 // arithmetic of a column does not depend on how many columns share the launch.
+// Complex tiles use four real products per step: (ar br - ai bi, ar bi + ai br).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <class S>
+struct Acc;
+template <>
+struct Acc<double> {
+  dbl4 v = {0.0, 0.0, 0.0, 0.0};
+  __device__ __forceinline__ void mma(double a, double b) {
+    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, v, 0, 0, 0);
+  }
+  __device__ __forceinline__ double get(int e) const { return v[e]; }
+};
+template <>
+struct Acc<Cplx> {
+  dbl4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+  __device__ __forceinline__ void mma(Cplx a, Cplx b) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, im, 0, 0, 0);
+  }
+  __device__ __forceinline__ Cplx get(int e) const { return {re[e], im[e]}; }
+};
 
 // acc += A(r0 + i, kk) * Bs(kk, c0 + j) over kk in [0, K); A(i, kk) = a(i, kk) for
 // i < M (zero beyond), Bs row-major with leading dimension ldb (LDS).
-template <class AF>
-__device__ __forceinline__ dbl4 tile_gemm(AF a, const double *Bs, int ldb, int K, int M, int r0,
-                                          int c0) {
+template <class S, class AF>
+__device__ __forceinline__ Acc<S> tile_gemm(AF a, const S *Bs, int ldb, int K, int M, int r0,
+                                            int c0) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
-  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  Acc<S> acc;
   const bool rowok = r0 + i < M;
   for (int k0 = 0; k0 < K; k0 += 4) {
     const int kk = k0 + kq;
     const bool kok = kk < K;
-    const double av = (rowok && kok) ? a(r0 + i, kk) : 0.0;
-    const double bv = kok ? Bs[kk * ldb + c0 + i] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    const S av = (rowok && kok) ? a(r0 + i, kk) : S(0.0);
+    const S bv = kok ? Bs[kk * ldb + c0 + i] : S(0.0);
+    acc.mma(av, bv);
   }
   return acc;
 }
 
-template <int NT>
-__device__ __forceinline__ void sweep_up_box_mfma(const SweepBox &B, double *__restrict__ W,
-                                                  int nrhs, int col0, double *sh) {
+template <class S, int NT>
+__device__ __forceinline__ void sweep_up_box_mfma(const SweepBox &B, S *__restrict__ W, int nrhs,
+                                                  int col0, S *sh) {
   constexpr int TN = NT / 16;
   const int k = B.k, r = B.r;
   const int nt = min(NT, nrhs - col0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4, cj = lane & 15;
-  double *bs = sh;              // k x NT
-  double *t = sh + k * NT;      // r x NT
+  const SweepOps<S> O(B);
+  S *bs = sh;              // k x NT
+  S *t = sh + k * NT;      // r x NT
   const int32_t *idx = B.idx;
   for (int e = threadIdx.x; e < (k + r) * NT; e += kThreads) {
     const int i = e / NT, c = e - i * NT;
-    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
   }
   __syncthreads();
-  const double *T = B.T;
+  const S *T = O.T;
   const int tm_r = (r + 15) >> 4, tm_k = (k + 15) >> 4;
   if (k > 0) {   // t = b_r - T^T b_s
     for (int tile = wave; tile < tm_r * TN; tile += kWaves) {
       const int tm = tile / TN, tn = tile - tm * TN;
-      const dbl4 acc = tile_gemm([&](int i, int kk) { return T[kk + (int64_t)k * i]; }, bs, NT,
-                                 k, r, tm * 16, tn * 16);
+      const Acc<S> acc = tile_gemm<S>([&](int i, int kk) { return T[kk + (int64_t)k * i]; }, bs,
+                                      NT, k, r, tm * 16, tn * 16);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = tm * 16 + kq + 4 * v;
-        if (row < r) t[row * NT + tn * 16 + cj] -= acc[v];
+        if (row < r) t[row * NT + tn * 16 + cj] -= acc.get(v);
       }
     }
     __syncthreads();
   }
-  const double *G = B.G;
+  const S *G = O.G;
   for (int tile = wave; tile < tm_r * TN; tile += kWaves) {   // b_r <- G t
     const int tm = tile / TN, tn = tile - tm * TN;
-    const dbl4 acc = tile_gemm([&](int i, int l) { return G[i + (int64_t)r * l]; }, t, NT, r, r,
-                               tm * 16, tn * 16);
+    const Acc<S> acc = tile_gemm<S>([&](int i, int l) { return G[i + (int64_t)r * l]; }, t, NT,
+                                    r, r, tm * 16, tn * 16);
     const int c = tn * 16 + cj;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = tm * 16 + kq + 4 * v;
-      if (row < r && c < nt) W[(int64_t)idx[k + row] * nrhs + col0 + c] = acc[v];
+      if (row < r && c < nt) W[(int64_t)idx[k + row] * nrhs + col0 + c] = acc.get(v);
     }
   }
-  const double *E = B.E;
+  const S *E = O.E;
   for (int tile = wave; tile < tm_k * TN; tile += kWaves) {   // b_s <- b_s - E t
     const int tm = tile / TN, tn = tile - tm * TN;
-    const dbl4 acc = tile_gemm([&](int i, int l) { return E[i + (int64_t)k * l]; }, t, NT, r, k,
-                               tm * 16, tn * 16);
+    const Acc<S> acc = tile_gemm<S>([&](int i, int l) { return E[i + (int64_t)k * l]; }, t, NT,
+                                    r, k, tm * 16, tn * 16);
     const int c = tn * 16 + cj;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = tm * 16 + kq + 4 * v;
-      if (row < k && c < nt) W[(int64_t)idx[row] * nrhs + col0 + c] = bs[row * NT + c] - acc[v];
+      if (row < k && c < nt)
+        W[(int64_t)idx[row] * nrhs + col0 + c] = bs[row * NT + c] - acc.get(v);
     }
   }
 }
 
-template <int NT>
-__device__ __forceinline__ void sweep_down_box_mfma(const SweepBox &B, double *__restrict__ W,
-                                                    int nrhs, int col0, double *sh) {
+template <class S, int NT>
+__device__ __forceinline__ void sweep_down_box_mfma(const SweepBox &B, S *__restrict__ W,
+                                                    int nrhs, int col0, S *sh) {
   constexpr int TN = NT / 16;
   const int k = B.k, r = B.r;
   const int nt = min(NT, nrhs - col0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4, cj = lane & 15;
-  double *z = sh;              // k x NT
-  double *u = sh + k * NT;     // r x NT
+  const SweepOps<S> O(B);
+  S *z = sh;              // k x NT
+  S *u = sh + k * NT;     // r x NT
   const int32_t *idx = B.idx;
   for (int e = threadIdx.x; e < (k + r) * NT; e += kThreads) {
     const int i = e / NT, c = e - i * NT;
-    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : 0.0;
+    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
   }
   __syncthreads();
   const int tm_r = (r + 15) >> 4, tm_k = (k + 15) >> 4;
-  const double *F = B.F;
+  const S *F = O.F;
   for (int tile = wave; tile < tm_r * TN; tile += kWaves) {   // u = y_r - F z
     const int tm = tile / TN, tn = tile - tm * TN;
-    const dbl4 acc = tile_gemm([&](int j, int i) { return F[j + (int64_t)r * i]; }, z, NT, k, r,
-                               tm * 16, tn * 16);
+    const Acc<S> acc = tile_gemm<S>([&](int j, int i) { return F[j + (int64_t)r * i]; }, z, NT,
+                                    k, r, tm * 16, tn * 16);
     const int c = tn * 16 + cj;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = tm * 16 + kq + 4 * v;
       if (row < r) {
-        const double val = u[row * NT + c] - acc[v];
+        const S val = u[row * NT + c] - acc.get(v);
         u[row * NT + c] = val;
         if (c < nt) W[(int64_t)idx[k + row] * nrhs + col0 + c] = val;
       }
     }
   }
   __syncthreads();
-  const double *T = B.T;
+  const S *T = O.T;
   for (int tile = wave; tile < tm_k * TN; tile += kWaves) {   // x_s = z - T u
     const int tm = tile / TN, tn = tile - tm * TN;
-    const dbl4 acc = tile_gemm([&](int i, int j) { return T[i + (int64_t)k * j]; }, u, NT, r, k,
-                               tm * 16, tn * 16);
+    const Acc<S> acc = tile_gemm<S>([&](int i, int j) { return T[i + (int64_t)k * j]; }, u, NT,
+                                    r, k, tm * 16, tn * 16);
     const int c = tn * 16 + cj;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = tm * 16 + kq + 4 * v;
-      if (row < k && c < nt) W[(int64_t)idx[row] * nrhs + col0 + c] = z[row * NT + c] - acc[v];
+      if (row < k && c < nt)
+        W[(int64_t)idx[row] * nrhs + col0 + c] = z[row * NT + c] - acc.get(v);
     }
   }
 }
 
-template <int NT>
+template <class S, int NT>
 __global__ __launch_bounds__(kThreads) void k_sweep_up_mfma(const SweepBox *__restrict__ boxes,
-                                                            int first, double *__restrict__ W,
+                                                            int first, S *__restrict__ W,
                                                             int nrhs) {
-  extern __shared__ double sh[];
+  extern __shared__ double sh_raw[];
   const SweepBox &B = boxes[first + blockIdx.x];
   if (B.r == 0) return;
-  sweep_up_box_mfma<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+  sweep_up_box_mfma<S, NT>(B, W, nrhs, blockIdx.y * NT, reinterpret_cast<S *>(sh_raw));
 }
 
-template <int NT>
+template <class S, int NT>
 __global__ __launch_bounds__(kThreads) void k_sweep_down_mfma(const SweepBox *__restrict__ boxes,
-                                                              int first, double *__restrict__ W,
+                                                              int first, S *__restrict__ W,
                                                               int nrhs) {
-  extern __shared__ double sh[];
+  extern __shared__ double sh_raw[];
   const SweepBox &B = boxes[first + blockIdx.x];
   if (B.r == 0 || B.k == 0) return;
-  sweep_down_box_mfma<NT>(B, W, nrhs, blockIdx.y * NT, sh);
+  sweep_down_box_mfma<S, NT>(B, W, nrhs, blockIdx.y * NT, reinterpret_cast<S *>(sh_raw));
 }
 
 // Segment lookup for launches that cover the boxes of several handles: the last
@@ -883,64 +1022,43 @@ __device__ __forceinline__ int find_seg(const SweepSeg *segs, int nseg) {
   return lo;
 }
 
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_up_seg(const SweepSeg *__restrict__ segs,
-                                                           int nseg) {
-  extern __shared__ double sh[];
-  const SweepSeg &S = segs[find_seg(segs, nseg)];
-  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
+template <class S, int NT, bool MFMA, bool UP>
+__global__ __launch_bounds__(kThreads) void k_sweep_seg(const SweepSeg *__restrict__ segs,
+                                                        int nseg) {
+  extern __shared__ double sh_raw[];
+  S *sh = reinterpret_cast<S *>(sh_raw);
+  const SweepSeg &Sg = segs[find_seg(segs, nseg)];
+  const SweepBox &B = Sg.boxes[blockIdx.x - Sg.block0];
   const int col0 = blockIdx.y * NT;
-  if (B.r == 0 || col0 >= S.nrhs) return;
-  sweep_up_box<NT>(B, S.W, S.nrhs, col0, sh);
-}
-
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_down_seg(const SweepSeg *__restrict__ segs,
-                                                             int nseg) {
-  extern __shared__ double sh[];
-  const SweepSeg &S = segs[find_seg(segs, nseg)];
-  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
-  const int col0 = blockIdx.y * NT;
-  if (B.r == 0 || B.k == 0 || col0 >= S.nrhs) return;
-  sweep_down_box<NT>(B, S.W, S.nrhs, col0, sh);
-}
-
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_up_seg_mfma(const SweepSeg *__restrict__ segs,
-                                                                int nseg) {
-  extern __shared__ double sh[];
-  const SweepSeg &S = segs[find_seg(segs, nseg)];
-  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
-  const int col0 = blockIdx.y * NT;
-  if (B.r == 0 || col0 >= S.nrhs) return;
-  sweep_up_box_mfma<NT>(B, S.W, S.nrhs, col0, sh);
-}
-
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_down_seg_mfma(
-    const SweepSeg *__restrict__ segs, int nseg) {
-  extern __shared__ double sh[];
-  const SweepSeg &S = segs[find_seg(segs, nseg)];
-  const SweepBox &B = S.boxes[blockIdx.x - S.block0];
-  const int col0 = blockIdx.y * NT;
-  if (B.r == 0 || B.k == 0 || col0 >= S.nrhs) return;
-  sweep_down_box_mfma<NT>(B, S.W, S.nrhs, col0, sh);
-}
-
-// Caller order <-> tree order for several right-hand-side blocks (grid.y = block).
-__global__ void k_permute_seg(const PermSeg *__restrict__ segs, int to_tree) {
-  const PermSeg &S = segs[blockIdx.y];
-  const int64_t total = S.n * S.nrhs;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / S.nrhs;
-    const int c = (int)(e - i * S.nrhs);
-    if (to_tree) S.W[e] = S.B[S.perm[i] + S.ldb * c];
-    else S.B[S.perm[i] + S.ldb * c] = S.W[e];
+  if (B.r == 0 || (!UP && B.k == 0) || col0 >= Sg.nrhs) return;
+  S *W = reinterpret_cast<S *>(Sg.W);
+  if constexpr (MFMA) {
+    if constexpr (UP) sweep_up_box_mfma<S, NT>(B, W, Sg.nrhs, col0, sh);
+    else sweep_down_box_mfma<S, NT>(B, W, Sg.nrhs, col0, sh);
+  } else {
+    if constexpr (UP) sweep_up_box<S, NT>(B, W, Sg.nrhs, col0, sh);
+    else sweep_down_box<S, NT>(B, W, Sg.nrhs, col0, sh);
   }
 }
 
-__global__ void k_permute_in(const double *__restrict__ B, int64_t ldb, double *__restrict__ W,
+// Caller order <-> tree order for several right-hand-side blocks (grid.y = block).
+template <class S>
+__global__ void k_permute_seg(const PermSeg *__restrict__ segs, int to_tree) {
+  const PermSeg &Pg = segs[blockIdx.y];
+  const int64_t total = Pg.n * Pg.nrhs;
+  S *Bm = reinterpret_cast<S *>(Pg.B);
+  S *W = reinterpret_cast<S *>(Pg.W);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / Pg.nrhs;
+    const int c = (int)(e - i * Pg.nrhs);
+    if (to_tree) W[e] = Bm[Pg.perm[i] + Pg.ldb * c];
+    else Bm[Pg.perm[i] + Pg.ldb * c] = W[e];
+  }
+}
+
+template <class S>
+__global__ void k_permute_in(const S *__restrict__ B, int64_t ldb, S *__restrict__ W,
                              const int64_t *__restrict__ perm, int64_t n, int nrhs) {
   const int64_t total = n * nrhs;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -951,7 +1069,8 @@ __global__ void k_permute_in(const double *__restrict__ B, int64_t ldb, double *
   }
 }
 
-__global__ void k_permute_out(double *__restrict__ B, int64_t ldb, const double *__restrict__ W,
+template <class S>
+__global__ void k_permute_out(S *__restrict__ B, int64_t ldb, const S *__restrict__ W,
                               const int64_t *__restrict__ perm, int64_t n, int nrhs) {
   const int64_t total = n * nrhs;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -967,274 +1086,308 @@ void check_launch(const char *what) {
   if (e != hipSuccess) throw DeviceError(what, e);
 }
 
-template <int NT>
-void sweep_up_nt(const SweepBox *boxes, int first, int count, double *W, int nrhs, int max_n,
-                 hipStream_t st) {
-  dim3 grid(count, (nrhs + NT - 1) / NT);
-  hipLaunchKernelGGL(k_sweep_up<NT>, grid, dim3(kThreads), (size_t)max_n * NT * sizeof(double),
-                     st, boxes, first, W, nrhs);
-  check_launch("k_sweep_up");
-}
-
-template <int NT>
-void sweep_down_nt(const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                   int max_n, hipStream_t st) {
-  dim3 grid(count, (nrhs + NT - 1) / NT);
-  hipLaunchKernelGGL(k_sweep_down<NT>, grid, dim3(kThreads),
-                     (size_t)max_n * NT * sizeof(double), st, boxes, first, W, nrhs);
-  check_launch("k_sweep_down");
-}
-
-int pick_nt(int nrhs, int max_n) {
-  // LDS holds max_n x NT doubles; keep it within 64 KiB.
-  int nt = nrhs <= 1 ? 1 : nrhs <= 4 ? 4 : nrhs <= 16 ? 16 : 32;
-  while (nt > 1 && (int64_t)max_n * nt * 8 > 65536) nt = nt == 32 ? 16 : nt == 16 ? 4 : 1;
-  return nt;
-}
-
 constexpr size_t kMaxLds = 160 * 1024;
 // Dynamic LDS requested per workgroup.
 constexpr size_t kLdsLimit = 64 * 1024;
 
-}  // namespace
+// Runs f with a value of the scalar type of the data (double or Cplx).
+template <class F>
+void with_scalar(bool cplx, F &&f) {
+  if (cplx) f(Cplx{});
+  else f(double{});
+}
 
-void launch_assemble(const CompBox *boxes, int first, int count, const ProbDev *probs,
-                     const int32_t *pool, double *Marena, int max_npx, hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_assemble, dim3(count), dim3(kThreads),
-                     (size_t)max_npx * 3 * sizeof(double), st, boxes, first, probs, pool, Marena);
-  check_launch("k_assemble");
+// VALU sweeps: LDS holds max_n x NT scalars; keep it within 64 KiB.
+int pick_nt(int nrhs, int max_n, int es) {
+  int nt = nrhs <= 1 ? 1 : nrhs <= 4 ? 4 : nrhs <= 16 ? 16 : 32;
+  while (nt > 1 && (int64_t)max_n * nt * 8 * es > 65536) nt = nt == 32 ? 16 : nt == 16 ? 4 : 1;
+  return nt;
+}
+
+// MFMA sweeps: NT in {16, 32, 64} columns per workgroup, LDS within 64 KiB (the class
+// limit guarantees NT = 16 fits).
+int pick_nt_mfma(int nrhs, int max_n, int es) {
+  int nt = nrhs <= 16 ? 16 : nrhs <= 32 ? 32 : 64;
+  while (nt > 16 && (int64_t)max_n * nt * 8 * es > 65536) nt /= 2;
+  return nt;
+}
+
+template <class S, int NT>
+void sweep_nt(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
+              int max_n, hipStream_t st) {
+  dim3 grid(count, (nrhs + NT - 1) / NT);
+  const size_t lds = (size_t)max_n * NT * sizeof(S);
+  S *Ws = reinterpret_cast<S *>(W);
+  if (up)
+    hipLaunchKernelGGL((k_sweep_up<S, NT>), grid, dim3(kThreads), lds, st, boxes, first, Ws,
+                       nrhs);
+  else
+    hipLaunchKernelGGL((k_sweep_down<S, NT>), grid, dim3(kThreads), lds, st, boxes, first, Ws,
+                       nrhs);
+  check_launch(up ? "k_sweep_up" : "k_sweep_down");
+}
+
+template <class S, int NT>
+void sweep_mfma_nt(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
+                   int max_n, hipStream_t st) {
+  dim3 grid(count, (nrhs + NT - 1) / NT);
+  const size_t lds = (size_t)max_n * NT * sizeof(S);
+  S *Ws = reinterpret_cast<S *>(W);
+  if (up)
+    hipLaunchKernelGGL((k_sweep_up_mfma<S, NT>), grid, dim3(kThreads), lds, st, boxes, first, Ws,
+                       nrhs);
+  else
+    hipLaunchKernelGGL((k_sweep_down_mfma<S, NT>), grid, dim3(kThreads), lds, st, boxes, first,
+                       Ws, nrhs);
+  check_launch("k_sweep_mfma");
+}
+
+template <class S, int NT, bool MFMA>
+void sweep_seg_nt(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs, int max_n,
+                  hipStream_t st) {
+  dim3 grid(nblocks, (max_nrhs + NT - 1) / NT);
+  const size_t lds = (size_t)max_n * NT * sizeof(S);
+  if (up)
+    hipLaunchKernelGGL((k_sweep_seg<S, NT, MFMA, true>), grid, dim3(kThreads), lds, st, segs,
+                       nseg);
+  else
+    hipLaunchKernelGGL((k_sweep_seg<S, NT, MFMA, false>), grid, dim3(kThreads), lds, st, segs,
+                       nseg);
+  check_launch("k_sweep_seg");
 }
 
 constexpr int kVldsMaxRows = 8192;
 
-size_t cpqr_lds_bytes_nt(int nth, int max_n, int max_m) {
+size_t cpqr_lds_bytes_nt(int nth, int max_n, int max_m, int es) {
   const int nw = nth / 64;
   size_t b = (size_t)max_n * sizeof(double) + (size_t)2 * max_n * sizeof(int) +
-             (size_t)nw * max_n * sizeof(double);
-  if (max_m <= kVldsMaxRows) b += (size_t)max_m * sizeof(double);
+             (size_t)nw * max_n * sizeof(double) * es;
+  if (max_m <= kVldsMaxRows) b += (size_t)max_m * sizeof(double) * es;
   return b;
 }
 
-size_t cpqr_lds_bytes(int max_n, int max_m) { return cpqr_lds_bytes_nt(256, max_n, max_m); }
-
-template <int NTH, int RT, int CB, bool VLDS>
+template <class S, int NTH, int RT, int CB, bool VLDS>
 void cpqr_variant(const CompBox *boxes, int first, int count, const ProbDev *probs,
                   double *Marena, int32_t *order_pool, int32_t *ranks, size_t lds,
                   hipStream_t st) {
-  auto kern = k_cpqr_id<NTH, RT, CB, VLDS>;
+  auto kern = k_cpqr_id<S, NTH, RT, CB, VLDS>;
   if (lds > 64 * 1024)
     RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, Marena,
-                     order_pool, ranks);
+  hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs,
+                     reinterpret_cast<S *>(Marena), order_pool, ranks);
   check_launch("k_cpqr_id");
 }
 
-template <int NTH>
+template <class S, int NTH>
 void cpqr_bucket(const CompBox *boxes, int first, int count, const ProbDev *probs,
                  double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                  hipStream_t st) {
-  const size_t lds = cpqr_lds_bytes_nt(NTH, max_n, max_m);
-  const size_t lds_nov = cpqr_lds_bytes_nt(NTH, max_n, kVldsMaxRows + 1);
+  constexpr int es = sizeof(S) / sizeof(double);
+  const size_t lds = cpqr_lds_bytes_nt(NTH, max_n, max_m, es);
+  const size_t lds_nov = cpqr_lds_bytes_nt(NTH, max_n, kVldsMaxRows + 1, es);
   if (lds_nov > kMaxLds)
     throw DeviceError("k_cpqr_id: box too large for LDS", hipErrorInvalidValue);
   // size buckets: rows held per lane (RT) and columns per wave (CB); 1024-thread
-  // workgroups have half the registers per lane, so they hold fewer columns
-  constexpr int CB4 = NTH >= 1024 ? 2 : 4;
-  constexpr int CB16 = NTH >= 1024 ? 1 : 2;
+  // workgroups have half the registers per lane, and complex entries twice the size,
+  // so both hold fewer columns
+  constexpr int CB4 = (NTH >= 1024 ? 2 : 4) / es;
+  constexpr int CB8 = NTH >= 1024 ? 1 : 4 / es;
+  constexpr int CB16 = (NTH >= 1024 || es == 2) ? 1 : 2;
   if (max_m <= 256 && lds <= kLdsLimit)
-    cpqr_variant<NTH, 4, CB4, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds,
-                                    st);
+    cpqr_variant<S, NTH, 4, CB4, true>(boxes, first, count, probs, Marena, order_pool, ranks,
+                                       lds, st);
   else if (max_m <= 512 && lds <= kLdsLimit)
-    cpqr_variant<NTH, 8, CB4 / 2 * (NTH >= 1024 ? 1 : 2), true>(
-        boxes, first, count, probs, Marena, order_pool, ranks, lds, st);
+    cpqr_variant<S, NTH, 8, CB8, true>(boxes, first, count, probs, Marena, order_pool, ranks,
+                                       lds, st);
   else if (lds <= kLdsLimit)
-    cpqr_variant<NTH, 16, CB16, true>(boxes, first, count, probs, Marena, order_pool, ranks, lds,
-                                      st);
+    cpqr_variant<S, NTH, 16, CB16, true>(boxes, first, count, probs, Marena, order_pool, ranks,
+                                         lds, st);
   else
-    cpqr_variant<NTH, 16, CB16, false>(boxes, first, count, probs, Marena, order_pool, ranks,
-                                       lds_nov, st);
+    cpqr_variant<S, NTH, 16, CB16, false>(boxes, first, count, probs, Marena, order_pool, ranks,
+                                          lds_nov, st);
 }
 
-void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *probs,
-                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
-                    hipStream_t st) {
-  if (count <= 0) return;
-  // Wide levels of small boxes: 256 threads, so several boxes share a CU; a few large
-  // boxes: 1024 threads, so more trailing columns are updated at once.
-  if (count >= 512 && max_n <= 96)
-    cpqr_bucket<256>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m, st);
-  else if (count <= 64 && max_m <= 512 &&
-           cpqr_lds_bytes_nt(1024, max_n, kVldsMaxRows + 1) <= kLdsLimit)
-    cpqr_bucket<1024>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m, st);
-  else
-    cpqr_bucket<512>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m, st);
-}
-
-// Dynamic LDS per workgroup is kept within 64 KiB: n^2 doubles + 12n bytes <= 64 KiB.
-constexpr int kDiagLdsMaxN = 88;
-
-template <int NTH, bool INLDS>
+template <class S, int NTH, bool INLDS>
 void diag_factor_nt(const FacBox *boxes, int first, int count, const ProbDev *probs,
                     const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
                     double *work, int32_t *err, int err_base, size_t lds, hipStream_t st) {
-  auto kern = k_diag_factor<NTH, INLDS>;
+  auto kern = k_diag_factor<S, NTH, INLDS>;
   if (lds > 64 * 1024)
     RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool,
-                     order_pool, ranks, work, err, err_base);
+                     order_pool, ranks, reinterpret_cast<S *>(work), err, err_base);
   check_launch("k_diag_factor");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+int mfma_max_n(bool cplx) { return cplx ? kMfmaMaxNComplex : kMfmaMaxN; }
+
+void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
+                     const int32_t *pool, double *Marena, int max_npx, hipStream_t st) {
+  if (count <= 0) return;
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_assemble<S>, dim3(count), dim3(kThreads),
+                       (size_t)max_npx * 3 * sizeof(double), st, boxes, first, probs, pool,
+                       reinterpret_cast<S *>(Marena));
+  });
+  check_launch("k_assemble");
+}
+
+size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m) {
+  return cpqr_lds_bytes_nt(256, max_n, max_m, cplx ? 2 : 1);
+}
+
+void launch_cpqr_id(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
+                    double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
+                    hipStream_t st) {
+  if (count <= 0) return;
+  const int es = cplx ? 2 : 1;
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    // Wide levels of small boxes: 256 threads, so several boxes share a CU; a few large
+    // boxes: 1024 threads, so more trailing columns are updated at once.
+    if (count >= 512 && max_n <= 96)
+      cpqr_bucket<S, 256>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m,
+                          st);
+    else if (count <= 64 && max_m <= 512 &&
+             cpqr_lds_bytes_nt(1024, max_n, kVldsMaxRows + 1, es) <= kLdsLimit)
+      cpqr_bucket<S, 1024>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m,
+                           st);
+    else
+      cpqr_bucket<S, 512>(boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m,
+                          st);
+  });
 }
 
 // Every box gets its own n x n workspace: the variant (LDS or global) is chosen per
 // launch from the largest box, so the smaller boxes of a launch need one too.
-size_t diag_work_doubles(int n) { return (size_t)n * n; }
+size_t diag_work_elems(int n) { return (size_t)n * n; }
 
-void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
-                        const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
-                        double *work, int32_t *err, int err_base, int max_n, hipStream_t st) {
+void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
+                        const ProbDev *probs, const int32_t *pool, const int32_t *order_pool,
+                        const int32_t *ranks, double *work, int32_t *err, int err_base,
+                        int max_n, hipStream_t st) {
   if (count <= 0) return;
-  if (max_n <= kDiagLdsMaxN) {
-    const size_t lds = (size_t)max_n * max_n * sizeof(double) + (size_t)max_n * 12;
-    diag_factor_nt<256, true>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
-                              err_base, lds, st);
-    return;
-  }
-  const size_t lds = (size_t)max_n * 12;
-  if (lds > kLdsLimit) throw DeviceError("k_diag_factor: box too large", hipErrorInvalidValue);
-  // Few large boxes (the root): one 1024-thread workgroup each; otherwise 256 threads.
-  if (count <= 64)
-    diag_factor_nt<1024, false>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
-                                err_base, lds, st);
-  else
-    diag_factor_nt<256, false>(boxes, first, count, probs, pool, order_pool, ranks, work, err,
-                               err_base, lds, st);
+  const size_t es = cplx ? 2 : 1;
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    // the whole block in LDS when n^2 scalars + the pivot column and indices fit 64 KiB
+    const size_t lds_in = (size_t)max_n * max_n * 8 * es + (size_t)max_n * (8 * es + 4);
+    if (lds_in <= kLdsLimit) {
+      diag_factor_nt<S, 256, true>(boxes, first, count, probs, pool, order_pool, ranks, work,
+                                   err, err_base, lds_in, st);
+      return;
+    }
+    const size_t lds = (size_t)max_n * (8 * es + 4);
+    if (lds > kLdsLimit) throw DeviceError("k_diag_factor: box too large", hipErrorInvalidValue);
+    // Few large boxes (the root): one 1024-thread workgroup each; otherwise 256 threads.
+    if (count <= 64)
+      diag_factor_nt<S, 1024, false>(boxes, first, count, probs, pool, order_pool, ranks, work,
+                                     err, err_base, lds, st);
+    else
+      diag_factor_nt<S, 256, false>(boxes, first, count, probs, pool, order_pool, ranks, work,
+                                    err, err_base, lds, st);
+  });
 }
 
-void launch_permute_in(const double *B, int64_t ldb, double *W, const int64_t *perm, int64_t n,
-                       int nrhs, hipStream_t st) {
+void launch_permute_in(bool cplx, const double *B, int64_t ldb, double *W, const int64_t *perm,
+                       int64_t n, int nrhs, hipStream_t st) {
   const int64_t total = n * nrhs;
   if (total == 0) return;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_permute_in, dim3(blocks), dim3(256), 0, st, B, ldb, W, perm, n, nrhs);
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_permute_in<S>, dim3(blocks), dim3(256), 0, st,
+                       reinterpret_cast<const S *>(B), ldb, reinterpret_cast<S *>(W), perm, n,
+                       nrhs);
+  });
   check_launch("k_permute_in");
 }
 
-void launch_permute_out(double *B, int64_t ldb, const double *W, const int64_t *perm,
+void launch_permute_out(bool cplx, double *B, int64_t ldb, const double *W, const int64_t *perm,
                         int64_t n, int nrhs, hipStream_t st) {
   const int64_t total = n * nrhs;
   if (total == 0) return;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_permute_out, dim3(blocks), dim3(256), 0, st, B, ldb, W, perm, n, nrhs);
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_permute_out<S>, dim3(blocks), dim3(256), 0, st,
+                       reinterpret_cast<S *>(B), ldb, reinterpret_cast<const S *>(W), perm, n,
+                       nrhs);
+  });
   check_launch("k_permute_out");
 }
 
-template <int NT>
-void sweep_seg_nt(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs, int max_n,
-                  hipStream_t st) {
-  dim3 grid(nblocks, (max_nrhs + NT - 1) / NT);
-  const size_t lds = (size_t)max_n * NT * sizeof(double);
-  if (up)
-    hipLaunchKernelGGL(k_sweep_up_seg<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
-  else
-    hipLaunchKernelGGL(k_sweep_down_seg<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
-  check_launch("k_sweep_seg");
-}
-
-void launch_sweep_seg(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
-                      int max_n, hipStream_t st) {
-  if (nseg <= 0 || nblocks <= 0 || max_nrhs <= 0) return;
-  switch (pick_nt(max_nrhs, max_n)) {
-    case 1: sweep_seg_nt<1>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-    case 4: sweep_seg_nt<4>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-    case 16: sweep_seg_nt<16>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-    default: sweep_seg_nt<32>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-  }
-}
-
-void launch_permute_seg(const PermSeg *segs, int nseg, int64_t max_elems, bool to_tree,
-                        hipStream_t st) {
+void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_elems,
+                        bool to_tree, hipStream_t st) {
   if (nseg <= 0 || max_elems <= 0) return;
   const int blocks = (int)std::min<int64_t>((max_elems + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_permute_seg, dim3(blocks, nseg), dim3(256), 0, st, segs, to_tree ? 1 : 0);
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_permute_seg<S>, dim3(blocks, nseg), dim3(256), 0, st, segs,
+                       to_tree ? 1 : 0);
+  });
   check_launch("k_permute_seg");
 }
 
-int pick_nt_mfma(int nrhs, int max_n) {
-  int nt = nrhs <= 16 ? 16 : nrhs <= 32 ? 32 : 64;
-  while (nt > 16 && (int64_t)max_n * nt * 8 > 65536) nt /= 2;
-  return nt;
-}
-
-template <int NT>
-void sweep_mfma_nt(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                   int max_n, hipStream_t st) {
-  dim3 grid(count, (nrhs + NT - 1) / NT);
-  const size_t lds = (size_t)max_n * NT * sizeof(double);
-  if (up)
-    hipLaunchKernelGGL(k_sweep_up_mfma<NT>, grid, dim3(kThreads), lds, st, boxes, first, W, nrhs);
-  else
-    hipLaunchKernelGGL(k_sweep_down_mfma<NT>, grid, dim3(kThreads), lds, st, boxes, first, W,
-                       nrhs);
-  check_launch("k_sweep_mfma");
-}
-
-void launch_sweep_mfma(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                       int max_n, hipStream_t st) {
+void launch_sweep(bool cplx, bool up, const SweepBox *boxes, int first, int count, double *W,
+                  int nrhs, int max_n, hipStream_t st) {
   if (count <= 0 || nrhs <= 0) return;
-  if (max_n > kMfmaMaxN) throw DeviceError("k_sweep_mfma: box too large", hipErrorInvalidValue);
-  switch (pick_nt_mfma(nrhs, max_n)) {
-    case 16: sweep_mfma_nt<16>(up, boxes, first, count, W, nrhs, max_n, st); break;
-    case 32: sweep_mfma_nt<32>(up, boxes, first, count, W, nrhs, max_n, st); break;
-    default: sweep_mfma_nt<64>(up, boxes, first, count, W, nrhs, max_n, st); break;
-  }
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    switch (pick_nt(nrhs, max_n, sizeof(S) / 8)) {
+      case 1: sweep_nt<S, 1>(up, boxes, first, count, W, nrhs, max_n, st); break;
+      case 4: sweep_nt<S, 4>(up, boxes, first, count, W, nrhs, max_n, st); break;
+      case 16: sweep_nt<S, 16>(up, boxes, first, count, W, nrhs, max_n, st); break;
+      default: sweep_nt<S, 32>(up, boxes, first, count, W, nrhs, max_n, st); break;
+    }
+  });
 }
 
-template <int NT>
-void sweep_seg_mfma_nt(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
-                       int max_n, hipStream_t st) {
-  dim3 grid(nblocks, (max_nrhs + NT - 1) / NT);
-  const size_t lds = (size_t)max_n * NT * sizeof(double);
-  if (up)
-    hipLaunchKernelGGL(k_sweep_up_seg_mfma<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
-  else
-    hipLaunchKernelGGL(k_sweep_down_seg_mfma<NT>, grid, dim3(kThreads), lds, st, segs, nseg);
-  check_launch("k_sweep_seg_mfma");
+void launch_sweep_mfma(bool cplx, bool up, const SweepBox *boxes, int first, int count,
+                       double *W, int nrhs, int max_n, hipStream_t st) {
+  if (count <= 0 || nrhs <= 0) return;
+  if (max_n > mfma_max_n(cplx))
+    throw DeviceError("k_sweep_mfma: box too large", hipErrorInvalidValue);
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    switch (pick_nt_mfma(nrhs, max_n, sizeof(S) / 8)) {
+      case 16: sweep_mfma_nt<S, 16>(up, boxes, first, count, W, nrhs, max_n, st); break;
+      case 32: sweep_mfma_nt<S, 32>(up, boxes, first, count, W, nrhs, max_n, st); break;
+      default: sweep_mfma_nt<S, 64>(up, boxes, first, count, W, nrhs, max_n, st); break;
+    }
+  });
 }
 
-void launch_sweep_seg_mfma(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
-                           int max_n, hipStream_t st) {
+void launch_sweep_seg(bool cplx, bool mfma, bool up, const SweepSeg *segs, int nseg,
+                      int nblocks, int max_nrhs, int max_n, hipStream_t st) {
   if (nseg <= 0 || nblocks <= 0 || max_nrhs <= 0) return;
-  if (max_n > kMfmaMaxN) throw DeviceError("k_sweep_seg_mfma: box too large", hipErrorInvalidValue);
-  switch (pick_nt_mfma(max_nrhs, max_n)) {
-    case 16: sweep_seg_mfma_nt<16>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-    case 32: sweep_seg_mfma_nt<32>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-    default: sweep_seg_mfma_nt<64>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-  }
-}
-
-void launch_sweep_up(const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                     int max_n, hipStream_t st) {
-  if (count <= 0 || nrhs <= 0) return;
-  switch (pick_nt(nrhs, max_n)) {
-    case 1: sweep_up_nt<1>(boxes, first, count, W, nrhs, max_n, st); break;
-    case 4: sweep_up_nt<4>(boxes, first, count, W, nrhs, max_n, st); break;
-    case 16: sweep_up_nt<16>(boxes, first, count, W, nrhs, max_n, st); break;
-    default: sweep_up_nt<32>(boxes, first, count, W, nrhs, max_n, st); break;
-  }
-}
-
-void launch_sweep_down(const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                       int max_n, hipStream_t st) {
-  if (count <= 0 || nrhs <= 0) return;
-  switch (pick_nt(nrhs, max_n)) {
-    case 1: sweep_down_nt<1>(boxes, first, count, W, nrhs, max_n, st); break;
-    case 4: sweep_down_nt<4>(boxes, first, count, W, nrhs, max_n, st); break;
-    case 16: sweep_down_nt<16>(boxes, first, count, W, nrhs, max_n, st); break;
-    default: sweep_down_nt<32>(boxes, first, count, W, nrhs, max_n, st); break;
-  }
+  if (mfma && max_n > mfma_max_n(cplx))
+    throw DeviceError("k_sweep_seg: box too large for the MFMA class", hipErrorInvalidValue);
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    constexpr int es = sizeof(S) / 8;
+    if (mfma) {
+      switch (pick_nt_mfma(max_nrhs, max_n, es)) {
+        case 16: sweep_seg_nt<S, 16, true>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+        case 32: sweep_seg_nt<S, 32, true>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+        default: sweep_seg_nt<S, 64, true>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+      }
+    } else {
+      switch (pick_nt(max_nrhs, max_n, es)) {
+        case 1: sweep_seg_nt<S, 1, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+        case 4: sweep_seg_nt<S, 4, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+        case 16: sweep_seg_nt<S, 16, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+        default: sweep_seg_nt<S, 32, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+      }
+    }
+  });
 }
 
 }  // namespace rs

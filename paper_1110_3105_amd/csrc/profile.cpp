@@ -66,46 +66,52 @@ void prof_add_work(int family, const Work &w) {
   t.entries += w.entries;
 }
 
-Work work_assemble(int m, int n) {
+// Complex data: a multiply-add is 8 real flops (4 for real data counted as 2 below, so
+// the factor is 4) and an entry occupies 16 bytes.
+static double flop_scale(bool cplx) { return cplx ? 4.0 : 1.0; }
+static double byte_size(bool cplx) { return cplx ? 16.0 : 8.0; }
+
+Work work_assemble(int m, int n, bool cplx) {
   Work w;
   w.entries = (double)m * n;
-  w.bytes = 8.0 * m * n;
+  w.bytes = byte_size(cplx) * m * n;
   return w;
 }
 
-Work work_id(int m, int n, int k) {
+Work work_id(int m, int n, int k, bool cplx) {
   Work w;
   double f = 2.0 * m * n;                       // initial column norms
   for (int j = 0; j < k; ++j)                   // reflector + update + recomputed norms
     f += 2.0 * (m - j) + 6.0 * (double)(m - j) * (n - j - 1);
   f += (double)k * k * (n - k);                 // T = R11^{-1} R12
-  w.flops = f;
-  w.bytes = 8.0 * m * n + 8.0 * k * (n - k) + 4.0 * n;
+  w.flops = f * flop_scale(cplx);
+  w.bytes = byte_size(cplx) * ((double)m * n + (double)k * (n - k)) + 4.0 * n;
   return w;
 }
 
-Work work_factor(int n, int k) {
+Work work_factor(int n, int k, bool cplx) {
   const double r = n - k, kk = k, nn = n;
   Work w;
-  w.flops = 4.0 * nn * r * kk + 2.0 * r * r * r + 4.0 * r * r * kk + 2.0 * kk * kk * r;
+  w.flops = (4.0 * nn * r * kk + 2.0 * r * r * r + 4.0 * r * r * kk + 2.0 * kk * kk * r) *
+            flop_scale(cplx);
   w.entries = nn * nn;
-  w.bytes = 8.0 * (3.0 * kk * r + r * r + kk * kk) + 8.0 * kk * r;
+  w.bytes = byte_size(cplx) * (3.0 * kk * r + r * r + kk * kk + kk * r);
   return w;
 }
 
-Work work_sweep_up(int k, int r, int nrhs) {
+Work work_sweep_up(int k, int r, int nrhs, bool cplx) {
   Work w;
   const double ops = (double)r * r + 2.0 * k * r;
-  w.flops = 2.0 * nrhs * ops;
-  w.bytes = 8.0 * ops + 16.0 * (k + r) * (double)nrhs;
+  w.flops = 2.0 * nrhs * ops * flop_scale(cplx);
+  w.bytes = byte_size(cplx) * (ops + 2.0 * (k + r) * (double)nrhs);
   return w;
 }
 
-Work work_sweep_down(int k, int r, int nrhs) {
+Work work_sweep_down(int k, int r, int nrhs, bool cplx) {
   Work w;
   const double ops = 2.0 * k * r;
-  w.flops = 2.0 * nrhs * ops;
-  w.bytes = 8.0 * ops + 16.0 * (k + r) * (double)nrhs;
+  w.flops = 2.0 * nrhs * ops * flop_scale(cplx);
+  w.bytes = byte_size(cplx) * (ops + 2.0 * (k + r) * (double)nrhs);
   return w;
 }
 

@@ -26,6 +26,8 @@ struct ProbDev {
   int32_t log_kernel;      // 1: append the charge and constant rows
   double eps;              // relative ID precision
   double ratio;            // proxy radius / box side
+  double kwave;            // Helmholtz wavenumber
+  double eta;              // Helmholtz combined-field coupling
 };
 
 // One box of one level, for the compression kernels (assembly + ID).
@@ -36,7 +38,7 @@ struct CompBox {
   int32_t m;               // rows of M = 2 nn + 2 npx (+2)
   int64_t J_off;           // int32 tree positions in the index pool
   int64_t N_off;           // near tree positions in the index pool
-  int64_t M_off;           // doubles, column-major m x n, ld = m
+  int64_t M_off;           // scalars, column-major m x n, ld = m
   double cen[3];
   double rho;              // proxy radius
   int64_t order_off;       // ints: out, sorted skeleton then redundant local positions
@@ -55,14 +57,15 @@ struct FacBox {
   int32_t nchild;
   int64_t J_off;           // tree positions (int32) of the active DOFs (local order)
   int64_t order_off;       // sorted s then r local positions (int32), from the ID
-  double *slot;            // T | G | E | F | Lambda (layout below)
-  int64_t work_off;        // doubles of workspace: n*n + r*2r
+  double *slot;            // T | G | E | F | Lambda (layout below; scalars of the problem)
+  int64_t work_off;        // scalars of workspace (n*n)
   int32_t child_lo[8];     // segment of each child in the local order
   int32_t child_k[8];
   const double *child_lam[8];  // Lambda of each child (k_c x k_c, column-major)
 };
 
-// One box for the solve sweeps.
+// One box for the solve sweeps.  Matrix pointers address scalars of the problem's type
+// (binary64, or complex128 as re/im pairs).
 struct SweepBox {
   int32_t k, r;            // skeleton / redundant counts
   const int32_t *idx;      // k skeleton tree positions, then r redundant ones
@@ -76,7 +79,7 @@ struct SweepBox {
 // handle's level, applied to that handle's workspace W (nrhs columns).
 struct SweepSeg {
   const SweepBox *boxes;
-  double *W;
+  double *W;               // scalars of the handle's type
   int32_t count;
   int32_t nrhs;
   int32_t block0;          // first block of the launch that belongs to this segment
@@ -94,7 +97,8 @@ struct PermSeg {
   int32_t pad;
 };
 
-// Slot layout of a factored box with n = k + r.
+// Slot layout of a factored box with n = k + r, in scalars (a complex scalar occupies
+// two doubles).
 __host__ __device__ inline int64_t slot_T(int k, int r) { (void)k; (void)r; return 0; }
 __host__ __device__ inline int64_t slot_G(int k, int r) { return (int64_t)k * r; }
 __host__ __device__ inline int64_t slot_E(int k, int r) { return (int64_t)k * r + (int64_t)r * r; }
@@ -109,36 +113,37 @@ __host__ __device__ inline int64_t slot_bound(int n) { return (5 * (int64_t)n * 
 
 // ------------------------------------------------------------------ launchers
 // All launchers enqueue on `st`; grid = one workgroup per box in [first, first+count).
-void launch_assemble(const CompBox *boxes, int first, int count, const ProbDev *probs,
+// `cplx` selects the scalar type of the arrays behind the double pointers: binary64, or
+// complex128 (re/im pairs) for the Helmholtz kernel.
+void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
                      const int32_t *pool, double *Marena, int max_npx, hipStream_t st);
-void launch_cpqr_id(const CompBox *boxes, int first, int count, const ProbDev *probs,
+void launch_cpqr_id(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
                     double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                     hipStream_t st);
-void launch_diag_factor(const FacBox *boxes, int first, int count, const ProbDev *probs,
-                        const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
-                        double *work, int32_t *err, int err_base, int max_n, hipStream_t st);
-size_t cpqr_lds_bytes(int max_n, int max_m);
-// Global workspace doubles reserved for a box of n DOFs in k_diag_factor.
-size_t diag_work_doubles(int n);
-void launch_permute_in(const double *B, int64_t ldb, double *W, const int64_t *perm, int64_t n,
-                       int nrhs, hipStream_t st);
-void launch_permute_out(double *B, int64_t ldb, const double *W, const int64_t *perm,
+void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
+                        const ProbDev *probs, const int32_t *pool, const int32_t *order_pool,
+                        const int32_t *ranks, double *work, int32_t *err, int err_base,
+                        int max_n, hipStream_t st);
+size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m);
+// Global workspace scalars reserved for a box of n DOFs in k_diag_factor.
+size_t diag_work_elems(int n);
+void launch_permute_in(bool cplx, const double *B, int64_t ldb, double *W, const int64_t *perm,
+                       int64_t n, int nrhs, hipStream_t st);
+void launch_permute_out(bool cplx, double *B, int64_t ldb, const double *W, const int64_t *perm,
                         int64_t n, int nrhs, hipStream_t st);
-void launch_sweep_up(const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                     int max_n, hipStream_t st);
-void launch_sweep_down(const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                       int max_n, hipStream_t st);
-void launch_sweep_seg(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
-                      int max_n, hipStream_t st);
-// Boxes with n = k + r <= kMfmaMaxN are swept with FP64 MFMA tiles (any nrhs); larger
+void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_elems,
+                        bool to_tree, hipStream_t st);
+// Boxes with n = k + r <= mfma_max_n are swept with FP64 MFMA tiles (any nrhs); larger
 // boxes with the FP64 VALU kernels.  The class of a box never depends on the launch.
 constexpr int kMfmaMaxN = 512;
-void launch_sweep_mfma(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
-                       int max_n, hipStream_t st);
-void launch_sweep_seg_mfma(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs,
-                           int max_n, hipStream_t st);
-void launch_permute_seg(const PermSeg *segs, int nseg, int64_t max_elems, bool to_tree,
-                        hipStream_t st);
+constexpr int kMfmaMaxNComplex = 256;
+int mfma_max_n(bool cplx);
+void launch_sweep(bool cplx, bool up, const SweepBox *boxes, int first, int count, double *W,
+                  int nrhs, int max_n, hipStream_t st);
+void launch_sweep_mfma(bool cplx, bool up, const SweepBox *boxes, int first, int count,
+                       double *W, int nrhs, int max_n, hipStream_t st);
+void launch_sweep_seg(bool cplx, bool mfma, bool up, const SweepSeg *segs, int nseg,
+                      int nblocks, int max_nrhs, int max_n, hipStream_t st);
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string &msg);

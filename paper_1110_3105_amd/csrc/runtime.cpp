@@ -21,10 +21,10 @@
 
 namespace rs {
 
-void LevelRec::partition_classes() {
+void LevelRec::partition_classes(int mfma_limit) {
   std::vector<int> order(sweep.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  auto small = [&](int i) { return sweep[i].k + sweep[i].r <= kMfmaMaxN; };
+  auto small = [&](int i) { return sweep[i].k + sweep[i].r <= mfma_limit; };
   std::stable_partition(order.begin(), order.end(), small);
   std::vector<SweepBox> s2;
   std::vector<int> b2;
@@ -186,6 +186,7 @@ void setup_problem(ProbState &ps, hipStream_t st) {
   h->dim = dim;
   h->n = n;
   h->kind = k.kind;
+  h->cplx = k.kind == RS_HELM2D_CFIE;
   std::vector<double> host((size_t)n * (2 * dim + 2), 0.0);
   double *hx = host.data();
   double *hn = hx + (size_t)dim * n;
@@ -219,9 +220,11 @@ void setup_problem(ProbState &ps, hipStream_t st) {
   P.dim = dim;
   P.c = k.identity;
   P.npx = k.proxy_points;
-  P.log_kernel = k.kind == RS_LAP2D_SL ? 1 : 0;
+  P.log_kernel = (k.kind == RS_LAP2D_SL || k.kind == RS_HELM2D_CFIE) ? 1 : 0;
   P.eps = ps.req->eps;
   P.ratio = k.proxy_ratio;
+  P.kwave = k.kind == RS_HELM2D_CFIE ? k.wavenumber : 0.0;
+  P.eta = k.kind == RS_HELM2D_CFIE ? k.eta : 0.0;
   ps.npx = k.proxy_points;
   ps.log_kernel = P.log_kernel != 0;
   const int nb = t.nbox();
@@ -272,7 +275,7 @@ void fill_children(ProbState &ps, int b, FacBox &fb) {
     const int nc = (int)ps.h->box_J[c].size();
     fb.child_lo[ci] = lo;
     fb.child_k[ci] = kc;
-    fb.child_lam[ci] = ps.h->box_slot[c] + slot_L(kc, nc - kc);
+    fb.child_lam[ci] = ps.h->box_slot[c] + slot_L(kc, nc - kc) * (ps.h->cplx ? 2 : 1);
     lo += kc;
   }
 }
@@ -299,9 +302,11 @@ double ms_since(Clock::time_point a) {
 }
 }  // namespace
 
-void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
-                 std::vector<rs_factor_s *> &out) {
-  std::lock_guard<std::mutex> lock(g_factor_mutex);
+namespace {
+
+// Factors requests that share one scalar type (all real or all complex).
+void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
+                  std::vector<rs_factor_s *> &out) {
   auto t0 = std::chrono::steady_clock::now();
   double plan_ms = 0.0, wait_ms = 0.0;
   const int np = (int)reqs.size();
@@ -323,6 +328,8 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
   }
   upload(S.probs, probs, st);
   const ProbDev *d_probs = S.probs.as<ProbDev>();
+  const bool cplx = np > 0 && handles[0]->cplx;
+  const int es = cplx ? 2 : 1;                 // doubles per scalar
   S.err.ensure(sizeof(int32_t));
   RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
@@ -387,43 +394,43 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       cb.order_off = order_total;
       order_total += cb.n;
       cb.kslot = i;
-      double *slot = P.h->arena.alloc_n<double>(slot_bound(cb.n));
+      double *slot = P.h->arena.alloc_n<double>(slot_bound(cb.n) * es);
       cb.T = slot;
       P.h->box_slot[b] = slot;
-      work_total += (int64_t)diag_work_doubles(cb.n);
+      work_total += (int64_t)diag_work_elems(cb.n);
       max_n = std::max(max_n, cb.n);
       max_m_step = std::max(max_m_step, cb.m);
       max_m_seen = std::max<int64_t>(max_m_seen, cb.m);
     }
     plan_ms += ms_since(tp);
-    if (cpqr_lds_bytes(max_n, 1 << 30) > 160 * 1024)
+    if (cpqr_lds_bytes(cplx, max_n, 1 << 30) > 160 * 1024)
       throw UserError{RS_ENOTSUP, "a box's active set exceeds the on-chip ID limit"};
     upload(S.pool, pool, st);
     upload(S.comp, comp, st);
-    S.M.ensure(std::max<int64_t>(M_total, 1) * sizeof(double));
+    S.M.ensure(std::max<int64_t>(M_total, 1) * sizeof(double) * es);
     S.order.ensure(std::max<int64_t>(order_total, 1) * sizeof(int32_t));
     S.ranks.ensure(std::max(cnt, 1) * sizeof(int32_t));
-    S.work.ensure(std::max<int64_t>(work_total, 1) * sizeof(double));
+    S.work.ensure(std::max<int64_t>(work_total, 1) * sizeof(double) * es);
     const CompBox *d_comp = S.comp.as<CompBox>();
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         {
           ProfScope ps_(RS_K_ASSEMBLE, st);
-          launch_assemble(d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
+          launch_assemble(cplx, d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
                           max_npx, st);
         }
         ProfScope ps_(RS_K_ID, st);
-        launch_cpqr_id(d_comp, i, 1, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
+        launch_cpqr_id(cplx, d_comp, i, 1, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
                        S.ranks.as<int32_t>(), comp[i].n, comp[i].m, st);
       }
     } else {
       {
         ProfScope ps_(RS_K_ASSEMBLE, st);
-        launch_assemble(d_comp, 0, cnt, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
+        launch_assemble(cplx, d_comp, 0, cnt, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
                         max_npx, st);
       }
       ProfScope ps_(RS_K_ID, st);
-      launch_cpqr_id(d_comp, 0, cnt, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
+      launch_cpqr_id(cplx, d_comp, 0, cnt, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
                      S.ranks.as<int32_t>(), max_n, max_m_step, st);
     }
     std::vector<int32_t> ranks(cnt), order(order_total);
@@ -451,9 +458,9 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       const int b = items[i].box;
       const CompBox &cb = comp[i];
       const int k = ranks[i];
-      w_asm += work_assemble(cb.m, cb.n);
-      w_id += work_id(cb.m, cb.n, k);
-      w_fac += work_factor(cb.n, k);
+      w_asm += work_assemble(cb.m, cb.n, cplx);
+      w_id += work_id(cb.m, cb.n, k, cplx);
+      w_fac += work_factor(cb.n, k, cplx);
       const std::vector<int32_t> &J = P.J[b];
       const int32_t *ord = order.data() + cb.order_off;
       std::vector<int32_t> &sk = P.skel[b];
@@ -473,7 +480,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       fb.order_off = cb.order_off;
       fb.slot = cb.T;
       fb.work_off = woff;
-      woff += (int64_t)diag_work_doubles(cb.n);
+      woff += (int64_t)diag_work_elems(cb.n);
       fill_children(P, b, fb);
     }
     plan_ms += ms_since(tp2);
@@ -485,13 +492,13 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         ProfScope ps_(RS_K_FACTOR, st);
-        launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
+        launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
                            S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
                            err_base, comp[i].n, st);
       }
     } else {
       ProfScope ps_(RS_K_FACTOR, st);
-      launch_diag_factor(d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
+      launch_diag_factor(cplx, d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
                          S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
                          err_base, max_n, st);
     }
@@ -522,10 +529,10 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       sb.r = n - k;
       sb.idx = d_idx;
       double *slot = comp[i].T;
-      sb.T = slot + slot_T(k, n - k);
-      sb.G = slot + slot_G(k, n - k);
-      sb.E = slot + slot_E(k, n - k);
-      sb.F = slot + slot_F(k, n - k);
+      sb.T = slot + slot_T(k, n - k) * es;
+      sb.G = slot + slot_G(k, n - k) * es;
+      sb.E = slot + slot_E(k, n - k) * es;
+      sb.F = slot + slot_F(k, n - k) * es;
       rs_factor_s *h = P.h;
       const int d = P.t->depth[b];
       if (h->levels.empty() || h->levels.back().depth != d) {
@@ -537,7 +544,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       lv.sweep.push_back(sb);
       lv.max_n = std::max(lv.max_n, n);
       h->stats.total_skeletons += k;
-      h->stats.factor_doubles += slot_size(k, n - k) - (int64_t)k * k;
+      h->stats.factor_doubles += (slot_size(k, n - k) - (int64_t)k * k) * es;
       h->stats.max_box_n = std::max<int64_t>(h->stats.max_box_n, n);
       h->stats.max_box_m = std::max<int64_t>(h->stats.max_box_m, comp[i].m);
     }
@@ -569,9 +576,9 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       fb.leaf = P.t->is_leaf(b) ? 1 : 0;
       fb.J_off = (int64_t)pool.size();
       pool.insert(pool.end(), J.begin(), J.end());
-      fb.slot = P.h->arena.alloc_n<double>(std::max<int64_t>((int64_t)fb.n * fb.n, 1));
+      fb.slot = P.h->arena.alloc_n<double>(std::max<int64_t>((int64_t)fb.n * fb.n, 1) * es);
       fb.work_off = woff;
-      woff += (int64_t)diag_work_doubles(fb.n);
+      woff += (int64_t)diag_work_elems(fb.n);
       fill_children(P, b, fb);
       fac.push_back(fb);
       items.push_back({&P, b});
@@ -582,24 +589,24 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     }
     upload(S.pool, pool, st);
     upload(S.fac, fac, st);
-    S.work.ensure(std::max<int64_t>(woff, 1) * sizeof(double));
+    S.work.ensure(std::max<int64_t>(woff, 1) * sizeof(double) * es);
     const FacBox *d_fac = S.fac.as<FacBox>();
     const int err_base = (int)all_items.size();
     all_items.insert(all_items.end(), items.begin(), items.end());
     {
       Work w;
-      for (const FacBox &f : fac) w += work_factor(f.n, 0);
+      for (const FacBox &f : fac) w += work_factor(f.n, 0, cplx);
       prof_add_work(RS_K_FACTOR, w);
     }
     if (per_box) {
       for (int i = 0; i < np; ++i) {
         ProfScope ps_(RS_K_FACTOR, st);
-        launch_diag_factor(d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
+        launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
                            S.work.as<double>(), S.err.as<int32_t>(), err_base, fac[i].n, st);
       }
     } else {
       ProfScope ps_(RS_K_FACTOR, st);
-      launch_diag_factor(d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
+      launch_diag_factor(cplx, d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
                          S.work.as<double>(), S.err.as<int32_t>(), err_base, max_n, st);
     }
     {
@@ -627,19 +634,19 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       h->root.sweep = {sb};
       h->root.max_n = n;
       h->stats.root_size = n;
-      h->stats.factor_doubles += (int64_t)n * n;
+      h->stats.factor_doubles += (int64_t)n * n * es;
     }
   }
   // ---- upload the sweep descriptors
   for (int p = 0; p < np; ++p) {
     rs_factor_s *h = handles[p].get();
     for (LevelRec &lv : h->levels) {
-      lv.partition_classes();
+      lv.partition_classes(mfma_max_n(cplx));
       lv.d_sweep = h->arena.alloc_n<SweepBox>((int64_t)lv.sweep.size());
       RS_HIP_CHECK(hipMemcpyAsync(lv.d_sweep, lv.sweep.data(), lv.sweep.size() * sizeof(SweepBox),
                                   hipMemcpyHostToDevice, st));
     }
-    h->root.partition_classes();
+    h->root.partition_classes(mfma_max_n(cplx));
     h->root.d_sweep = h->arena.alloc_n<SweepBox>(1);
     RS_HIP_CHECK(hipMemcpyAsync(h->root.d_sweep, h->root.sweep.data(), sizeof(SweepBox),
                                 hipMemcpyHostToDevice, st));
@@ -654,6 +661,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     h->stats.nbox = ps[p].t->nbox();
     h->stats.maxdepth = ps[p].t->maxdepth;
     h->stats.dim = h->dim;
+    h->stats.complex_values = h->cplx ? 1 : 0;
     h->stats.factor_ms = ms;
     h->stats.plan_ms = plan_ms;
     h->stats.wait_ms = wait_ms;
@@ -661,12 +669,45 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
   }
 }
 
-void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode,
+}  // namespace
+
+void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
+                 std::vector<rs_factor_s *> &out) {
+  std::lock_guard<std::mutex> lock(g_factor_mutex);
+  // Launches are typed by the scalar: real and complex problems are factored in two
+  // groups (each problem's arithmetic is the same either way).
+  std::vector<int> idx[2];
+  for (int i = 0; i < (int)reqs.size(); ++i)
+    idx[reqs[i].k->kind == RS_HELM2D_CFIE ? 1 : 0].push_back(i);
+  if (idx[0].empty() || idx[1].empty()) {
+    factor_group(reqs, launch_mode, st, out);
+    return;
+  }
+  out.assign(reqs.size(), nullptr);
+  try {
+    for (int g = 0; g < 2; ++g) {
+      std::vector<FactorRequest> sub;
+      for (int i : idx[g]) sub.push_back(reqs[i]);
+      std::vector<rs_factor_s *> o;
+      factor_group(sub, launch_mode, st, o);
+      for (size_t j = 0; j < o.size(); ++j) out[idx[g][j]] = o[j];
+    }
+  } catch (...) {
+    for (rs_factor_s *h : out) delete h;
+    out.clear();
+    throw;
+  }
+}
+
+void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
                hipStream_t st) {
   if (nrhs == 0) return;
   const int64_t n = h->n;
+  const bool cplx = h->cplx;
+  const int es = cplx ? 2 : 1;
+  double *B = static_cast<double *>(Bv);
   double *W = nullptr;
-  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)n * nrhs * sizeof(double), st));
+  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)n * nrhs * sizeof(double) * es, st));
   struct Freer {
     double *W;
     hipStream_t st;
@@ -675,50 +716,52 @@ void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
   const bool prof = prof_on();
   Work wperm;
-  wperm.bytes = 16.0 * n * nrhs + 8.0 * n;
+  wperm.bytes = 16.0 * es * n * nrhs + 8.0 * n;
   prof_add_work(RS_K_PERMUTE, wperm);
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_in(B, ldb, W, h->d_perm, n, nrhs, st);
+    launch_permute_in(cplx, B, ldb, W, h->d_perm, n, nrhs, st);
   }
   auto up = [&](const LevelRec &lv) {
     const int cnt = (int)lv.sweep.size();
     if (prof) {
       Work w;
-      for (const SweepBox &sb : lv.sweep) w += work_sweep_up(sb.k, sb.r, nrhs);
+      for (const SweepBox &sb : lv.sweep) w += work_sweep_up(sb.k, sb.r, nrhs, cplx);
       prof_add_work(RS_K_SWEEP_UP, w);
     }
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         ProfScope ps_(RS_K_SWEEP_UP, st);
         const int n = lv.sweep[i].k + lv.sweep[i].r;
-        if (i < lv.n_small) launch_sweep_mfma(true, lv.d_sweep, i, 1, W, nrhs, n, st);
-        else launch_sweep_up(lv.d_sweep, i, 1, W, nrhs, n, st);
+        if (i < lv.n_small) launch_sweep_mfma(cplx, true, lv.d_sweep, i, 1, W, nrhs, n, st);
+        else launch_sweep(cplx, true, lv.d_sweep, i, 1, W, nrhs, n, st);
       }
     } else {
       ProfScope ps_(RS_K_SWEEP_UP, st);
-      launch_sweep_mfma(true, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
-      launch_sweep_up(lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs, lv.max_n_large, st);
+      launch_sweep_mfma(cplx, true, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
+      launch_sweep(cplx, true, lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs,
+                   lv.max_n_large, st);
     }
   };
   auto down = [&](const LevelRec &lv) {
     const int cnt = (int)lv.sweep.size();
     if (prof) {
       Work w;
-      for (const SweepBox &sb : lv.sweep) w += work_sweep_down(sb.k, sb.r, nrhs);
+      for (const SweepBox &sb : lv.sweep) w += work_sweep_down(sb.k, sb.r, nrhs, cplx);
       prof_add_work(RS_K_SWEEP_DOWN, w);
     }
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         ProfScope ps_(RS_K_SWEEP_DOWN, st);
         const int n = lv.sweep[i].k + lv.sweep[i].r;
-        if (i < lv.n_small) launch_sweep_mfma(false, lv.d_sweep, i, 1, W, nrhs, n, st);
-        else launch_sweep_down(lv.d_sweep, i, 1, W, nrhs, n, st);
+        if (i < lv.n_small) launch_sweep_mfma(cplx, false, lv.d_sweep, i, 1, W, nrhs, n, st);
+        else launch_sweep(cplx, false, lv.d_sweep, i, 1, W, nrhs, n, st);
       }
     } else {
       ProfScope ps_(RS_K_SWEEP_DOWN, st);
-      launch_sweep_mfma(false, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
-      launch_sweep_down(lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs, lv.max_n_large, st);
+      launch_sweep_mfma(cplx, false, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
+      launch_sweep(cplx, false, lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs,
+                   lv.max_n_large, st);
     }
   };
   for (const LevelRec &lv : h->levels) up(lv);
@@ -727,7 +770,7 @@ void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode
   prof_add_work(RS_K_PERMUTE, wperm);
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_out(B, ldb, W, h->d_perm, n, nrhs, st);
+    launch_permute_out(cplx, B, ldb, W, h->d_perm, n, nrhs, st);
   }
 }
 
@@ -744,12 +787,14 @@ struct LaunchRec {
 void release_host_vector(void *p) { delete static_cast<std::vector<char> *>(p); }
 }  // namespace
 
-void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
-  std::vector<SolveRequest> rq;
-  for (const SolveRequest &q : reqs)
-    if (q.nrhs > 0) rq.push_back(q);
+namespace {
+
+// Requests whose handles share one scalar type.
+void solve_group(const std::vector<SolveRequest> &rq, hipStream_t st) {
   if (rq.empty()) return;
   const int nq = (int)rq.size();
+  const bool cplx = rq[0].h->cplx;
+  const int es = cplx ? 2 : 1;
   // workspace offsets
   std::vector<int64_t> woff(nq);
   int64_t wtot = 0;
@@ -760,15 +805,15 @@ void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
     max_levels = std::max(max_levels, (int)rq[i].h->levels.size());
   }
   double *W = nullptr;
-  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)wtot * sizeof(double), st));
+  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)wtot * sizeof(double) * es, st));
   // segment tables: permutations, then upward steps (finest level first), the roots,
   // then downward steps; each launch's segments are contiguous.
   std::vector<PermSeg> perm(nq);
   int64_t max_elems = 0;
   for (int i = 0; i < nq; ++i) {
-    perm[i].B = rq[i].B;
+    perm[i].B = static_cast<double *>(rq[i].B);
     perm[i].ldb = rq[i].ldb;
-    perm[i].W = W + woff[i];
+    perm[i].W = W + woff[i] * es;
     perm[i].perm = rq[i].h->d_perm;
     perm[i].n = rq[i].h->n;
     perm[i].nrhs = rq[i].nrhs;
@@ -788,7 +833,7 @@ void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
         if (cnt <= 0) continue;
         SweepSeg s;
         s.boxes = lv->d_sweep + lo;
-        s.W = W + woff[i];
+        s.W = W + woff[i] * es;
         s.count = cnt;
         s.nrhs = rq[i].nrhs;
         s.block0 = L.nblocks;
@@ -825,21 +870,29 @@ void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
   const SweepSeg *d_segs = reinterpret_cast<const SweepSeg *>(dtab + perm_bytes);
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_seg(d_perm, nq, max_elems, true, st);
+    launch_permute_seg(cplx, d_perm, nq, max_elems, true, st);
   }
   for (const LaunchRec &L : launches) {
     ProfScope ps_(L.up ? RS_K_SWEEP_UP : RS_K_SWEEP_DOWN, st);
-    if (L.mfma)
-      launch_sweep_seg_mfma(L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs, L.max_n, st);
-    else
-      launch_sweep_seg(L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs, L.max_n, st);
+    launch_sweep_seg(cplx, L.mfma, L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs,
+                     L.max_n, st);
   }
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_seg(d_perm, nq, max_elems, false, st);
+    launch_permute_seg(cplx, d_perm, nq, max_elems, false, st);
   }
   RS_HIP_CHECK(hipFreeAsync(dtab, st));
   RS_HIP_CHECK(hipFreeAsync(W, st));
+}
+
+}  // namespace
+
+void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
+  std::vector<SolveRequest> rq[2];
+  for (const SolveRequest &q : reqs)
+    if (q.nrhs > 0) rq[q.h->cplx ? 1 : 0].push_back(q);
+  solve_group(rq[0], st);
+  solve_group(rq[1], st);
 }
 
 }  // namespace rs

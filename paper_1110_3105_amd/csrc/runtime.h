@@ -53,8 +53,8 @@ struct LevelRec {
   int max_n = 0;
   int n_small = 0;                 // sweep[0, n_small): MFMA class (n <= kMfmaMaxN)
   int max_n_small = 0, max_n_large = 0;
-  // Orders the boxes MFMA class first and records the class boundary.
-  void partition_classes();
+  // Orders the boxes MFMA class (n <= mfma_limit) first and records the class boundary.
+  void partition_classes(int mfma_limit);
 };
 
 }  // namespace rs
@@ -63,6 +63,7 @@ struct rs_factor_s {
   int dim = 0;
   int64_t n = 0;
   int kind = 0;
+  bool cplx = false;                     // complex128 operator (Helmholtz)
   rs::Arena arena;                       // geometry, factors, index lists, descriptors
   int64_t *d_perm = nullptr;             // tree position -> caller index
   rs::ProbDev prob{};                    // device view of the geometry
@@ -71,7 +72,7 @@ struct rs_factor_s {
   // host-side record for queries
   std::vector<int32_t> box_k;            // -1 for the root
   std::vector<std::vector<int32_t>> box_J, box_skel;
-  std::vector<double *> box_slot;
+  std::vector<double *> box_slot;        // factor slot per box (scalars of the handle's type)
   int nbox = 0;
   rs_stats stats{};
   std::atomic<int> busy{0};
@@ -92,12 +93,13 @@ struct FactorRequest {
 void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
                  std::vector<rs_factor_s *> &out);
 
-void solve_one(rs_factor_s *h, double *B, int64_t ldb, int nrhs, int launch_mode,
+// B: device, column-major, scalars of the handle's type (complex128 as re/im pairs).
+void solve_one(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_mode,
                hipStream_t st);
 
 struct SolveRequest {
   rs_factor_s *h;
-  double *B;
+  void *B;
   int64_t ldb;
   int nrhs;
 };
@@ -145,11 +147,12 @@ class ProfScope {
   bool active_ = false;
 };
 
-// Algorithmic work of one box (counts documented with rs_profile_read).
-Work work_assemble(int m, int n);
-Work work_id(int m, int n, int k);
-Work work_factor(int n, int k);
-Work work_sweep_up(int k, int r, int nrhs);
-Work work_sweep_down(int k, int r, int nrhs);
+// Algorithmic work of one box (counts documented with rs_profile_read).  For complex
+// data a multiply-add counts 8 real flops and an entry 16 bytes.
+Work work_assemble(int m, int n, bool cplx);
+Work work_id(int m, int n, int k, bool cplx);
+Work work_factor(int n, int k, bool cplx);
+Work work_sweep_up(int k, int r, int nrhs, bool cplx);
+Work work_sweep_down(int k, int r, int nrhs, bool cplx);
 
 }  // namespace rs

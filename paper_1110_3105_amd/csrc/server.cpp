@@ -102,9 +102,10 @@ size_t handle_bytes(rs_handle h) {
 
 // Device bytes a factorization needs while it runs: the resident factor plus the
 // transient compression blocks, workspaces and index pools.  Proportional to N with a
-// per-dimension constant (2D: ~4 KB per unknown at eps = 1e-9; 3D larger).
+// per-kernel constant (2D Laplace: ~4 KB per unknown at eps = 1e-9; complex Helmholtz
+// entries are twice the size and its ranks higher; 3D larger).
 size_t factor_estimate(const rs_kernel &k, int64_t n) {
-  const size_t per = k.dim == 2 ? 6144 : 65536;
+  const size_t per = k.kind == RS_HELM2D_CFIE ? 16384 : k.dim == 2 ? 6144 : 65536;
   return (size_t)n * per + (size_t(64) << 20);
 }
 
@@ -346,7 +347,7 @@ rs_status rs_server_submit_factor(rs_server s, const rs_kernel *k, rs_tree t,
   return RS_OK;
 }
 
-rs_status rs_server_submit_solve(rs_server s, rs_handle h, double *B, int64_t ldb, int32_t nrhs,
+rs_status rs_server_submit_solve(rs_server s, rs_handle h, void *B, int64_t ldb, int32_t nrhs,
                                  uint64_t *ticket) {
   if (!s || !h || !ticket || nrhs < 1 || !B || ldb < h->n) {
     set_error("bad solve request (NULL argument, nrhs < 1 or ldb < n)");

@@ -80,6 +80,11 @@ def test_factor_argument_validation_before_device_use():
                       proxy_points=args.get("proxy_points", 64),
                       proxy_ratio=args.get("proxy_ratio", 1.5))
         assert ei.value.code == 1, c
-    with pytest.raises(rs.RSError) as ei:
-        rs.factor("helm2d_cfie", t, g.points, g.weights, 1e-9)
-    assert ei.value.code == 6
+    helm = [dict(),                                            # no normals / curvature
+            dict(normals=g.normals, curvature=g.curvature),     # wavenumber 0
+            dict(normals=g.normals, curvature=g.curvature, wavenumber=float("nan")),
+            dict(normals=g.normals, curvature=g.curvature, wavenumber=10.0, eta=float("inf"))]
+    for c in helm:
+        with pytest.raises(rs.RSError) as ei:
+            rs.factor("helm2d_cfie", t, g.points, g.weights, 1e-9, **c)
+        assert ei.value.code == 1, c

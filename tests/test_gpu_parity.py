@@ -19,9 +19,7 @@ import pytest
 import workloads as W
 from oracle import Problem, dense
 from oracle import factor as ofactor
-from oracle.rs import compression_block
-
-U = np.finfo(np.float64).eps
+from parity_util import compare_skeletons
 
 pytestmark = pytest.mark.gpu
 
@@ -53,36 +51,7 @@ def _gpu_solve(h, b, mode="level"):
     return B.cpu().numpy()
 
 
-def _compare_skeletons(h, F, residual_every=1):
-    """Skeleton sets equal on every box whose subtree has no tie; returns #compared."""
-    ks, sk = h.box_skeletons()
-    t = F.tree
-    tied = set()
-    for b in sorted(F.records, key=lambda b: -t.depth[b]):
-        r = F.records[b]
-        if r.idr.first_tie >= 0 or r.idr.near_threshold or any(c in tied for c in t.children[b]):
-            tied.add(b)
-    compared = 0
-    for b, r in F.records.items():
-        if b in tied:
-            continue
-        assert ks[b] == r.k, f"rank differs at box {b}: {ks[b]} vs {r.k}"
-        assert np.array_equal(np.sort(sk[b]), r.skel), f"skeletons differ at box {b}"
-        J, T = h.box_export(b)
-        assert np.array_equal(J, r.J)
-        if r.k and r.n - r.k:
-            scale = max(np.abs(r.idr.T).max(), 1.0)
-            cond = r.idr.rdiag[0] / r.idr.rdiag[r.k - 1]
-            assert np.abs(T - r.idr.T).max() <= 1e3 * U * cond * scale, f"T differs at box {b}"
-            if b % residual_every == 0:
-                tr = F.tree
-                M = compression_block(F.prob, r.J, r.near, tr.center[b],
-                                      F.opts.proxy_ratio * tr.side[b], F.opts.proxy_points)
-                res = M[:, r.idr.redund] - M[:, r.idr.skel] @ T
-                bound = 2.0 * r.idr.rdiag[r.k] + 1e-13 * r.idr.rdiag[0]
-                assert np.linalg.norm(res, axis=0).max() <= bound, f"ID residual at box {b}"
-        compared += 1
-    return compared, len(tied)
+_compare_skeletons = compare_skeletons
 
 
 @pytest.mark.parametrize("kind,n,eps,leaf,npx", [

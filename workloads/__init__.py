@@ -164,6 +164,14 @@ def random_curve_problem(p: int):
     return random_curve(n, amps, phases), b
 
 
+def helmholtz_wavenumber(g: Geometry, wavelengths: float) -> float:
+    """Wavenumber k with the given number of wavelengths across the curve, the width
+    taken as the diameter of the smallest origin-centred disc holding the nodes
+    (2 max|x_i|; 2.6 for the star curve): k = 2 pi wavelengths / width."""
+    width = 2.0 * float(np.sqrt((g.points ** 2).sum(axis=1)).max())
+    return 2.0 * np.pi * wavelengths / width
+
+
 # Named workloads (sizes of the benchmark and parity configurations).
 WORKLOADS = {
     "lap2d_dl_star_4096": dict(geom=("star", 4096), kind="lap2d_dl", eps=1e-9, leaf=64,
@@ -172,6 +180,10 @@ WORKLOADS = {
                                 proxy=64, nrhs=512, seed=1),
     "lap3d_sl_sphere_20480": dict(geom=("sphere", 20480), kind="lap3d_sl", eps=1e-6,
                                   leaf=128, proxy=512, nrhs=64, seed=2),
+    # exterior combined field 1/2 I + D_k - i k S_k, 10 wavelengths across the star
+    "helm2d_cfie_star_32768": dict(geom=("star", 32768), kind="helm2d_cfie", eps=1e-9,
+                                   leaf=64, proxy=64, nrhs=1, seed=3, wavelengths=10.0,
+                                   identity=0.5),
 }
 
 
