@@ -77,6 +77,35 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// ---------------------------------------------------------------- FP64 MFMA tiles
+// v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l & 15][l >> 4] and
+// B[l >> 4][l & 15]; element v of its result holds D[(l >> 4) + 4 v][l & 15].
+// Complex tiles use four real products per step: (ar br - ai bi, ar bi + ai br).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <class S>
+struct Acc;
+template <>
+struct Acc<double> {
+  dbl4 v = {0.0, 0.0, 0.0, 0.0};
+  __device__ __forceinline__ void mma(double a, double b) {
+    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, v, 0, 0, 0);
+  }
+  __device__ __forceinline__ double get(int e) const { return v[e]; }
+};
+template <>
+struct Acc<Cplx> {
+  dbl4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+  __device__ __forceinline__ void mma(Cplx a, Cplx b) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, im, 0, 0, 0);
+  }
+  __device__ __forceinline__ Cplx get(int e) const { return {re[e], im[e]}; }
+};
+
+
 // ---------------------------------------------------------------- kernels K(t, s)
 // Laplace: eqs. (2d-laplace), (3d-laplace) and the double-layer kernel of eq.
 // (double-layer), with the unit normal ns at the source.
@@ -507,6 +536,173 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
   if (threadIdx.x == 0) ranks[B.kslot] = k;
 }
 
+
+// --------------------------------------------------------------------------
+// Blocked Gauss-Jordan inversion with partial pivoting for large blocks (r >= kGjBlockMinR).
+// Pivot rows are not swapped: piv[j] records the row that eliminates column j.  Columns
+// are processed in panels of kPB: the panel's steps run on an LDS (or workspace) copy of
+// its columns; their combined effect on every other column q is the rank-kPB update
+//   A(i, q) <- [i not a pivot of the panel] A(i, q) + P(i, :) W(:, q),
+// where P is the panel after its steps and W(s, q) = A(piv[p0 + s], q) before them
+// (the panel's columns equal those of the accumulated row-operation matrix), done with
+// FP64 MFMA tiles.  At the end the in-place array Y holds the inverse as
+// A^{-1}(a, b) = Y(piv[a], q[b]) with q = piv^{-1}; it is written to G (r x r) in that
+// order.  Returns false on a zero or non-finite pivot.
+constexpr int kPB = 16;           // panel width
+constexpr int kQC = 128;          // columns per chunk of the deferred update
+constexpr int kGjBlockMinR = 129;  // r at which a box switches to the blocked inversion
+
+template <class S>
+__host__ __device__ constexpr size_t gj_panel_lds_max() { return 64 * 1024; }
+
+// LDS bytes of the blocked inversion's buffers for r unknowns (panel copy included when
+// it fits gj_panel_lds_max, otherwise it lives in the workspace).
+template <class S>
+__host__ __device__ inline size_t gj_blocked_lds(int r, int nw) {
+  // the panel is in LDS iff it fits; a launch reserves for every r <= its largest box
+  const size_t panel = (size_t)r * kPB * sizeof(S);
+  size_t b = panel <= gj_panel_lds_max<S>() ? panel : gj_panel_lds_max<S>();
+  b += (size_t)kPB * kQC * sizeof(S) + (size_t)kPB * sizeof(S);
+  b += (size_t)nw * (sizeof(double) + sizeof(int));
+  b += (size_t)3 * r * sizeof(int);
+  return b;
+}
+
+template <class S, int NTH>
+__device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
+                           char *lds, S *__restrict__ pn_work) {
+  constexpr int NW = NTH / 64;
+  __shared__ int s_p, s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool pn_lds = (size_t)r * kPB * sizeof(S) <= gj_panel_lds_max<S>();
+  char *p = lds;
+  S *PN = pn_lds ? reinterpret_cast<S *>(p) : pn_work;          // r x kPB, ld = r
+  if (pn_lds) p += (size_t)r * kPB * sizeof(S);
+  S *Wt = reinterpret_cast<S *>(p);                               // kPB x kQC
+  p += (size_t)kPB * kQC * sizeof(S);
+  S *prow = reinterpret_cast<S *>(p);                             // kPB
+  p += (size_t)kPB * sizeof(S);
+  double *red_v = reinterpret_cast<double *>(p);
+  p += (size_t)NW * sizeof(double);
+  int *red_i = reinterpret_cast<int *>(p);
+  p += (size_t)NW * sizeof(int);
+  int *piv = reinterpret_cast<int *>(p);                          // r
+  int *qinv = piv + r;                                            // r
+  int *ustep = qinv + r;                                          // r: step that used row
+
+  for (int i = tid; i < r; i += NTH) ustep[i] = -1;
+  __syncthreads();
+  for (int p0 = 0; p0 < r; p0 += kPB) {
+    const int pb = min(kPB, r - p0);
+    for (int c = wave; c < pb; c += NW) {
+      const S *Ac = A + (int64_t)(p0 + c) * lda;
+      for (int i = lane; i < r; i += 64) PN[i + (int64_t)c * r] = Ac[i];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < pb; ++jj) {
+      const int j = p0 + jj;
+      double best = -1.0;
+      int brow = INT_MAX;
+      for (int i = tid; i < r; i += NTH) {
+        if (ustep[i] >= 0) continue;
+        const double v = mag(PN[i + (int64_t)jj * r]);
+        if (v > best || (v == best && i < brow)) { best = v; brow = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int orow = __shfl_xor(brow, off, 64);
+        if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+      }
+      if (lane == 0) { red_v[wave] = best; red_i[wave] = brow; }
+      __syncthreads();
+      if (tid == 0) {
+        double bv = red_v[0];
+        int bi = red_i[0];
+        for (int w = 1; w < NW; ++w)
+          if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) { bv = red_v[w]; bi = red_i[w]; }
+        const int bad = !(bv > 0.0) || !isfinite(bv);
+        if (!bad) {
+          ustep[bi] = j;
+          piv[j] = bi;
+          const S inv = recip(PN[bi + (int64_t)jj * r]);
+          for (int c = 0; c < pb; ++c) prow[c] = c == jj ? inv : PN[bi + (int64_t)c * r] * inv;
+        }
+        s_p = bi;
+        s_bad = bad;
+      }
+      __syncthreads();
+      if (s_bad) return false;
+      const int pr = s_p;
+      const S inv = prow[jj];
+      for (int i = tid; i < r; i += NTH) {
+        if (i == pr) {
+          for (int c = 0; c < pb; ++c) PN[i + (int64_t)c * r] = prow[c];
+        } else {
+          const S f = PN[i + (int64_t)jj * r];
+          for (int c = 0; c < pb; ++c) {
+            S *e = PN + i + (int64_t)c * r;
+            *e = c == jj ? S(0.0) - f * inv : *e - f * prow[c];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // the panel's columns are final for this panel: write them back
+    for (int c = wave; c < pb; c += NW) {
+      S *Ac = A + (int64_t)(p0 + c) * lda;
+      for (int i = lane; i < r; i += 64) Ac[i] = PN[i + (int64_t)c * r];
+    }
+    // deferred update of every other column, kQC columns at a time
+    for (int q0 = 0; q0 < r; q0 += kQC) {
+      const int qc = min(kQC, r - q0);
+      for (int sidx = wave; sidx < pb; sidx += NW) {
+        const int prw = piv[p0 + sidx];
+        for (int c = lane; c < qc; c += 64) {
+          const int q = q0 + c;
+          Wt[sidx * kQC + c] = (q >= p0 && q < p0 + pb) ? S(0.0) : A[(int64_t)q * lda + prw];
+        }
+      }
+      __syncthreads();
+      const int tr = (r + 15) >> 4, tq = (qc + 15) >> 4;
+      const int ci = lane & 15, kq = lane >> 4;
+      for (int tile = wave; tile < tr * tq; tile += NW) {
+        const int ti = tile / tq, tc = tile - ti * tq;
+        Acc<S> acc;
+        const int i = ti * 16 + ci;
+        const int cc = tc * 16 + ci;
+        for (int k0 = 0; k0 < pb; k0 += 4) {
+          const int kk = k0 + kq;
+          const S av = (i < r && kk < pb) ? PN[i + (int64_t)kk * r] : S(0.0);
+          const S bv = (kk < pb && cc < qc) ? Wt[kk * kQC + cc] : S(0.0);
+          acc.mma(av, bv);
+        }
+        const int q = q0 + cc;
+        if (cc < qc && !(q >= p0 && q < p0 + pb)) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = ti * 16 + kq + 4 * v;
+            if (row < r) {
+              const int us = ustep[row];
+              S *ap = A + (int64_t)q * lda + row;
+              *ap = ((us >= p0 && us < p0 + pb) ? S(0.0) : *ap) + acc.get(v);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = tid; j < r; j += NTH) qinv[piv[j]] = j;
+  __syncthreads();
+  for (int b = wave; b < r; b += NW) {
+    const S *col = A + (int64_t)qinv[b] * lda;
+    for (int a = lane; a < r; a += 64) G[(int64_t)b * r + a] = col[piv[a]];
+  }
+  __syncthreads();
+  return true;
+}
+
 // --------------------------------------------------------------------------
 // Diagonal block and box factorization (Section 3.4 in Schur form).
 // With the box's DOFs ordered (s, r), X = P D Q where P = [[I, 0], [-T^T, I]] and
@@ -602,6 +798,19 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   }
   // In-place Gauss-Jordan inversion of A = X_rr, A(i, c) = X[(k + c) n + k + i].
   S *A = X + (int64_t)k * n + k;
+  S *G = slot + slot_G(k, r);
+  const S *Gi = A;                 // the inverse as the products below read it
+  int ldg = n;
+  if (!INLDS && r >= kGjBlockMinR) {
+    if (!gj_blocked<S, NTH>(A, n, r, G, reinterpret_cast<char *>(sh_raw),
+                            workbase + B.work_off + (int64_t)n * n)) {
+      if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned int *>(err),
+                                      (unsigned int)(err_base + first + (int)blockIdx.x));
+      return;
+    }
+    Gi = G;
+    ldg = r;
+  } else {
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();      // every thread reads s_bad below, also when r == 0
   for (int j = 0; j < r; ++j) {
@@ -698,9 +907,9 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
       __syncthreads();
     }
   }
-  S *G = slot + slot_G(k, r);
   for (int c = wave; c < r; c += NW)
     for (int a = lane; a < r; a += 64) G[(int64_t)c * r + a] = A[(int64_t)c * n + a];
+  }
   if (k == 0) return;
   S *E = slot + slot_E(k, r);
   S *F = slot + slot_F(k, r);
@@ -710,13 +919,13 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
     const S *Xi = X + (int64_t)i * n + k;
     for (int a = lane; a < r; a += 64) {
       S s = S(0.0);
-      for (int l = 0; l < r; ++l) s += A[(int64_t)l * n + a] * Xi[l];
+      for (int l = 0; l < r; ++l) s += Gi[(int64_t)l * ldg + a] * Xi[l];
       F[(int64_t)i * r + a] = s;
     }
   }
   // E = X_sr G (k x r); X_sr(i, l) = X[(k + l) n + i]
   for (int a = wave; a < r; a += NW) {
-    const S *Ga = A + (int64_t)a * n;
+    const S *Ga = Gi + (int64_t)a * ldg;
     for (int i = lane; i < k; i += 64) {
       S s = S(0.0);
       for (int l = 0; l < r; ++l) s += X[(int64_t)(k + l) * n + i] * Ga[l];
@@ -836,35 +1045,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restr
 }
 
 // ---- FP64 MFMA variants of the sweeps (boxes with n <= the MFMA class limit) --------
-// v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l & 15][l >> 4] and
-// B[l >> 4][l & 15]; element v of its result holds D[(l >> 4) + 4 v][l & 15].
 // Every 16 x 16 output tile is produced by one wave with the full K loop, so the
 // arithmetic of a column does not depend on how many columns share the launch.
-// Complex tiles use four real products per step: (ar br - ai bi, ar bi + ai br).
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-template <class S>
-struct Acc;
-template <>
-struct Acc<double> {
-  dbl4 v = {0.0, 0.0, 0.0, 0.0};
-  __device__ __forceinline__ void mma(double a, double b) {
-    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, v, 0, 0, 0);
-  }
-  __device__ __forceinline__ double get(int e) const { return v[e]; }
-};
-template <>
-struct Acc<Cplx> {
-  dbl4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
-  __device__ __forceinline__ void mma(Cplx a, Cplx b) {
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, re, 0, 0, 0);
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, re, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, im, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, im, 0, 0, 0);
-  }
-  __device__ __forceinline__ Cplx get(int e) const { return {re[e], im[e]}; }
-};
-
 // acc += A(r0 + i, kk) * Bs(kk, c0 + j) over kk in [0, K); A(i, kk) = a(i, kk) for
 // i < M (zero beyond), Bs row-major with leading dimension ldb (LDS).
 template <class S, class AF>
@@ -1265,9 +1447,10 @@ void launch_cpqr_id(bool cplx, const CompBox *boxes, int first, int count, const
   });
 }
 
-// Every box gets its own n x n workspace: the variant (LDS or global) is chosen per
-// launch from the largest box, so the smaller boxes of a launch need one too.
-size_t diag_work_elems(int n) { return (size_t)n * n; }
+// Every box gets its own n x n workspace (plus a panel of the blocked inversion): the
+// variant (LDS or global) is chosen per launch from the largest box, so the smaller
+// boxes of a launch need one too.
+size_t diag_work_elems(int n) { return (size_t)n * n + (size_t)kPB * n; }
 
 void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
                         const ProbDev *probs, const int32_t *pool, const int32_t *order_pool,
@@ -1277,17 +1460,25 @@ void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
   const size_t es = cplx ? 2 : 1;
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
-    // the whole block in LDS when n^2 scalars + the pivot column and indices fit 64 KiB
+    // The whole block in LDS when n^2 scalars + the pivot column and indices fit (such
+    // boxes always take the unblocked inversion: n < kGjBlockMinR); up to 64 KiB with
+    // 256 threads (several workgroups per CU), beyond that one 1024-thread workgroup.
     const size_t lds_in = (size_t)max_n * max_n * 8 * es + (size_t)max_n * (8 * es + 4);
-    if (lds_in <= kLdsLimit) {
-      diag_factor_nt<S, 256, true>(boxes, first, count, probs, pool, order_pool, ranks, work,
-                                   err, err_base, lds_in, st);
+    if (max_n < kGjBlockMinR && lds_in <= kMaxLds) {
+      if (lds_in <= kLdsLimit)
+        diag_factor_nt<S, 256, true>(boxes, first, count, probs, pool, order_pool, ranks, work,
+                                     err, err_base, lds_in, st);
+      else
+        diag_factor_nt<S, 1024, true>(boxes, first, count, probs, pool, order_pool, ranks,
+                                      work, err, err_base, lds_in, st);
       return;
     }
-    const size_t lds = (size_t)max_n * (8 * es + 4);
-    if (lds > kLdsLimit) throw DeviceError("k_diag_factor: box too large", hipErrorInvalidValue);
     // Few large boxes (the root): one 1024-thread workgroup each; otherwise 256 threads.
-    if (count <= 64)
+    const int nth = count <= 64 ? 1024 : 256;
+    size_t lds = (size_t)max_n * (8 * es + 4);
+    if (max_n >= kGjBlockMinR) lds = std::max(lds, gj_blocked_lds<S>(max_n, nth / 64));
+    if (lds > kMaxLds) throw DeviceError("k_diag_factor: box too large", hipErrorInvalidValue);
+    if (nth == 1024)
       diag_factor_nt<S, 1024, false>(boxes, first, count, probs, pool, order_pool, ranks, work,
                                      err, err_base, lds, st);
     else

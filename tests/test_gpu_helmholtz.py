@@ -182,3 +182,18 @@ def test_server_complex_factor_and_solves(gpu_lib):
         assert np.array_equal(B.cpu().numpy(), ref)
     hs.free()
     srv.close()
+
+
+@pytest.mark.parametrize("n", [130, 300])
+def test_helmholtz_eps_zero_is_dense_lu(gpu_lib, n):
+    # eps = 0 keeps every DOF: the root is the whole system (blocked inversion for
+    # r >= 129), so the solution is dense Gaussian elimination's.
+    rs = gpu_lib
+    g = W.star_curve(n)
+    k = W.helmholtz_wavenumber(g, 3.0)
+    _, h = _gpu_factor(rs, g, k, 0.0, 32)
+    assert h.stats()["root_size"] == n
+    b = W.gaussian_rhs(n, 2, 9, complex_valued=True)
+    x = _gpu_solve(h, b)
+    xd = dense.solve(_oracle_problem(g, k), b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-11
