@@ -164,8 +164,9 @@ def serving(rs, torch, load=0.5, nreq=1500):
     Resident: 8 log single-layer problems on random curves (N = 65536, seeds 2000-2007)
     and 8 double-layer problems (N = 16384, seeds 3000-3007), eps = 1e-9.  Requests
     pick a factor uniformly and nrhs ~ U{1..256}; arrivals are Poisson at `load` times
-    the saturated throughput measured first with a burst; two double-layer factor
-    requests (N = 32768) arrive during the run and are admitted by memory.
+    the saturated throughput measured first with a burst; two complex Helmholtz
+    combined-field factor requests (N = 32768, 10 wavelengths across) arrive during the
+    run and are admitted by memory.
     """
     import threading
     import numpy as np
@@ -237,9 +238,9 @@ def serving(rs, torch, load=0.5, nreq=1500):
     mean_nrhs = float(np.mean([n for _, n in reqs]))
     rate = load * sat / mean_nrhs                 # requests per second
     gaps = rng.exponential(1.0 / rate, nreq)
-    fgeo = [W.random_curve(32768, np.random.default_rng(5000 + i).uniform(0, 0.04, 8),
-                           np.random.default_rng(6000 + i).uniform(0, 2 * np.pi, 8))
-            for i in range(2)]
+    fgeo = [W.star_curve(32768),
+            W.random_curve(32768, np.random.default_rng(5000).uniform(0, 0.04, 8),
+                           np.random.default_rng(6000).uniform(0, 2 * np.pi, 8))]
     ftk = []
     t0 = time.perf_counter()
     tnext = t0
@@ -250,23 +251,65 @@ def serving(rs, torch, load=0.5, nreq=1500):
         submit(hi, nrhs)
         if i in (nreq // 3, 2 * nreq // 3):
             g = fgeo[len(ftk)]
-            ftk.append(srv.submit_factor("lap2d_dl", rs.build_tree(g.points, LEAF), g.points,
+            kw = W.helmholtz_wavenumber(g, 10.0)
+            ftk.append(srv.submit_factor("helm2d_cfie", rs.build_tree(g.points, LEAF), g.points,
                                          g.weights, EPS, normals=g.normals,
-                                         curvature=g.curvature, identity=-0.5))
+                                         curvature=g.curvature, identity=0.5, wavenumber=kw,
+                                         eta=kw))
     drain()
     wall = time.perf_counter() - t0
     st = srv.stats()
     extra = [srv.wait(t) for t in ftk]
+    assert all(h.is_complex for h in extra)
     for h in handles + extra:
         h.free()
     srv.close()
     return {"workload": "16 resident factors (8 x log single layer N=65536, 8 x double layer "
                         "N=16384, random curves), Poisson solve arrivals, nrhs~U{1..256}, "
-                        "2 double-layer N=32768 factor requests admitted mid-run",
+                        "2 complex Helmholtz combined-field N=32768 factor requests (10 "
+                        "wavelengths across) admitted mid-run",
             "requests": nreq, "offered_load": load, "saturated_rhs_per_s": sat,
             "rhs_per_s": st["rhs_done"] / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
             "mean_ms": st["mean_ms"], "batches": st["batches"],
             "factors_admitted": st["factors_done"]}
+
+
+def helmholtz(rs, torch):
+    """Complex128 combined-field factor of the serving configuration, on its own: star,
+    N = 32768, 10 wavelengths across, eps = 1e-9; factor time and solve rates."""
+    import numpy as np
+    import workloads as W
+    g = W.star_curve(32768)
+    k = W.helmholtz_wavenumber(g, 10.0)
+    t = rs.build_tree(g.points, LEAF)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        h = rs.factor("helm2d_cfie", t, g.points, g.weights, EPS, normals=g.normals,
+                      curvature=g.curvature, identity=0.5, wavenumber=k, eta=k)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - a) * 1e3)
+        st = h.stats()
+        if len(times) < 3:
+            h.free()
+    out = {"workload": "star N=32768, exterior combined field 1/2 I + D_k - i k S_k, "
+                       "k=%.3f (10 wavelengths across), eps=1e-9, leaf 64, 64 proxies" % k,
+           "factor_ms_median": float(np.median(times)), "root_size": st["root_size"],
+           "factor_bytes": 8 * st["factor_doubles"], "solve": {}}
+    for nrhs in (1, 64):
+        B = torch.randn(32768, nrhs, dtype=torch.complex128, device="cuda").t().contiguous().t()
+        h.solve(B)
+        torch.cuda.synchronize()
+        reps = 20
+        a = time.perf_counter()
+        for _ in range(reps):
+            h.solve(B)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3 / reps
+        out["solve"][str(nrhs)] = {"ms": ms, "rhs_per_s": nrhs / ms * 1e3}
+    h.free()
+    return out
 
 
 def main():
@@ -407,6 +450,7 @@ def main():
             / extras["level"]["solve"]["512"]["ms"]}
         out["latency_ms"] = extras["level"]["latency"]
         out["many_problems"] = many_problems(rs, torch, stream)
+        out["helmholtz"] = helmholtz(rs, torch)
         out["serving"] = serving(rs, torch)
         out["paper_context"] = {"hardware": "2.66 GHz single CPU core, Fortran (Section 6)",
                                 "table5_N65536_ellipse_dl": {"T_cm_s": 2.3, "T_lu_s": 1.8,
