@@ -64,11 +64,66 @@ __device__ __forceinline__ Cplx shfl_xor(Cplx v, int off) {
   return {__shfl_xor(v.re, off, 64), __shfl_xor(v.im, off, 64)};
 }
 
-template <class S>
-__device__ __forceinline__ S wave_sum(S v) {
+// ---- wave64 reductions: DPP steps inside each row of 16 lanes (xor 1, xor 2, half-row
+// mirror, row mirror: every lane ends with its row's total), then the four row totals
+// read with readlane and combined in a fixed order.  The result is uniform across the
+// wave and its rounding does not depend on anything but the 64 inputs.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = dpp_i32<CTRL>(__double2loint(v));
+  const int hi = dpp_i32<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
+__device__ __forceinline__ Cplx wave_sum(Cplx v) { return {wave_sum_f64(v.re), wave_sum_f64(v.im)}; }
+
+// Largest value over the wave with its key; ties (and NaN-free equal values) go to the
+// smallest key.  `val` carries a payload chosen with the winner.  Uniform result.
+struct ArgMax {
+  double v;
+  int key, val;
+};
+__device__ __forceinline__ void argmax_merge(ArgMax &a, double ov, int ok, int oval) {
+  if (ov > a.v || (ov == a.v && ok < a.key)) { a.v = ov; a.key = ok; a.val = oval; }
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(ArgMax &a) {
+  const double ov = dpp_f64<CTRL>(a.v);
+  const int ok = dpp_i32<CTRL>(a.key);
+  const int oval = dpp_i32<CTRL>(a.val);
+  argmax_merge(a, ov, ok, oval);
+}
+__device__ __forceinline__ ArgMax wave_argmax(double v, int key, int val) {
+  ArgMax a{v, key, val};
+  argmax_step<kDppXor1>(a);
+  argmax_step<kDppXor2>(a);
+  argmax_step<kDppHalfMirror>(a);
+  argmax_step<kDppMirror>(a);
+  ArgMax r{readlane_f64(a.v, 0), __builtin_amdgcn_readlane(a.key, 0),
+           __builtin_amdgcn_readlane(a.val, 0)};
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += shfl_xor(v, off);
-  return v;
+  for (int row = 16; row < 64; row += 16)
+    argmax_merge(r, readlane_f64(a.v, row), __builtin_amdgcn_readlane(a.key, row),
+                 __builtin_amdgcn_readlane(a.val, row));
+  return r;
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -242,6 +297,105 @@ __device__ double block_max(double v, double *red) {
 //   rows [2nn+np, 2nn+2np)  proxies as sources        (K(J, Gamma) W_Gamma)^T
 //   rows m-2, m-1 (kernels with a logarithmic part): total charge and constant field,
 //                           scaled to the largest proxy entry.
+// Entry (i, j) of M_B for the rows i < 2 nn + 2 np (the two log rows are separate).
+template <class S>
+__device__ __forceinline__ S comp_entry(const ProbDev &P, const CompBox &B, const int32_t *J,
+                                        const int32_t *N, const double *sh_u, double wG, int i,
+                                        int j) {
+  const int nn = B.nn, npx = P.npx;
+  const int g = J[j];
+  double xs[3], ns[3];
+  load_pt(P, g, xs);
+  if (i < nn) {
+    double xq[3];
+    load_nrm(P, g, ns);
+    load_pt(P, N[i], xq);
+    return kernel_val<S>(P, xq, xs, ns) * P.w[g];
+  } else if (i < 2 * nn) {
+    const int q = N[i - nn];
+    double xq[3], nq[3];
+    load_pt(P, q, xq);
+    load_nrm(P, q, nq);
+    return kernel_val<S>(P, xs, xq, nq) * P.w[q];
+  } else if (i < 2 * nn + npx) {
+    const double *u = sh_u + 3 * (i - 2 * nn);
+    double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
+    load_nrm(P, g, ns);
+    return kernel_val<S>(P, y, xs, ns) * P.w[g];
+  } else {
+    const double *u = sh_u + 3 * (i - 2 * nn - npx);
+    double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
+    return kernel_val<S>(P, xs, y, u) * wG;
+  }
+}
+
+// The same entry with the box's active points (index j) and near points (index i or
+// i - nn) staged in LDS as structure of arrays: x[a][idx], nrm[a][idx], w[idx].
+struct StagedPts {
+  const double *x[3], *nrm[3], *w;
+  __device__ __forceinline__ void load(int dim, int idx, double *p, double *nv) const {
+    p[0] = x[0][idx];
+    p[1] = x[1][idx];
+    p[2] = dim == 3 ? x[2][idx] : 0.0;
+    if (nrm[0]) {
+      nv[0] = nrm[0][idx];
+      nv[1] = nrm[1][idx];
+      nv[2] = dim == 3 ? nrm[2][idx] : 0.0;
+    } else {
+      nv[0] = nv[1] = nv[2] = 0.0;
+    }
+  }
+};
+
+template <class S>
+__device__ __forceinline__ S comp_entry_staged(const ProbDev &P, const CompBox &B,
+                                               const StagedPts &Jp, const StagedPts &Np,
+                                               const double *sh_u, double wG, int i, int j) {
+  const int nn = B.nn, npx = P.npx, dim = P.dim;
+  double xs[3], ns[3];
+  Jp.load(dim, j, xs, ns);
+  if (i < nn) {
+    double xq[3], nq[3];
+    Np.load(dim, i, xq, nq);
+    return kernel_val<S>(P, xq, xs, ns) * Jp.w[j];
+  } else if (i < 2 * nn) {
+    double xq[3], nq[3];
+    Np.load(dim, i - nn, xq, nq);
+    return kernel_val<S>(P, xs, xq, nq) * Np.w[i - nn];
+  } else if (i < 2 * nn + npx) {
+    const double *u = sh_u + 3 * (i - 2 * nn);
+    double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
+    return kernel_val<S>(P, y, xs, ns) * Jp.w[j];
+  } else {
+    const double *u = sh_u + 3 * (i - 2 * nn - npx);
+    double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
+    return kernel_val<S>(P, xs, y, u) * wG;
+  }
+}
+
+// Copies the points of idx[0..cnt) into LDS arrays at `base` (7 cnt doubles: x, y, z,
+// three normal components (zero without normals), weight); returns the view.
+__device__ __forceinline__ StagedPts stage_points(const ProbDev &P, const int32_t *idx, int cnt,
+                                                  double *base, int nth) {
+  StagedPts v;
+  for (int a = 0; a < 3; ++a) v.x[a] = base + a * cnt;
+  for (int a = 0; a < 3; ++a) v.nrm[a] = P.nrm[0] ? base + (3 + a) * cnt : nullptr;
+  v.w = base + 6 * cnt;
+  for (int e = threadIdx.x; e < cnt; e += nth) {
+    const int g = idx[e];
+    base[e] = P.x[0][g];
+    base[cnt + e] = P.x[1][g];
+    base[2 * cnt + e] = P.dim == 3 ? P.x[2][g] : 0.0;
+    if (P.nrm[0]) {
+      base[3 * cnt + e] = P.nrm[0][g];
+      base[4 * cnt + e] = P.nrm[1][g];
+      base[5 * cnt + e] = P.dim == 3 ? P.nrm[2][g] : 0.0;
+    }
+    base[6 * cnt + e] = P.w[g];
+  }
+  return v;
+}
+
 template <class S>
 __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict__ boxes,
                                                        int first,
@@ -267,33 +421,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict
   const int64_t total = (int64_t)rows * n;
   for (int64_t e = threadIdx.x; e < total; e += kThreads) {
     const int j = (int)(e / rows), i = (int)(e - (int64_t)j * rows);
-    const int g = J[j];
-    double xs[3], ns[3];
-    S v;
-    load_pt(P, g, xs);
-    if (i < nn) {
-      double xq[3];
-      load_nrm(P, g, ns);
-      load_pt(P, N[i], xq);
-      v = kernel_val<S>(P, xq, xs, ns) * P.w[g];
-    } else if (i < 2 * nn) {
-      const int q = N[i - nn];
-      double xq[3], nq[3];
-      load_pt(P, q, xq);
-      load_nrm(P, q, nq);
-      v = kernel_val<S>(P, xs, xq, nq) * P.w[q];
-    } else if (i < 2 * nn + npx) {
-      const double *u = sh_u + 3 * (i - 2 * nn);
-      double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
-      load_nrm(P, g, ns);
-      v = kernel_val<S>(P, y, xs, ns) * P.w[g];
-      pmax = fmax(pmax, mag(v));
-    } else {
-      const double *u = sh_u + 3 * (i - 2 * nn - npx);
-      double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1], B.cen[2] + B.rho * u[2]};
-      v = kernel_val<S>(P, xs, y, u) * wG;
-      pmax = fmax(pmax, mag(v));
-    }
+    const S v = comp_entry<S>(P, B, J, N, sh_u, wG, i, j);
+    if (i >= 2 * nn) pmax = fmax(pmax, mag(v));
     M[(int64_t)j * m + i] = v;
   }
   if (P.log_kernel) {
@@ -303,6 +432,248 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict
       M[(int64_t)j * m + rows + 1] = S(pmax);
     }
   }
+}
+
+
+// --------------------------------------------------------------------------
+// Fused compression of small boxes (real data, n <= 16 CPW, m <= 64 RT): M_B is evaluated
+// into registers and factored there by column-pivoted Householder QR with the same rules
+// as k_cpqr_id (largest recomputed norm, ties to the lowest column, stop at
+// |R_jj| <= eps |R_00|).  With NW = NTH / 64 waves, wave w holds columns c = w + NW q
+// (q < CPW), lane l rows l + 64 t (t < RT); a column's reductions stay inside its wave,
+// so a pivot step needs two workgroup barriers (reflector ready, norms ready) and
+// touches no global memory.  Columns are not moved: piv[j] is the column of pivot step
+// j.  The first k rows of R go to the box's scratch (k x n) for T = R11^{-1} R12.  The
+// arithmetic of a box does not depend on NTH, RT or CPW (a column's sums run over its
+// rows in the same lanes and order; rows and columns beyond the box are zeros).
+template <int NW>
+__device__ __forceinline__ double block_max_w(double v, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_max(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < NW; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+template <int NTH, int RT, int CPW>
+__global__ __launch_bounds__(NTH) void k_compress_fused(
+    const CompBox *__restrict__ boxes, int first, const ProbDev *__restrict__ probs,
+    const int32_t *__restrict__ pool, double *__restrict__ Rarena,
+    int32_t *__restrict__ order_pool, int32_t *__restrict__ ranks) {
+  constexpr int NW = NTH / 64;
+  extern __shared__ double smem[];
+  __shared__ double red[NW];
+  __shared__ double s_ctau;
+  const CompBox &B = boxes[first + blockIdx.x];
+  const ProbDev &P = probs[B.prob];
+  const int n = B.n, nn = B.nn, m = B.m, npx = P.npx, dim = P.dim;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (n == 0) {
+    if (tid == 0) ranks[B.kslot] = 0;
+    return;
+  }
+  const int32_t *J = pool + B.J_off;
+  const int32_t *N = pool + B.N_off;
+  double *sh_u = smem;                                 // 3 npx
+  double *norms = sh_u + 3 * npx;                      // n
+  double *sv = norms + n;                              // m
+  double *wbuf = sv + m;                               // NW * n
+  double *tile = wbuf + NW * n;                        // NW * m (assembly staging)
+  double *pts = tile + NW * m;                         // 7 (n + nn): staged points
+  int *piv = reinterpret_cast<int *>(pts + 7 * (n + nn));   // n
+  int *rk = piv + n;                                   // n
+  int *done = rk + n;                                  // n
+
+  // ---- assembly, NW columns at a time through LDS
+  for (int p = tid; p < npx; p += NTH) proxy_unit(dim, p, npx, sh_u + 3 * p);
+  const StagedPts Jp = stage_points(P, J, n, pts, NTH);
+  const StagedPts Np = stage_points(P, N, nn, pts + 7 * n, NTH);
+  double wmax = 0.0;
+  for (int j = tid; j < n; j += NTH) wmax = fmax(wmax, P.w[J[j]]);
+  wmax = block_max_w<NW>(wmax, red);      // barrier: proxy vectors and points visible
+  const double wG = dim == 2 ? 2.0 * kPi * B.rho / npx : 4.0 * kPi * B.rho * B.rho / npx;
+  const int rows = 2 * nn + 2 * npx;
+  double pmax = 0.0;
+  double val[CPW][RT];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c0 = NW * q;
+    const int cols = min(NW, n - c0);
+    if (cols > 0) {
+      for (int e = tid; e < cols * rows; e += NTH) {
+        const int cc = e / rows, i = e - cc * rows;
+        const double v = comp_entry_staged<double>(P, B, Jp, Np, sh_u, wG, i, c0 + cc);
+        if (i >= 2 * nn) pmax = fmax(pmax, fabs(v));
+        tile[cc * m + i] = v;
+      }
+    }
+    __syncthreads();
+    const int c = wave + NW * q;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      val[q][t] = (c < n && i < rows) ? tile[wave * m + i] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (P.log_kernel) {
+    pmax = block_max_w<NW>(pmax, red);
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const int c = wave + NW * q;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int i = lane + 64 * t;
+        if (c < n && i == rows) val[q][t] = pmax * P.w[J[c]] / wmax;
+        if (c < n && i == rows + 1) val[q][t] = pmax;
+      }
+    }
+  }
+
+  // ---- column-pivoted QR in registers
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = wave + NW * q;
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) s += val[q][t] * val[q][t];
+    s = wave_sum(s);
+    if (lane == 0 && c < n) norms[c] = sqrt(s);
+  }
+  for (int c = tid; c < n; c += NTH) done[c] = 0;
+  __syncthreads();
+  const double eps = P.eps;
+  const int kmax = min(m, n);
+  int k = kmax;
+  double r00 = 0.0;
+  unsigned mine_done = 0;
+  for (int j = 0; j < kmax; ++j) {
+    double lbest = -1.0;
+    int lbc = INT_MAX;
+    for (int c = lane; c < n; c += 64) {
+      if (done[c]) continue;
+      const double v = norms[c];
+      if (v > lbest || (v == lbest && c < lbc)) { lbest = v; lbc = c; }
+    }
+    const ArgMax am = wave_argmax(lbest, lbc, lbc);
+    const double best = am.v;
+    const int bc = am.key;
+    if (j == 0) r00 = best;
+    if (best == 0.0 || best <= eps * r00) { k = j; break; }
+    const int p = bc, pw = p & (NW - 1), pq = p / NW;
+    if (wave == pw) {   // reflector of column p, rows j..m-1
+      double s = 0.0, mine = 0.0;
+#pragma unroll
+      for (int q = 0; q < CPW; ++q)
+        if (q == pq)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int i = lane + 64 * t;
+            if (i >= j) s += val[q][t] * val[q][t];
+            if (t == (j >> 6)) mine = val[q][t];
+          }
+      s = wave_sum(s);
+      const double alpha = sqrt(s);
+      const double x0 = __shfl(mine, j & 63, 64);
+      const double beta = x0 >= 0.0 ? -alpha : alpha;
+      const double scale = 1.0 / (x0 - beta);
+#pragma unroll
+      for (int q = 0; q < CPW; ++q)
+        if (q == pq)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int i = lane + 64 * t;
+            if (i > j && i < m) {
+              val[q][t] *= scale;
+              sv[i] = val[q][t];
+            } else if (i == j) {
+              val[q][t] = beta;
+              sv[j] = 1.0;
+            }
+          }
+      mine_done |= 1u << pq;
+      if (lane == 0) s_ctau = (beta - x0) / beta;
+    }
+    __syncthreads();
+    // every wave has finished this step's pivot search: the pivot can be marked
+    if (tid == 0) {
+      done[p] = 1;
+      piv[j] = p;
+    }
+    const double ctau = s_ctau;
+    double vi[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      vi[t] = (i >= j && i < m) ? sv[i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const int c = wave + NW * q;
+      if (c < n && !((mine_done >> q) & 1u)) {
+        double dot = 0.0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) dot += vi[t] * val[q][t];
+        dot = wave_sum(dot) * ctau;
+        double nr = 0.0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = lane + 64 * t;
+          const double nv = val[q][t] - dot * vi[t];
+          val[q][t] = nv;
+          if (i > j) nr += nv * nv;
+        }
+        nr = wave_sum(nr);
+        if (lane == 0) norms[c] = sqrt(nr);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- R rows < k to the box scratch (k x n, column c at c k), then T = R11^{-1} R12
+  double *R = Rarena + B.M_off;
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = wave + NW * q;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      if (c < n && i < k) R[(int64_t)c * k + i] = val[q][t];
+    }
+  }
+  __syncthreads();
+  int32_t *order = order_pool + B.order_off;
+  for (int c = tid; c < n; c += NTH) {
+    int r = 0;
+    if (done[c]) {
+      for (int b = 0; b < k; ++b) r += piv[b] < c;
+      order[r] = c;
+    } else {
+      for (int c2 = 0; c2 < c; ++c2) r += !done[c2];
+      order[k + r] = c;
+    }
+    rk[c] = r;
+  }
+  __syncthreads();
+  double *T = B.T;
+  double *buf = wbuf + wave * n;
+  for (int c = wave; c < n; c += NW) {
+    if (done[c]) continue;
+    const double *col = R + (int64_t)c * k;
+    for (int i = lane; i < k; i += 64) buf[i] = col[i];
+    for (int i = k - 1; i >= 0; --i) {
+      const double *ri = R + (int64_t)piv[i] * k;
+      const double xi = buf[i] / ri[i];
+      for (int l = lane; l < i; l += 64) buf[l] -= xi * ri[l];
+      if (lane == 0) buf[i] = xi;
+    }
+    double *Tc = T + (int64_t)k * rk[c];
+    for (int i = lane; i < k; i += 64) Tc[rk[piv[i]]] = buf[i];
+  }
+  if (tid == 0) ranks[B.kslot] = k;
 }
 
 // --------------------------------------------------------------------------
@@ -369,14 +740,8 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
         const int pc = perm[c];
         if (v > best || (v == best && pc < bperm)) { best = v; bperm = pc; bc = c; }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int op = __shfl_xor(bperm, off, 64);
-        const int oc = __shfl_xor(bc, off, 64);
-        if (ob > best || (ob == best && op < bperm)) { best = ob; bperm = op; bc = oc; }
-      }
-      if (lane == 0) { s_best = best; s_p = bc; }
+      const ArgMax a = wave_argmax(best, bperm, bc);
+      if (lane == 0) { s_best = a.v; s_p = a.val; }
     }
     __syncthreads();
     const double best = s_best;
@@ -572,7 +937,7 @@ template <class S, int NTH>
 __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
                            char *lds, S *__restrict__ pn_work) {
   constexpr int NW = NTH / 64;
-  __shared__ int s_p, s_bad;
+  static_assert(NW <= 64, "one lane per wave in the combine");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool pn_lds = (size_t)r * kPB * sizeof(S) <= gj_panel_lds_max<S>();
   char *p = lds;
@@ -601,49 +966,44 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
     __syncthreads();
     for (int jj = 0; jj < pb; ++jj) {
       const int j = p0 + jj;
-      double best = -1.0;
-      int brow = INT_MAX;
+      double lb = -1.0;
+      int li = INT_MAX;
       for (int i = tid; i < r; i += NTH) {
         if (ustep[i] >= 0) continue;
         const double v = mag(PN[i + (int64_t)jj * r]);
-        if (v > best || (v == best && i < brow)) { best = v; brow = i; }
+        if (v > lb || (v == lb && i < li)) { lb = v; li = i; }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int orow = __shfl_xor(brow, off, 64);
-        if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
-      }
-      if (lane == 0) { red_v[wave] = best; red_i[wave] = brow; }
+      const ArgMax am = wave_argmax(lb, li, li);
+      if (lane == 0) { red_v[wave] = am.v; red_i[wave] = am.key; }
       __syncthreads();
-      if (tid == 0) {
-        double bv = red_v[0];
-        int bi = red_i[0];
-        for (int w = 1; w < NW; ++w)
-          if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) { bv = red_v[w]; bi = red_i[w]; }
-        const int bad = !(bv > 0.0) || !isfinite(bv);
-        if (!bad) {
-          ustep[bi] = j;
-          piv[j] = bi;
-          const S inv = recip(PN[bi + (int64_t)jj * r]);
-          for (int c = 0; c < pb; ++c) prow[c] = c == jj ? inv : PN[bi + (int64_t)c * r] * inv;
+      // every wave combines the per-wave winners (uniform result, no broadcast needed)
+      const ArgMax g = wave_argmax(lane < NW ? red_v[lane] : -1.0, lane < NW ? red_i[lane] : INT_MAX, 0);
+      if (!(g.v > 0.0) || !isfinite(g.v)) return false;
+      const int pr = g.key;
+      if (wave == 0) {     // scaled pivot row (old values) into LDS, lanes in parallel
+        const S inv = recip(PN[pr + (int64_t)jj * r]);
+        if (lane < pb) prow[lane] = lane == jj ? inv : PN[pr + (int64_t)lane * r] * inv;
+        if (lane == 0) {
+          ustep[pr] = j;
+          piv[j] = pr;
         }
-        s_p = bi;
-        s_bad = bad;
       }
       __syncthreads();
-      if (s_bad) return false;
-      const int pr = s_p;
       const S inv = prow[jj];
       for (int i = tid; i < r; i += NTH) {
+        S *row = PN + i;
         if (i == pr) {
-          for (int c = 0; c < pb; ++c) PN[i + (int64_t)c * r] = prow[c];
+#pragma unroll
+          for (int c = 0; c < kPB; ++c)
+            if (c < pb) row[(int64_t)c * r] = prow[c];
         } else {
-          const S f = PN[i + (int64_t)jj * r];
-          for (int c = 0; c < pb; ++c) {
-            S *e = PN + i + (int64_t)c * r;
-            *e = c == jj ? S(0.0) - f * inv : *e - f * prow[c];
-          }
+          const S f = row[(int64_t)jj * r];
+          S v[kPB];
+#pragma unroll
+          for (int c = 0; c < kPB; ++c) v[c] = c < pb ? row[(int64_t)c * r] : S(0.0);
+#pragma unroll
+          for (int c = 0; c < kPB; ++c)
+            if (c < pb) row[(int64_t)c * r] = c == jj ? S(0.0) - f * inv : v[c] - f * prow[c];
         }
       }
       __syncthreads();
@@ -815,19 +1175,16 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   __syncthreads();      // every thread reads s_bad below, also when r == 0
   for (int j = 0; j < r; ++j) {
     if (wave == 0) {
-      double best = -1.0;
-      int brow = INT_MAX;
+      double lbest = -1.0;
+      int lrow = INT_MAX;
       const S *Aj = A + (int64_t)j * n;
       for (int i = j + lane; i < r; i += 64) {
         const double v = mag(Aj[i]);
-        if (v > best || (v == best && i < brow)) { best = v; brow = i; }
+        if (v > lbest || (v == lbest && i < lrow)) { lbest = v; lrow = i; }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int orow = __shfl_xor(brow, off, 64);
-        if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
-      }
+      const ArgMax am = wave_argmax(lbest, lrow, lrow);
+      const double best = am.v;
+      const int brow = am.key;
       if (lane == 0) {
         s_prow = brow;
         ipiv[j] = brow;
@@ -1419,6 +1776,51 @@ void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, cons
                        reinterpret_cast<S *>(Marena));
   });
   check_launch("k_assemble");
+}
+
+bool fused_class(bool cplx, int n, int m) { return !cplx && n <= kFusedMaxN && m <= kFusedMaxM; }
+
+size_t fused_lds_bytes(int nth, int max_n, int max_m, int max_npx) {
+  const int nw = nth / 64;
+  const size_t max_nn = (size_t)max_m / 2;       // m >= 2 nn
+  return sizeof(double) * ((size_t)3 * max_npx + max_n + max_m + (size_t)nw * max_n +
+                           (size_t)nw * max_m + 7 * ((size_t)max_n + max_nn)) +
+         sizeof(int) * (size_t)3 * max_n;
+}
+
+template <int NTH, int RT, int CPW>
+void fused_variant(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                   const int32_t *pool, double *Rarena, int32_t *order_pool, int32_t *ranks,
+                   int max_n, int max_m, int max_npx, hipStream_t st) {
+  static_assert(CPW <= 32, "column mask");
+  if (max_n > (NTH / 64) * CPW || max_m > 64 * RT)
+    throw DeviceError("k_compress_fused: variant too small", hipErrorInvalidValue);
+  const size_t lds = fused_lds_bytes(NTH, max_n, max_m, max_npx);
+  if (lds > kMaxLds) throw DeviceError("k_compress_fused: LDS", hipErrorInvalidValue);
+  auto kern = k_compress_fused<NTH, RT, CPW>;
+  if (lds > 64 * 1024)
+    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool, Rarena,
+                     order_pool, ranks);
+  check_launch("k_compress_fused");
+}
+
+void launch_compress_fused(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                           const int32_t *pool, double *Rarena, int32_t *order_pool,
+                           int32_t *ranks, int max_n, int max_m, int max_npx, hipStream_t st) {
+  if (count <= 0) return;
+  if (max_n > kFusedMaxN || max_m > kFusedMaxM)
+    throw DeviceError("k_compress_fused: box outside the fused class", hipErrorInvalidValue);
+  if (max_n <= 48 && max_m <= 320)
+    fused_variant<1024, 5, 3>(boxes, first, count, probs, pool, Rarena, order_pool, ranks, max_n,
+                              max_m, max_npx, st);
+  else if (max_n <= 64 && max_m <= 448)
+    fused_variant<512, 7, 8>(boxes, first, count, probs, pool, Rarena, order_pool, ranks, max_n,
+                             max_m, max_npx, st);
+  else
+    fused_variant<512, 8, 10>(boxes, first, count, probs, pool, Rarena, order_pool, ranks, max_n,
+                              max_m, max_npx, st);
 }
 
 size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m) {

@@ -89,6 +89,13 @@ Work work_id(int m, int n, int k, bool cplx) {
   return w;
 }
 
+Work work_fused(int m, int n, int k) {
+  Work w = work_id(m, n, k, false);
+  w.entries = (double)m * n;
+  w.bytes = 8.0 * ((double)k * n + (double)k * (n - k)) + 4.0 * n;
+  return w;
+}
+
 Work work_factor(int n, int k, bool cplx) {
   const double r = n - k, kk = k, nn = n;
   Work w;

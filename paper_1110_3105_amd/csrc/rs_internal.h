@@ -125,6 +125,15 @@ void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
                         const int32_t *ranks, double *work, int32_t *err, int err_base,
                         int max_n, hipStream_t st);
 size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m);
+// Small real boxes (n <= kFusedMaxN, m <= kFusedMaxM) are assembled and compressed by one
+// fused kernel with the block held in registers; their M_off region holds n x n scalars
+// (the first k rows of R).  The class depends on the box alone.
+constexpr int kFusedMaxN = 80;
+constexpr int kFusedMaxM = 512;
+bool fused_class(bool cplx, int n, int m);
+void launch_compress_fused(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                           const int32_t *pool, double *Rarena, int32_t *order_pool,
+                           int32_t *ranks, int max_n, int max_m, int max_npx, hipStream_t st);
 // Global workspace scalars reserved for a box of n DOFs in k_diag_factor.
 size_t diag_work_elems(int n);
 void launch_permute_in(bool cplx, const double *B, int64_t ldb, double *W, const int64_t *perm,

@@ -369,10 +369,38 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         for (auto &v : nr) near_all[idx++] = std::move(v);
       }
     }
+    // boxes of the fused (register-resident) compression class first, so that each
+    // class is one contiguous range of the launch
+    int nf = 0;
+    {
+      std::vector<char> fz(cnt);
+      for (int i = 0; i < cnt; ++i) {
+        const ProbState &P = *items[i].ps;
+        const int n = (int)P.J[items[i].box].size();
+        const int m = 2 * (int)near_all[i].size() + 2 * P.npx + (P.log_kernel ? 2 : 0);
+        fz[i] = fused_class(cplx, n, m) ? 1 : 0;
+        nf += fz[i];
+      }
+      if (nf > 0 && nf < cnt) {
+        std::vector<StepBox> it2;
+        std::vector<std::vector<int32_t>> nr2;
+        it2.reserve(cnt);
+        nr2.reserve(cnt);
+        for (int pass = 1; pass >= 0; --pass)
+          for (int i = 0; i < cnt; ++i)
+            if (fz[i] == pass) {
+              it2.push_back(items[i]);
+              nr2.push_back(std::move(near_all[i]));
+            }
+        items.swap(it2);
+        near_all.swap(nr2);
+      }
+    }
     std::vector<int32_t> pool;
     std::vector<CompBox> comp(cnt);
     int64_t M_total = 0, order_total = 0, work_total = 0;
     int max_n = 0, max_m_step = 0;
+    int max_n_f = 0, max_m_f = 0, max_n_d = 0, max_m_d = 0;
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
@@ -388,7 +416,15 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       cb.N_off = (int64_t)pool.size();
       pool.insert(pool.end(), near_all[i].begin(), near_all[i].end());
       cb.M_off = M_total;
-      M_total += (int64_t)cb.m * cb.n;
+      // fused boxes keep only the first k rows of R (k <= n): n x n scalars
+      M_total += (int64_t)(i < nf ? cb.n : cb.m) * cb.n;
+      if (i < nf) {
+        max_n_f = std::max(max_n_f, cb.n);
+        max_m_f = std::max(max_m_f, cb.m);
+      } else {
+        max_n_d = std::max(max_n_d, cb.n);
+        max_m_d = std::max(max_m_d, cb.m);
+      }
       for (int a = 0; a < 3; ++a) cb.cen[a] = P.t->center[3 * b + a];
       cb.rho = P.req->k->proxy_ratio * P.t->side[b];
       cb.order_off = order_total;
@@ -414,6 +450,13 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     const CompBox *d_comp = S.comp.as<CompBox>();
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
+        if (i < nf) {
+          ProfScope ps_(RS_K_ID, st);
+          launch_compress_fused(d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
+                                S.order.as<int32_t>(), S.ranks.as<int32_t>(), comp[i].n,
+                                comp[i].m, max_npx, st);
+          continue;
+        }
         {
           ProfScope ps_(RS_K_ASSEMBLE, st);
           launch_assemble(cplx, d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
@@ -424,14 +467,22 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                        S.ranks.as<int32_t>(), comp[i].n, comp[i].m, st);
       }
     } else {
-      {
-        ProfScope ps_(RS_K_ASSEMBLE, st);
-        launch_assemble(cplx, d_comp, 0, cnt, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
-                        max_npx, st);
+      if (nf > 0) {
+        ProfScope ps_(RS_K_ID, st);
+        launch_compress_fused(d_comp, 0, nf, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
+                              S.order.as<int32_t>(), S.ranks.as<int32_t>(), max_n_f, max_m_f,
+                              max_npx, st);
       }
-      ProfScope ps_(RS_K_ID, st);
-      launch_cpqr_id(cplx, d_comp, 0, cnt, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
-                     S.ranks.as<int32_t>(), max_n, max_m_step, st);
+      if (nf < cnt) {
+        {
+          ProfScope ps_(RS_K_ASSEMBLE, st);
+          launch_assemble(cplx, d_comp, nf, cnt - nf, d_probs, S.pool.as<int32_t>(),
+                          S.M.as<double>(), max_npx, st);
+        }
+        ProfScope ps_(RS_K_ID, st);
+        launch_cpqr_id(cplx, d_comp, nf, cnt - nf, d_probs, S.M.as<double>(),
+                       S.order.as<int32_t>(), S.ranks.as<int32_t>(), max_n_d, max_m_d, st);
+      }
     }
     std::vector<int32_t> ranks(cnt), order(order_total);
     RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), S.ranks.p, cnt * sizeof(int32_t),
@@ -458,8 +509,12 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       const int b = items[i].box;
       const CompBox &cb = comp[i];
       const int k = ranks[i];
-      w_asm += work_assemble(cb.m, cb.n, cplx);
-      w_id += work_id(cb.m, cb.n, k, cplx);
+      if (i < nf) {
+        w_id += work_fused(cb.m, cb.n, k);
+      } else {
+        w_asm += work_assemble(cb.m, cb.n, cplx);
+        w_id += work_id(cb.m, cb.n, k, cplx);
+      }
       w_fac += work_factor(cb.n, k, cplx);
       const std::vector<int32_t> &J = P.J[b];
       const int32_t *ord = order.data() + cb.order_off;

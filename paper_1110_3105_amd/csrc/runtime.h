@@ -151,6 +151,9 @@ class ProfScope {
 // data a multiply-add counts 8 real flops and an entry 16 bytes.
 Work work_assemble(int m, int n, bool cplx);
 Work work_id(int m, int n, int k, bool cplx);
+// Fused assembly + ID of a real box: the ID's flops, m n kernel entries, and the bytes of
+// its outputs (R rows, T, skeleton order); the block itself never leaves the chip.
+Work work_fused(int m, int n, int k);
 Work work_factor(int n, int k, bool cplx);
 Work work_sweep_up(int k, int r, int nrhs, bool cplx);
 Work work_sweep_down(int k, int r, int nrhs, bool cplx);
