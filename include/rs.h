@@ -168,6 +168,44 @@ rs_status rs_factor_batched(int32_t count, const rs_kernel *kernels, const rs_tr
 rs_status rs_solve_batched(int32_t count, const rs_handle *h, void *const *B,
                            const int64_t *ldb, const int32_t *nrhs, const rs_options *opts);
 
+/* --------------------------------------------- captured solves (HIP graphs) ---- */
+
+/* A solve plan: the launches of rs_solve_batched for fixed requests (handles h[i],
+ * device blocks B[i] with leading dimension ldb[i] and nrhs[i] >= 1 columns) captured
+ * once into a HIP graph, with a workspace and launch tables of its own.  Each
+ * rs_plan_launch replays the graph on `stream`, solving the current contents of the
+ * same B blocks in place; results are bitwise identical to rs_solve_batched and
+ * rs_solve.  For callers that solve into fixed buffers in a loop (launch overhead of
+ * the per-level sweeps paid once).  The handles stay busy (rs_free returns RS_EBUSY)
+ * until rs_plan_free.  Replays on one plan must not overlap (they share the plan's
+ * workspace).  Errors: RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
+typedef struct rs_plan_s *rs_plan;
+rs_status rs_plan_create(int32_t count, const rs_handle *h, void *const *B, const int64_t *ldb,
+                         const int32_t *nrhs, rs_plan *out);
+rs_status rs_plan_launch(rs_plan p, void *stream);
+/* Waits for the device, then frees the plan; RS_OK for NULL. */
+rs_status rs_plan_free(rs_plan p);
+
+/* ----------------------------------------------------------- autotuner ---- */
+
+/* Times every valid tile width of the solve sweeps (MFMA class: 16, 32, 64 right-hand
+ * sides per workgroup; VALU class: 1, 4, 16, 32) on handle h's own levels for each
+ * nrhs in nrhs_list[count], reps timed repetitions each, and records the fastest width
+ * per bucket -- (class, real/complex, ceil(log2 nrhs), largest box of the launch in
+ * steps of 32) -- in a process-wide table that every later solve consults.  A width
+ * changes the work distribution only: results are bitwise the same with any table.
+ * Synchronous on `stream`.  Errors: RS_EINVAL, RS_EDEVICE. */
+rs_status rs_autotune(rs_handle h, const int32_t *nrhs_list, int32_t count, int32_t reps,
+                      void *stream);
+/* Copies the table (bucket keys and widths, cap entries at most); *count receives its
+ * size.  Key bits: 0 MFMA class, 1 complex, 2..7 ceil(log2 nrhs), 8..15 box bucket. */
+rs_status rs_tune_entries(uint32_t *keys, int32_t *widths, int32_t cap, int32_t *count);
+rs_status rs_tune_clear(void);
+/* Text file of "key width" lines; load merges into the current table and rejects
+ * widths that do not exist.  Errors: RS_EINVAL (unreadable, malformed). */
+rs_status rs_tune_save(const char *path);
+rs_status rs_tune_load(const char *path);
+
 /* Releases a handle.  Waits for the library's own queued work on it; returns
  * RS_OK for NULL. */
 rs_status rs_free(rs_handle h);

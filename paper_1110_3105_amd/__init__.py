@@ -11,7 +11,9 @@ from .binding import (  # noqa: F401
     rs_profile_enable, rs_profile_read, rs_profile_reset, factor_batched, solve_batched,
     rs_factor_batched, rs_solve_batched, Server, rs_server_create, rs_server_destroy,
     rs_server_poll, rs_server_query, rs_server_release, rs_server_reset_stats,
-    rs_server_submit_factor, rs_server_submit_solve,
+    rs_server_submit_factor, rs_server_submit_solve, Plan, autotune, tune_entries, tune_clear,
+    tune_save, tune_load, rs_plan_create, rs_plan_launch, rs_plan_free, rs_autotune,
+    rs_tune_entries, rs_tune_clear, rs_tune_save, rs_tune_load,
 )
 
 

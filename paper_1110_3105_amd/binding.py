@@ -37,7 +37,9 @@ EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "
             "rs_profile_enable", "rs_profile_reset", "rs_profile_read", "rs_factor_batched",
             "rs_solve_batched", "rs_server_create", "rs_server_submit_factor",
             "rs_server_submit_solve", "rs_server_poll", "rs_server_release", "rs_server_query",
-            "rs_server_reset_stats", "rs_server_destroy"]
+            "rs_server_reset_stats", "rs_server_destroy", "rs_plan_create", "rs_plan_launch",
+            "rs_plan_free", "rs_autotune", "rs_tune_entries", "rs_tune_clear", "rs_tune_save",
+            "rs_tune_load"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -109,6 +111,15 @@ _sig = {
     "rs_server_query": (C.c_int, [_P, C.POINTER(rs_server_stats)]),
     "rs_server_reset_stats": (C.c_int, [_P]),
     "rs_server_destroy": (None, [_P]),
+    "rs_plan_create": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(C.c_void_p), _PI64, _PI32,
+                                 C.POINTER(_P)]),
+    "rs_plan_launch": (C.c_int, [_P, _P]),
+    "rs_plan_free": (C.c_int, [_P]),
+    "rs_autotune": (C.c_int, [_P, _PI32, C.c_int32, C.c_int32, _P]),
+    "rs_tune_entries": (C.c_int, [C.POINTER(C.c_uint32), _PI32, C.c_int32, _PI32]),
+    "rs_tune_clear": (C.c_int, []),
+    "rs_tune_save": (C.c_int, [C.c_char_p]),
+    "rs_tune_load": (C.c_int, [C.c_char_p]),
     "rs_profile_enable": (C.c_int, [C.c_int32]),
     "rs_profile_reset": (C.c_int, []),
     "rs_profile_read": (C.c_int, [C.c_int32, _PI64, _PD, _PD, _PD, _PD]),
@@ -384,6 +395,20 @@ def solve_batched(handles, blocks, stream=None):
     count = len(handles)
     if len(blocks) != count:
         raise ValueError("one block per handle")
+    ptrs, ldbs, nrhs = _block_args(handles, blocks)
+    H = (_P * count)(*[h.handle for h in handles])
+    Bp = (C.c_void_p * count)(*ptrs)
+    L = (C.c_int64 * count)(*ldbs)
+    R = (C.c_int32 * count)(*nrhs)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o = rs_options(LAUNCH["level"], _stream_ptr(stream))
+    _check(_lib.rs_solve_batched(count, H, Bp, L, R, C.byref(o)))
+
+
+def _block_args(handles, blocks):
+    """(pointers, ldb, nrhs) of column-major device blocks, checked against the handles."""
+    import torch
     ptrs, ldbs, nrhs = [], [], []
     for h, B in zip(handles, blocks):
         if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == h.dtype):
@@ -394,14 +419,80 @@ def solve_batched(handles, blocks, stream=None):
         ptrs.append(X.data_ptr())
         ldbs.append(X.stride(1) if X.shape[1] > 1 else h.n)
         nrhs.append(X.shape[1])
-    H = (_P * count)(*[h.handle for h in handles])
-    Bp = (C.c_void_p * count)(*ptrs)
-    L = (C.c_int64 * count)(*ldbs)
-    R = (C.c_int32 * count)(*nrhs)
+    return ptrs, ldbs, nrhs
+
+
+class Plan:
+    """A solve captured into a HIP graph (rs_plan_*): replaying it solves the current
+    contents of the same device blocks in place, bitwise as rs_solve_batched."""
+
+    def __init__(self, handles, blocks):
+        if len(handles) != len(blocks) or not handles:
+            raise ValueError("one block per handle, at least one")
+        ptrs, ldbs, nrhs = _block_args(handles, blocks)
+        count = len(handles)
+        H = (_P * count)(*[h.handle for h in handles])
+        Bp = (C.c_void_p * count)(*ptrs)
+        L = (C.c_int64 * count)(*ldbs)
+        R = (C.c_int32 * count)(*nrhs)
+        p = _P()
+        _check(_lib.rs_plan_create(count, H, Bp, L, R, C.byref(p)))
+        self._p = p
+        self._keep = (list(handles), list(blocks))
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(_lib.rs_plan_launch(self._p, _stream_ptr(stream)))
+
+    def free(self):
+        if getattr(self, "_p", None):
+            _check(_lib.rs_plan_free(self._p))
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def autotune(handle: "Handle", nrhs_list=(1, 16, 64, 512), reps: int = 3, stream=None):
+    """Times the sweep tile widths on the handle's levels and records the fastest per
+    bucket in the library's process-wide table (speed only; results never change)."""
+    import torch
+    lst = (C.c_int32 * len(nrhs_list))(*[int(x) for x in nrhs_list])
     if stream is None:
         stream = torch.cuda.current_stream()
-    o = rs_options(LAUNCH["level"], _stream_ptr(stream))
-    _check(_lib.rs_solve_batched(count, H, Bp, L, R, C.byref(o)))
+    _check(_lib.rs_autotune(handle.handle, lst, len(nrhs_list), int(reps), _stream_ptr(stream)))
+
+
+def tune_entries() -> dict:
+    """{bucket: width} with buckets decoded as (mfma, complex, log2 nrhs, box bucket)."""
+    cnt = C.c_int32()
+    _check(_lib.rs_tune_entries(None, None, 0, C.byref(cnt)))
+    n = cnt.value
+    keys = (C.c_uint32 * max(n, 1))()
+    widths = (C.c_int32 * max(n, 1))()
+    _check(_lib.rs_tune_entries(keys, widths, max(n, 1), C.byref(cnt)))
+    out = {}
+    for i in range(cnt.value):
+        k = keys[i]
+        out[(bool(k & 1), bool(k & 2), (k >> 2) & 63, (k >> 8) & 255)] = widths[i]
+    return out
+
+
+def tune_clear():
+    _check(_lib.rs_tune_clear())
+
+
+def tune_save(path: str):
+    _check(_lib.rs_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(_lib.rs_tune_load(path.encode()))
 
 
 class Server:

@@ -23,7 +23,7 @@ COMMON = ["-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(ROOT, "include")]
 DEVICE_SOURCES = ["kernels.hip"]
-HOST_SOURCES = ["tree.cpp", "runtime.cpp", "profile.cpp", "abi.cpp", "server.cpp"]
+HOST_SOURCES = ["tree.cpp", "runtime.cpp", "profile.cpp", "abi.cpp", "server.cpp", "tune.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -247,6 +247,99 @@ rs_status rs_solve(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream
   return rs_solve_ex(h, B, ldb, nrhs, &o);
 }
 
+rs_status rs_plan_create(int32_t count, const rs_handle *h, void *const *B, const int64_t *ldb,
+                         const int32_t *nrhs, rs_plan *out) {
+  return guarded([&]() -> rs_status {
+    if (!out) fail(RS_EINVAL, "NULL output");
+    if (count < 1) fail(RS_EINVAL, "count must be >= 1");
+    if (!h || !B || !ldb || !nrhs) fail(RS_EINVAL, "NULL argument");
+    std::vector<SolveRequest> reqs(count);
+    for (int i = 0; i < count; ++i) {
+      if (!h[i]) fail(RS_EINVAL, "NULL handle");
+      if (nrhs[i] < 1) fail(RS_EINVAL, "nrhs must be >= 1");
+      if (!B[i]) fail(RS_EINVAL, "NULL right-hand side");
+      if (ldb[i] < h[i]->n) fail(RS_EINVAL, "ldb < n");
+      reqs[i] = SolveRequest{h[i], B[i], ldb[i], nrhs[i]};
+    }
+    require_device();
+    *out = reinterpret_cast<rs_plan>(make_plan(reqs));
+    return RS_OK;
+  });
+}
+
+rs_status rs_plan_launch(rs_plan p, void *stream) {
+  return guarded([&]() -> rs_status {
+    if (!p) fail(RS_EINVAL, "NULL plan");
+    launch_plan(reinterpret_cast<SolvePlan *>(p), static_cast<hipStream_t>(stream));
+    return RS_OK;
+  });
+}
+
+rs_status rs_plan_free(rs_plan p) {
+  return guarded([&]() -> rs_status {
+    if (!p) return RS_OK;
+    RS_HIP_CHECK(hipDeviceSynchronize());
+    delete reinterpret_cast<SolvePlan *>(p);
+    return RS_OK;
+  });
+}
+
+rs_status rs_autotune(rs_handle h, const int32_t *nrhs_list, int32_t count, int32_t reps,
+                      void *stream) {
+  return guarded([&]() -> rs_status {
+    if (!h || !nrhs_list || count < 1) fail(RS_EINVAL, "NULL handle or empty nrhs list");
+    if (reps < 1) fail(RS_EINVAL, "reps must be >= 1");
+    std::vector<int> lst;
+    for (int i = 0; i < count; ++i) {
+      if (nrhs_list[i] < 1 || nrhs_list[i] > (1 << 16)) fail(RS_EINVAL, "nrhs out of range");
+      lst.push_back(nrhs_list[i]);
+    }
+    h->busy.fetch_add(1);
+    struct Dec {
+      rs_handle h;
+      ~Dec() { h->busy.fetch_sub(1); }
+    } dec{h};
+    autotune(h, lst, reps, static_cast<hipStream_t>(stream));
+    return RS_OK;
+  });
+}
+
+rs_status rs_tune_entries(uint32_t *keys, int32_t *widths, int32_t cap, int32_t *count) {
+  return guarded([&]() -> rs_status {
+    const auto e = tune_entries();
+    if (count) *count = (int32_t)e.size();
+    if ((keys || widths) && cap < (int32_t)e.size()) fail(RS_EINVAL, "buffer too small");
+    for (size_t i = 0; i < e.size(); ++i) {
+      if (keys) keys[i] = e[i].first;
+      if (widths) widths[i] = e[i].second;
+    }
+    return RS_OK;
+  });
+}
+
+rs_status rs_tune_clear(void) {
+  return guarded([&]() -> rs_status {
+    tune_clear();
+    return RS_OK;
+  });
+}
+
+rs_status rs_tune_save(const char *path) {
+  return guarded([&]() -> rs_status {
+    if (!path) fail(RS_EINVAL, "NULL path");
+    tune_save(path);
+    return RS_OK;
+  });
+}
+
+rs_status rs_tune_load(const char *path) {
+  return guarded([&]() -> rs_status {
+    if (!path) fail(RS_EINVAL, "NULL path");
+    tune_load(path);
+    return RS_OK;
+  });
+}
+
 rs_status rs_free(rs_handle h) {
   return guarded([&]() -> rs_status {
     if (!h) return RS_OK;

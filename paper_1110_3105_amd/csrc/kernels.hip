@@ -8,6 +8,11 @@
 #include <float.h>
 #include <limits.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -1636,8 +1641,11 @@ void with_scalar(bool cplx, F &&f) {
   else f(double{});
 }
 
-// VALU sweeps: LDS holds max_n x NT scalars; keep it within 64 KiB.
+// VALU sweeps: LDS holds max_n x NT scalars; keep it within 64 KiB.  A tuned choice
+// (rs_autotune) for the launch's bucket wins when it is valid.
 int pick_nt(int nrhs, int max_n, int es) {
+  const int tuned = tune_lookup(false, es, nrhs, max_n);
+  if (tuned && sweep_nt_valid(false, tuned, max_n, es)) return tuned;
   int nt = nrhs <= 1 ? 1 : nrhs <= 4 ? 4 : nrhs <= 16 ? 16 : 32;
   while (nt > 1 && (int64_t)max_n * nt * 8 * es > 65536) nt = nt == 32 ? 16 : nt == 16 ? 4 : 1;
   return nt;
@@ -1646,6 +1654,8 @@ int pick_nt(int nrhs, int max_n, int es) {
 // MFMA sweeps: NT in {16, 32, 64} columns per workgroup, LDS within 64 KiB (the class
 // limit guarantees NT = 16 fits).
 int pick_nt_mfma(int nrhs, int max_n, int es) {
+  const int tuned = tune_lookup(true, es, nrhs, max_n);
+  if (tuned && sweep_nt_valid(true, tuned, max_n, es)) return tuned;
   int nt = nrhs <= 16 ? 16 : nrhs <= 32 ? 32 : 64;
   while (nt > 16 && (int64_t)max_n * nt * 8 * es > 65536) nt /= 2;
   return nt;
@@ -1761,6 +1771,48 @@ void diag_factor_nt(const FacBox *boxes, int first, int count, const ProbDev *pr
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ tuning table
+namespace {
+std::mutex g_tune_mu;
+std::map<uint32_t, int> g_tune;   // bucket key -> tile width
+}  // namespace
+
+uint32_t tune_key(bool mfma, int es, int nrhs, int max_n) {
+  int nb = 0;
+  while ((1 << nb) < nrhs && nb < 20) ++nb;               // ceil(log2 nrhs)
+  const int sb = std::min((max_n + 31) / 32, 255);        // box size in steps of 32
+  return (uint32_t)(mfma ? 1 : 0) | (uint32_t)(es == 2 ? 2 : 0) | ((uint32_t)nb << 2) |
+         ((uint32_t)sb << 8);
+}
+
+int tune_lookup(bool mfma, int es, int nrhs, int max_n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune.empty()) return 0;
+  auto it = g_tune.find(tune_key(mfma, es, nrhs, max_n));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void tune_set(uint32_t key, int nt) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = nt;
+}
+
+std::vector<std::pair<uint32_t, int>> tune_entries() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return std::vector<std::pair<uint32_t, int>>(g_tune.begin(), g_tune.end());
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+bool sweep_nt_valid(bool mfma, int nt, int max_n, int es) {
+  const bool allowed = mfma ? (nt == 16 || nt == 32 || nt == 64)
+                            : (nt == 1 || nt == 4 || nt == 16 || nt == 32);
+  return allowed && (int64_t)max_n * nt * 8 * es <= 65536;
+}
 
 // ------------------------------------------------------------------ launchers
 
@@ -1930,11 +1982,13 @@ void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_el
 }
 
 void launch_sweep(bool cplx, bool up, const SweepBox *boxes, int first, int count, double *W,
-                  int nrhs, int max_n, hipStream_t st) {
+                  int nrhs, int max_n, hipStream_t st, int nt) {
   if (count <= 0 || nrhs <= 0) return;
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
-    switch (pick_nt(nrhs, max_n, sizeof(S) / 8)) {
+    if (nt && !sweep_nt_valid(false, nt, max_n, sizeof(S) / 8))
+      throw DeviceError("k_sweep: invalid tile width", hipErrorInvalidValue);
+    switch (nt ? nt : pick_nt(nrhs, max_n, sizeof(S) / 8)) {
       case 1: sweep_nt<S, 1>(up, boxes, first, count, W, nrhs, max_n, st); break;
       case 4: sweep_nt<S, 4>(up, boxes, first, count, W, nrhs, max_n, st); break;
       case 16: sweep_nt<S, 16>(up, boxes, first, count, W, nrhs, max_n, st); break;
@@ -1944,13 +1998,15 @@ void launch_sweep(bool cplx, bool up, const SweepBox *boxes, int first, int coun
 }
 
 void launch_sweep_mfma(bool cplx, bool up, const SweepBox *boxes, int first, int count,
-                       double *W, int nrhs, int max_n, hipStream_t st) {
+                       double *W, int nrhs, int max_n, hipStream_t st, int nt) {
   if (count <= 0 || nrhs <= 0) return;
   if (max_n > mfma_max_n(cplx))
     throw DeviceError("k_sweep_mfma: box too large", hipErrorInvalidValue);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
-    switch (pick_nt_mfma(nrhs, max_n, sizeof(S) / 8)) {
+    if (nt && !sweep_nt_valid(true, nt, max_n, sizeof(S) / 8))
+      throw DeviceError("k_sweep_mfma: invalid tile width", hipErrorInvalidValue);
+    switch (nt ? nt : pick_nt_mfma(nrhs, max_n, sizeof(S) / 8)) {
       case 16: sweep_mfma_nt<S, 16>(up, boxes, first, count, W, nrhs, max_n, st); break;
       case 32: sweep_mfma_nt<S, 32>(up, boxes, first, count, W, nrhs, max_n, st); break;
       default: sweep_mfma_nt<S, 64>(up, boxes, first, count, W, nrhs, max_n, st); break;

@@ -42,8 +42,14 @@ void drain_locked() {
 
 bool prof_on() { return g_prof_on.load(std::memory_order_relaxed); }
 
+namespace {
+thread_local int t_capture_depth = 0;
+}
+CaptureScope::CaptureScope() { ++t_capture_depth; }
+CaptureScope::~CaptureScope() { --t_capture_depth; }
+
 ProfScope::ProfScope(int family, hipStream_t st) : family_(family), st_(st) {
-  if (!prof_on()) return;
+  if (!prof_on() || t_capture_depth > 0) return;
   RS_HIP_CHECK(hipEventCreate(&start_));
   RS_HIP_CHECK(hipEventCreate(&stop_));
   RS_HIP_CHECK(hipEventRecord(start_, st_));

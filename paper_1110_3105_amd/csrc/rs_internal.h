@@ -147,12 +147,25 @@ void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_el
 constexpr int kMfmaMaxN = 512;
 constexpr int kMfmaMaxNComplex = 256;
 int mfma_max_n(bool cplx);
+// nt = 0: tile width from the tuning table, else the built-in choice; nt > 0 forces a
+// width (used by the autotuner; must be valid for the class and LDS budget).
 void launch_sweep(bool cplx, bool up, const SweepBox *boxes, int first, int count, double *W,
-                  int nrhs, int max_n, hipStream_t st);
+                  int nrhs, int max_n, hipStream_t st, int nt = 0);
 void launch_sweep_mfma(bool cplx, bool up, const SweepBox *boxes, int first, int count,
-                       double *W, int nrhs, int max_n, hipStream_t st);
+                       double *W, int nrhs, int max_n, hipStream_t st, int nt = 0);
 void launch_sweep_seg(bool cplx, bool mfma, bool up, const SweepSeg *segs, int nseg,
                       int nblocks, int max_nrhs, int max_n, hipStream_t st);
+
+// ------------------------------------------------------------------ tuning table
+// Tile widths of the sweep kernels per bucket (class, scalar size, ceil(log2 nrhs),
+// largest box in steps of 32).  Every width computes each output element with the same
+// arithmetic, so a table changes speed only, never results.
+bool sweep_nt_valid(bool mfma, int nt, int max_n, int es);
+uint32_t tune_key(bool mfma, int es, int nrhs, int max_n);
+int tune_lookup(bool mfma, int es, int nrhs, int max_n);
+void tune_set(uint32_t key, int nt);
+std::vector<std::pair<uint32_t, int>> tune_entries();
+void tune_clear();
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string &msg);

@@ -844,13 +844,30 @@ void release_host_vector(void *p) { delete static_cast<std::vector<char> *>(p); 
 
 namespace {
 
-// Requests whose handles share one scalar type.
-void solve_group(const std::vector<SolveRequest> &rq, hipStream_t st) {
-  if (rq.empty()) return;
+// Launch tables of one group's solve (requests whose handles share one scalar type):
+// permutation segments, then upward steps (finest level first), the roots, then
+// downward steps; each launch's segments are contiguous.  W is the group's workspace.
+struct SolveTables {
+  bool cplx = false;
+  int nq = 0;
+  int64_t max_elems = 0;
+  std::vector<PermSeg> perm;
+  std::vector<SweepSeg> segs;
+  std::vector<LaunchRec> launches;
+};
+
+int64_t group_workspace(const std::vector<SolveRequest> &rq) {
+  int64_t wtot = 0;
+  for (const SolveRequest &q : rq) wtot += q.h->n * (int64_t)q.nrhs;
+  return wtot * (rq.empty() || !rq[0].h->cplx ? 1 : 2);    // doubles
+}
+
+SolveTables build_tables(const std::vector<SolveRequest> &rq, double *W) {
+  SolveTables T;
   const int nq = (int)rq.size();
-  const bool cplx = rq[0].h->cplx;
-  const int es = cplx ? 2 : 1;
-  // workspace offsets
+  T.nq = nq;
+  T.cplx = rq[0].h->cplx;
+  const int es = T.cplx ? 2 : 1;
   std::vector<int64_t> woff(nq);
   int64_t wtot = 0;
   int max_levels = 0;
@@ -859,27 +876,21 @@ void solve_group(const std::vector<SolveRequest> &rq, hipStream_t st) {
     wtot += rq[i].h->n * (int64_t)rq[i].nrhs;
     max_levels = std::max(max_levels, (int)rq[i].h->levels.size());
   }
-  double *W = nullptr;
-  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)wtot * sizeof(double) * es, st));
-  // segment tables: permutations, then upward steps (finest level first), the roots,
-  // then downward steps; each launch's segments are contiguous.
-  std::vector<PermSeg> perm(nq);
-  int64_t max_elems = 0;
+  T.perm.resize(nq);
   for (int i = 0; i < nq; ++i) {
-    perm[i].B = static_cast<double *>(rq[i].B);
-    perm[i].ldb = rq[i].ldb;
-    perm[i].W = W + woff[i] * es;
-    perm[i].perm = rq[i].h->d_perm;
-    perm[i].n = rq[i].h->n;
-    perm[i].nrhs = rq[i].nrhs;
-    perm[i].pad = 0;
-    max_elems = std::max<int64_t>(max_elems, rq[i].h->n * (int64_t)rq[i].nrhs);
+    PermSeg &p = T.perm[i];
+    p.B = static_cast<double *>(rq[i].B);
+    p.ldb = rq[i].ldb;
+    p.W = W + woff[i] * es;
+    p.perm = rq[i].h->d_perm;
+    p.n = rq[i].h->n;
+    p.nrhs = rq[i].nrhs;
+    p.pad = 0;
+    T.max_elems = std::max<int64_t>(T.max_elems, rq[i].h->n * (int64_t)rq[i].nrhs);
   }
-  std::vector<SweepSeg> segs;
-  std::vector<LaunchRec> launches;
   auto add_step = [&](bool up, auto level_of) {
     for (int mfma = 1; mfma >= 0; --mfma) {
-      LaunchRec L{(int64_t)segs.size(), 0, 0, 0, 0, up, mfma == 1};
+      LaunchRec L{(int64_t)T.segs.size(), 0, 0, 0, 0, up, mfma == 1};
       for (int i = 0; i < nq; ++i) {
         const LevelRec *lv = level_of(rq[i].h);
         if (!lv || lv->sweep.empty()) continue;
@@ -893,13 +904,13 @@ void solve_group(const std::vector<SolveRequest> &rq, hipStream_t st) {
         s.nrhs = rq[i].nrhs;
         s.block0 = L.nblocks;
         s.pad = 0;
-        segs.push_back(s);
+        T.segs.push_back(s);
         L.nseg++;
         L.nblocks += s.count;
         L.max_nrhs = std::max(L.max_nrhs, s.nrhs);
         L.max_n = std::max(L.max_n, mfma ? lv->max_n_small : lv->max_n_large);
       }
-      if (L.nseg) launches.push_back(L);
+      if (L.nseg) T.launches.push_back(L);
     }
   };
   for (int t = 0; t < max_levels; ++t)
@@ -911,31 +922,52 @@ void solve_group(const std::vector<SolveRequest> &rq, hipStream_t st) {
     add_step(false, [t](rs_factor_s *h) -> const LevelRec * {
       return t < (int)h->levels.size() ? &h->levels[t] : nullptr;
     });
-  // one upload of all tables; the host copy is released by a stream callback
-  const size_t perm_bytes = perm.size() * sizeof(PermSeg);
-  const size_t seg_bytes = segs.size() * sizeof(SweepSeg);
+  return T;
+}
+
+// Packs the tables (PermSeg array, then SweepSeg array) into one host buffer.
+std::vector<char> *pack_tables(const SolveTables &T) {
+  const size_t perm_bytes = T.perm.size() * sizeof(PermSeg);
+  const size_t seg_bytes = T.segs.size() * sizeof(SweepSeg);
   auto *host = new std::vector<char>(perm_bytes + seg_bytes);
-  std::memcpy(host->data(), perm.data(), perm_bytes);
-  if (seg_bytes) std::memcpy(host->data() + perm_bytes, segs.data(), seg_bytes);
-  char *dtab = nullptr;
-  RS_HIP_CHECK(hipMallocAsync((void **)&dtab, host->size(), st));
-  RS_HIP_CHECK(hipMemcpyAsync(dtab, host->data(), host->size(), hipMemcpyHostToDevice, st));
-  RS_HIP_CHECK(hipLaunchHostFunc(st, release_host_vector, host));
+  std::memcpy(host->data(), T.perm.data(), perm_bytes);
+  if (seg_bytes) std::memcpy(host->data() + perm_bytes, T.segs.data(), seg_bytes);
+  return host;
+}
+
+// The kernel launches of a group's solve; kernels only (no copies or fills), so the
+// sequence can be captured into a graph.
+void enqueue_group(const SolveTables &T, const char *dtab, hipStream_t st) {
   const PermSeg *d_perm = reinterpret_cast<const PermSeg *>(dtab);
-  const SweepSeg *d_segs = reinterpret_cast<const SweepSeg *>(dtab + perm_bytes);
+  const SweepSeg *d_segs =
+      reinterpret_cast<const SweepSeg *>(dtab + T.perm.size() * sizeof(PermSeg));
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_seg(cplx, d_perm, nq, max_elems, true, st);
+    launch_permute_seg(T.cplx, d_perm, T.nq, T.max_elems, true, st);
   }
-  for (const LaunchRec &L : launches) {
+  for (const LaunchRec &L : T.launches) {
     ProfScope ps_(L.up ? RS_K_SWEEP_UP : RS_K_SWEEP_DOWN, st);
-    launch_sweep_seg(cplx, L.mfma, L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs,
+    launch_sweep_seg(T.cplx, L.mfma, L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs,
                      L.max_n, st);
   }
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_seg(cplx, d_perm, nq, max_elems, false, st);
+    launch_permute_seg(T.cplx, d_perm, T.nq, T.max_elems, false, st);
   }
+}
+
+void solve_group(const std::vector<SolveRequest> &rq, hipStream_t st) {
+  if (rq.empty()) return;
+  double *W = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)group_workspace(rq) * sizeof(double), st));
+  const SolveTables T = build_tables(rq, W);
+  // one upload of all tables; the host copy is released by a stream callback
+  std::vector<char> *host = pack_tables(T);
+  char *dtab = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&dtab, host->size(), st));
+  RS_HIP_CHECK(hipMemcpyAsync(dtab, host->data(), host->size(), hipMemcpyHostToDevice, st));
+  RS_HIP_CHECK(hipLaunchHostFunc(st, release_host_vector, host));
+  enqueue_group(T, dtab, st);
   RS_HIP_CHECK(hipFreeAsync(dtab, st));
   RS_HIP_CHECK(hipFreeAsync(W, st));
 }
@@ -949,5 +981,63 @@ void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st) {
   solve_group(rq[0], st);
   solve_group(rq[1], st);
 }
+
+// ---- captured solves
+SolvePlan::~SolvePlan() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  for (rs_factor_s *h : handles) h->busy.fetch_sub(1);
+}
+
+SolvePlan *make_plan(const std::vector<SolveRequest> &reqs) {
+  std::unique_ptr<SolvePlan> plan(new SolvePlan());
+  std::vector<SolveRequest> rq[2];
+  for (const SolveRequest &q : reqs) {
+    plan->handles.push_back(q.h);
+    q.h->busy.fetch_add(1);
+    if (q.nrhs > 0) rq[q.h->cplx ? 1 : 0].push_back(q);
+  }
+  // persistent workspace and tables, uploaded before capture
+  std::vector<SolveTables> tabs;
+  std::vector<char *> dtabs;
+  for (int g = 0; g < 2; ++g) {
+    if (rq[g].empty()) continue;
+    void *W = nullptr;
+    RS_HIP_CHECK(hipMalloc(&W, std::max<size_t>((size_t)group_workspace(rq[g]), 1) * sizeof(double)));
+    plan->bufs.push_back(W);
+    tabs.push_back(build_tables(rq[g], static_cast<double *>(W)));
+    std::unique_ptr<std::vector<char>> host(pack_tables(tabs.back()));
+    void *dtab = nullptr;
+    RS_HIP_CHECK(hipMalloc(&dtab, std::max<size_t>(host->size(), 1)));
+    plan->bufs.push_back(dtab);
+    RS_HIP_CHECK(hipMemcpy(dtab, host->data(), host->size(), hipMemcpyHostToDevice));
+    dtabs.push_back(static_cast<char *>(dtab));
+  }
+  hipStream_t cs = nullptr;
+  RS_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } guard{cs};
+  {
+    CaptureScope capture;              // the profiler records no events while capturing
+    RS_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      for (size_t g = 0; g < tabs.size(); ++g) enqueue_group(tabs[g], dtabs[g], cs);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(cs, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    RS_HIP_CHECK(hipStreamEndCapture(cs, &plan->graph));
+  }
+  RS_HIP_CHECK(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+  return plan.release();
+}
+
+void launch_plan(SolvePlan *p, hipStream_t st) { RS_HIP_CHECK(hipGraphLaunch(p->exec, st)); }
 
 }  // namespace rs

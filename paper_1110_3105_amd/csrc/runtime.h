@@ -107,6 +107,25 @@ struct SolveRequest {
 // depth of each handle; all roots in one launch).  Enqueued on st; asynchronous.
 void solve_many(const std::vector<SolveRequest> &reqs, hipStream_t st);
 
+// A solve captured into a HIP graph: the launches of solve_many for fixed requests
+// (handles, B buffers, nrhs), with a workspace and launch tables of its own.  Replaying
+// it solves the current contents of the same B buffers; the handles stay busy until
+// the plan is destroyed.
+struct SolvePlan {
+  std::vector<rs_factor_s *> handles;
+  std::vector<void *> bufs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~SolvePlan();
+};
+SolvePlan *make_plan(const std::vector<SolveRequest> &reqs);
+void launch_plan(SolvePlan *p, hipStream_t st);
+
+// Sweep tile-width autotuner (tune.cpp).
+void autotune(rs_factor_s *h, const std::vector<int> &nrhs_list, int reps, hipStream_t st);
+void tune_save(const char *path);
+void tune_load(const char *path);
+
 struct UserError {
   rs_status code;
   std::string what;
@@ -127,6 +146,12 @@ struct Work {
   }
 };
 bool prof_on();
+// While alive on a thread, launches issued by that thread record no profiler events
+// (stream capture: the graph holds kernel nodes only).
+struct CaptureScope {
+  CaptureScope();
+  ~CaptureScope();
+};
 void prof_enable(bool on);
 void prof_reset();
 void prof_read(int family, int64_t *launches, double *ms, double *flops, double *bytes,
