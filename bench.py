@@ -46,17 +46,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (used under rocprofv3)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the sweep tile-width autotuning done before the timed region")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
-KERNEL_OF_FAMILY = {"assemble": "k_assemble", "id": "k_cpqr_id", "factor": "k_diag_factor",
-                    "sweep_up": "k_sweep_up", "sweep_down": "k_sweep_down"}
+# kernels (rocprofv3 names, template arguments dropped) of each profiler family
+KERNELS_OF_FAMILY = {"assemble": ["k_assemble"], "id": ["k_compress_fused", "k_cpqr_id"],
+                     "factor": ["k_diag_factor"],
+                     "sweep_up": ["k_sweep_up_mfma", "k_sweep_up", "k_sweep_seg"],
+                     "sweep_down": ["k_sweep_down_mfma", "k_sweep_down"],
+                     "permute": ["k_permute_in", "k_permute_out", "k_permute_seg"]}
 
 
-def measured_traffic(family):
-    """HBM bytes per dispatch from the committed counter summary, if still current."""
+def measured_traffic(family, launches_per_step):
+    """HBM bytes per family launch from the committed counter summary (one bench step
+    counted), if kernels.hip still has the hash the counters were taken with."""
     import hashlib
     import re
     try:
@@ -65,7 +72,8 @@ def measured_traffic(family):
         src = open(os.path.join(ROOT, "paper_1110_3105_amd", "csrc", "kernels.hip"), "rb").read()
         if hashlib.sha256(src).hexdigest()[:16] != blob["kernels_sha"]:
             return None
-        return blob["traffic_bytes_per_dispatch"].get(KERNEL_OF_FAMILY.get(family))
+        total = sum(blob["bytes_per_step"].get(k, 0.0) for k in KERNELS_OF_FAMILY[family])
+        return total / launches_per_step if total else None
     except Exception:
         return None
 
@@ -342,6 +350,20 @@ def main():
         h.free()
         return st
 
+    tune = None
+    if not args.no_autotune:
+        # sweep tile widths chosen by the library's autotuner on this workload's factor
+        # (setup, outside the timed region; widths never change results)
+        t = rs.build_tree(g.points, LEAF)
+        h = rs.factor("lap2d_sl", t, g.points, g.weights, EPS, proxy_points=NPX, stream=stream)
+        a = time.perf_counter()
+        rs.autotune(h, (1, 64, NRHS), reps=3, stream=stream)
+        tune = {"ms": (time.perf_counter() - a) * 1e3,
+                "table": {"%s%s nrhs<=%d n<=%d" % ("mfma" if k[0] else "valu",
+                                                   " c128" if k[1] else "", 1 << k[2],
+                                                   32 * k[3]): w
+                          for k, w in sorted(rs.tune_entries().items())}}
+        h.free()
     if args.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -383,7 +405,8 @@ def main():
     dom = max(fams, key=lambda k: fams[k]["ms_per_step"])
     D = fams[dom]
     roofline = {"kernel": dom, "bound": D["bound"], "achieved": D["achieved"], "peak": D["peak"],
-                "unit": D["unit"], "frac": D["frac"], "traffic": measured_traffic(dom),
+                "unit": D["unit"], "frac": D["frac"],
+                "traffic": measured_traffic(dom, D["launches_per_step"]),
                 "avg_launch_ms": D["avg_launch_ms"],
                 "work_per_launch": D["bytes_per_launch"] if D["bound"] == "hbm"
                 else D["flops_per_launch"]}
@@ -396,7 +419,7 @@ def main():
                                   "eps=1e-9, leaf 64, 64 proxies at 1.5x, nrhs=512",
                       "n": N, "eps": EPS, "leaf": LEAF, "proxy_points": NPX, "nrhs": NRHS,
                       "step": "tree + factor + solve(512) + free"},
-           "roofline": roofline, "kernels": fams,
+           "roofline": roofline, "kernels": fams, "autotune": tune,
            "factor_stats": {k: st[k] for k in ("nbox", "maxdepth", "root_size",
                                                "total_skeletons", "factor_doubles",
                                                "max_box_n", "max_box_m")}}
@@ -438,6 +461,19 @@ def main():
                         stream.synchronize()
                         xs.append((time.perf_counter() - a) * 1e3)
                     lat[str(nrhs)] = {"p50_ms": percentile(xs, 50), "p99_ms": percentile(xs, 99)}
+                    # the same solve replayed from a captured HIP graph
+                    plan = rs.Plan([h], [X])
+                    plan.launch(stream)
+                    stream.synchronize()
+                    xs = []
+                    for _ in range(200):
+                        a = time.perf_counter()
+                        plan.launch(stream)
+                        stream.synchronize()
+                        xs.append((time.perf_counter() - a) * 1e3)
+                    plan.free()
+                    lat[str(nrhs)]["graph_p50_ms"] = percentile(xs, 50)
+                    lat[str(nrhs)]["graph_p99_ms"] = percentile(xs, 99)
             h.free()
             extras[mode] = {"factor_ms_median": float(np.median(fms)), "solve": solve}
             if lat:
