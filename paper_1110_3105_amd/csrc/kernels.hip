@@ -1585,6 +1585,75 @@ __global__ __launch_bounds__(kThreads) void k_sweep_seg(const SweepSeg *__restri
   }
 }
 
+// Tiled caller <-> tree order permutation for wide right-hand-side blocks: a tile of
+// 64 tree positions x 32 columns passes through LDS, so B (column-major, caller order)
+// is read or written along tree positions -- caller indices perm[i], contiguous runs on
+// curves and surfaces -- and W (row-major, tree order) along its columns.
+constexpr int kPermTI = 64, kPermTC = 32;
+
+template <class S, bool TO_TREE>
+__device__ __forceinline__ void permute_tiles(S *__restrict__ Bm, int64_t ldb, S *__restrict__ W,
+                                              const int64_t *__restrict__ perm, int64_t n,
+                                              int nrhs, S (*tile)[kPermTI + 1]) {
+  const int t = threadIdx.x;                       // 256 threads
+  const int64_t tiles_i = (n + kPermTI - 1) / kPermTI;
+  const int tiles_c = (nrhs + kPermTC - 1) / kPermTC;
+  const int64_t ntiles = tiles_i * tiles_c;
+  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int64_t i0 = (tl / tiles_c) * kPermTI;
+    const int c0 = (int)(tl % tiles_c) * kPermTC;
+    // B side: consecutive threads take consecutive tree positions
+    const int il = t & (kPermTI - 1), cq = t >> 6;
+    const int64_t i = i0 + il;
+    const int64_t g = i < n ? perm[i] : 0;
+    // W side: consecutive threads take consecutive columns
+    const int cl = t & (kPermTC - 1), iq = t >> 5;
+    if (TO_TREE) {
+#pragma unroll
+      for (int r = 0; r < kPermTC / 4; ++r) {
+        const int c = cq + 4 * r;
+        if (i < n && c0 + c < nrhs) tile[c][il] = Bm[g + ldb * (c0 + c)];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kPermTI / 8; ++r) {
+        const int ii = iq + 8 * r;
+        if (i0 + ii < n && c0 + cl < nrhs) W[(i0 + ii) * nrhs + c0 + cl] = tile[cl][ii];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kPermTI / 8; ++r) {
+        const int ii = iq + 8 * r;
+        if (i0 + ii < n && c0 + cl < nrhs) tile[cl][ii] = W[(i0 + ii) * nrhs + c0 + cl];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kPermTC / 4; ++r) {
+        const int c = cq + 4 * r;
+        if (i < n && c0 + c < nrhs) Bm[g + ldb * (c0 + c)] = tile[c][il];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class S, bool TO_TREE>
+__global__ __launch_bounds__(256) void k_permute_tiled(S *__restrict__ B, int64_t ldb,
+                                                       S *__restrict__ W,
+                                                       const int64_t *__restrict__ perm,
+                                                       int64_t n, int nrhs) {
+  __shared__ S tile[kPermTC][kPermTI + 1];
+  permute_tiles<S, TO_TREE>(B, ldb, W, perm, n, nrhs, tile);
+}
+
+template <class S, bool TO_TREE>
+__global__ __launch_bounds__(256) void k_permute_seg_tiled(const PermSeg *__restrict__ segs) {
+  __shared__ S tile[kPermTC][kPermTI + 1];
+  const PermSeg &Pg = segs[blockIdx.y];
+  permute_tiles<S, TO_TREE>(reinterpret_cast<S *>(Pg.B), Pg.ldb, reinterpret_cast<S *>(Pg.W),
+                            Pg.perm, Pg.n, Pg.nrhs, tile);
+}
+
 // Caller order <-> tree order for several right-hand-side blocks (grid.y = block).
 template <class S>
 __global__ void k_permute_seg(const PermSeg *__restrict__ segs, int to_tree) {
@@ -1941,10 +2010,28 @@ void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
   });
 }
 
+// Right-hand-side blocks at least this wide use the LDS-tiled permutation.
+constexpr int kPermTiledMinNrhs = 8;
+
+int perm_tiled_blocks(int64_t n, int nrhs) {
+  const int64_t tiles = ((n + kPermTI - 1) / kPermTI) * ((nrhs + kPermTC - 1) / kPermTC);
+  return (int)std::min<int64_t>(tiles, 4096);
+}
+
 void launch_permute_in(bool cplx, const double *B, int64_t ldb, double *W, const int64_t *perm,
                        int64_t n, int nrhs, hipStream_t st) {
   const int64_t total = n * nrhs;
   if (total == 0) return;
+  if (nrhs >= kPermTiledMinNrhs) {
+    with_scalar(cplx, [&](auto z) {
+      using S = decltype(z);
+      hipLaunchKernelGGL((k_permute_tiled<S, true>), dim3(perm_tiled_blocks(n, nrhs)), dim3(256),
+                         0, st, reinterpret_cast<S *>(const_cast<double *>(B)), ldb,
+                         reinterpret_cast<S *>(W), perm, n, nrhs);
+    });
+    check_launch("k_permute_tiled");
+    return;
+  }
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
@@ -1959,6 +2046,16 @@ void launch_permute_out(bool cplx, double *B, int64_t ldb, const double *W, cons
                         int64_t n, int nrhs, hipStream_t st) {
   const int64_t total = n * nrhs;
   if (total == 0) return;
+  if (nrhs >= kPermTiledMinNrhs) {
+    with_scalar(cplx, [&](auto z) {
+      using S = decltype(z);
+      hipLaunchKernelGGL((k_permute_tiled<S, false>), dim3(perm_tiled_blocks(n, nrhs)),
+                         dim3(256), 0, st, reinterpret_cast<S *>(B), ldb,
+                         reinterpret_cast<S *>(const_cast<double *>(W)), perm, n, nrhs);
+    });
+    check_launch("k_permute_tiled");
+    return;
+  }
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
@@ -1970,8 +2067,23 @@ void launch_permute_out(bool cplx, double *B, int64_t ldb, const double *W, cons
 }
 
 void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_elems,
-                        bool to_tree, hipStream_t st) {
+                        int max_nrhs, bool to_tree, hipStream_t st) {
   if (nseg <= 0 || max_elems <= 0) return;
+  if (max_nrhs >= kPermTiledMinNrhs) {
+    const int blocks = (int)std::min<int64_t>((max_elems + kPermTI * kPermTC - 1) /
+                                              (kPermTI * kPermTC), 2048);
+    with_scalar(cplx, [&](auto z) {
+      using S = decltype(z);
+      if (to_tree)
+        hipLaunchKernelGGL((k_permute_seg_tiled<S, true>), dim3(blocks, nseg), dim3(256), 0, st,
+                           segs);
+      else
+        hipLaunchKernelGGL((k_permute_seg_tiled<S, false>), dim3(blocks, nseg), dim3(256), 0,
+                           st, segs);
+    });
+    check_launch("k_permute_seg_tiled");
+    return;
+  }
   const int blocks = (int)std::min<int64_t>((max_elems + 255) / 256, 2048);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);

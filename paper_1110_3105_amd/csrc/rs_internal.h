@@ -141,7 +141,7 @@ void launch_permute_in(bool cplx, const double *B, int64_t ldb, double *W, const
 void launch_permute_out(bool cplx, double *B, int64_t ldb, const double *W, const int64_t *perm,
                         int64_t n, int nrhs, hipStream_t st);
 void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_elems,
-                        bool to_tree, hipStream_t st);
+                        int max_nrhs, bool to_tree, hipStream_t st);
 // Boxes with n = k + r <= mfma_max_n are swept with FP64 MFMA tiles (any nrhs); larger
 // boxes with the FP64 VALU kernels.  The class of a box never depends on the launch.
 constexpr int kMfmaMaxN = 512;

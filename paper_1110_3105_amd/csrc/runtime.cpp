@@ -16,6 +16,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <condition_variable>
+#include <functional>
 #include <thread>
 #include <unordered_map>
 
@@ -45,12 +47,51 @@ void LevelRec::partition_classes(int mfma_limit) {
   if (!boxes.empty()) boxes.swap(b2);
 }
 
+namespace {
+struct ChunkCache {
+  std::mutex mu;
+  std::vector<std::unique_ptr<DevBuf>> free;
+  size_t bytes = 0;
+  // smallest cached chunk of at least `need` bytes, or null
+  std::unique_ptr<DevBuf> take(size_t need) {
+    std::lock_guard<std::mutex> lk(mu);
+    int best = -1;
+    for (int i = 0; i < (int)free.size(); ++i)
+      if (free[i]->bytes >= need && (best < 0 || free[i]->bytes < free[best]->bytes)) best = i;
+    if (best < 0) return nullptr;
+    std::unique_ptr<DevBuf> c = std::move(free[best]);
+    free.erase(free.begin() + best);
+    bytes -= c->bytes;
+    return c;
+  }
+  void give(std::unique_ptr<DevBuf> c) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (bytes + c->bytes > kChunkCacheBytes) return;      // released by its destructor
+    bytes += c->bytes;
+    free.push_back(std::move(c));
+  }
+};
+ChunkCache &chunk_cache() {
+  static ChunkCache *c = new ChunkCache();   // lives for the process
+  return *c;
+}
+}  // namespace
+
+Arena::~Arena() {
+  for (auto &c : chunks)
+    if (c && c->p) chunk_cache().give(std::move(c));
+}
+
 void *Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
   if (chunks.empty() || used + bytes > chunks.back()->bytes) {
-    auto c = std::make_unique<DevBuf>();
-    c->ensure(std::max<size_t>(bytes, size_t(8) << 20));
+    const size_t want = std::max<size_t>(bytes, size_t(8) << 20);
+    std::unique_ptr<DevBuf> c = chunk_cache().take(want);
+    if (!c) {
+      c = std::make_unique<DevBuf>();
+      c->ensure(want);
+    }
     chunks.push_back(std::move(c));
     used = 0;
   }
@@ -92,24 +133,88 @@ struct ProbState {
   bool log_kernel = false;
 };
 
-// Runs f(i) for i in [0, n) on up to kPlanThreads host threads.
+// Persistent pool of host worker threads for the level planner (created on first use,
+// alive for the process).  parallel_for(n, f) runs f(i) for i in [0, n) in contiguous
+// chunks on the calling thread plus the workers, and returns when all are done.
 constexpr int kPlanThreads = 16;
+class PlanPool {
+ public:
+  static PlanPool &get() {
+    static PlanPool *p = new PlanPool();     // never destroyed: workers may outlive main
+    return *p;
+  }
+  int workers() const { return (int)th_.size(); }
+  void run(int nchunks, const std::function<void(int)> &job) {
+    std::unique_lock<std::mutex> lk(mu_);
+    job_ = &job;
+    nchunks_ = nchunks;
+    next_ = 1;                 // chunk 0 runs on the caller
+    pending_ = nchunks - 1;
+    ++gen_;
+    cv_.notify_all();
+    lk.unlock();
+    job(0);
+    lk.lock();
+    while (true) {             // the caller helps with the remaining chunks
+      if (next_ < nchunks_) {
+        const int c = next_++;
+        lk.unlock();
+        job(c);
+        lk.lock();
+        --pending_;
+        continue;
+      }
+      break;
+    }
+    done_cv_.wait(lk, [&] { return pending_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  PlanPool() {
+    const int n = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()),
+                                          kPlanThreads) - 1;
+    for (int i = 0; i < n; ++i) th_.emplace_back([this] { loop(); });
+    for (auto &t : th_) t.detach();
+  }
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    while (true) {
+      cv_.wait(lk, [&] { return gen_ != seen; });
+      seen = gen_;
+      while (job_ && next_ < nchunks_) {
+        const int c = next_++;
+        const std::function<void(int)> *job = job_;
+        lk.unlock();
+        (*job)(c);
+        lk.lock();
+        if (--pending_ == 0) done_cv_.notify_all();
+      }
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)> *job_ = nullptr;
+  int nchunks_ = 0, next_ = 0, pending_ = 0;
+  uint64_t gen_ = 0;
+};
+
 template <class F>
 void parallel_for(int n, F &&f) {
-  int nt = (int)std::min<unsigned>(std::thread::hardware_concurrency(), kPlanThreads);
-  nt = std::max(1, std::min(nt, n / 32));
+  PlanPool &pool = PlanPool::get();
+  const int nt = std::max(1, std::min(pool.workers() + 1, n / 32));
   if (nt <= 1) {
     for (int i = 0; i < n; ++i) f(i);
     return;
   }
-  std::vector<std::thread> th;
-  const int chunk = (n + nt - 1) / nt;
-  for (int t = 1; t < nt; ++t)
-    th.emplace_back([&, t] {
-      for (int i = t * chunk; i < std::min(n, (t + 1) * chunk); ++i) f(i);
-    });
-  for (int i = 0; i < std::min(n, chunk); ++i) f(i);
-  for (auto &x : th) x.join();
+  const int nchunks = std::min(n, 4 * nt);
+  const int chunk = (n + nchunks - 1) / nchunks;
+  const std::function<void(int)> job = [&](int c) {
+    for (int i = c * chunk; i < std::min(n, (c + 1) * chunk); ++i) f(i);
+  };
+  pool.run((n + chunk - 1) / chunk, job);
 }
 
 uint64_t cell_key(int64_t x, int64_t y, int64_t z) {
@@ -272,7 +377,7 @@ void fill_children(ProbState &ps, int b, FacBox &fb) {
   for (int ci = 0; ci < fb.nchild; ++ci) {
     const int c = t.first_child[b] + ci;
     const int kc = ps.h->box_k[c];
-    const int nc = (int)ps.h->box_J[c].size();
+    const int nc = (int)ps.J[c].size();
     fb.child_lo[ci] = lo;
     fb.child_k[ci] = kc;
     fb.child_lam[ci] = ps.h->box_slot[c] + slot_L(kc, nc - kc) * (ps.h->cplx ? 2 : 1);
@@ -502,7 +607,43 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     all_items.insert(all_items.end(), items.begin(), items.end());
     std::vector<FacBox> &fac = cur_stage.fac;
     fac.assign(cnt, FacBox{});
+    // descriptors first (the factor launch waits on them); bookkeeping after the launch
     int64_t woff = 0;
+    for (int i = 0; i < cnt; ++i) {
+      ProbState &P = *items[i].ps;
+      const int b = items[i].box;
+      const CompBox &cb = comp[i];
+      P.h->box_k[b] = ranks[i];
+      FacBox &fb = fac[i];
+      std::memset(&fb, 0, sizeof(fb));
+      fb.prob = P.pidx;
+      fb.n = cb.n;
+      fb.kslot = i;
+      fb.force_k0 = 0;
+      fb.leaf = P.t->is_leaf(b) ? 1 : 0;
+      fb.J_off = cb.J_off;
+      fb.order_off = cb.order_off;
+      fb.slot = cb.T;
+      fb.work_off = woff;
+      woff += (int64_t)diag_work_elems(cb.n);
+      fill_children(P, b, fb);
+    }
+    upload(S.fac, fac, st);
+    const FacBox *d_fac = S.fac.as<FacBox>();
+    if (per_box) {
+      for (int i = 0; i < cnt; ++i) {
+        ProfScope ps_(RS_K_FACTOR, st);
+        launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
+                           S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
+                           err_base, comp[i].n, st);
+      }
+    } else {
+      ProfScope ps_(RS_K_FACTOR, st);
+      launch_diag_factor(cplx, d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
+                         S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
+                         err_base, max_n, st);
+    }
+    // skeleton lists (the next level's active sets) and profiler work counts
     Work w_asm, w_id, w_fac;
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
@@ -521,42 +662,10 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       std::vector<int32_t> &sk = P.skel[b];
       sk.resize(k);
       for (int a = 0; a < k; ++a) sk[a] = J[ord[a]];
-      P.h->box_k[b] = k;
-      P.h->box_J[b] = J;
-      P.h->box_skel[b] = sk;
-      FacBox &fb = fac[i];
-      std::memset(&fb, 0, sizeof(fb));
-      fb.prob = P.pidx;
-      fb.n = cb.n;
-      fb.kslot = i;
-      fb.force_k0 = 0;
-      fb.leaf = P.t->is_leaf(b) ? 1 : 0;
-      fb.J_off = cb.J_off;
-      fb.order_off = cb.order_off;
-      fb.slot = cb.T;
-      fb.work_off = woff;
-      woff += (int64_t)diag_work_elems(cb.n);
-      fill_children(P, b, fb);
     }
-    plan_ms += ms_since(tp2);
-    upload(S.fac, fac, st);
-    const FacBox *d_fac = S.fac.as<FacBox>();
     prof_add_work(RS_K_ASSEMBLE, w_asm);
     prof_add_work(RS_K_ID, w_id);
     prof_add_work(RS_K_FACTOR, w_fac);
-    if (per_box) {
-      for (int i = 0; i < cnt; ++i) {
-        ProfScope ps_(RS_K_FACTOR, st);
-        launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
-                           S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
-                           err_base, comp[i].n, st);
-      }
-    } else {
-      ProfScope ps_(RS_K_FACTOR, st);
-      launch_diag_factor(cplx, d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
-                         S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
-                         err_base, max_n, st);
-    }
     // persistent solve data: index lists (skeletons then redundant, tree positions),
     // one contiguous block and one upload per problem and level
     std::vector<std::vector<int32_t>> &idx_keep = cur_stage.idx;
@@ -609,6 +718,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                                     idx_keep[p].size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                     st));
     std::swap(prev_stage, cur_stage);   // released after the next level's readback
+    plan_ms += ms_since(tp2);
   }
 
   // ---- roots: the dense block of the surviving skeletons, fully eliminated
@@ -712,6 +822,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   out.resize(np);
   for (int p = 0; p < np; ++p) {
     rs_factor_s *h = handles[p].get();
+    h->box_J = std::move(ps[p].J);          // per-box active sets and skeletons (queries)
+    h->box_skel = std::move(ps[p].skel);
     h->stats.n = h->n;
     h->stats.nbox = ps[p].t->nbox();
     h->stats.maxdepth = ps[p].t->maxdepth;
@@ -851,6 +963,7 @@ struct SolveTables {
   bool cplx = false;
   int nq = 0;
   int64_t max_elems = 0;
+  int max_nrhs = 0;
   std::vector<PermSeg> perm;
   std::vector<SweepSeg> segs;
   std::vector<LaunchRec> launches;
@@ -887,6 +1000,7 @@ SolveTables build_tables(const std::vector<SolveRequest> &rq, double *W) {
     p.nrhs = rq[i].nrhs;
     p.pad = 0;
     T.max_elems = std::max<int64_t>(T.max_elems, rq[i].h->n * (int64_t)rq[i].nrhs);
+    T.max_nrhs = std::max(T.max_nrhs, rq[i].nrhs);
   }
   auto add_step = [&](bool up, auto level_of) {
     for (int mfma = 1; mfma >= 0; --mfma) {
@@ -943,7 +1057,7 @@ void enqueue_group(const SolveTables &T, const char *dtab, hipStream_t st) {
       reinterpret_cast<const SweepSeg *>(dtab + T.perm.size() * sizeof(PermSeg));
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_seg(T.cplx, d_perm, T.nq, T.max_elems, true, st);
+    launch_permute_seg(T.cplx, d_perm, T.nq, T.max_elems, T.max_nrhs, true, st);
   }
   for (const LaunchRec &L : T.launches) {
     ProfScope ps_(L.up ? RS_K_SWEEP_UP : RS_K_SWEEP_DOWN, st);
@@ -952,7 +1066,7 @@ void enqueue_group(const SolveTables &T, const char *dtab, hipStream_t st) {
   }
   {
     ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_seg(T.cplx, d_perm, T.nq, T.max_elems, false, st);
+    launch_permute_seg(T.cplx, d_perm, T.nq, T.max_elems, T.max_nrhs, false, st);
   }
 }
 

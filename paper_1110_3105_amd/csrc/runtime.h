@@ -35,13 +35,22 @@ struct DevBuf {
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
-// Bump allocator over device chunks; everything lives until the owner is freed.
+// Bump allocator over device chunks; everything lives until the owner is freed.  Chunks
+// come from (and return to) a process-wide cache of released chunks, so a factorization
+// that follows a freed one reuses its device memory instead of hipFree + hipMalloc; the
+// cache keeps at most kChunkCacheBytes.  Owners release an arena only once no queued
+// work uses it (rs_free and the server's release wait for the device first).
+constexpr size_t kChunkCacheBytes = size_t(2) << 30;
 struct Arena {
   std::vector<std::unique_ptr<DevBuf>> chunks;
   size_t used = 0;
   size_t total = 0;
   void *alloc(size_t bytes);
   template <class T> T *alloc_n(int64_t n) { return static_cast<T *>(alloc(sizeof(T) * (size_t)n)); }
+  Arena() = default;
+  Arena(const Arena &) = delete;
+  Arena &operator=(const Arena &) = delete;
+  ~Arena();
 };
 
 // One compressed level (or the root) of one factored problem.
