@@ -4,9 +4,13 @@
 // is a single IEEE operation, so the tree is a deterministic function of the points.
 #include "tree.h"
 
+#include <array>
+
 #include <algorithm>
 #include <cmath>
 #include <stdexcept>
+
+#include "pool.h"
 
 namespace rs {
 
@@ -52,43 +56,61 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   };
   add(c0, s0, 0, -1, 0, n, 0);
   const int ncode = 1 << dim;
-  std::vector<int64_t> tmp;
-  std::vector<int> code;
-  for (size_t q = 0; q < side.size(); ++q) {
-    const int64_t b = begin[q], e = end[q];
-    if (!(e - b > leaf_size && depth[q] < kMaxDepth && side[q] > 0.0)) continue;
-    const double c[3] = {center[3 * q], center[3 * q + 1], center[3 * q + 2]};
-    const double s = side[q];
-    const int64_t cnt = e - b;
-    code.assign(cnt, 0);
-    int64_t count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t i = 0; i < cnt; ++i) {
-      const int64_t g = perm[b + i];
-      int cc = 0;
-      for (int a = 0; a < dim; ++a) cc |= (pts[g * dim + a] >= c[a] ? 1 : 0) << a;
-      code[i] = cc;
-      count[cc]++;
+  // Level by level: the boxes of one depth partition their (disjoint) index ranges in
+  // parallel, then their children are numbered in box order -- the same breadth-first
+  // numbering and stable order as splitting the boxes one after another.
+  std::vector<int64_t> tmp(n);
+  std::vector<int> code(n);
+  std::vector<int> cur = {0};
+  while (!cur.empty()) {
+    const int nb = (int)cur.size();
+    std::vector<std::array<int64_t, 8>> counts(nb);
+    std::vector<char> split(nb, 0);
+    parallel_for(nb, [&](int bi) {
+      const int q = cur[bi];
+      const int64_t b = begin[q], e = end[q];
+      if (!(e - b > leaf_size && depth[q] < kMaxDepth && side[q] > 0.0)) return;
+      split[bi] = 1;
+      const double c[3] = {center[3 * q], center[3 * q + 1], center[3 * q + 2]};
+      std::array<int64_t, 8> &cnt = counts[bi];
+      cnt.fill(0);
+      for (int64_t i = b; i < e; ++i) {
+        const int64_t g = perm[i];
+        int cc = 0;
+        for (int a = 0; a < dim; ++a) cc |= (pts[g * dim + a] >= c[a] ? 1 : 0) << a;
+        code[i] = cc;
+        cnt[cc]++;
+      }
+      int64_t pos[8];
+      int64_t acc = b;
+      for (int cc = 0; cc < ncode; ++cc) {
+        pos[cc] = acc;
+        acc += cnt[cc];
+      }
+      for (int64_t i = b; i < e; ++i) tmp[pos[code[i]]++] = perm[i];
+      std::copy(tmp.begin() + b, tmp.begin() + e, perm.begin() + b);
+    }, 1);
+    std::vector<int> next;
+    for (int bi = 0; bi < nb; ++bi) {
+      if (!split[bi]) continue;
+      const int q = cur[bi];
+      const double c[3] = {center[3 * q], center[3 * q + 1], center[3 * q + 2]};
+      const double sq = side[q];
+      int64_t off = begin[q];
+      for (int cc = 0; cc < ncode; ++cc) {
+        const int64_t cnt = counts[bi][cc];
+        if (cnt == 0) continue;
+        double cch[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) cch[a] = ((cc >> a) & 1) ? c[a] + sq * 0.25 : c[a] - sq * 0.25;
+        const int id = (int)side.size();
+        if (first_child[q] < 0) first_child[q] = id;
+        nchild[q]++;
+        add(cch, sq * 0.5, depth[q] + 1, q, off, off + cnt, cc);
+        next.push_back(id);
+        off += cnt;
+      }
     }
-    int64_t off[8];
-    int64_t acc = 0;
-    for (int cc = 0; cc < ncode; ++cc) {
-      off[cc] = acc;
-      acc += count[cc];
-    }
-    tmp.assign(cnt, 0);
-    int64_t pos[8];
-    for (int cc = 0; cc < ncode; ++cc) pos[cc] = off[cc];
-    for (int64_t i = 0; i < cnt; ++i) tmp[pos[code[i]]++] = perm[b + i];
-    std::copy(tmp.begin(), tmp.end(), perm.begin() + b);
-    for (int cc = 0; cc < ncode; ++cc) {
-      if (count[cc] == 0) continue;
-      double cch[3] = {0, 0, 0};
-      for (int a = 0; a < dim; ++a) cch[a] = ((cc >> a) & 1) ? c[a] + s * 0.25 : c[a] - s * 0.25;
-      const int id = (int)side.size();
-      if (first_child[q] < 0) first_child[q] = id;
-      nchild[q]++;
-      add(cch, s * 0.5, depth[q] + 1, (int)q, b + off[cc], b + off[cc] + count[cc], cc);
-    }
+    cur.swap(next);
   }
   maxdepth = 0;
   for (int d : depth) maxdepth = std::max(maxdepth, d);
