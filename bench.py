@@ -78,6 +78,11 @@ def measured_traffic(family, launches_per_step):
         return None
 
 
+def progress(msg):
+    """One line per finished phase, on stderr (the JSON result stays alone on stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q))
@@ -169,8 +174,9 @@ def many_problems(rs, torch, stream, count=256):
 def serving(rs, torch, load=0.5, nreq=1500):
     """Request server with 16 resident factors and Poisson solve arrivals.
 
-    Resident: 8 log single-layer problems on random curves (N = 65536, seeds 2000-2007)
-    and 8 double-layer problems (N = 16384, seeds 3000-3007), eps = 1e-9.  Requests
+    Resident: 8 log single-layer problems on random curves (N = 65536, seeds 2000-2007),
+    6 double-layer problems (N = 16384, seeds 3000-3005), eps = 1e-9, and 2 single-layer
+    problems on randomly rotated Fibonacci spheres (N = 20480, eps = 1e-6).  Requests
     pick a factor uniformly and nrhs ~ U{1..256}; arrivals are Poisson at `load` times
     the saturated throughput measured first with a burst; two complex Helmholtz
     combined-field factor requests (N = 32768, 10 wavelengths across) arrive during the
@@ -185,17 +191,27 @@ def serving(rs, torch, load=0.5, nreq=1500):
         r = np.random.default_rng(2000 + i)
         geoms.append(("lap2d_sl", W.random_curve(65536, r.uniform(0, 0.04, 8),
                                                  r.uniform(0, 2 * np.pi, 8))))
-    for i in range(8):
+    for i in range(6):
         r = np.random.default_rng(3000 + i)
         geoms.append(("lap2d_dl", W.random_curve(16384, r.uniform(0, 0.04, 8),
                                                  r.uniform(0, 2 * np.pi, 8))))
+    for i in range(2):
+        geoms.append(("lap3d_sl", W.fibonacci_sphere(
+            20480, W.random_rotation(np.random.default_rng(3100 + i)))))
     srv = rs.Server(64 << 30, max_batch_requests=32, max_batch_rhs=2048)
     tks = []
     for kind, g in geoms:
+        if kind == "lap3d_sl":
+            t = rs.build_tree(g.points, 128)
+            tks.append(srv.submit_factor(kind, t, g.points, g.weights, 1e-6, proxy_points=512))
+            continue
         t = rs.build_tree(g.points, LEAF)
         kw = dict(normals=g.normals, curvature=g.curvature, identity=-0.5) if kind == "lap2d_dl" else {}
         tks.append(srv.submit_factor(kind, t, g.points, g.weights, EPS, **kw))
-    handles = [srv.wait(t) for t in tks]
+    handles = []
+    for t in tks:
+        handles.append(srv.wait(t))
+        progress(f"serving: {len(handles)} of {len(tks)} resident factors ready")
     nslot = 48
     slots = [torch.randn(256, 65536, dtype=torch.float64, device="cuda").t() for _ in range(nslot)]
     free = list(range(nslot))
@@ -272,14 +288,58 @@ def serving(rs, torch, load=0.5, nreq=1500):
     for h in handles + extra:
         h.free()
     srv.close()
-    return {"workload": "16 resident factors (8 x log single layer N=65536, 8 x double layer "
-                        "N=16384, random curves), Poisson solve arrivals, nrhs~U{1..256}, "
+    return {"workload": "16 resident factors (8 x 2D log single layer N=65536, 6 x 2D double "
+                        "layer N=16384 on random curves, 2 x 3D single layer N=20480 on "
+                        "rotated spheres), Poisson solve arrivals, nrhs~U{1..256}, "
                         "2 complex Helmholtz combined-field N=32768 factor requests (10 "
                         "wavelengths across) admitted mid-run",
             "requests": nreq, "offered_load": load, "saturated_rhs_per_s": sat,
             "rhs_per_s": st["rhs_done"] / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
             "mean_ms": st["mean_ms"], "batches": st["batches"],
             "factors_admitted": st["factors_done"]}
+
+
+def sphere(rs, torch):
+    """The 3D configuration: unit sphere, N = 20480 Fibonacci points, single layer,
+    eps = 1e-6, octree leaf 128, 512 proxies; factor time, 64-RHS solve, and the
+    residual on sampled rows against the exact matrix (oracle rows, outside the timing)."""
+    import numpy as np
+    import workloads as W
+    from oracle import Problem, dense
+    g = W.fibonacci_sphere(20480)
+    t = rs.build_tree(g.points, 128)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    h = rs.factor("lap3d_sl", t, g.points, g.weights, 1e-6, proxy_points=512)
+    torch.cuda.synchronize()
+    fms = (time.perf_counter() - a) * 1e3
+    st = h.stats()
+    b = W.gaussian_rhs(20480, 64, 2)
+    B = torch.tensor(b.T.copy(), device="cuda").t()
+    X = B.clone()
+    h.solve(X)
+    torch.cuda.synchronize()
+    reps = 10
+    a = time.perf_counter()
+    for _ in range(reps):
+        X.copy_(B)
+        h.solve(X)
+    torch.cuda.synchronize()
+    sms = (time.perf_counter() - a) * 1e3 / reps
+    x = X.cpu().numpy()
+    rows = np.random.default_rng(1).choice(20480, 32, replace=False)
+    p = Problem("lap3d_sl", g.points, g.weights)
+    ax = dense.matvec_rows(p, rows, x)
+    res = float(np.linalg.norm(ax - b[rows]) / np.linalg.norm(ax))
+    h.free()
+    return {"workload": "unit sphere N=20480 (Fibonacci), 3D Laplace single layer, eps=1e-6, "
+                        "leaf 128, 512 proxies, nrhs=64",
+            "factor_ms": fms, "root_size": st["root_size"], "max_box_n": st["max_box_n"],
+            "max_box_m": st["max_box_m"], "factor_bytes": 8 * st["factor_doubles"],
+            "solve_ms_64": sms, "rhs_per_s": 64 / sms * 1e3,
+            "sampled_relative_residual": res,
+            "paper_context": "Table 6 (unit sphere, N=20480, eps=1e-6): T_cm+T_lu about 411 s "
+                             "on one 2.66 GHz core"}
 
 
 def helmholtz(rs, torch):
@@ -364,6 +424,7 @@ def main():
                                                    32 * k[3]): w
                           for k, w in sorted(rs.tune_entries().items())}}
         h.free()
+        progress("autotuned sweep tile widths")
     if args.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -381,6 +442,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rs.profile_enable(False)
+    progress(f"{args.steps} timed steps done")
     prof = rs.profile_read()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
@@ -475,6 +537,7 @@ def main():
                     lat[str(nrhs)]["graph_p50_ms"] = percentile(xs, 50)
                     lat[str(nrhs)]["graph_p99_ms"] = percentile(xs, 99)
             h.free()
+            progress(f"{mode} launches measured")
             extras[mode] = {"factor_ms_median": float(np.median(fms)), "solve": solve}
             if lat:
                 extras[mode]["latency"] = lat
@@ -486,13 +549,19 @@ def main():
             / extras["level"]["solve"]["512"]["ms"]}
         out["latency_ms"] = extras["level"]["latency"]
         out["many_problems"] = many_problems(rs, torch, stream)
+        progress("many-problem batch done")
         out["helmholtz"] = helmholtz(rs, torch)
+        progress("Helmholtz factor done")
+        out["sphere"] = sphere(rs, torch)
+        progress("sphere factor done")
         out["serving"] = serving(rs, torch)
+        progress("serving scenario done")
         out["paper_context"] = {"hardware": "2.66 GHz single CPU core, Fortran (Section 6)",
                                 "table5_N65536_ellipse_dl": {"T_cm_s": 2.3, "T_lu_s": 1.8,
                                                              "T_sv_s": 0.038}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, b_host)
+        progress("CPU baseline (oracle) done")
     print(json.dumps(out))
 
 

@@ -22,7 +22,14 @@ class PlanPool {
     return *p;
   }
   int workers() const { return (int)th_.size(); }
+  // Runs job(0..nchunks) on the caller plus the workers.  One job at a time: a caller
+  // that finds the pool busy (another thread's job) runs all of its chunks itself.
   void run(int nchunks, const std::function<void(int)> &job) {
+    std::unique_lock<std::mutex> owner(run_mu_, std::try_to_lock);
+    if (!owner.owns_lock()) {
+      for (int c = 0; c < nchunks; ++c) job(c);
+      return;
+    }
     std::unique_lock<std::mutex> lk(mu_);
     job_ = &job;
     nchunks_ = nchunks;
@@ -72,6 +79,7 @@ class PlanPool {
     }
   }
   std::vector<std::thread> th_;
+  std::mutex run_mu_;      // held by the caller whose job the workers serve
   std::mutex mu_;
   std::condition_variable cv_, done_cv_;
   const std::function<void(int)> *job_ = nullptr;

@@ -88,3 +88,33 @@ def test_factor_argument_validation_before_device_use():
         with pytest.raises(rs.RSError) as ei:
             rs.factor("helm2d_cfie", t, g.points, g.weights, 1e-9, **c)
         assert ei.value.code == 1, c
+
+
+def test_tree_builds_from_concurrent_threads():
+    # the host worker pool is shared by every thread that builds trees or plans levels;
+    # concurrent callers must each get their own complete, correct result
+    import threading
+    import paper_1110_3105_amd as rs
+    geoms = [W.star_curve(16384), W.random_curve(9000, [0.03, 0.01], [0.2, 1.3]),
+             W.fibonacci_sphere(8000), W.ellipse(12000)]
+    leaf = [64, 48, 128, 64]
+    ref = [rs.build_tree(g.points, lf).export() for g, lf in zip(geoms, leaf)]
+    errors = []
+
+    def work(i):
+        try:
+            for _ in range(6):
+                e = rs.build_tree(geoms[i].points, leaf[i]).export()
+                for key in ("perm", "begin", "end", "parent", "depth"):
+                    if not np.array_equal(e[key], ref[i][key]):
+                        errors.append((i, key))
+        except Exception as exc:          # pragma: no cover
+            errors.append((i, repr(exc)))
+
+    threads = [threading.Thread(target=work, args=(i % 4,)) for i in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors

@@ -184,3 +184,22 @@ def test_headline_size_parity(gpu_lib):
     r = dense.matvec_rows(p, rows, x) - b[rows]
     ax = dense.matvec_rows(p, rows, xo)
     assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(ax)
+
+
+def test_sphere_full_size_sampled_residual(gpu_lib):
+    """The 3D configuration at full size: unit sphere, N = 20480 Fibonacci points, single
+    layer, eps = 1e-6, octree leaf 128, 512 proxies, 64 right-hand sides.  The oracle's
+    exact rows of A give the residual on sampled rows (backward-error form)."""
+    rs = gpu_lib
+    n, eps = 20480, 1e-6
+    g = W.fibonacci_sphere(n)
+    p = _problem("lap3d_sl", g)
+    _, h = _gpu_factor(rs, "lap3d_sl", g, eps, 128, 512)
+    st = h.stats()
+    assert st["dim"] == 3 and st["root_size"] > 0
+    b = W.gaussian_rhs(n, 64, 2)
+    x = _gpu_solve(h, b)
+    rows = np.random.default_rng(1).choice(n, 48, replace=False)
+    r = dense.matvec_rows(p, rows, x) - b[rows]
+    ax = dense.matvec_rows(p, rows, x)
+    assert np.linalg.norm(r) <= 100 * eps * np.linalg.norm(ax)
