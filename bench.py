@@ -56,8 +56,11 @@ def parse():
 # kernels (rocprofv3 names, template arguments dropped) of each profiler family
 KERNELS_OF_FAMILY = {"assemble": ["k_assemble"], "id": ["k_compress_fused", "k_cpqr_id"],
                      "factor": ["k_diag_factor"],
-                     "sweep_up": ["k_sweep_up_mfma", "k_sweep_up", "k_sweep_seg"],
-                     "sweep_down": ["k_sweep_down_mfma", "k_sweep_down"],
+                     # k_sweep_seg / k_wide_* serve both directions; the workload timed
+                     # here sweeps with the per-handle kernels and has no wide boxes
+                     "sweep_up": ["k_sweep_up_mfma", "k_sweep_seg", "k_wide_gather",
+                                  "k_wide_gemm"],
+                     "sweep_down": ["k_sweep_down_mfma"],
                      "permute": ["k_permute_in", "k_permute_out", "k_permute_seg"]}
 
 
@@ -419,9 +422,7 @@ def main():
         a = time.perf_counter()
         rs.autotune(h, (1, 64, NRHS), reps=3, stream=stream)
         tune = {"ms": (time.perf_counter() - a) * 1e3,
-                "table": {"%s%s nrhs<=%d n<=%d" % ("mfma" if k[0] else "valu",
-                                                   " c128" if k[1] else "", 1 << k[2],
-                                                   32 * k[3]): w
+                "table": {"%snrhs<=%d n<=%d" % ("c128 " if k[1] else "", 1 << k[2], 32 * k[3]): w
                           for k, w in sorted(rs.tune_entries().items())}}
         h.free()
         progress("autotuned sweep tile widths")

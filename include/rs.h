@@ -188,11 +188,12 @@ rs_status rs_plan_free(rs_plan p);
 
 /* ----------------------------------------------------------- autotuner ---- */
 
-/* Times every valid tile width of the solve sweeps (MFMA class: 16, 32, 64 right-hand
- * sides per workgroup; VALU class: 1, 4, 16, 32) on handle h's own levels for each
+/* Times every valid tile width of the solve sweeps of small boxes (16, 32, 64
+ * right-hand sides per workgroup; boxes with n <= 512 real, 256 complex -- larger ones
+ * go through row-tiled GEMMs with nothing to tune) on handle h's own levels for each
  * nrhs in nrhs_list[count], reps timed repetitions each, and records the fastest width
- * per bucket -- (class, real/complex, ceil(log2 nrhs), largest box of the launch in
- * steps of 32) -- in a process-wide table that every later solve consults.  A width
+ * per bucket -- (real/complex, ceil(log2 nrhs), largest box of the launch in steps of
+ * 32) -- in a process-wide table that every later solve consults.  A width
  * changes the work distribution only: results are bitwise the same with any table.
  * Synchronous on `stream`.  Errors: RS_EINVAL, RS_EDEVICE. */
 rs_status rs_autotune(rs_handle h, const int32_t *nrhs_list, int32_t count, int32_t reps,

@@ -10,6 +10,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -1321,92 +1322,7 @@ struct SweepOps {
         E(reinterpret_cast<const S *>(B.E)), F(reinterpret_cast<const S *>(B.F)) {}
 };
 
-template <class S, int NT>
-__device__ __forceinline__ void sweep_up_box(const SweepBox &B, S *__restrict__ W, int nrhs,
-                                             int col0, S *sh) {
-  const int k = B.k, r = B.r;
-  const int nt = min(NT, nrhs - col0);
-  const SweepOps<S> O(B);
-  S *bs = sh;              // k x NT
-  S *t = sh + k * NT;      // r x NT
-  const int32_t *idx = B.idx;
-  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
-    const int i = e / NT, c = e - i * NT;
-    bs[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < r * NT; e += kThreads) {
-    const int j = e / NT, c = e - j * NT;
-    S s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : S(0.0);
-    const S *Tj = O.T + (int64_t)k * j;
-    for (int i = 0; i < k; ++i) s -= Tj[i] * bs[i * NT + c];
-    t[e] = s;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < r * NT; e += kThreads) {
-    const int j = e / NT, c = e - j * NT;
-    S s = S(0.0);
-    for (int l = 0; l < r; ++l) s += O.G[j + (int64_t)r * l] * t[l * NT + c];
-    if (c < nt) W[(int64_t)idx[k + j] * nrhs + col0 + c] = s;
-  }
-  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
-    const int i = e / NT, c = e - i * NT;
-    S s = bs[e];
-    for (int l = 0; l < r; ++l) s -= O.E[i + (int64_t)k * l] * t[l * NT + c];
-    if (c < nt) W[(int64_t)idx[i] * nrhs + col0 + c] = s;
-  }
-}
-
-template <class S, int NT>
-__device__ __forceinline__ void sweep_down_box(const SweepBox &B, S *__restrict__ W, int nrhs,
-                                               int col0, S *sh) {
-  const int k = B.k, r = B.r;
-  const int nt = min(NT, nrhs - col0);
-  const SweepOps<S> O(B);
-  S *z = sh;              // k x NT
-  S *u = sh + k * NT;     // r x NT
-  const int32_t *idx = B.idx;
-  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
-    const int i = e / NT, c = e - i * NT;
-    z[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < r * NT; e += kThreads) {
-    const int j = e / NT, c = e - j * NT;
-    S s = c < nt ? W[(int64_t)idx[k + j] * nrhs + col0 + c] : S(0.0);
-    for (int i = 0; i < k; ++i) s -= O.F[j + (int64_t)r * i] * z[i * NT + c];
-    u[e] = s;
-    if (c < nt) W[(int64_t)idx[k + j] * nrhs + col0 + c] = s;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < k * NT; e += kThreads) {
-    const int i = e / NT, c = e - i * NT;
-    S s = z[e];
-    for (int j = 0; j < r; ++j) s -= O.T[i + (int64_t)k * j] * u[j * NT + c];
-    if (c < nt) W[(int64_t)idx[i] * nrhs + col0 + c] = s;
-  }
-}
-
-template <class S, int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_up(const SweepBox *__restrict__ boxes,
-                                                       int first, S *__restrict__ W, int nrhs) {
-  extern __shared__ double sh_raw[];
-  const SweepBox &B = boxes[first + blockIdx.x];
-  if (B.r == 0) return;
-  sweep_up_box<S, NT>(B, W, nrhs, blockIdx.y * NT, reinterpret_cast<S *>(sh_raw));
-}
-
-template <class S, int NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_down(const SweepBox *__restrict__ boxes,
-                                                         int first, S *__restrict__ W,
-                                                         int nrhs) {
-  extern __shared__ double sh_raw[];
-  const SweepBox &B = boxes[first + blockIdx.x];
-  if (B.r == 0 || B.k == 0) return;
-  sweep_down_box<S, NT>(B, W, nrhs, blockIdx.y * NT, reinterpret_cast<S *>(sh_raw));
-}
-
-// ---- FP64 MFMA variants of the sweeps (boxes with n <= the MFMA class limit) --------
+// ---- FP64 MFMA sweeps (boxes with n <= the MFMA class limit) -----------------------
 // Every 16 x 16 output tile is produced by one wave with the full K loop, so the
 // arithmetic of a column does not depend on how many columns share the launch.
 // acc += A(r0 + i, kk) * Bs(kk, c0 + j) over kk in [0, K); A(i, kk) = a(i, kk) for
@@ -1554,6 +1470,119 @@ __global__ __launch_bounds__(kThreads) void k_sweep_down_mfma(const SweepBox *__
   sweep_down_box_mfma<S, NT>(B, W, nrhs, blockIdx.y * NT, reinterpret_cast<S *>(sh_raw));
 }
 
+
+// ---- wide boxes: row-tiled GEMMs over many workgroups ------------------------------
+// A box above the MFMA sweep class is applied as a short chain of products, each spread
+// over many workgroups: its rows of W are first gathered into a per-box scratch b
+// (n x nrhs, row-major, skeleton rows first), then
+//   up:   t = b_r - T^T b_s -> s1;  W_r <- G t;  W_s <- b_s - E t
+//   down: u = b_r - F b_s -> s1 and W_r;  W_s <- b_s - T u
+// Every output entry is one wave's full-length dot product in a fixed order, so results
+// depend on the box alone, never on the launch.
+enum WideStage { kWideUp1 = 0, kWideUp2, kWideUp3, kWideDn1, kWideDn2 };
+
+template <class S>
+__global__ void k_wide_gather(const SweepBox *__restrict__ boxes, const S *__restrict__ W,
+                              int nrhs, S *__restrict__ s0, int64_t stride0) {
+  const SweepBox bx = boxes[blockIdx.y];
+  const int64_t total = (int64_t)(bx.k + bx.r) * nrhs;
+  S *dst = s0 + blockIdx.y * stride0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / nrhs;
+    const int c = (int)(e - i * nrhs);
+    dst[e] = W[(int64_t)bx.idx[i] * nrhs + c];
+  }
+}
+
+// blockIdx.x = box * rt + row tile (16 rows), blockIdx.y = column block (16 CT columns).
+// The four waves of a workgroup take fixed quarters of the box's K range (a function of
+// K alone), each accumulating its 16 x 16 CT partial tile in k order with FP64 MFMA; the
+// partials meet in LDS and are summed in wave order.  A column's arithmetic is therefore
+// the same for every CT, nrhs and launch.
+template <class S, int STAGE, int CT>
+__global__ __launch_bounds__(kThreads) void k_wide_gemm(const SweepBox *__restrict__ boxes, int rt,
+                                                        S *__restrict__ W, int nrhs, S *s0,
+                                                        int64_t stride0, S *s1, int64_t stride1) {
+  constexpr int LD = 16 * CT + 1;                         // padded row of a partial tile
+  __shared__ double part_raw[kWaves * 16 * LD * (sizeof(S) / 8)];
+  S *part = reinterpret_cast<S *>(part_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, ci = lane & 15, kq = lane >> 4;
+  const int b = blockIdx.x / rt;
+  const int r0 = (blockIdx.x - b * rt) * 16, cb = blockIdx.y * 16 * CT;
+  const SweepBox bx = boxes[b];
+  const int k = bx.k, r = bx.r;
+  const int N = nrhs;
+  S *bs = s0 + b * stride0;
+  S *br = bs + (int64_t)k * N;
+  S *sb1 = s1 + b * stride1;
+  // out(i, c) = C0(i, c) - sum_l A(i, l) Bm(l, c)  (plain product for the G stage)
+  int M, K;
+  const S *A, *Bm, *C0;
+  int64_t sa_i, sa_l;
+  S *out_s = nullptr;
+  const int32_t *oidx = nullptr;
+  if (STAGE == kWideUp1) {
+    if (k == 0) return;                                   // the G stage reads b_r directly
+    M = r; K = k; A = reinterpret_cast<const S *>(bx.T); sa_i = k; sa_l = 1;
+    Bm = bs; C0 = br; out_s = sb1;
+  } else if (STAGE == kWideUp2) {
+    M = r; K = r; A = reinterpret_cast<const S *>(bx.G); sa_i = 1; sa_l = r;
+    Bm = k == 0 ? br : sb1; C0 = nullptr; oidx = bx.idx + k;
+  } else if (STAGE == kWideUp3) {
+    M = k; K = r; A = reinterpret_cast<const S *>(bx.E); sa_i = 1; sa_l = k;
+    Bm = sb1; C0 = bs; oidx = bx.idx;
+  } else if (STAGE == kWideDn1) {
+    M = r; K = k; A = reinterpret_cast<const S *>(bx.F); sa_i = 1; sa_l = r;
+    Bm = bs; C0 = br; out_s = sb1; oidx = bx.idx + k;
+  } else {
+    M = k; K = r; A = reinterpret_cast<const S *>(bx.T); sa_i = 1; sa_l = k;
+    Bm = sb1; C0 = bs; oidx = bx.idx;
+  }
+  if (r0 >= M) return;                                    // uniform over the workgroup
+  const int Kc = (K + 4 * kWaves - 1) / (4 * kWaves) * 4;
+  const int kb = wave * Kc, ke = min(K, kb + Kc);
+  const int i = r0 + ci;
+  const bool iok = i < M;
+  Acc<S> acc[CT];
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    S av[4], bv[4][CT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + 4 * u + kq;
+      const bool kok = kk < ke;
+      av[u] = (iok && kok) ? A[i * sa_i + kk * sa_l] : S(0.0);
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        const int c = cb + 16 * t + ci;
+        bv[u][t] = (kok && c < N) ? Bm[(int64_t)kk * N + c] : S(0.0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) acc[t].mma(av[u], bv[u][t]);
+  }
+  S *pw = part + wave * 16 * LD;
+#pragma unroll
+  for (int t = 0; t < CT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pw[(kq + 4 * v) * LD + 16 * t + ci] = acc[t].get(v);
+  __syncthreads();
+  for (int e = threadIdx.x; e < 16 * 16 * CT; e += kThreads) {
+    const int row = e / (16 * CT), col = e - row * (16 * CT);
+    const int gi = r0 + row, c = cb + col;
+    if (gi >= M || c >= N) continue;
+    const int o = row * LD + col;
+    S p = part[o];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) p = p + part[w * 16 * LD + o];
+    const S val = C0 ? C0[(int64_t)gi * N + c] - p : p;
+    if (out_s) out_s[(int64_t)gi * N + c] = val;
+    if (oidx) W[(int64_t)oidx[gi] * N + c] = val;
+  }
+}
+
 // Segment lookup for launches that cover the boxes of several handles: the last
 // segment whose first block is <= blockIdx.x.
 __device__ __forceinline__ int find_seg(const SweepSeg *segs, int nseg) {
@@ -1566,7 +1595,7 @@ __device__ __forceinline__ int find_seg(const SweepSeg *segs, int nseg) {
   return lo;
 }
 
-template <class S, int NT, bool MFMA, bool UP>
+template <class S, int NT, bool UP>
 __global__ __launch_bounds__(kThreads) void k_sweep_seg(const SweepSeg *__restrict__ segs,
                                                         int nseg) {
   extern __shared__ double sh_raw[];
@@ -1576,13 +1605,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_seg(const SweepSeg *__restri
   const int col0 = blockIdx.y * NT;
   if (B.r == 0 || (!UP && B.k == 0) || col0 >= Sg.nrhs) return;
   S *W = reinterpret_cast<S *>(Sg.W);
-  if constexpr (MFMA) {
-    if constexpr (UP) sweep_up_box_mfma<S, NT>(B, W, Sg.nrhs, col0, sh);
-    else sweep_down_box_mfma<S, NT>(B, W, Sg.nrhs, col0, sh);
-  } else {
-    if constexpr (UP) sweep_up_box<S, NT>(B, W, Sg.nrhs, col0, sh);
-    else sweep_down_box<S, NT>(B, W, Sg.nrhs, col0, sh);
-  }
+  if constexpr (UP) sweep_up_box_mfma<S, NT>(B, W, Sg.nrhs, col0, sh);
+  else sweep_down_box_mfma<S, NT>(B, W, Sg.nrhs, col0, sh);
 }
 
 // Tiled caller <-> tree order permutation for wide right-hand-side blocks: a tile of
@@ -1710,16 +1734,6 @@ void with_scalar(bool cplx, F &&f) {
   else f(double{});
 }
 
-// VALU sweeps: LDS holds max_n x NT scalars; keep it within 64 KiB.  A tuned choice
-// (rs_autotune) for the launch's bucket wins when it is valid.
-int pick_nt(int nrhs, int max_n, int es) {
-  const int tuned = tune_lookup(false, es, nrhs, max_n);
-  if (tuned && sweep_nt_valid(false, tuned, max_n, es)) return tuned;
-  int nt = nrhs <= 1 ? 1 : nrhs <= 4 ? 4 : nrhs <= 16 ? 16 : 32;
-  while (nt > 1 && (int64_t)max_n * nt * 8 * es > 65536) nt = nt == 32 ? 16 : nt == 16 ? 4 : 1;
-  return nt;
-}
-
 // MFMA sweeps: NT in {16, 32, 64} columns per workgroup, LDS within 64 KiB (the class
 // limit guarantees NT = 16 fits).
 int pick_nt_mfma(int nrhs, int max_n, int es) {
@@ -1728,21 +1742,6 @@ int pick_nt_mfma(int nrhs, int max_n, int es) {
   int nt = nrhs <= 16 ? 16 : nrhs <= 32 ? 32 : 64;
   while (nt > 16 && (int64_t)max_n * nt * 8 * es > 65536) nt /= 2;
   return nt;
-}
-
-template <class S, int NT>
-void sweep_nt(bool up, const SweepBox *boxes, int first, int count, double *W, int nrhs,
-              int max_n, hipStream_t st) {
-  dim3 grid(count, (nrhs + NT - 1) / NT);
-  const size_t lds = (size_t)max_n * NT * sizeof(S);
-  S *Ws = reinterpret_cast<S *>(W);
-  if (up)
-    hipLaunchKernelGGL((k_sweep_up<S, NT>), grid, dim3(kThreads), lds, st, boxes, first, Ws,
-                       nrhs);
-  else
-    hipLaunchKernelGGL((k_sweep_down<S, NT>), grid, dim3(kThreads), lds, st, boxes, first, Ws,
-                       nrhs);
-  check_launch(up ? "k_sweep_up" : "k_sweep_down");
 }
 
 template <class S, int NT>
@@ -1760,16 +1759,16 @@ void sweep_mfma_nt(bool up, const SweepBox *boxes, int first, int count, double 
   check_launch("k_sweep_mfma");
 }
 
-template <class S, int NT, bool MFMA>
+template <class S, int NT>
 void sweep_seg_nt(bool up, const SweepSeg *segs, int nseg, int nblocks, int max_nrhs, int max_n,
                   hipStream_t st) {
   dim3 grid(nblocks, (max_nrhs + NT - 1) / NT);
   const size_t lds = (size_t)max_n * NT * sizeof(S);
   if (up)
-    hipLaunchKernelGGL((k_sweep_seg<S, NT, MFMA, true>), grid, dim3(kThreads), lds, st, segs,
+    hipLaunchKernelGGL((k_sweep_seg<S, NT, true>), grid, dim3(kThreads), lds, st, segs,
                        nseg);
   else
-    hipLaunchKernelGGL((k_sweep_seg<S, NT, MFMA, false>), grid, dim3(kThreads), lds, st, segs,
+    hipLaunchKernelGGL((k_sweep_seg<S, NT, false>), grid, dim3(kThreads), lds, st, segs,
                        nseg);
   check_launch("k_sweep_seg");
 }
@@ -1878,8 +1877,7 @@ void tune_clear() {
 }
 
 bool sweep_nt_valid(bool mfma, int nt, int max_n, int es) {
-  const bool allowed = mfma ? (nt == 16 || nt == 32 || nt == 64)
-                            : (nt == 1 || nt == 4 || nt == 16 || nt == 32);
+  const bool allowed = mfma && (nt == 16 || nt == 32 || nt == 64);
   return allowed && (int64_t)max_n * nt * 8 * es <= 65536;
 }
 
@@ -2093,18 +2091,56 @@ void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_el
   check_launch("k_permute_seg");
 }
 
-void launch_sweep(bool cplx, bool up, const SweepBox *boxes, int first, int count, double *W,
-                  int nrhs, int max_n, hipStream_t st, int nt) {
-  if (count <= 0 || nrhs <= 0) return;
+
+int64_t wide_scratch_doubles(int count, int max_n, int max_r, int nrhs, bool cplx) {
+  return (int64_t)count * ((int64_t)max_n + max_r) * nrhs * (cplx ? 2 : 1);
+}
+
+void launch_wide_level(bool cplx, bool up, const SweepBox *boxes, int count, int max_n,
+                       int max_k, int max_r, double *W, int nrhs, double *scratch,
+                       int64_t scratch_doubles, hipStream_t st) {
+  if (count <= 0 || nrhs <= 0 || max_r <= 0) return;
+  const int64_t per_box = wide_scratch_doubles(1, max_n, max_r, nrhs, cplx);
+  if (scratch_doubles < per_box) throw std::runtime_error("wide sweep: scratch too small");
+  const int chunk = (int)std::min<int64_t>(count, scratch_doubles / per_box);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
-    if (nt && !sweep_nt_valid(false, nt, max_n, sizeof(S) / 8))
-      throw DeviceError("k_sweep: invalid tile width", hipErrorInvalidValue);
-    switch (nt ? nt : pick_nt(nrhs, max_n, sizeof(S) / 8)) {
-      case 1: sweep_nt<S, 1>(up, boxes, first, count, W, nrhs, max_n, st); break;
-      case 4: sweep_nt<S, 4>(up, boxes, first, count, W, nrhs, max_n, st); break;
-      case 16: sweep_nt<S, 16>(up, boxes, first, count, W, nrhs, max_n, st); break;
-      default: sweep_nt<S, 32>(up, boxes, first, count, W, nrhs, max_n, st); break;
+    S *Ws = reinterpret_cast<S *>(W);
+    const int64_t stride0 = (int64_t)max_n * nrhs, stride1 = (int64_t)max_r * nrhs;
+    for (int first = 0; first < count; first += chunk) {
+      const int cnt = std::min(chunk, count - first);
+      const SweepBox *bx = boxes + first;
+      S *s0 = reinterpret_cast<S *>(scratch);
+      S *s1 = s0 + (int64_t)cnt * stride0;
+      const int gx = (int)std::min<int64_t>((stride0 + 255) / 256, 1024);
+      hipLaunchKernelGGL(k_wide_gather<S>, dim3(gx, cnt), dim3(256), 0, st, bx,
+                         reinterpret_cast<const S *>(Ws), nrhs, s0, stride0);
+      check_launch("k_wide_gather");
+      const int ct = nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : 4;   // column tiles per wave
+      auto stage = [&](auto tag, int max_m) {
+        constexpr int ST = decltype(tag)::value;
+        if (max_m <= 0) return;
+        const int rt = (max_m + 15) / 16;
+        const dim3 grid(rt * cnt, (nrhs + 16 * ct - 1) / (16 * ct));
+        if (ct == 1)
+          hipLaunchKernelGGL((k_wide_gemm<S, ST, 1>), grid, dim3(kThreads), 0, st, bx, rt, Ws,
+                             nrhs, s0, stride0, s1, stride1);
+        else if (ct == 2)
+          hipLaunchKernelGGL((k_wide_gemm<S, ST, 2>), grid, dim3(kThreads), 0, st, bx, rt, Ws,
+                             nrhs, s0, stride0, s1, stride1);
+        else
+          hipLaunchKernelGGL((k_wide_gemm<S, ST, 4>), grid, dim3(kThreads), 0, st, bx, rt, Ws,
+                             nrhs, s0, stride0, s1, stride1);
+        check_launch("k_wide_gemm");
+      };
+      if (up) {
+        if (max_k > 0) stage(std::integral_constant<int, kWideUp1>{}, max_r);
+        stage(std::integral_constant<int, kWideUp2>{}, max_r);
+        stage(std::integral_constant<int, kWideUp3>{}, max_k);
+      } else {
+        stage(std::integral_constant<int, kWideDn1>{}, max_r);
+        stage(std::integral_constant<int, kWideDn2>{}, max_k);
+      }
     }
   });
 }
@@ -2126,27 +2162,18 @@ void launch_sweep_mfma(bool cplx, bool up, const SweepBox *boxes, int first, int
   });
 }
 
-void launch_sweep_seg(bool cplx, bool mfma, bool up, const SweepSeg *segs, int nseg,
-                      int nblocks, int max_nrhs, int max_n, hipStream_t st) {
+void launch_sweep_seg(bool cplx, bool up, const SweepSeg *segs, int nseg, int nblocks,
+                      int max_nrhs, int max_n, hipStream_t st) {
   if (nseg <= 0 || nblocks <= 0 || max_nrhs <= 0) return;
-  if (mfma && max_n > mfma_max_n(cplx))
+  if (max_n > mfma_max_n(cplx))
     throw DeviceError("k_sweep_seg: box too large for the MFMA class", hipErrorInvalidValue);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
     constexpr int es = sizeof(S) / 8;
-    if (mfma) {
-      switch (pick_nt_mfma(max_nrhs, max_n, es)) {
-        case 16: sweep_seg_nt<S, 16, true>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-        case 32: sweep_seg_nt<S, 32, true>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-        default: sweep_seg_nt<S, 64, true>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-      }
-    } else {
-      switch (pick_nt(max_nrhs, max_n, es)) {
-        case 1: sweep_seg_nt<S, 1, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-        case 4: sweep_seg_nt<S, 4, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-        case 16: sweep_seg_nt<S, 16, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-        default: sweep_seg_nt<S, 32, false>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
-      }
+    switch (pick_nt_mfma(max_nrhs, max_n, es)) {
+      case 16: sweep_seg_nt<S, 16>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+      case 32: sweep_seg_nt<S, 32>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
+      default: sweep_seg_nt<S, 64>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
     }
   });
 }

@@ -142,23 +142,32 @@ void launch_permute_out(bool cplx, double *B, int64_t ldb, const double *W, cons
                         int64_t n, int nrhs, hipStream_t st);
 void launch_permute_seg(bool cplx, const PermSeg *segs, int nseg, int64_t max_elems,
                         int max_nrhs, bool to_tree, hipStream_t st);
-// Boxes with n = k + r <= mfma_max_n are swept with FP64 MFMA tiles (any nrhs); larger
-// boxes with the FP64 VALU kernels.  The class of a box never depends on the launch.
+// Boxes with n = k + r <= mfma_max_n are swept with FP64 MFMA tiles, one workgroup per
+// box and column tile (any nrhs); larger boxes by the wide path (launch_wide_level), each
+// product a row-tiled MFMA GEMM over many workgroups.  The class of a box never depends
+// on the launch.
 constexpr int kMfmaMaxN = 512;
 constexpr int kMfmaMaxNComplex = 256;
 int mfma_max_n(bool cplx);
 // nt = 0: tile width from the tuning table, else the built-in choice; nt > 0 forces a
-// width (used by the autotuner; must be valid for the class and LDS budget).
-void launch_sweep(bool cplx, bool up, const SweepBox *boxes, int first, int count, double *W,
-                  int nrhs, int max_n, hipStream_t st, int nt = 0);
+// width (used by the autotuner; must be valid for the LDS budget).
 void launch_sweep_mfma(bool cplx, bool up, const SweepBox *boxes, int first, int count,
                        double *W, int nrhs, int max_n, hipStream_t st, int nt = 0);
-void launch_sweep_seg(bool cplx, bool mfma, bool up, const SweepSeg *segs, int nseg,
-                      int nblocks, int max_nrhs, int max_n, hipStream_t st);
+void launch_sweep_seg(bool cplx, bool up, const SweepSeg *segs, int nseg, int nblocks,
+                      int max_nrhs, int max_n, hipStream_t st);
+// Wide path over count boxes of one level (device descriptors): gathers each box's rows
+// of W (nrhs columns) into scratch, then up: t = b_r - T^T b_s, b_r <- G t,
+// b_s <- b_s - E t; down: u = y_r - F z, b_r <- u, b_s <- z - T u; one launch per stage
+// for all boxes.  max_n, max_k, max_r bound the boxes' n = k + r, k and r.  Boxes are
+// processed in chunks whose scratch fits scratch_doubles (at least one box's).
+int64_t wide_scratch_doubles(int count, int max_n, int max_r, int nrhs, bool cplx);
+void launch_wide_level(bool cplx, bool up, const SweepBox *boxes, int count, int max_n,
+                       int max_k, int max_r, double *W, int nrhs, double *scratch,
+                       int64_t scratch_doubles, hipStream_t st);
 
 // ------------------------------------------------------------------ tuning table
-// Tile widths of the sweep kernels per bucket (class, scalar size, ceil(log2 nrhs),
-// largest box in steps of 32).  Every width computes each output element with the same
+// Tile widths of the MFMA-class sweep kernels per bucket (class flag, scalar size,
+// ceil(log2 nrhs), largest box in steps of 32); only MFMA-class keys are valid.  Every width computes each output element with the same
 // arithmetic, so a table changes speed only, never results.
 bool sweep_nt_valid(bool mfma, int nt, int max_n, int es);
 uint32_t tune_key(bool mfma, int es, int nrhs, int max_n);

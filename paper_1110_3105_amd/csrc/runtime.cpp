@@ -32,7 +32,7 @@ void LevelRec::partition_classes(int mfma_limit) {
   std::vector<SweepBox> s2;
   std::vector<int> b2;
   n_small = 0;
-  max_n_small = max_n_large = 0;
+  max_n_small = max_n_large = max_k_large = max_r_large = 0;
   for (int i : order) {
     s2.push_back(sweep[i]);
     if (!boxes.empty()) b2.push_back(boxes[i]);
@@ -42,6 +42,8 @@ void LevelRec::partition_classes(int mfma_limit) {
       max_n_small = std::max(max_n_small, n);
     } else {
       max_n_large = std::max(max_n_large, n);
+      max_k_large = std::max(max_k_large, (int)sweep[i].k);
+      max_r_large = std::max(max_r_large, (int)sweep[i].r);
     }
   }
   sweep.swap(s2);
@@ -783,6 +785,23 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
   }
 }
 
+namespace {
+// Wide-class scratch of one level at nrhs columns: every wide box at once when that fits
+// kWideScratchCap doubles, else chunks of boxes (at least one box).
+constexpr int64_t kWideScratchCap = int64_t(64) << 20;
+int64_t wide_scratch_for(const LevelRec &lv, int nrhs, bool cplx) {
+  const int cnt = (int)lv.sweep.size() - lv.n_small;
+  if (cnt <= 0 || nrhs <= 0) return 0;
+  const int64_t per = wide_scratch_doubles(1, lv.max_n_large, lv.max_r_large, nrhs, cplx);
+  return std::min<int64_t>(per * cnt, std::max<int64_t>(per, kWideScratchCap));
+}
+int64_t wide_scratch_for(const rs_factor_s *h, int nrhs) {
+  int64_t m = wide_scratch_for(h->root, nrhs, h->cplx);
+  for (const LevelRec &lv : h->levels) m = std::max(m, wide_scratch_for(lv, nrhs, h->cplx));
+  return m;
+}
+}  // namespace
+
 void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
                hipStream_t st) {
   if (nrhs == 0) return;
@@ -795,8 +814,15 @@ void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
   struct Freer {
     double *W;
     hipStream_t st;
-    ~Freer() { (void)hipFreeAsync(W, st); }
+    ~Freer() {
+      if (W) (void)hipFreeAsync(W, st);
+    }
   } freer{W, st};
+  const int64_t wide_sz = wide_scratch_for(h, nrhs);
+  double *wide = nullptr;
+  if (wide_sz > 0)
+    RS_HIP_CHECK(hipMallocAsync((void **)&wide, (size_t)wide_sz * sizeof(double), st));
+  Freer wide_freer{wide, st};
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
   const bool prof = prof_on();
   Work wperm;
@@ -817,14 +843,17 @@ void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
       for (int i = 0; i < cnt; ++i) {
         ProfScope ps_(RS_K_SWEEP_UP, st);
         const int n = lv.sweep[i].k + lv.sweep[i].r;
-        if (i < lv.n_small) launch_sweep_mfma(cplx, true, lv.d_sweep, i, 1, W, nrhs, n, st);
-        else launch_sweep(cplx, true, lv.d_sweep, i, 1, W, nrhs, n, st);
+        if (i < lv.n_small)
+          launch_sweep_mfma(cplx, true, lv.d_sweep, i, 1, W, nrhs, n, st);
+        else
+          launch_wide_level(cplx, true, lv.d_sweep + i, 1, n, lv.sweep[i].k, lv.sweep[i].r, W,
+                            nrhs, wide, wide_sz, st);
       }
     } else {
       ProfScope ps_(RS_K_SWEEP_UP, st);
       launch_sweep_mfma(cplx, true, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
-      launch_sweep(cplx, true, lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs,
-                   lv.max_n_large, st);
+      launch_wide_level(cplx, true, lv.d_sweep + lv.n_small, cnt - lv.n_small, lv.max_n_large,
+                        lv.max_k_large, lv.max_r_large, W, nrhs, wide, wide_sz, st);
     }
   };
   auto down = [&](const LevelRec &lv) {
@@ -838,14 +867,17 @@ void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
       for (int i = 0; i < cnt; ++i) {
         ProfScope ps_(RS_K_SWEEP_DOWN, st);
         const int n = lv.sweep[i].k + lv.sweep[i].r;
-        if (i < lv.n_small) launch_sweep_mfma(cplx, false, lv.d_sweep, i, 1, W, nrhs, n, st);
-        else launch_sweep(cplx, false, lv.d_sweep, i, 1, W, nrhs, n, st);
+        if (i < lv.n_small)
+          launch_sweep_mfma(cplx, false, lv.d_sweep, i, 1, W, nrhs, n, st);
+        else
+          launch_wide_level(cplx, false, lv.d_sweep + i, 1, n, lv.sweep[i].k, lv.sweep[i].r, W,
+                            nrhs, wide, wide_sz, st);
       }
     } else {
       ProfScope ps_(RS_K_SWEEP_DOWN, st);
       launch_sweep_mfma(cplx, false, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
-      launch_sweep(cplx, false, lv.d_sweep, lv.n_small, cnt - lv.n_small, W, nrhs,
-                   lv.max_n_large, st);
+      launch_wide_level(cplx, false, lv.d_sweep + lv.n_small, cnt - lv.n_small, lv.max_n_large,
+                        lv.max_k_large, lv.max_r_large, W, nrhs, wide, wide_sz, st);
     }
   };
   for (const LevelRec &lv : h->levels) up(lv);
@@ -867,6 +899,14 @@ struct LaunchRec {
   int64_t seg_off;
   int nseg, nblocks, max_nrhs, max_n;
   bool up, mfma;
+  int64_t wide_off;   // wide class (mfma false): T.wide[wide_off, wide_off + nwide)
+  int nwide;
+};
+// Wide-class boxes of one handle's level (launch_wide_level arguments).
+struct WideRec {
+  const SweepBox *boxes;
+  double *W;
+  int count, max_n, max_k, max_r, nrhs;
 };
 void release_host_vector(void *p) { delete static_cast<std::vector<char> *>(p); }
 }  // namespace
@@ -883,6 +923,8 @@ struct SolveTables {
   int max_nrhs = 0;
   std::vector<PermSeg> perm;
   std::vector<SweepSeg> segs;
+  std::vector<WideRec> wide;
+  int64_t wide_scratch = 0;          // doubles
   std::vector<LaunchRec> launches;
 };
 
@@ -921,13 +963,20 @@ SolveTables build_tables(const std::vector<SolveRequest> &rq, double *W) {
   }
   auto add_step = [&](bool up, auto level_of) {
     for (int mfma = 1; mfma >= 0; --mfma) {
-      LaunchRec L{(int64_t)T.segs.size(), 0, 0, 0, 0, up, mfma == 1};
+      LaunchRec L{(int64_t)T.segs.size(), 0, 0, 0, 0, up, mfma == 1, (int64_t)T.wide.size(), 0};
       for (int i = 0; i < nq; ++i) {
         const LevelRec *lv = level_of(rq[i].h);
         if (!lv || lv->sweep.empty()) continue;
         const int lo = mfma ? 0 : lv->n_small;
         const int cnt = mfma ? lv->n_small : (int)lv->sweep.size() - lv->n_small;
         if (cnt <= 0) continue;
+        if (!mfma) {
+          T.wide.push_back(WideRec{lv->d_sweep + lo, W + woff[i] * es, cnt, lv->max_n_large,
+                                   lv->max_k_large, lv->max_r_large, rq[i].nrhs});
+          T.wide_scratch = std::max(T.wide_scratch, wide_scratch_for(*lv, rq[i].nrhs, T.cplx));
+          L.nwide++;
+          continue;
+        }
         SweepSeg s;
         s.boxes = lv->d_sweep + lo;
         s.W = W + woff[i] * es;
@@ -941,7 +990,7 @@ SolveTables build_tables(const std::vector<SolveRequest> &rq, double *W) {
         L.max_nrhs = std::max(L.max_nrhs, s.nrhs);
         L.max_n = std::max(L.max_n, mfma ? lv->max_n_small : lv->max_n_large);
       }
-      if (L.nseg) T.launches.push_back(L);
+      if (L.nseg || L.nwide) T.launches.push_back(L);
     }
   };
   for (int t = 0; t < max_levels; ++t)
@@ -968,7 +1017,7 @@ std::vector<char> *pack_tables(const SolveTables &T) {
 
 // The kernel launches of a group's solve; kernels only (no copies or fills), so the
 // sequence can be captured into a graph.
-void enqueue_group(const SolveTables &T, const char *dtab, hipStream_t st) {
+void enqueue_group(const SolveTables &T, const char *dtab, double *wide, hipStream_t st) {
   const PermSeg *d_perm = reinterpret_cast<const PermSeg *>(dtab);
   const SweepSeg *d_segs =
       reinterpret_cast<const SweepSeg *>(dtab + T.perm.size() * sizeof(PermSeg));
@@ -978,8 +1027,14 @@ void enqueue_group(const SolveTables &T, const char *dtab, hipStream_t st) {
   }
   for (const LaunchRec &L : T.launches) {
     ProfScope ps_(L.up ? RS_K_SWEEP_UP : RS_K_SWEEP_DOWN, st);
-    launch_sweep_seg(T.cplx, L.mfma, L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs,
-                     L.max_n, st);
+    if (L.nseg)
+      launch_sweep_seg(T.cplx, L.up, d_segs + L.seg_off, L.nseg, L.nblocks, L.max_nrhs, L.max_n,
+                       st);
+    for (int w = 0; w < L.nwide; ++w) {
+      const WideRec &R = T.wide[L.wide_off + w];
+      launch_wide_level(T.cplx, L.up, R.boxes, R.count, R.max_n, R.max_k, R.max_r, R.W, R.nrhs,
+                        wide, T.wide_scratch, st);
+    }
   }
   {
     ProfScope ps_(RS_K_PERMUTE, st);
@@ -998,7 +1053,11 @@ void solve_group(const std::vector<SolveRequest> &rq, hipStream_t st) {
   RS_HIP_CHECK(hipMallocAsync((void **)&dtab, host->size(), st));
   RS_HIP_CHECK(hipMemcpyAsync(dtab, host->data(), host->size(), hipMemcpyHostToDevice, st));
   RS_HIP_CHECK(hipLaunchHostFunc(st, release_host_vector, host));
-  enqueue_group(T, dtab, st);
+  double *wide = nullptr;
+  if (T.wide_scratch > 0)
+    RS_HIP_CHECK(hipMallocAsync((void **)&wide, (size_t)T.wide_scratch * sizeof(double), st));
+  enqueue_group(T, dtab, wide, st);
+  if (wide) RS_HIP_CHECK(hipFreeAsync(wide, st));
   RS_HIP_CHECK(hipFreeAsync(dtab, st));
   RS_HIP_CHECK(hipFreeAsync(W, st));
 }
@@ -1033,6 +1092,7 @@ SolvePlan *make_plan(const std::vector<SolveRequest> &reqs) {
   // persistent workspace and tables, uploaded before capture
   std::vector<SolveTables> tabs;
   std::vector<char *> dtabs;
+  std::vector<double *> wides;
   for (int g = 0; g < 2; ++g) {
     if (rq[g].empty()) continue;
     void *W = nullptr;
@@ -1045,6 +1105,12 @@ SolvePlan *make_plan(const std::vector<SolveRequest> &reqs) {
     plan->bufs.push_back(dtab);
     RS_HIP_CHECK(hipMemcpy(dtab, host->data(), host->size(), hipMemcpyHostToDevice));
     dtabs.push_back(static_cast<char *>(dtab));
+    void *wide = nullptr;
+    if (tabs.back().wide_scratch > 0) {
+      RS_HIP_CHECK(hipMalloc(&wide, (size_t)tabs.back().wide_scratch * sizeof(double)));
+      plan->bufs.push_back(wide);
+    }
+    wides.push_back(static_cast<double *>(wide));
   }
   hipStream_t cs = nullptr;
   RS_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1056,7 +1122,7 @@ SolvePlan *make_plan(const std::vector<SolveRequest> &reqs) {
     CaptureScope capture;              // the profiler records no events while capturing
     RS_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
-      for (size_t g = 0; g < tabs.size(); ++g) enqueue_group(tabs[g], dtabs[g], cs);
+      for (size_t g = 0; g < tabs.size(); ++g) enqueue_group(tabs[g], dtabs[g], wides[g], cs);
     } catch (...) {
       hipGraph_t junk = nullptr;
       (void)hipStreamEndCapture(cs, &junk);

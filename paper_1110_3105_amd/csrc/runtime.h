@@ -62,6 +62,7 @@ struct LevelRec {
   int max_n = 0;
   int n_small = 0;                 // sweep[0, n_small): MFMA class (n <= kMfmaMaxN)
   int max_n_small = 0, max_n_large = 0;
+  int max_k_large = 0, max_r_large = 0;   // over the wide class sweep[n_small, end)
   // Orders the boxes MFMA class (n <= mfma_limit) first and records the class boundary.
   void partition_classes(int mfma_limit);
 };

@@ -1,11 +1,11 @@
 // Autotuner of the solve sweeps' tile widths.
 //
-// For each requested nrhs, every level of a handle (and its root) is swept with each
-// valid tile width of its kernel class (MFMA: 16, 32, 64 columns per workgroup; VALU:
-// 1, 4, 16, 32), timed with HIP events on the caller's stream; the times are summed per
-// bucket of the tuning table (class, scalar type, ceil(log2 nrhs), largest box in steps
-// of 32) and the fastest width of each bucket is recorded.  Widths change only the
-// work distribution, never a result.
+// For each requested nrhs, the MFMA-class boxes of every level of a handle (and of its
+// root) are swept with each valid tile width (16, 32, 64 columns per workgroup), timed
+// with HIP events on the caller's stream; the times are summed per bucket of the tuning
+// table (scalar type, ceil(log2 nrhs), largest box in steps of 32) and the fastest width
+// of each bucket is recorded.  Widths change only the work distribution, never a result.
+// Wide-class boxes have no width to choose (one 16 x 16 tile per wave).
 #include <cstdio>
 #include <map>
 
@@ -34,22 +34,15 @@ void autotune(rs_factor_s *h, const std::vector<int> &nrhs_list, int reps, hipSt
     RS_HIP_CHECK(hipMemsetAsync(W.p, 0, W.bytes, st));
     double *w = W.as<double>();
     auto time_level = [&](const LevelRec &lv) {
-      for (int cls = 0; cls < 2; ++cls) {
-        const bool mfma = cls == 0;
-        const int first = mfma ? 0 : lv.n_small;
-        const int cnt = mfma ? lv.n_small : (int)lv.sweep.size() - lv.n_small;
-        const int mx = mfma ? lv.max_n_small : lv.max_n_large;
-        if (cnt <= 0) continue;
-        const uint32_t key = tune_key(mfma, es, nrhs, mx);
-        static const int cm[] = {16, 32, 64}, cv[] = {1, 4, 16, 32};
-        const int *cands = mfma ? cm : cv;
-        const int ncand = mfma ? 3 : 4;
-        for (int ci = 0; ci < ncand; ++ci) {
-          const int nt = cands[ci];
-          if (!sweep_nt_valid(mfma, nt, mx, es)) continue;
+      {
+        const int cnt = lv.n_small, mx = lv.max_n_small;
+        if (cnt <= 0) return;
+        const uint32_t key = tune_key(true, es, nrhs, mx);
+        static const int cands[] = {16, 32, 64};
+        for (int nt : cands) {
+          if (!sweep_nt_valid(true, nt, mx, es)) continue;
           auto run = [&](bool up) {
-            if (mfma) launch_sweep_mfma(cplx, up, lv.d_sweep, first, cnt, w, nrhs, mx, st, nt);
-            else launch_sweep(cplx, up, lv.d_sweep, first, cnt, w, nrhs, mx, st, nt);
+            launch_sweep_mfma(cplx, up, lv.d_sweep, 0, cnt, w, nrhs, mx, st, nt);
           };
           run(true);                                   // warm-up
           RS_HIP_CHECK(hipEventRecord(ev0, st));
@@ -102,9 +95,7 @@ void tune_load(const char *path) {
       std::fclose(f);
       throw UserError{RS_EINVAL, "malformed tuning file"};
     }
-    const bool mfma = key & 1u;
-    const bool ok = mfma ? (nt == 16 || nt == 32 || nt == 64)
-                         : (nt == 1 || nt == 4 || nt == 16 || nt == 32);
+    const bool ok = (key & 1u) && (nt == 16 || nt == 32 || nt == 64);
     if (!ok) {
       std::fclose(f);
       throw UserError{RS_EINVAL, "tuning file names an invalid tile width"};

@@ -1,0 +1,113 @@
+"""Boxes above the MFMA sweep class (n > 512 real, n > 256 complex) on the MI355X.
+
+Such boxes are applied by the wide path of the solve (the inverse application of
+Section 3.4): their rows of the right-hand side are gathered, and each product of the
+box's step (T^T b_s, G t, E t on the way up; F z, T u on the way down) runs as a
+row-tiled FP64 MFMA GEMM over many workgroups.  Leaves of up to 900 points (real) and
+330 points (complex) on the star put some non-root boxes with both skeleton and
+redundant DOFs in that class, beside boxes of the small class in the same level;
+eps = 0 puts the whole system in the root.  Criteria: the oracle's solution
+within 10 eps; residuals below 10 eps (second kind) or within 10 times the oracle's
+(first kind); bitwise equality across launch modes, batched solves and captured plans.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Problem, dense
+from oracle import factor as ofactor
+from parity_util import compare_skeletons, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _wide_boxes(F, limit):
+    return [b for b, r in F.records.items() if r.n > limit and 0 < r.k < r.n]
+
+
+def _solve(h, b, dtype, mode="level"):
+    import torch
+    B = to_device(b, dtype)
+    h.solve(B, launch_mode=mode)
+    torch.cuda.synchronize()
+    return B.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,n,leaf", [("lap2d_sl", 6000, 900), ("helm2d_cfie", 4000, 330)])
+def test_wide_boxes_parity_and_bitwise(gpu_lib, kind, n, leaf):
+    import torch
+    rs = gpu_lib
+    eps = 1e-9
+    g = W.star_curve(n)
+    cplx = kind == "helm2d_cfie"
+    if cplx:
+        k = W.helmholtz_wavenumber(g, 6.0)
+        p = Problem(kind, g.points, g.weights, g.normals, g.curvature, identity=0.5,
+                    wavenumber=k, eta=k)
+        extra = dict(normals=g.normals, curvature=g.curvature, identity=0.5, wavenumber=k,
+                     eta=k)
+        dtype, limit = torch.complex128, 256
+    else:
+        p = Problem(kind, g.points, g.weights)
+        extra = {}
+        dtype, limit = torch.float64, 512
+    F = ofactor(p, eps, leaf, 64)
+    assert _wide_boxes(F, limit), "workload has no wide non-root box"
+    t = rs.build_tree(g.points, leaf)
+    h = rs.factor(kind, t, g.points, g.weights, eps, proxy_points=64, **extra)
+    h2 = rs.factor(kind, t, g.points, g.weights, eps, proxy_points=64, launch_mode="per_box",
+                   **extra)
+    compared, tied = compare_skeletons(h, F)
+    assert compared >= 0.9 * len(F.records)
+    A = dense.matrix(p)
+    for nrhs in (1, 17, 64, 100):
+        b = W.gaussian_rhs(n, nrhs, 70 + nrhs, complex_valued=cplx)
+        x = _solve(h, b, dtype)
+        xo = F.solve(b)
+        if tied == 0:
+            assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
+        res = np.linalg.norm(A @ x - b) / np.linalg.norm(b)
+        if cplx:                       # second kind: the residual is of the size of eps
+            assert res <= 10 * eps, res
+        else:                          # first kind: within the oracle's own residual
+            reso = np.linalg.norm(A @ xo - b) / np.linalg.norm(b)
+            assert res <= 10 * max(eps, reso), (res, reso)
+        assert np.array_equal(x, _solve(h, b, dtype, "per_box"))
+        assert np.array_equal(x, _solve(h2, b, dtype, "per_box"))
+        # batched with a second, differently sized block of the same handle
+        b2 = W.gaussian_rhs(n, 3, 5, complex_valued=cplx)
+        B1, B2 = to_device(b, dtype), to_device(b2, dtype)
+        rs.solve_batched([h, h], [B1, B2])
+        torch.cuda.synchronize()
+        assert np.array_equal(B1.cpu().numpy(), x)
+        assert np.array_equal(B2.cpu().numpy(), _solve(h, b2, dtype))
+    # captured plan: replays equal the eager solve
+    b = W.gaussian_rhs(n, 9, 3, complex_valued=cplx)
+    ref = _solve(h, b, dtype)
+    B = to_device(b, dtype)
+    plan = rs.Plan([h], [B])
+    for rep in range(3):
+        B.copy_(to_device(b, dtype))
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(B.cpu().numpy(), ref), rep
+        _solve(h, W.gaussian_rhs(n, 2, rep, complex_valued=cplx), dtype)   # eager work between
+    plan.free()
+
+
+def test_wide_root_real_eps_zero(gpu_lib):
+    # eps = 0 keeps every DOF: a 1100 x 1100 root in the wide class, so the solve is
+    # dense Gaussian elimination's (blocked inversion of the root).
+    rs = gpu_lib
+    n = 1100
+    g = W.star_curve(n)
+    p = Problem("lap2d_sl", g.points, g.weights)
+    t = rs.build_tree(g.points, 32)
+    h = rs.factor("lap2d_sl", t, g.points, g.weights, 0.0, proxy_points=64)
+    assert h.stats()["root_size"] == n
+    for nrhs in (1, 33):
+        b = W.gaussian_rhs(n, nrhs, 13 + nrhs)
+        x = _solve(h, b, None)
+        xd = dense.solve(p, b)
+        assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-11
