@@ -2,6 +2,8 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <cstdint>
 #include <functional>
@@ -14,7 +16,15 @@ namespace rs {
 // Persistent pool of host worker threads for the level planner (created on first use,
 // alive for the process).  parallel_for(n, f) runs f(i) for i in [0, n) in contiguous
 // chunks on the calling thread plus the workers, and returns when all are done.
+//
+// Dispatch is one atomic word: (generation << 40) | (chunk count << 20) | next chunk.
+// A job publishes a new generation; workers claim chunks with compare-and-swap on that
+// word, so a worker still finishing one job can never take a chunk of the next.  Idle
+// workers spin for kSpinUs before sleeping on a condition variable (a planner issues
+// its parallel loops in bursts a few hundred microseconds apart; waking sleeping
+// threads costs tens of microseconds per loop).
 constexpr int kPlanThreads = 16;
+constexpr int kSpinUs = 300;
 class PlanPool {
  public:
   static PlanPool &get() {
@@ -22,40 +32,50 @@ class PlanPool {
     return *p;
   }
   int workers() const { return (int)th_.size(); }
-  // Runs job(0..nchunks) on the caller plus the workers.  One job at a time: a caller
-  // that finds the pool busy (another thread's job) runs all of its chunks itself.
+  // Runs job(0..nchunks) on the caller plus the workers (nchunks < 2^20).  One job at a
+  // time: a caller that finds the pool busy (another thread's job) runs all of its
+  // chunks itself.
   void run(int nchunks, const std::function<void(int)> &job) {
     std::unique_lock<std::mutex> owner(run_mu_, std::try_to_lock);
-    if (!owner.owns_lock()) {
+    if (!owner.owns_lock() || nchunks >= (1 << 20)) {
       for (int c = 0; c < nchunks; ++c) job(c);
       return;
     }
-    std::unique_lock<std::mutex> lk(mu_);
     job_ = &job;
-    nchunks_ = nchunks;
-    next_ = 1;                 // chunk 0 runs on the caller
-    pending_ = nchunks - 1;
-    ++gen_;
-    cv_.notify_all();
-    lk.unlock();
-    job(0);
-    lk.lock();
-    while (true) {             // the caller helps with the remaining chunks
-      if (next_ < nchunks_) {
-        const int c = next_++;
-        lk.unlock();
-        job(c);
-        lk.lock();
-        --pending_;
-        continue;
-      }
-      break;
+    pending_.store(nchunks, std::memory_order_relaxed);
+    gen_ = (gen_ + 1) & 0xFFFFFF;
+    slot_.store(pack(gen_, nchunks, 0), std::memory_order_release);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (sleepers_ > 0) cv_.notify_all();
     }
-    done_cv_.wait(lk, [&] { return pending_ == 0; });
+    int c;
+    while (claim(gen_, c)) {
+      job(c);
+      pending_.fetch_sub(1, std::memory_order_acq_rel);
+    }
+    while (pending_.load(std::memory_order_acquire) != 0) relax();
     job_ = nullptr;
   }
 
  private:
+  static uint64_t pack(uint32_t g, int n, int next) {
+    return ((uint64_t)g << 40) | ((uint64_t)n << 20) | (uint64_t)next;
+  }
+  static uint32_t gen_of(uint64_t v) { return (uint32_t)(v >> 40); }
+  static void relax() { __builtin_ia32_pause(); }
+  bool claim(uint32_t g, int &c) {
+    uint64_t v = slot_.load(std::memory_order_acquire);
+    while (true) {
+      if (gen_of(v) != g) return false;
+      const int n = (int)((v >> 20) & 0xFFFFF), next = (int)(v & 0xFFFFF);
+      if (next >= n) return false;
+      if (slot_.compare_exchange_weak(v, v + 1, std::memory_order_acq_rel)) {
+        c = next;
+        return true;
+      }
+    }
+  }
   PlanPool() {
     const int n = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()),
                                           kPlanThreads) - 1;
@@ -63,28 +83,40 @@ class PlanPool {
     for (auto &t : th_) t.detach();
   }
   void loop() {
-    uint64_t seen = 0;
-    std::unique_lock<std::mutex> lk(mu_);
+    uint32_t seen = 0;
     while (true) {
-      cv_.wait(lk, [&] { return gen_ != seen; });
-      seen = gen_;
-      while (job_ && next_ < nchunks_) {
-        const int c = next_++;
-        const std::function<void(int)> *job = job_;
-        lk.unlock();
-        (*job)(c);
-        lk.lock();
-        if (--pending_ == 0) done_cv_.notify_all();
+      auto t0 = std::chrono::steady_clock::now();
+      uint64_t v = slot_.load(std::memory_order_acquire);
+      int spins = 0;
+      while (gen_of(v) == seen) {
+        if (++spins % 64 == 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinUs)) {
+          std::unique_lock<std::mutex> lk(mu_);
+          ++sleepers_;
+          cv_.wait(lk, [&] { return gen_of(slot_.load(std::memory_order_acquire)) != seen; });
+          --sleepers_;
+        } else {
+          relax();
+        }
+        v = slot_.load(std::memory_order_acquire);
+      }
+      seen = gen_of(v);
+      int c;
+      while (claim(seen, c)) {
+        (*job_)(c);
+        pending_.fetch_sub(1, std::memory_order_acq_rel);
       }
     }
   }
   std::vector<std::thread> th_;
   std::mutex run_mu_;      // held by the caller whose job the workers serve
-  std::mutex mu_;
-  std::condition_variable cv_, done_cv_;
+  std::mutex mu_;          // sleeping workers
+  std::condition_variable cv_;
+  int sleepers_ = 0;
+  uint32_t gen_ = 0;       // written by the run_mu_ holder only
   const std::function<void(int)> *job_ = nullptr;
-  int nchunks_ = 0, next_ = 0, pending_ = 0;
-  uint64_t gen_ = 0;
+  std::atomic<uint64_t> slot_{0};
+  std::atomic<int> pending_{0};
 };
 
 template <class F>

@@ -20,7 +20,6 @@
 #include <condition_variable>
 #include <functional>
 #include <thread>
-#include <unordered_map>
 
 namespace rs {
 
@@ -130,32 +129,65 @@ struct ProbState {
   const Tree *t = nullptr;
   int pidx = 0;
   std::vector<std::vector<int32_t>> J, skel;
-  std::vector<int> leaves_by_depth;   // leaves sorted by depth
-  std::vector<std::unordered_map<uint64_t, int>> leaf_map;   // per depth: cell -> leaf
+  // Near-test candidates per box: boxes of its depth within nbr_radius cells (itself
+  // excluded) and coarser leaves within Rc cells of each of its ancestors.
+  std::vector<std::vector<int32_t>> nbr, coarse;
+  int R = 0, Rc = 0;
   int npx = 0;
   bool log_kernel = false;
 };
 
-uint64_t cell_key(int64_t x, int64_t y, int64_t z) {
-  return ((uint64_t)(x + (1 << 20)) << 42) | ((uint64_t)(y + (1 << 20)) << 21) |
-         (uint64_t)(z + (1 << 20));
+int cheb(const Tree &t, int a, int b) {
+  int64_t m = 0;
+  for (int x = 0; x < 3; ++x) m = std::max<int64_t>(m, std::abs(t.icoord[3 * a + x] - t.icoord[3 * b + x]));
+  return (int)std::min<int64_t>(m, INT32_MAX);
+}
+
+// Candidate lists of the near test (Section 3.2), top-down over the depths with no
+// hashing: a box's same-depth neighbours within Rl = max(R, Rc) cells are children of
+// its parent or of the parent's neighbours (whose list covers the needed ceil(Rl/2)
+// cells), and its coarse-leaf candidates are its parent's plus the leaves among the
+// parent's neighbours within Rc cells.  R and Rc are the cell radii that contain every
+// point within the proxy radius at the box's depth and at each coarser depth.
+void plan_neighbors(ProbState &ps) {
+  const Tree &t = *ps.t;
+  const double ratio = ps.req->k->proxy_ratio;
+  ps.R = (int)std::ceil(ratio - 0.5) + 1;
+  ps.Rc = (int)std::ceil((ratio - 0.5) * 0.5) + 1;
+  const int Rl = std::max(ps.R, ps.Rc);
+  const int nb = t.nbox();
+  ps.nbr.assign(nb, {});
+  ps.coarse.assign(nb, {});
+  for (int d = 1; d <= t.maxdepth; ++d) {
+    const std::vector<int> &boxes = t.levels[d];
+    parallel_for((int)boxes.size(), [&](int bi) {
+      const int b = boxes[bi], p = t.parent[b];
+      std::vector<int32_t> &out = ps.nbr[b];
+      auto children_of = [&](int q) {
+        for (int c = t.first_child[q]; c < t.first_child[q] + t.nchild[q]; ++c)
+          if (c != b && cheb(t, c, b) <= Rl) out.push_back(c);
+      };
+      children_of(p);
+      for (int q : ps.nbr[p]) children_of(q);
+      std::vector<int32_t> &co = ps.coarse[b];
+      co = ps.coarse[p];
+      for (int q : ps.nbr[p])
+        if (t.is_leaf(q) && cheb(t, q, p) <= ps.Rc) co.push_back(q);
+    }, 16);
+  }
 }
 
 // Near DOFs of every box of depth d: active DOFs outside the box's own active set,
-// strictly inside the proxy radius (Section 3.2).  Candidates come from the boxes of
-// the same depth in the surrounding cells and from coarser leaves around the box's
-// ancestors (exact integer box coordinates); each candidate is then tested with
-// |x - c|^2 < rho^2.
+// strictly inside the proxy radius (Section 3.2).  The active DOFs at depth d are the
+// active sets of the boxes of depth d and the points of coarser leaves; candidates come
+// from the lists of plan_neighbors and each is tested with |x - c|^2 < rho^2.  Candidate
+// boxes own disjoint, ascending ranges of tree positions, so visiting them by range
+// start yields the list in ascending order.
 void plan_near(ProbState &ps, int d, std::vector<std::vector<int32_t>> &near) {
   const Tree &t = *ps.t;
   const std::vector<int> &boxes = t.levels[d];
   const int dim = t.dim;
   const double ratio = ps.req->k->proxy_ratio;
-  std::unordered_map<uint64_t, int> same;
-  same.reserve(boxes.size() * 2 + 8);
-  for (int b : boxes) same[cell_key(t.icoord[3 * b], t.icoord[3 * b + 1], t.icoord[3 * b + 2])] = b;
-  const int R = (int)std::ceil(ratio - 0.5) + 1;                // same-depth cell radius
-  const int Rc = (int)std::ceil((ratio - 0.5) * 0.5) + 1;      // coarser-depth cell radius
   near.assign(boxes.size(), {});
   parallel_for((int)boxes.size(), [&](int bi) {
     const int b = boxes[bi];
@@ -171,33 +203,21 @@ void plan_near(ProbState &ps, int d, std::vector<std::vector<int32_t>> &near) {
       }
       if (d2 < rho2) out.push_back(g);
     };
-    const int64_t *ic = &t.icoord[3 * b];
-    const int Rz = dim == 3 ? R : 0;
-    for (int64_t o0 = -R; o0 <= R; ++o0)
-      for (int64_t o1 = -R; o1 <= R; ++o1)
-        for (int64_t o2 = -Rz; o2 <= Rz; ++o2) {
-          if (o0 == 0 && o1 == 0 && o2 == 0) continue;
-          auto it = same.find(cell_key(ic[0] + o0, ic[1] + o1, ic[2] + o2));
-          if (it == same.end()) continue;
-          for (int32_t g : ps.J[it->second]) test(g);
-        }
-    const int Rcz = dim == 3 ? Rc : 0;
-    for (int dc = 0; dc < d; ++dc) {
-      const auto &lm = ps.leaf_map[dc];
-      if (lm.empty()) continue;
-      const int sh = d - dc;
-      const int64_t a0 = ic[0] >> sh, a1 = ic[1] >> sh, a2 = ic[2] >> sh;
-      for (int64_t o0 = -Rc; o0 <= Rc; ++o0)
-        for (int64_t o1 = -Rc; o1 <= Rc; ++o1)
-          for (int64_t o2 = -Rcz; o2 <= Rcz; ++o2) {
-            auto it = lm.find(cell_key(a0 + o0, a1 + o1, a2 + o2));
-            if (it == lm.end()) continue;
-            const int L = it->second;
-            for (int64_t g = t.begin[L]; g < t.end[L]; ++g) test((int32_t)g);
-          }
+    thread_local std::vector<int32_t> cand;
+    cand.clear();
+    for (int q : ps.nbr[b])
+      if (cheb(t, q, b) <= ps.R) cand.push_back(q);
+    cand.insert(cand.end(), ps.coarse[b].begin(), ps.coarse[b].end());
+    std::sort(cand.begin(), cand.end(),
+              [&](int32_t x, int32_t y) { return t.begin[x] < t.begin[y]; });
+    for (int q : cand) {
+      if (t.depth[q] == d) {
+        for (int32_t g : ps.J[q]) test(g);
+      } else {
+        for (int64_t g = t.begin[q]; g < t.end[q]; ++g) test((int32_t)g);
+      }
     }
-    std::sort(out.begin(), out.end());
-  });
+  }, 8);
 }
 
 // Copies the geometry of one request to device memory in tree order.
@@ -254,15 +274,7 @@ void setup_problem(ProbState &ps, hipStream_t st) {
   const int nb = t.nbox();
   ps.J.assign(nb, {});
   ps.skel.assign(nb, {});
-  ps.leaf_map.assign(t.maxdepth + 1, {});
-  for (int b = 0; b < t.nbox(); ++b)
-    if (t.is_leaf(b))
-      ps.leaf_map[t.depth[b]][cell_key(t.icoord[3 * b], t.icoord[3 * b + 1], t.icoord[3 * b + 2])] = b;
-  ps.leaves_by_depth.clear();
-  for (int b = 0; b < nb; ++b)
-    if (t.is_leaf(b)) ps.leaves_by_depth.push_back(b);
-  std::stable_sort(ps.leaves_by_depth.begin(), ps.leaves_by_depth.end(),
-                   [&](int a, int b) { return t.depth[a] < t.depth[b]; });
+  plan_neighbors(ps);
   h->nbox = nb;
   h->box_k.assign(nb, -1);
   h->box_J.assign(nb, {});
@@ -387,7 +399,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       for (int p = 0; p < np; ++p) {
         const int d = ps[p].t->maxdepth - step;
         if (d < 1) continue;
-        for (int b : ps[p].t->levels[d]) gather_J(ps[p], b);
+        const std::vector<int> &lvb = ps[p].t->levels[d];
+        parallel_for((int)lvb.size(), [&](int i) { gather_J(ps[p], lvb[i]); }, 64);
         std::vector<std::vector<int32_t>> nr;
         plan_near(ps[p], d, nr);
         for (auto &v : nr) near_all[idx++] = std::move(v);
@@ -420,9 +433,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         near_all.swap(nr2);
       }
     }
-    std::vector<int32_t> pool;
     std::vector<CompBox> comp(cnt);
-    int64_t M_total = 0, order_total = 0, work_total = 0;
+    int64_t M_total = 0, order_total = 0, work_total = 0, pool_total = 0;
     int max_n = 0, max_m_step = 0;
     int max_n_f = 0, max_m_f = 0, max_n_d = 0, max_m_d = 0;
     for (int i = 0; i < cnt; ++i) {
@@ -435,10 +447,9 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       cb.n = (int)J.size();
       cb.nn = (int)near_all[i].size();
       cb.m = 2 * cb.nn + 2 * P.npx + (P.log_kernel ? 2 : 0);
-      cb.J_off = (int64_t)pool.size();
-      pool.insert(pool.end(), J.begin(), J.end());
-      cb.N_off = (int64_t)pool.size();
-      pool.insert(pool.end(), near_all[i].begin(), near_all[i].end());
+      cb.J_off = pool_total;
+      cb.N_off = pool_total + cb.n;
+      pool_total += cb.n + cb.nn;
       cb.M_off = M_total;
       // fused boxes keep only the first k rows of R (k <= n): n x n scalars
       M_total += (int64_t)(i < nf ? cb.n : cb.m) * cb.n;
@@ -462,6 +473,12 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       max_m_step = std::max(max_m_step, cb.m);
       max_m_seen = std::max<int64_t>(max_m_seen, cb.m);
     }
+    std::vector<int32_t> pool(pool_total);
+    parallel_for(cnt, [&](int i) {
+      const std::vector<int32_t> &J = items[i].ps->J[items[i].box];
+      std::copy(J.begin(), J.end(), pool.begin() + comp[i].J_off);
+      std::copy(near_all[i].begin(), near_all[i].end(), pool.begin() + comp[i].N_off);
+    }, 64);
     plan_ms += ms_since(tp);
     if (cpqr_lds_bytes(cplx, max_n, 1 << 30) > 160 * 1024)
       throw UserError{RS_ENOTSUP, "a box's active set exceeds the on-chip ID limit"};
@@ -565,8 +582,6 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     // skeleton lists (the next level's active sets) and profiler work counts
     Work w_asm, w_id, w_fac;
     for (int i = 0; i < cnt; ++i) {
-      ProbState &P = *items[i].ps;
-      const int b = items[i].box;
       const CompBox &cb = comp[i];
       const int k = ranks[i];
       if (i < nf) {
@@ -576,12 +591,16 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         w_id += work_id(cb.m, cb.n, k, cplx);
       }
       w_fac += work_factor(cb.n, k, cplx);
-      const std::vector<int32_t> &J = P.J[b];
-      const int32_t *ord = order.data() + cb.order_off;
-      std::vector<int32_t> &sk = P.skel[b];
-      sk.resize(k);
-      for (int a = 0; a < k; ++a) sk[a] = J[ord[a]];
     }
+    parallel_for(cnt, [&](int i) {
+      ProbState &P = *items[i].ps;
+      const int b = items[i].box;
+      const std::vector<int32_t> &J = P.J[b];
+      const int32_t *ord = order.data() + comp[i].order_off;
+      std::vector<int32_t> &sk = P.skel[b];
+      sk.resize(ranks[i]);
+      for (int a = 0; a < ranks[i]; ++a) sk[a] = J[ord[a]];
+    }, 64);
     prof_add_work(RS_K_ASSEMBLE, w_asm);
     prof_add_work(RS_K_ID, w_id);
     prof_add_work(RS_K_FACTOR, w_fac);
@@ -598,15 +617,24 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       idx_keep[p].resize(idx_fill[p]);
       idx_fill[p] = 0;
     }
+    std::vector<int64_t> idx_at(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      const int pi = items[i].ps->pidx;
+      idx_at[i] = idx_fill[pi];
+      idx_fill[pi] += comp[i].n;
+    }
+    parallel_for(cnt, [&](int i) {
+      ProbState &P = *items[i].ps;
+      const int32_t *ord = order.data() + comp[i].order_off;
+      int32_t *idx = idx_keep[P.pidx].data() + idx_at[i];
+      const std::vector<int32_t> &J = P.J[items[i].box];
+      for (int a = 0; a < comp[i].n; ++a) idx[a] = J[ord[a]];
+    }, 64);
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
       const int k = ranks[i], n = comp[i].n;
-      const int32_t *ord = order.data() + comp[i].order_off;
-      int32_t *idx = idx_keep[P.pidx].data() + idx_fill[P.pidx];
-      for (int a = 0; a < n; ++a) idx[a] = P.J[b][ord[a]];
-      int32_t *d_idx = d_idx_base[P.pidx] + idx_fill[P.pidx];
-      idx_fill[P.pidx] += n;
+      int32_t *d_idx = d_idx_base[P.pidx] + idx_at[i];
       SweepBox sb;
       sb.k = k;
       sb.r = n - k;

@@ -20,17 +20,30 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   dim = dim_;
   n = n_;
   leaf_size = leaf;
+  // bounding box: per-chunk extremes, combined in chunk order (min / max are exact)
+  constexpr int64_t kPtsChunk = 16384;
+  const int nck = (int)std::max<int64_t>(1, (n + kPtsChunk - 1) / kPtsChunk);
+  std::vector<std::array<double, 6>> ext(nck);
+  parallel_for(nck, [&](int ci) {
+    const int64_t i0 = ci * kPtsChunk, i1 = std::min(n, i0 + kPtsChunk);
+    std::array<double, 6> &x = ext[ci];
+    for (int a = 0; a < dim; ++a) x[a] = x[3 + a] = pts[(i0 < n ? i0 : 0) * dim + a];
+    for (int64_t i = i0; i < i1; ++i)
+      for (int a = 0; a < dim; ++a) {
+        const double v = pts[i * dim + a];
+        x[a] = std::min(x[a], v);
+        x[3 + a] = std::max(x[3 + a], v);
+      }
+  }, 1);
   double lo[3], hi[3];
   for (int a = 0; a < dim; ++a) {
-    lo[a] = pts[a];
-    hi[a] = pts[a];
-  }
-  for (int64_t i = 0; i < n; ++i)
-    for (int a = 0; a < dim; ++a) {
-      const double v = pts[i * dim + a];
-      lo[a] = std::min(lo[a], v);
-      hi[a] = std::max(hi[a], v);
+    lo[a] = ext[0][a];
+    hi[a] = ext[0][3 + a];
+    for (int ci = 1; ci < nck; ++ci) {
+      lo[a] = std::min(lo[a], ext[ci][a]);
+      hi[a] = std::max(hi[a], ext[ci][3 + a]);
     }
+  }
   double c0[3] = {0, 0, 0};
   double s0 = 0.0;
   for (int a = 0; a < dim; ++a) {
@@ -38,7 +51,9 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
     s0 = std::max(s0, hi[a] - lo[a]);
   }
   perm.resize(n);
-  for (int64_t i = 0; i < n; ++i) perm[i] = i;
+  parallel_for(nck, [&](int ci) {
+    for (int64_t i = ci * kPtsChunk; i < std::min(n, (ci + 1) * kPtsChunk); ++i) perm[i] = i;
+  }, 1);
   center.clear(); side.clear(); depth.clear(); parent.clear(); begin.clear(); end.clear();
   first_child.clear(); nchild.clear(); icoord.clear();
 
@@ -62,34 +77,89 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   std::vector<int64_t> tmp(n);
   std::vector<int> code(n);
   std::vector<int> cur = {0};
+  // A box with more than kPartChunk points is partitioned by several tasks (consecutive
+  // chunks of its range): each counts its codes, the counts are prefix-summed in chunk
+  // order, and each task scatters its points -- the same stable order as one pass.
+  constexpr int64_t kPartChunk = 4096;
+  struct Task {
+    int bi;
+    int64_t i0, i1;
+    std::array<int64_t, 8> cnt, pos;
+  };
   while (!cur.empty()) {
     const int nb = (int)cur.size();
     std::vector<std::array<int64_t, 8>> counts(nb);
     std::vector<char> split(nb, 0);
-    parallel_for(nb, [&](int bi) {
+    std::vector<Task> tasks;
+    for (int bi = 0; bi < nb; ++bi) {
       const int q = cur[bi];
       const int64_t b = begin[q], e = end[q];
-      if (!(e - b > leaf_size && depth[q] < kMaxDepth && side[q] > 0.0)) return;
+      if (!(e - b > leaf_size && depth[q] < kMaxDepth && side[q] > 0.0)) continue;
       split[bi] = 1;
+      for (int64_t i0 = b; i0 < e; i0 += kPartChunk) {
+        Task tk;
+        tk.bi = bi;
+        tk.i0 = i0;
+        tk.i1 = std::min(e, i0 + kPartChunk);
+        tasks.push_back(tk);
+      }
+    }
+    const int nt = (int)tasks.size();
+    auto count_task = [&](Task &tk) {
+      const int q = cur[tk.bi];
       const double c[3] = {center[3 * q], center[3 * q + 1], center[3 * q + 2]};
-      std::array<int64_t, 8> &cnt = counts[bi];
-      cnt.fill(0);
-      for (int64_t i = b; i < e; ++i) {
+      tk.cnt.fill(0);
+      for (int64_t i = tk.i0; i < tk.i1; ++i) {
         const int64_t g = perm[i];
         int cc = 0;
         for (int a = 0; a < dim; ++a) cc |= (pts[g * dim + a] >= c[a] ? 1 : 0) << a;
         code[i] = cc;
-        cnt[cc]++;
+        tk.cnt[cc]++;
       }
-      int64_t pos[8];
-      int64_t acc = b;
-      for (int cc = 0; cc < ncode; ++cc) {
-        pos[cc] = acc;
-        acc += cnt[cc];
+    };
+    bool one_per_box = true;
+    for (int ti = 1; ti < nt; ++ti) one_per_box = one_per_box && tasks[ti].bi != tasks[ti - 1].bi;
+    if (one_per_box) {   // every box in one task: count, scatter and copy back in place
+      parallel_for(nt, [&](int ti) {
+        Task &tk = tasks[ti];
+        count_task(tk);
+        std::array<int64_t, 8> &cnt = counts[tk.bi];
+        cnt = tk.cnt;
+        int64_t pos[8], acc = tk.i0;
+        for (int cc = 0; cc < ncode; ++cc) {
+          pos[cc] = acc;
+          acc += cnt[cc];
+        }
+        for (int64_t i = tk.i0; i < tk.i1; ++i) tmp[pos[code[i]]++] = perm[i];
+        std::copy(tmp.begin() + tk.i0, tmp.begin() + tk.i1, perm.begin() + tk.i0);
+      }, 1);
+    } else {
+      parallel_for(nt, [&](int ti) { count_task(tasks[ti]); }, 1);
+      for (int ti = 0; ti < nt;) {      // per box: child offsets, then each task's start
+        const int bi = tasks[ti].bi;
+        int te = ti;
+        std::array<int64_t, 8> &cnt = counts[bi];
+        cnt.fill(0);
+        for (; te < nt && tasks[te].bi == bi; ++te)
+          for (int cc = 0; cc < ncode; ++cc) cnt[cc] += tasks[te].cnt[cc];
+        int64_t acc = begin[cur[bi]];
+        for (int cc = 0; cc < ncode; ++cc) {
+          for (int t2 = ti; t2 < te; ++t2) {
+            tasks[t2].pos[cc] = acc;
+            acc += tasks[t2].cnt[cc];
+          }
+        }
+        ti = te;
       }
-      for (int64_t i = b; i < e; ++i) tmp[pos[code[i]]++] = perm[i];
-      std::copy(tmp.begin() + b, tmp.begin() + e, perm.begin() + b);
-    }, 1);
+      parallel_for(nt, [&](int ti) {
+        Task &tk = tasks[ti];
+        for (int64_t i = tk.i0; i < tk.i1; ++i) tmp[tk.pos[code[i]]++] = perm[i];
+      }, 1);
+      parallel_for(nt, [&](int ti) {
+        std::copy(tmp.begin() + tasks[ti].i0, tmp.begin() + tasks[ti].i1,
+                  perm.begin() + tasks[ti].i0);
+      }, 1);
+    }
     std::vector<int> next;
     for (int bi = 0; bi < nb; ++bi) {
       if (!split[bi]) continue;
@@ -118,8 +188,11 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   for (int bx = 0; bx < (int)side.size(); ++bx) levels[depth[bx]].push_back(bx);
   // tree-order coordinates (structure of arrays)
   coords.assign((size_t)dim * n, 0.0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int a = 0; a < dim; ++a) coords[(size_t)a * n + i] = pts[perm[i] * dim + a];
+  parallel_for(nck, [&](int ci) {
+    const int64_t i0 = ci * kPtsChunk, i1 = std::min(n, i0 + kPtsChunk);
+    for (int64_t i = i0; i < i1; ++i)
+      for (int a = 0; a < dim; ++a) coords[(size_t)a * n + i] = pts[perm[i] * dim + a];
+  }, 1);
 }
 
 }  // namespace rs
