@@ -909,46 +909,120 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
 
 
 // --------------------------------------------------------------------------
-// Blocked Gauss-Jordan inversion with partial pivoting for large blocks (r >= kGjBlockMinR).
-// Pivot rows are not swapped: piv[j] records the row that eliminates column j.  Columns
-// are processed in panels of kPB: the panel's steps run on an LDS (or workspace) copy of
-// its columns; their combined effect on every other column q is the rank-kPB update
+// Blocked Gauss-Jordan inversion with partial pivoting (the box inversions of Section
+// 3.4).  Pivot rows are not swapped: piv[j] records the row that eliminates column j.
+// Columns are processed in panels of kPB: the panel's steps run on the panel's columns
+// only (in place when A is in LDS, else on an LDS or workspace copy); their combined
+// effect on every other column q is the rank-kPB update
 //   A(i, q) <- [i not a pivot of the panel] A(i, q) + P(i, :) W(:, q),
 // where P is the panel after its steps and W(s, q) = A(piv[p0 + s], q) before them
 // (the panel's columns equal those of the accumulated row-operation matrix), done with
 // FP64 MFMA tiles.  At the end the in-place array Y holds the inverse as
 // A^{-1}(a, b) = Y(piv[a], q[b]) with q = piv^{-1}; it is written to G (r x r) in that
 // order.  Returns false on a zero or non-finite pivot.
+//
+// For r <= kWavePanelMaxR one wave runs a panel's steps alone (lanes over rows, no
+// workgroup barrier between steps; the other waves wait once per panel); larger blocks
+// spread each step over the workgroup.  Both perform the same operations on every
+// element, so the result depends on the block alone.
 constexpr int kPB = 16;           // panel width
 constexpr int kQC = 128;          // columns per chunk of the deferred update
-constexpr int kGjBlockMinR = 129;  // r at which a box switches to the blocked inversion
+constexpr int kWavePanelMaxR = 512;
 
 template <class S>
 __host__ __device__ constexpr size_t gj_panel_lds_max() { return 64 * 1024; }
 
-// LDS bytes of the blocked inversion's buffers for r unknowns (panel copy included when
-// it fits gj_panel_lds_max, otherwise it lives in the workspace).
+// LDS bytes of the blocked inversion's buffers for up to r unknowns; with a_in_lds the
+// panel needs no copy, otherwise the copy is in LDS when it fits gj_panel_lds_max.  A
+// launch reserves for its largest box, and any smaller box whose copy fits must find
+// room too: the reservation is min(copy, gj_panel_lds_max), never zero.
 template <class S>
-__host__ __device__ inline size_t gj_blocked_lds(int r, int nw) {
-  // the panel is in LDS iff it fits; a launch reserves for every r <= its largest box
+__host__ __device__ inline size_t gj_blocked_lds(int r, int nw, bool a_in_lds) {
   const size_t panel = (size_t)r * kPB * sizeof(S);
-  size_t b = panel <= gj_panel_lds_max<S>() ? panel : gj_panel_lds_max<S>();
+  size_t b = a_in_lds ? 0 : (panel <= gj_panel_lds_max<S>() ? panel : gj_panel_lds_max<S>());
   b += (size_t)kPB * kQC * sizeof(S) + (size_t)kPB * sizeof(S);
   b += (size_t)nw * (sizeof(double) + sizeof(int));
-  b += (size_t)3 * r * sizeof(int);
-  return b;
+  b += (size_t)3 * r * sizeof(int) + 2 * sizeof(int);
+  return (b + 15) & ~(size_t)15;
+}
+
+// Orders the memory operations of the lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One non-pivot row of a panel step: A(i, c) <- A(i, c) - f prow[c] (c != jj) and
+// A(i, jj) <- -f inv with f = A(i, jj).  The row's entries are loaded in groups of 8
+// before any store, so the loads are in flight together.
+template <class S>
+__device__ __forceinline__ void gj_row_update(S *row, int ldp, int pb, int jj, S inv,
+                                              const S *prow) {
+  const S f = row[jj * ldp];
+#pragma unroll
+  for (int h = 0; h < kPB; h += 8) {
+    S v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = h + c < pb ? row[(h + c) * ldp] : S(0.0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (h + c < pb) row[(h + c) * ldp] = h + c == jj ? S(0.0) - f * inv : v[c] - f * prow[h + c];
+  }
+}
+
+// All rows i = i0, i0 + stride, ... < r of one panel step: the pivot row pr becomes
+// prow, every other row gets gj_row_update's values.  Full panels (pb = kPB) take a
+// branch-free path with the row's entries loaded before any store.
+template <class S>
+__device__ __forceinline__ void gj_step_rows(S *PN, int ldp, int r, int i0, int stride, int pr,
+                                             int pb, int jj, S inv, const S *prow) {
+  if (pb == kPB) {
+    constexpr int G = sizeof(S) == sizeof(double) ? kPB : kPB / 2;
+    for (int i = i0; i < r; i += stride) {
+      S *row = PN + i;
+      if (i == pr) {
+#pragma unroll
+        for (int c = 0; c < kPB; ++c) row[c * ldp] = prow[c];
+      } else {
+        const S f = row[jj * ldp];
+        const S fj = S(0.0) - f * inv;
+#pragma unroll
+        for (int h = 0; h < kPB; h += G) {
+          S v[G];
+#pragma unroll
+          for (int c = 0; c < G; ++c) v[c] = row[(h + c) * ldp];
+#pragma unroll
+          for (int c = 0; c < G; ++c) {
+            const S u = v[c] - f * prow[h + c];
+            row[(h + c) * ldp] = h + c == jj ? fj : u;
+          }
+        }
+      }
+    }
+    return;
+  }
+  for (int i = i0; i < r; i += stride) {
+    S *row = PN + i;
+    if (i == pr) {
+      for (int c = 0; c < pb; ++c) row[c * ldp] = prow[c];
+    } else {
+      gj_row_update<S>(row, ldp, pb, jj, inv, prow);
+    }
+  }
 }
 
 template <class S, int NTH>
-__device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
-                           char *lds, S *__restrict__ pn_work) {
+__device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
+                                           S *__restrict__ G, char *lds,
+                                           S *__restrict__ pn_work, bool a_in_lds) {
   constexpr int NW = NTH / 64;
   static_assert(NW <= 64, "one lane per wave in the combine");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool pn_lds = (size_t)r * kPB * sizeof(S) <= gj_panel_lds_max<S>();
+  const bool pn_lds = !a_in_lds && (size_t)r * kPB * sizeof(S) <= gj_panel_lds_max<S>();
   char *p = lds;
-  S *PN = pn_lds ? reinterpret_cast<S *>(p) : pn_work;          // r x kPB, ld = r
-  if (pn_lds) p += (size_t)r * kPB * sizeof(S);
+  S *PNl = reinterpret_cast<S *>(p);                              // panel copy in LDS, ld = r
+  if (!a_in_lds) p += std::min((size_t)r * kPB * sizeof(S), gj_panel_lds_max<S>());
   S *Wt = reinterpret_cast<S *>(p);                               // kPB x kQC
   p += (size_t)kPB * kQC * sizeof(S);
   S *prow = reinterpret_cast<S *>(p);                             // kPB
@@ -960,23 +1034,49 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
   int *piv = reinterpret_cast<int *>(p);                          // r
   int *qinv = piv + r;                                            // r
   int *ustep = qinv + r;                                          // r: step that used row
+  int *s_fail = ustep + r;
 
-  for (int i = tid; i < r; i += NTH) ustep[i] = -1;
-  __syncthreads();
-  for (int p0 = 0; p0 < r; p0 += kPB) {
-    const int pb = min(kPB, r - p0);
-    for (int c = wave; c < pb; c += NW) {
-      const S *Ac = A + (int64_t)(p0 + c) * lda;
-      for (int i = lane; i < r; i += 64) PN[i + (int64_t)c * r] = Ac[i];
+  // Steps p0 .. p0 + pb - 1 on the panel PN (ld ldp).  Returns false on a bad pivot
+  // (uniform over the workgroup).
+  auto panel = [&](S *PN, int ldp, int p0, int pb) -> bool {
+    if (r <= kWavePanelMaxR) {
+      if (wave == 0) {
+        for (int jj = 0; jj < pb; ++jj) {
+          const int j = p0 + jj;
+          double lb = -1.0;
+          int li = INT_MAX;
+          for (int i = lane; i < r; i += 64) {
+            if (ustep[i] >= 0) continue;
+            const double v = mag(PN[i + jj * ldp]);
+            if (v > lb || (v == lb && i < li)) { lb = v; li = i; }
+          }
+          const ArgMax am = wave_argmax(lb, li, li);
+          if (!(am.v > 0.0) || !isfinite(am.v)) {
+            if (lane == 0) *s_fail = 1;
+            break;
+          }
+          const int pr = am.key;
+          const S inv = recip(PN[pr + jj * ldp]);
+          if (lane < pb) prow[lane] = lane == jj ? inv : PN[pr + lane * ldp] * inv;
+          wave_sync();                 // the scaled pivot row is complete and visible
+          gj_step_rows<S>(PN, ldp, r, lane, 64, pr, pb, jj, inv, prow);
+          if (lane == 0) {
+            ustep[pr] = j;
+            piv[j] = pr;
+          }
+          wave_sync();
+        }
+      }
+      __syncthreads();
+      return *s_fail == 0;
     }
-    __syncthreads();
     for (int jj = 0; jj < pb; ++jj) {
       const int j = p0 + jj;
       double lb = -1.0;
       int li = INT_MAX;
       for (int i = tid; i < r; i += NTH) {
         if (ustep[i] >= 0) continue;
-        const double v = mag(PN[i + (int64_t)jj * r]);
+        const double v = mag(PN[i + jj * ldp]);
         if (v > lb || (v == lb && i < li)) { lb = v; li = i; }
       }
       const ArgMax am = wave_argmax(lb, li, li);
@@ -987,8 +1087,8 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
       if (!(g.v > 0.0) || !isfinite(g.v)) return false;
       const int pr = g.key;
       if (wave == 0) {     // scaled pivot row (old values) into LDS, lanes in parallel
-        const S inv = recip(PN[pr + (int64_t)jj * r]);
-        if (lane < pb) prow[lane] = lane == jj ? inv : PN[pr + (int64_t)lane * r] * inv;
+        const S inv = recip(PN[pr + jj * ldp]);
+        if (lane < pb) prow[lane] = lane == jj ? inv : PN[pr + lane * ldp] * inv;
         if (lane == 0) {
           ustep[pr] = j;
           piv[j] = pr;
@@ -996,37 +1096,21 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
       }
       __syncthreads();
       const S inv = prow[jj];
-      for (int i = tid; i < r; i += NTH) {
-        S *row = PN + i;
-        if (i == pr) {
-#pragma unroll
-          for (int c = 0; c < kPB; ++c)
-            if (c < pb) row[(int64_t)c * r] = prow[c];
-        } else {
-          const S f = row[(int64_t)jj * r];
-          S v[kPB];
-#pragma unroll
-          for (int c = 0; c < kPB; ++c) v[c] = c < pb ? row[(int64_t)c * r] : S(0.0);
-#pragma unroll
-          for (int c = 0; c < kPB; ++c)
-            if (c < pb) row[(int64_t)c * r] = c == jj ? S(0.0) - f * inv : v[c] - f * prow[c];
-        }
-      }
+      gj_step_rows<S>(PN, ldp, r, tid, NTH, pr, pb, jj, inv, prow);
       __syncthreads();
     }
-    // the panel's columns are final for this panel: write them back
-    for (int c = wave; c < pb; c += NW) {
-      S *Ac = A + (int64_t)(p0 + c) * lda;
-      for (int i = lane; i < r; i += 64) Ac[i] = PN[i + (int64_t)c * r];
-    }
-    // deferred update of every other column, kQC columns at a time
+    return true;
+  };
+
+  // Deferred update of every column outside the panel, kQC columns at a time.
+  auto update = [&](const S *PN, int ldp, int p0, int pb) {
     for (int q0 = 0; q0 < r; q0 += kQC) {
       const int qc = min(kQC, r - q0);
       for (int sidx = wave; sidx < pb; sidx += NW) {
         const int prw = piv[p0 + sidx];
         for (int c = lane; c < qc; c += 64) {
           const int q = q0 + c;
-          Wt[sidx * kQC + c] = (q >= p0 && q < p0 + pb) ? S(0.0) : A[(int64_t)q * lda + prw];
+          Wt[sidx * kQC + c] = (q >= p0 && q < p0 + pb) ? S(0.0) : A[q * lda + prw];
         }
       }
       __syncthreads();
@@ -1039,7 +1123,7 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
         const int cc = tc * 16 + ci;
         for (int k0 = 0; k0 < pb; k0 += 4) {
           const int kk = k0 + kq;
-          const S av = (i < r && kk < pb) ? PN[i + (int64_t)kk * r] : S(0.0);
+          const S av = (i < r && kk < pb) ? PN[i + kk * ldp] : S(0.0);
           const S bv = (kk < pb && cc < qc) ? Wt[kk * kQC + cc] : S(0.0);
           acc.mma(av, bv);
         }
@@ -1050,7 +1134,7 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
             const int row = ti * 16 + kq + 4 * v;
             if (row < r) {
               const int us = ustep[row];
-              S *ap = A + (int64_t)q * lda + row;
+              S *ap = A + q * lda + row;
               *ap = ((us >= p0 && us < p0 + pb) ? S(0.0) : *ap) + acc.get(v);
             }
           }
@@ -1058,15 +1142,85 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
       }
       __syncthreads();
     }
+  };
+
+  // One panel through a copy PN (ld r): copy in, steps, write back, update.
+  auto via_copy = [&](S *PN, int p0, int pb) -> bool {
+    for (int c = wave; c < pb; c += NW) {
+      const S *Ac = A + (p0 + c) * lda;
+      for (int i = lane; i < r; i += 64) PN[i + c * r] = Ac[i];
+    }
+    __syncthreads();
+    if (!panel(PN, r, p0, pb)) return false;
+    for (int c = wave; c < pb; c += NW) {
+      S *Ac = A + (p0 + c) * lda;
+      for (int i = lane; i < r; i += 64) Ac[i] = PN[i + c * r];
+    }
+    update(PN, r, p0, pb);
+    return true;
+  };
+
+  for (int i = tid; i < r; i += NTH) ustep[i] = -1;
+  if (tid == 0) *s_fail = 0;
+  __syncthreads();
+  for (int p0 = 0; p0 < r; p0 += kPB) {
+    const int pb = min(kPB, r - p0);
+    if (a_in_lds) {            // in place
+      if (!panel(A + p0 * lda, lda, p0, pb)) return false;
+      update(A + p0 * lda, lda, p0, pb);
+    } else if (pn_lds) {
+      if (!via_copy(PNl, p0, pb)) return false;
+    } else {
+      if (!via_copy(pn_work, p0, pb)) return false;
+    }
   }
   for (int j = tid; j < r; j += NTH) qinv[piv[j]] = j;
   __syncthreads();
   for (int b = wave; b < r; b += NW) {
-    const S *col = A + (int64_t)qinv[b] * lda;
-    for (int a = lane; a < r; a += 64) G[(int64_t)b * r + a] = col[piv[a]];
+    const S *col = A + qinv[b] * lda;
+    for (int a = lane; a < r; a += 64) G[b * r + a] = col[piv[a]];
   }
   __syncthreads();
   return true;
+}
+
+// --------------------------------------------------------------------------
+// Small dense products of a box factorization with FP64 MFMA tiles (16 x 16 per wave,
+// the full K loop in k order): out(i, j) = c0(i, j) - sum_l a(i, l) b(l, j) when
+// subtract (c0 defaults to out's current value), else the plain product.  Each output
+// element is read and written by one lane only, so out may overlap c0 element-wise.
+template <class S, int NW, class FA, class FB, class FO>
+__device__ __forceinline__ void block_gemm(int M, int N, int K, FA a, FB b, FO out,
+                                           bool subtract) {
+  block_gemm<S, NW>(M, N, K, a, b, out, subtract, [&](int i, int j) { return out(i, j); });
+}
+
+template <class S, int NW, class FA, class FB, class FO, class FC>
+__device__ __forceinline__ void block_gemm(int M, int N, int K, FA a, FB b, FO out,
+                                           bool subtract, FC c0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, ci = lane & 15, kq = lane >> 4;
+  const int tn = (N + 15) >> 4, nt = ((M + 15) >> 4) * tn;
+  for (int tile = wave; tile < nt; tile += NW) {
+    const int ti = tile / tn, tj = tile - ti * tn;
+    const int i = ti * 16 + ci, j = tj * 16 + ci;
+    Acc<S> acc;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int kk = k0 + kq;
+      const S av = (i < M && kk < K) ? a(i, kk) : S(0.0);
+      const S bv = (kk < K && j < N) ? b(kk, j) : S(0.0);
+      acc.mma(av, bv);
+    }
+    if (j < N) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + kq + 4 * v;
+        if (row < M) {
+          S &o = out(row, j);
+          o = subtract ? c0(row, j) - acc.get(v) : acc.get(v);
+        }
+      }
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1083,7 +1237,7 @@ __device__ bool gj_blocked(S *__restrict__ A, int lda, int r, S *__restrict__ G,
 // block lives in LDS (small boxes); otherwise in the global workspace.
 // Index loops are two-level (waves over columns, lanes over rows): no integer division.
 template <class S, int NTH, bool INLDS>
-__global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ boxes, int first,
+__global__ __launch_bounds__(NTH, 4) void k_diag_factor(const FacBox *__restrict__ boxes, int first,
                                                      const ProbDev *__restrict__ probs,
                                                      const int32_t *__restrict__ pool,
                                                      const int32_t *__restrict__ order_pool,
@@ -1091,12 +1245,8 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
                                                      S *__restrict__ workbase,
                                                      int32_t *__restrict__ err, int err_base) {
   constexpr int NW = NTH / 64;
-  constexpr int CB = 4;    // columns per wave in the elimination
-  constexpr int RB = 4 / (int)(sizeof(S) / sizeof(double));   // rows per lane per chunk
   extern __shared__ double sh_raw[];
   S *sh = reinterpret_cast<S *>(sh_raw);
-  __shared__ S s_inv;
-  __shared__ int s_prow, s_bad;
   const FacBox &B = boxes[first + blockIdx.x];
   const ProbDev &P = probs[B.prob];
   const int n = B.n;
@@ -1108,8 +1258,6 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   S *slot = reinterpret_cast<S *>(B.slot);
   const S *T = slot + slot_T(k, r);
   S *X = INLDS ? sh : workbase + B.work_off;                 // n x n, (s, r) order
-  S *fac = INLDS ? sh + (int64_t)n * n : sh;                 // r
-  int *ipiv = reinterpret_cast<int *>(fac + r);              // r
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   // D in (s, r) order.
@@ -1139,172 +1287,57 @@ __global__ __launch_bounds__(NTH) void k_diag_factor(const FacBox *__restrict__ 
   }
   __syncthreads();
   if (k > 0 && r > 0) {
-    // Y = D Q: redundant columns minus the skeleton columns times T.
-    for (int jr = wave; jr < r; jr += NW) {
-      const S *Tj = T + (int64_t)k * jr;
-      S *Xc = X + (int64_t)(k + jr) * n;
-      for (int a = lane; a < n; a += 64) {
-        S s = Xc[a];
-        for (int i = 0; i < k; ++i) s -= X[(int64_t)i * n + a] * Tj[i];
-        Xc[a] = s;
-      }
-    }
+    // Y = D Q: redundant columns minus the skeleton columns times T (n x r).
+    block_gemm<S, NW>(n, r, k, [&](int a, int i) { return X[i * n + a]; },
+                      [&](int i, int jr) { return T[i + k * jr]; },
+                      [&](int a, int jr) -> S & { return X[(k + jr) * n + a]; }, true);
     __syncthreads();
-    // X = P Y: redundant rows minus T^T times the skeleton rows.
-    for (int b = wave; b < n; b += NW) {
-      S *Xb = X + (int64_t)b * n;
-      for (int jr = lane; jr < r; jr += 64) {
-        const S *Tj = T + (int64_t)k * jr;
-        S s = Xb[k + jr];
-        for (int i = 0; i < k; ++i) s -= Tj[i] * Xb[i];
-        Xb[k + jr] = s;
-      }
-    }
+    // X = P Y: redundant rows minus T^T times the skeleton rows (r x n).
+    block_gemm<S, NW>(r, n, k, [&](int jr, int i) { return T[i + k * jr]; },
+                      [&](int i, int b) { return X[b * n + i]; },
+                      [&](int jr, int b) -> S & { return X[b * n + k + jr]; }, true);
     __syncthreads();
   }
-  // In-place Gauss-Jordan inversion of A = X_rr, A(i, c) = X[(k + c) n + k + i].
+  // Inversion of A = X_rr, A(i, c) = X[(k + c) n + k + i], into G (blocked
+  // Gauss-Jordan).  With the block in LDS the inverse is copied back over A, so the
+  // products below read it from LDS.
   S *A = X + (int64_t)k * n + k;
   S *G = slot + slot_G(k, r);
-  const S *Gi = A;                 // the inverse as the products below read it
-  int ldg = n;
-  if (!INLDS && r >= kGjBlockMinR) {
-    if (!gj_blocked<S, NTH>(A, n, r, G, reinterpret_cast<char *>(sh_raw),
-                            workbase + B.work_off + (int64_t)n * n)) {
+  const S *Gi = G;                 // the inverse as the products below read it
+  int ldg = r;
+  if (r > 0) {
+    char *gl = INLDS ? reinterpret_cast<char *>(sh + (int64_t)n * n) : reinterpret_cast<char *>(sh_raw);
+    if (!gj_blocked<S, NTH>(A, n, r, G, gl, workbase + B.work_off + (int64_t)n * n, INLDS)) {
       if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned int *>(err),
                                       (unsigned int)(err_base + first + (int)blockIdx.x));
       return;
     }
-    Gi = G;
-    ldg = r;
-  } else {
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();      // every thread reads s_bad below, also when r == 0
-  for (int j = 0; j < r; ++j) {
-    if (wave == 0) {
-      double lbest = -1.0;
-      int lrow = INT_MAX;
-      const S *Aj = A + (int64_t)j * n;
-      for (int i = j + lane; i < r; i += 64) {
-        const double v = mag(Aj[i]);
-        if (v > lbest || (v == lbest && i < lrow)) { lbest = v; lrow = i; }
-      }
-      const ArgMax am = wave_argmax(lbest, lrow, lrow);
-      const double best = am.v;
-      const int brow = am.key;
-      if (lane == 0) {
-        s_prow = brow;
-        ipiv[j] = brow;
-        if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
-      }
-    }
-    __syncthreads();
-    if (s_bad) break;
-    const int pr = s_prow;
-    if (pr != j) {
-      for (int c = threadIdx.x; c < r; c += NTH) {
-        S *Ac = A + (int64_t)c * n;
-        const S a = Ac[j];
-        Ac[j] = Ac[pr];
-        Ac[pr] = a;
-      }
+    if (INLDS) {
+      for (int c = wave; c < r; c += NW)
+        for (int a = lane; a < r; a += 64) A[(int64_t)c * n + a] = G[(int64_t)c * r + a];
       __syncthreads();
+      Gi = A;
+      ldg = n;
     }
-    {
-      const S *Aj = A + (int64_t)j * n;
-      for (int i = threadIdx.x; i < r; i += NTH) fac[i] = Aj[i];
-      if (threadIdx.x == 0) s_inv = recip(Aj[j]);
-    }
-    __syncthreads();
-    const S inv = s_inv;
-    for (int c = threadIdx.x; c < r; c += NTH) {
-      S *Ac = A + (int64_t)c * n;
-      Ac[j] = c == j ? inv : Ac[j] * inv;
-    }
-    __syncthreads();
-    // A(i, c) <- [c != j] A(i, c) - fac[i] A(j, c) for i != j.  All loads of a chunk of
-    // RB rows x CB columns are issued before its stores, so they overlap in flight.
-    for (int c0 = wave * CB; c0 < r; c0 += NW * CB) {
-      S aj[CB];
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
-        aj[cb] = c0 + cb < r ? A[(int64_t)(c0 + cb) * n + j] : S(0.0);
-      for (int i0 = 0; i0 < r; i0 += 64 * RB) {
-        S v[RB][CB], f[RB];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const int i = i0 + lane + 64 * rb;
-          const bool ok = i < r && i != j;
-          f[rb] = ok ? fac[i] : S(0.0);
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb)
-            v[rb][cb] = (ok && c0 + cb < r && c0 + cb != j) ? A[(int64_t)(c0 + cb) * n + i]
-                                                            : S(0.0);
-        }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const int i = i0 + lane + 64 * rb;
-          if (i < r && i != j) {
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-              if (c0 + cb < r) A[(int64_t)(c0 + cb) * n + i] = v[rb][cb] - f[rb] * aj[cb];
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (s_bad) {
-    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned int *>(err),
-                                    (unsigned int)(err_base + first + (int)blockIdx.x));
-    return;
-  }
-  for (int j = r - 1; j >= 0; --j) {      // undo the row interchanges on the columns
-    const int pr = ipiv[j];
-    if (pr != j) {
-      S *Aj = A + (int64_t)j * n, *Ap = A + (int64_t)pr * n;
-      for (int i = threadIdx.x; i < r; i += NTH) {
-        const S a = Aj[i];
-        Aj[i] = Ap[i];
-        Ap[i] = a;
-      }
-      __syncthreads();
-    }
-  }
-  for (int c = wave; c < r; c += NW)
-    for (int a = lane; a < r; a += 64) G[(int64_t)c * r + a] = A[(int64_t)c * n + a];
   }
   if (k == 0) return;
   S *E = slot + slot_E(k, r);
   S *F = slot + slot_F(k, r);
   S *L = slot + slot_L(k, r);
   // F = G X_rs (r x k); X_rs(l, i) = X[i n + k + l]
-  for (int i = wave; i < k; i += NW) {
-    const S *Xi = X + (int64_t)i * n + k;
-    for (int a = lane; a < r; a += 64) {
-      S s = S(0.0);
-      for (int l = 0; l < r; ++l) s += Gi[(int64_t)l * ldg + a] * Xi[l];
-      F[(int64_t)i * r + a] = s;
-    }
-  }
+  block_gemm<S, NW>(r, k, r, [&](int a, int l) { return Gi[l * ldg + a]; },
+                    [&](int l, int i) { return X[i * n + k + l]; },
+                    [&](int a, int i) -> S & { return F[i * r + a]; }, false);
   // E = X_sr G (k x r); X_sr(i, l) = X[(k + l) n + i]
-  for (int a = wave; a < r; a += NW) {
-    const S *Ga = Gi + (int64_t)a * ldg;
-    for (int i = lane; i < k; i += 64) {
-      S s = S(0.0);
-      for (int l = 0; l < r; ++l) s += X[(int64_t)(k + l) * n + i] * Ga[l];
-      E[(int64_t)a * k + i] = s;
-    }
-  }
+  block_gemm<S, NW>(k, r, r, [&](int i, int l) { return X[(k + l) * n + i]; },
+                    [&](int l, int a) { return Gi[a * ldg + l]; },
+                    [&](int i, int a) -> S & { return E[a * k + i]; }, false);
   __syncthreads();
   // Lambda = X_ss - X_sr F (k x k)
-  for (int i2 = wave; i2 < k; i2 += NW) {
-    const S *Fi = F + (int64_t)i2 * r;
-    for (int i = lane; i < k; i += 64) {
-      S s = X[(int64_t)i2 * n + i];
-      for (int a = 0; a < r; ++a) s -= X[(int64_t)(k + a) * n + i] * Fi[a];
-      L[(int64_t)i2 * k + i] = s;
-    }
-  }
+  block_gemm<S, NW>(k, k, r, [&](int i, int a) { return X[(k + a) * n + i]; },
+                    [&](int a, int i2) { return F[i2 * r + a]; },
+                    [&](int i, int i2) -> S & { return L[i2 * k + i]; }, true,
+                    [&](int i, int i2) { return X[i2 * n + i]; });
 }
 
 // --------------------------------------------------------------------------
@@ -1981,23 +2014,25 @@ void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
   const size_t es = cplx ? 2 : 1;
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
-    // The whole block in LDS when n^2 scalars + the pivot column and indices fit (such
-    // boxes always take the unblocked inversion: n < kGjBlockMinR); up to 64 KiB with
-    // 256 threads (several workgroups per CU), beyond that one 1024-thread workgroup.
-    const size_t lds_in = (size_t)max_n * max_n * 8 * es + (size_t)max_n * (8 * es + 4);
-    if (max_n < kGjBlockMinR && lds_in <= kMaxLds) {
-      if (lds_in <= kLdsLimit)
-        diag_factor_nt<S, 256, true>(boxes, first, count, probs, pool, order_pool, ranks, work,
-                                     err, err_base, lds_in, st);
-      else
-        diag_factor_nt<S, 1024, true>(boxes, first, count, probs, pool, order_pool, ranks,
-                                      work, err, err_base, lds_in, st);
+    // The whole block in LDS when n^2 scalars plus the inversion's buffers fit: up to
+    // 64 KiB with 256 threads (several workgroups per CU), beyond that one 1024-thread
+    // workgroup.  The arithmetic of a box is the same in every variant.
+    auto lds_in = [&](int nth) {
+      return (size_t)max_n * max_n * 8 * es + gj_blocked_lds<S>(max_n, nth / 64, true);
+    };
+    if (lds_in(256) <= kLdsLimit) {
+      diag_factor_nt<S, 256, true>(boxes, first, count, probs, pool, order_pool, ranks, work,
+                                   err, err_base, lds_in(256), st);
+      return;
+    }
+    if (lds_in(1024) <= kMaxLds) {
+      diag_factor_nt<S, 1024, true>(boxes, first, count, probs, pool, order_pool, ranks, work,
+                                    err, err_base, lds_in(1024), st);
       return;
     }
     // Few large boxes (the root): one 1024-thread workgroup each; otherwise 256 threads.
     const int nth = count <= 64 ? 1024 : 256;
-    size_t lds = (size_t)max_n * (8 * es + 4);
-    if (max_n >= kGjBlockMinR) lds = std::max(lds, gj_blocked_lds<S>(max_n, nth / 64));
+    const size_t lds = gj_blocked_lds<S>(max_n, nth / 64, false);
     if (lds > kMaxLds) throw DeviceError("k_diag_factor: box too large", hipErrorInvalidValue);
     if (nth == 1024)
       diag_factor_nt<S, 1024, false>(boxes, first, count, probs, pool, order_pool, ranks, work,

@@ -186,8 +186,8 @@ def test_server_complex_factor_and_solves(gpu_lib):
 
 @pytest.mark.parametrize("n", [130, 300])
 def test_helmholtz_eps_zero_is_dense_lu(gpu_lib, n):
-    # eps = 0 keeps every DOF: the root is the whole system (blocked inversion for
-    # r >= 129), so the solution is dense Gaussian elimination's.
+    # eps = 0 keeps every DOF: the root is the whole system (blocked Gauss-Jordan
+    # inversion), so the solution is dense Gaussian elimination's.
     rs = gpu_lib
     g = W.star_curve(n)
     k = W.helmholtz_wavenumber(g, 3.0)
