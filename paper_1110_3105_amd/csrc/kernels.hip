@@ -99,6 +99,36 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
+
+// Wave sums of eight per-lane values at once: afterwards every lane of the 8-lane group
+// g = lane >> 3 holds the total of value g.  Lane bits 5, 4 and 3 are folded by
+// exchanges in which each lane keeps half of its values and adds its partner's copy of
+// that half; bits 2..0 by DPP as in wave_sum_f64.  Every value is summed over the same
+// tree (addition commutes), so its rounding depends on its 64 inputs only -- not on
+// its slot or on the other values.
+__device__ __forceinline__ double wave_sum8(const double (&x)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double y[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double keep = b5 ? x[j + 4] : x[j];
+    const double send = b5 ? x[j] : x[j + 4];
+    y[j] = keep + __shfl_xor(send, 32, 64);
+  }
+  double z[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double keep = b4 ? y[j + 2] : y[j];
+    const double send = b4 ? y[j] : y[j + 2];
+    z[j] = keep + __shfl_xor(send, 16, 64);
+  }
+  double w = (b3 ? z[1] : z[0]) + __shfl_xor(b3 ? z[0] : z[1], 8, 64);
+  w += dpp_f64<kDppXor1>(w);
+  w += dpp_f64<kDppXor2>(w);
+  w += dpp_f64<kDppHalfMirror>(w);
+  return w;
+}
 __device__ __forceinline__ Cplx wave_sum(Cplx v) { return {wave_sum_f64(v.re), wave_sum_f64(v.im)}; }
 
 // Largest value over the wave with its key; ties (and NaN-free equal values) go to the
@@ -465,7 +495,7 @@ __device__ __forceinline__ double block_max_w(double v, double *red) {
 }
 
 template <int NTH, int RT, int CPW>
-__global__ __launch_bounds__(NTH) void k_compress_fused(
+__global__ __launch_bounds__(NTH, 2) void k_compress_fused(
     const CompBox *__restrict__ boxes, int first, const ProbDev *__restrict__ probs,
     const int32_t *__restrict__ pool, double *__restrict__ Rarena,
     int32_t *__restrict__ order_pool, int32_t *__restrict__ ranks) {
@@ -539,15 +569,25 @@ __global__ __launch_bounds__(NTH) void k_compress_fused(
     }
   }
 
-  // ---- column-pivoted QR in registers
+  // ---- column-pivoted QR in registers.  Column sums are taken eight columns at a
+  // time (wave_sum8); lane 8 g + 0 holds the result for column slot g of the group.
+  constexpr int NG = (CPW + 7) / 8;
 #pragma unroll
-  for (int q = 0; q < CPW; ++q) {
-    const int c = wave + NW * q;
-    double s = 0.0;
+  for (int g = 0; g < NG; ++g) {
+    double x[8];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) s += val[q][t] * val[q][t];
-    s = wave_sum(s);
-    if (lane == 0 && c < n) norms[c] = sqrt(s);
+    for (int qq = 0; qq < 8; ++qq) {
+      const int q = 8 * g + qq;
+      double s = 0.0;
+      if (q < CPW) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) s += val[q][t] * val[q][t];
+      }
+      x[qq] = s;
+    }
+    const double tot = wave_sum8(x);
+    const int q = 8 * g + (lane >> 3), c = wave + NW * q;
+    if ((lane & 7) == 0 && q < CPW && c < n) norms[c] = sqrt(tot);
   }
   for (int c = tid; c < n; c += NTH) done[c] = 0;
   __syncthreads();
@@ -617,24 +657,38 @@ __global__ __launch_bounds__(NTH) void k_compress_fused(
       vi[t] = (i >= j && i < m) ? sv[i] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < CPW; ++q) {
-      const int c = wave + NW * q;
-      if (c < n && !((mine_done >> q) & 1u)) {
+    for (int g = 0; g < NG; ++g) {
+      double x[8];
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) {
+        const int q = 8 * g + qq;
         double dot = 0.0;
+        if (q < CPW && wave + NW * q < n && !((mine_done >> q) & 1u)) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) dot += vi[t] * val[q][t];
-        dot = wave_sum(dot) * ctau;
-        double nr = 0.0;
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const int i = lane + 64 * t;
-          const double nv = val[q][t] - dot * vi[t];
-          val[q][t] = nv;
-          if (i > j) nr += nv * nv;
+          for (int t = 0; t < RT; ++t) dot += vi[t] * val[q][t];
         }
-        nr = wave_sum(nr);
-        if (lane == 0) norms[c] = sqrt(nr);
+        x[qq] = dot;
       }
+      const double dots = wave_sum8(x);
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) {
+        const int q = 8 * g + qq;
+        double nr = 0.0;
+        if (q < CPW && wave + NW * q < n && !((mine_done >> q) & 1u)) {
+          const double dot = readlane_f64(dots, 8 * qq) * ctau;
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int i = lane + 64 * t;
+            const double nv = val[q][t] - dot * vi[t];
+            val[q][t] = nv;
+            if (i > j) nr += nv * nv;
+          }
+        }
+        x[qq] = nr;
+      }
+      const double nrs = wave_sum8(x);
+      const int q = 8 * g + (lane >> 3), c = wave + NW * q;
+      if ((lane & 7) == 0 && q < CPW && c < n && !((mine_done >> q) & 1u)) norms[c] = sqrt(nrs);
     }
     __syncthreads();
   }
@@ -1932,6 +1986,18 @@ void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, cons
 
 bool fused_class(bool cplx, int n, int m) { return !cplx && n <= kFusedMaxN && m <= kFusedMaxM; }
 
+// Register-resident variants (threads, rows per lane, columns per wave), smallest first;
+// a box takes the first whose column (NW * CPW) and row (64 RT) capacity covers it.
+// Fewer waves per box mean less per-step overhead and more boxes resident per CU; the
+// arithmetic of a box is the same in every variant.
+int fused_variant_of(int n, int m) {
+  if (n <= 24 && m <= 320) return 0;     // <256, 5, 6>
+  if (n <= 32 && m <= 512) return 1;     // <256, 8, 8>
+  if (n <= 48 && m <= 320) return 2;     // <512, 5, 6>
+  if (n <= 64 && m <= 448) return 3;     // <512, 7, 8>
+  return 4;                              // <512, 8, 10>
+}
+
 size_t fused_lds_bytes(int nth, int max_n, int max_m, int max_npx) {
   const int nw = nth / 64;
   const size_t max_nn = (size_t)max_m / 2;       // m >= 2 nn
@@ -1964,15 +2030,27 @@ void launch_compress_fused(const CompBox *boxes, int first, int count, const Pro
   if (count <= 0) return;
   if (max_n > kFusedMaxN || max_m > kFusedMaxM)
     throw DeviceError("k_compress_fused: box outside the fused class", hipErrorInvalidValue);
-  if (max_n <= 48 && max_m <= 320)
-    fused_variant<1024, 5, 3>(boxes, first, count, probs, pool, Rarena, order_pool, ranks, max_n,
-                              max_m, max_npx, st);
-  else if (max_n <= 64 && max_m <= 448)
-    fused_variant<512, 7, 8>(boxes, first, count, probs, pool, Rarena, order_pool, ranks, max_n,
-                             max_m, max_npx, st);
-  else
-    fused_variant<512, 8, 10>(boxes, first, count, probs, pool, Rarena, order_pool, ranks, max_n,
-                              max_m, max_npx, st);
+  switch (fused_variant_of(max_n, max_m)) {
+    case 0:
+      fused_variant<256, 5, 6>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
+                               max_n, max_m, max_npx, st);
+      break;
+    case 1:
+      fused_variant<256, 8, 8>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
+                               max_n, max_m, max_npx, st);
+      break;
+    case 2:
+      fused_variant<512, 5, 6>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
+                               max_n, max_m, max_npx, st);
+      break;
+    case 3:
+      fused_variant<512, 7, 8>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
+                               max_n, max_m, max_npx, st);
+      break;
+    default:
+      fused_variant<512, 8, 10>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
+                                max_n, max_m, max_npx, st);
+  }
 }
 
 size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m) {

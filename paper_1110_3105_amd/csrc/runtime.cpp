@@ -105,9 +105,38 @@ void *Arena::alloc(size_t bytes) {
 
 namespace {
 
-// Transient device buffers shared by all factor calls (grown on demand).
+// Pinned host staging (grow-only; a grow waits for the device first).
+struct PinnedBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    RS_HIP_CHECK(hipDeviceSynchronize());
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    RS_HIP_CHECK(hipHostMalloc(&p, b < 256 ? 256 : b, hipHostMallocDefault));
+    bytes = b < 256 ? 256 : b;
+  }
+};
+
+// Transient device buffers shared by all factor calls (grown on demand).  The buffers a
+// level's box factorization reads (index pool, skeleton order, ranks, descriptors) come
+// in two sets used by alternate levels: the factorization of one level runs on a second
+// stream while the next level is compressed.
 struct Scratch {
   DevBuf pool, comp, fac, M, order, ranks, work, err, probs;
+  DevBuf pool2[2], order2[2], ranks2[2], fac2[2];
+  PinnedBuf hfac[2];
+  hipStream_t side = nullptr;                 // box factorizations of compressed levels
+  hipEvent_t ev_comp = nullptr, ev_side = nullptr, ev_diag[2] = {nullptr, nullptr};
+  void init_streams() {
+    if (side) return;
+    RS_HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    RS_HIP_CHECK(hipEventCreateWithFlags(&ev_comp, hipEventDisableTiming));
+    RS_HIP_CHECK(hipEventCreateWithFlags(&ev_side, hipEventDisableTiming));
+    for (auto &e : ev_diag) RS_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
 };
 
 std::mutex g_factor_mutex;
@@ -349,6 +378,13 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   std::vector<std::unique_ptr<rs_factor_s>> handles(np);
   std::vector<ProbState> ps(np);
   Scratch &S = scratch();
+  S.init_streams();
+  hipStream_t side = S.side;
+  bool diag_pending[2] = {false, false};
+  struct SideSync {      // no side-stream work outlives this call (also on errors)
+    hipStream_t s;
+    ~SideSync() { (void)hipStreamSynchronize(s); }
+  } side_sync{side};
   std::vector<ProbDev> probs(np);
   int max_npx = 0, max_depth = 0;
   for (int p = 0; p < np; ++p) {
@@ -407,7 +443,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       }
     }
     // boxes of the fused (register-resident) compression class first, so that each
-    // class is one contiguous range of the launch
+    // class is one contiguous range of the launch (stable order)
     int nf = 0;
     {
       std::vector<char> fz(cnt);
@@ -482,54 +518,60 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     plan_ms += ms_since(tp);
     if (cpqr_lds_bytes(cplx, max_n, 1 << 30) > 160 * 1024)
       throw UserError{RS_ENOTSUP, "a box's active set exceeds the on-chip ID limit"};
-    upload(S.pool, pool, st);
+    // this level's buffer set was last read by the box factorization two levels back
+    const int par = step & 1;
+    DevBuf &Dpool = S.pool2[par], &Dorder = S.order2[par], &Dranks = S.ranks2[par];
+    DevBuf &Dfac = S.fac2[par];
+    if (diag_pending[par]) RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_diag[par], 0));
+    upload(Dpool, pool, st);
     upload(S.comp, comp, st);
     S.M.ensure(std::max<int64_t>(M_total, 1) * sizeof(double) * es);
-    S.order.ensure(std::max<int64_t>(order_total, 1) * sizeof(int32_t));
-    S.ranks.ensure(std::max(cnt, 1) * sizeof(int32_t));
+    Dorder.ensure(std::max<int64_t>(order_total, 1) * sizeof(int32_t));
+    Dranks.ensure(std::max(cnt, 1) * sizeof(int32_t));
     S.work.ensure(std::max<int64_t>(work_total, 1) * sizeof(double) * es);
     const CompBox *d_comp = S.comp.as<CompBox>();
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         if (i < nf) {
           ProfScope ps_(RS_K_ID, st);
-          launch_compress_fused(d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
-                                S.order.as<int32_t>(), S.ranks.as<int32_t>(), comp[i].n,
+          launch_compress_fused(d_comp, i, 1, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
+                                Dorder.as<int32_t>(), Dranks.as<int32_t>(), comp[i].n,
                                 comp[i].m, max_npx, st);
           continue;
         }
         {
           ProfScope ps_(RS_K_ASSEMBLE, st);
-          launch_assemble(cplx, d_comp, i, 1, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
+          launch_assemble(cplx, d_comp, i, 1, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
                           max_npx, st);
         }
         ProfScope ps_(RS_K_ID, st);
-        launch_cpqr_id(cplx, d_comp, i, 1, d_probs, S.M.as<double>(), S.order.as<int32_t>(),
-                       S.ranks.as<int32_t>(), comp[i].n, comp[i].m, st);
+        launch_cpqr_id(cplx, d_comp, i, 1, d_probs, S.M.as<double>(), Dorder.as<int32_t>(),
+                       Dranks.as<int32_t>(), comp[i].n, comp[i].m, st);
       }
     } else {
       if (nf > 0) {
         ProfScope ps_(RS_K_ID, st);
-        launch_compress_fused(d_comp, 0, nf, d_probs, S.pool.as<int32_t>(), S.M.as<double>(),
-                              S.order.as<int32_t>(), S.ranks.as<int32_t>(), max_n_f, max_m_f,
+        launch_compress_fused(d_comp, 0, nf, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
+                              Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_f, max_m_f,
                               max_npx, st);
       }
       if (nf < cnt) {
         {
           ProfScope ps_(RS_K_ASSEMBLE, st);
-          launch_assemble(cplx, d_comp, nf, cnt - nf, d_probs, S.pool.as<int32_t>(),
+          launch_assemble(cplx, d_comp, nf, cnt - nf, d_probs, Dpool.as<int32_t>(),
                           S.M.as<double>(), max_npx, st);
         }
         ProfScope ps_(RS_K_ID, st);
         launch_cpqr_id(cplx, d_comp, nf, cnt - nf, d_probs, S.M.as<double>(),
-                       S.order.as<int32_t>(), S.ranks.as<int32_t>(), max_n_d, max_m_d, st);
+                       Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_d, max_m_d, st);
       }
     }
+    RS_HIP_CHECK(hipEventRecord(S.ev_comp, st));   // ranks, order and pool of this level
     std::vector<int32_t> ranks(cnt), order(order_total);
-    RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), S.ranks.p, cnt * sizeof(int32_t),
+    RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), Dranks.p, cnt * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, st));
     if (order_total)
-      RS_HIP_CHECK(hipMemcpyAsync(order.data(), S.order.p, order_total * sizeof(int32_t),
+      RS_HIP_CHECK(hipMemcpyAsync(order.data(), Dorder.p, order_total * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, st));
     {
       auto tw = Clock::now();
@@ -564,21 +606,30 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       woff += (int64_t)diag_work_elems(cb.n);
       fill_children(P, b, fb);
     }
-    upload(S.fac, fac, st);
-    const FacBox *d_fac = S.fac.as<FacBox>();
+    // descriptors through pinned staging (its previous user, two levels back, is done)
+    if (diag_pending[par]) RS_HIP_CHECK(hipEventSynchronize(S.ev_diag[par]));
+    const size_t fac_bytes = fac.size() * sizeof(FacBox);
+    S.hfac[par].ensure(fac_bytes);
+    Dfac.ensure(fac_bytes);
+    std::memcpy(S.hfac[par].p, fac.data(), fac_bytes);
+    RS_HIP_CHECK(hipStreamWaitEvent(side, S.ev_comp, 0));
+    RS_HIP_CHECK(hipMemcpyAsync(Dfac.p, S.hfac[par].p, fac_bytes, hipMemcpyHostToDevice, side));
+    const FacBox *d_fac = Dfac.as<FacBox>();
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
-        ProfScope ps_(RS_K_FACTOR, st);
-        launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
-                           S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
-                           err_base, comp[i].n, st);
+        ProfScope ps_(RS_K_FACTOR, side);
+        launch_diag_factor(cplx, d_fac, i, 1, d_probs, Dpool.as<int32_t>(), Dorder.as<int32_t>(),
+                           Dranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
+                           err_base, comp[i].n, side);
       }
     } else {
-      ProfScope ps_(RS_K_FACTOR, st);
-      launch_diag_factor(cplx, d_fac, 0, cnt, d_probs, S.pool.as<int32_t>(), S.order.as<int32_t>(),
-                         S.ranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
-                         err_base, max_n, st);
+      ProfScope ps_(RS_K_FACTOR, side);
+      launch_diag_factor(cplx, d_fac, 0, cnt, d_probs, Dpool.as<int32_t>(), Dorder.as<int32_t>(),
+                         Dranks.as<int32_t>(), S.work.as<double>(), S.err.as<int32_t>(),
+                         err_base, max_n, side);
     }
+    RS_HIP_CHECK(hipEventRecord(S.ev_diag[par], side));
+    diag_pending[par] = true;
     // skeleton lists (the next level's active sets) and profiler work counts
     Work w_asm, w_id, w_fac;
     for (int i = 0; i < cnt; ++i) {
@@ -668,7 +719,10 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     plan_ms += ms_since(tp2);
   }
 
-  // ---- roots: the dense block of the surviving skeletons, fully eliminated
+  // ---- roots: the dense block of the surviving skeletons, fully eliminated (on st,
+  // after every box factorization of the side stream)
+  RS_HIP_CHECK(hipEventRecord(S.ev_side, side));
+  RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_side, 0));
   {
     std::vector<StepBox> items;
     std::vector<int32_t> pool;
