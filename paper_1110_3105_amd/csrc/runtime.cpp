@@ -129,13 +129,15 @@ struct Scratch {
   DevBuf pool2[2], order2[2], ranks2[2], fac2[2];
   PinnedBuf hfac[2];
   hipStream_t side = nullptr;                 // box factorizations of compressed levels
+  hipStream_t aux = nullptr;                  // the direct compression class of a level
   hipEvent_t ev_comp = nullptr, ev_side = nullptr, ev_diag[2] = {nullptr, nullptr};
+  hipEvent_t ev_up = nullptr, ev_aux = nullptr;
   void init_streams() {
     if (side) return;
     RS_HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
-    RS_HIP_CHECK(hipEventCreateWithFlags(&ev_comp, hipEventDisableTiming));
-    RS_HIP_CHECK(hipEventCreateWithFlags(&ev_side, hipEventDisableTiming));
-    for (auto &e : ev_diag) RS_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    RS_HIP_CHECK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&ev_comp, &ev_side, &ev_diag[0], &ev_diag[1], &ev_up, &ev_aux})
+      RS_HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }
 };
 
@@ -381,10 +383,10 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   S.init_streams();
   hipStream_t side = S.side;
   bool diag_pending[2] = {false, false};
-  struct SideSync {      // no side-stream work outlives this call (also on errors)
+  struct SideSync {      // no side- or aux-stream work outlives this call (also on errors)
     hipStream_t s;
     ~SideSync() { (void)hipStreamSynchronize(s); }
-  } side_sync{side};
+  } side_sync{side}, aux_sync{S.aux};
   std::vector<ProbDev> probs(np);
   int max_npx = 0, max_depth = 0;
   for (int p = 0; p < np; ++p) {
@@ -549,6 +551,14 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                        Dranks.as<int32_t>(), comp[i].n, comp[i].m, st);
       }
     } else {
+      // the two classes touch disjoint boxes: with both present, the direct class runs
+      // on the auxiliary stream beside the fused one
+      const bool both = nf > 0 && nf < cnt;
+      hipStream_t dst = both ? S.aux : st;
+      if (both) {
+        RS_HIP_CHECK(hipEventRecord(S.ev_up, st));
+        RS_HIP_CHECK(hipStreamWaitEvent(S.aux, S.ev_up, 0));
+      }
       if (nf > 0) {
         ProfScope ps_(RS_K_ID, st);
         launch_compress_fused(d_comp, 0, nf, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
@@ -557,13 +567,17 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       }
       if (nf < cnt) {
         {
-          ProfScope ps_(RS_K_ASSEMBLE, st);
+          ProfScope ps_(RS_K_ASSEMBLE, dst);
           launch_assemble(cplx, d_comp, nf, cnt - nf, d_probs, Dpool.as<int32_t>(),
-                          S.M.as<double>(), max_npx, st);
+                          S.M.as<double>(), max_npx, dst);
         }
-        ProfScope ps_(RS_K_ID, st);
+        ProfScope ps_(RS_K_ID, dst);
         launch_cpqr_id(cplx, d_comp, nf, cnt - nf, d_probs, S.M.as<double>(),
-                       Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_d, max_m_d, st);
+                       Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_d, max_m_d, dst);
+      }
+      if (both) {
+        RS_HIP_CHECK(hipEventRecord(S.ev_aux, S.aux));
+        RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_aux, 0));
       }
     }
     RS_HIP_CHECK(hipEventRecord(S.ev_comp, st));   // ranks, order and pool of this level
