@@ -975,9 +975,9 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
 // A^{-1}(a, b) = Y(piv[a], q[b]) with q = piv^{-1}; it is written to G (r x r) in that
 // order.  Returns false on a zero or non-finite pivot.
 //
-// For r <= kWavePanelMaxR one wave runs a panel's steps alone (lanes over rows, no
-// workgroup barrier between steps; the other waves wait once per panel); larger blocks
-// spread each step over the workgroup.  Both perform the same operations on every
+// For r <= kWavePanelMaxR with the panel in LDS one wave runs a panel's steps alone
+// (lanes over rows, no workgroup barrier between steps; the other waves wait once per
+// panel); otherwise each step is spread over the workgroup.  Both perform the same operations on every
 // element, so the result depends on the block alone.
 constexpr int kPB = 16;           // panel width
 constexpr int kQC = 128;          // columns per chunk of the deferred update
@@ -1090,10 +1090,10 @@ __device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
   int *ustep = qinv + r;                                          // r: step that used row
   int *s_fail = ustep + r;
 
-  // Steps p0 .. p0 + pb - 1 on the panel PN (ld ldp).  Returns false on a bad pivot
-  // (uniform over the workgroup).
-  auto panel = [&](S *PN, int ldp, int p0, int pb) -> bool {
-    if (r <= kWavePanelMaxR) {
+  // Steps p0 .. p0 + pb - 1 on the panel PN (ld ldp; in LDS when pn_on_chip).  Returns
+  // false on a bad pivot (uniform over the workgroup).
+  auto panel = [&](S *PN, int ldp, int p0, int pb, bool pn_on_chip) -> bool {
+    if (r <= kWavePanelMaxR && pn_on_chip) {
       if (wave == 0) {
         for (int jj = 0; jj < pb; ++jj) {
           const int j = p0 + jj;
@@ -1199,13 +1199,13 @@ __device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
   };
 
   // One panel through a copy PN (ld r): copy in, steps, write back, update.
-  auto via_copy = [&](S *PN, int p0, int pb) -> bool {
+  auto via_copy = [&](S *PN, int p0, int pb, bool pn_on_chip) -> bool {
     for (int c = wave; c < pb; c += NW) {
       const S *Ac = A + (p0 + c) * lda;
       for (int i = lane; i < r; i += 64) PN[i + c * r] = Ac[i];
     }
     __syncthreads();
-    if (!panel(PN, r, p0, pb)) return false;
+    if (!panel(PN, r, p0, pb, pn_on_chip)) return false;
     for (int c = wave; c < pb; c += NW) {
       S *Ac = A + (p0 + c) * lda;
       for (int i = lane; i < r; i += 64) Ac[i] = PN[i + c * r];
@@ -1220,12 +1220,12 @@ __device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
   for (int p0 = 0; p0 < r; p0 += kPB) {
     const int pb = min(kPB, r - p0);
     if (a_in_lds) {            // in place
-      if (!panel(A + p0 * lda, lda, p0, pb)) return false;
+      if (!panel(A + p0 * lda, lda, p0, pb, true)) return false;
       update(A + p0 * lda, lda, p0, pb);
     } else if (pn_lds) {
-      if (!via_copy(PNl, p0, pb)) return false;
+      if (!via_copy(PNl, p0, pb, true)) return false;
     } else {
-      if (!via_copy(pn_work, p0, pb)) return false;
+      if (!via_copy(pn_work, p0, pb, false)) return false;
     }
   }
   for (int j = tid; j < r; j += NTH) qinv[piv[j]] = j;
