@@ -4,6 +4,7 @@
 #include <string>
 
 #include "runtime.h"
+#include "pool.h"
 
 namespace rs {
 
@@ -345,7 +346,8 @@ rs_status rs_free(rs_handle h) {
     if (!h) return RS_OK;
     if (h->busy.load() != 0) fail(RS_EBUSY, "handle is in use by a running call");
     RS_HIP_CHECK(hipDeviceSynchronize());
-    delete h;
+    h->arena.release();                  // device memory back to the cache now
+    Reaper::get().defer([h] { delete h; });   // host lists freed in the background
     return RS_OK;
   });
 }

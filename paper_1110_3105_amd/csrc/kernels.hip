@@ -523,7 +523,7 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
   int *rk = piv + n;                                   // n
   int *done = rk + n;                                  // n
 
-  // ---- assembly, NW columns at a time through LDS
+  // ---- assembly
   for (int p = tid; p < npx; p += NTH) proxy_unit(dim, p, npx, sh_u + 3 * p);
   const StagedPts Jp = stage_points(P, J, n, pts, NTH);
   const StagedPts Np = stage_points(P, N, nn, pts + 7 * n, NTH);
@@ -534,26 +534,24 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
   const int rows = 2 * nn + 2 * npx;
   double pmax = 0.0;
   double val[CPW][RT];
+  // each wave evaluates its own columns; a lane stages exactly the rows it keeps (its
+  // slice of the wave's LDS column), so no barrier is needed
+  double *mytile = tile + wave * m;
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
-    const int c0 = NW * q;
-    const int cols = min(NW, n - c0);
-    if (cols > 0) {
-      for (int e = tid; e < cols * rows; e += NTH) {
-        const int cc = e / rows, i = e - cc * rows;
-        const double v = comp_entry_staged<double>(P, B, Jp, Np, sh_u, wG, i, c0 + cc);
+    const int c = wave + NW * q;
+    if (c < n) {
+      for (int i = lane; i < rows; i += 64) {
+        const double v = comp_entry_staged<double>(P, B, Jp, Np, sh_u, wG, i, c);
         if (i >= 2 * nn) pmax = fmax(pmax, fabs(v));
-        tile[cc * m + i] = v;
+        mytile[i] = v;
       }
     }
-    __syncthreads();
-    const int c = wave + NW * q;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int i = lane + 64 * t;
-      val[q][t] = (c < n && i < rows) ? tile[wave * m + i] : 0.0;
+      val[q][t] = (c < n && i < rows) ? mytile[i] : 0.0;
     }
-    __syncthreads();
   }
   if (P.log_kernel) {
     pmax = block_max_w<NW>(pmax, red);

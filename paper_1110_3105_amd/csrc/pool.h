@@ -5,6 +5,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <deque>
 #include <cstdint>
 #include <functional>
 #include <mutex>
@@ -117,6 +118,43 @@ class PlanPool {
   const std::function<void(int)> *job_ = nullptr;
   std::atomic<uint64_t> slot_{0};
   std::atomic<int> pending_{0};
+};
+
+// Background release of large host structures made of many small allocations (the
+// per-box lists of a factorization), off the caller's path.  One thread, created on
+// first use, runs the deferred jobs in order; jobs still queued at process exit are
+// dropped (their memory goes with the process).
+class Reaper {
+ public:
+  static Reaper &get() {
+    static Reaper *r = new Reaper();
+    return *r;
+  }
+  void defer(std::function<void()> f) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      q_.push_back(std::move(f));
+    }
+    cv_.notify_one();
+  }
+
+ private:
+  Reaper() { std::thread([this] { loop(); }).detach(); }
+  void loop() {
+    while (true) {
+      std::function<void()> f;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return !q_.empty(); });
+        f = std::move(q_.front());
+        q_.pop_front();
+      }
+      f();
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::function<void()>> q_;
 };
 
 template <class F>

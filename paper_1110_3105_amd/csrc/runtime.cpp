@@ -79,10 +79,14 @@ ChunkCache &chunk_cache() {
 }
 }  // namespace
 
-Arena::~Arena() {
+void Arena::release() {
   for (auto &c : chunks)
     if (c && c->p) chunk_cache().give(std::move(c));
+  chunks.clear();
+  used = total = 0;
 }
+
+Arena::~Arena() { release(); }
 
 void *Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
@@ -849,6 +853,9 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     h->stats.wait_ms = wait_ms;
     out[p] = handles[p].release();
   }
+  // the per-box candidate lists and other planner state go to the background thread
+  auto *left = new std::vector<ProbState>(std::move(ps));
+  Reaper::get().defer([left] { delete left; });
 }
 
 }  // namespace

@@ -46,6 +46,9 @@ struct Arena {
   size_t used = 0;
   size_t total = 0;
   void *alloc(size_t bytes);
+  // Returns every chunk to the process-wide cache now (the owner must not use the
+  // arena's memory afterwards).
+  void release();
   template <class T> T *alloc_n(int64_t n) { return static_cast<T *>(alloc(sizeof(T) * (size_t)n)); }
   Arena() = default;
   Arena(const Arena &) = delete;
