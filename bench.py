@@ -61,7 +61,8 @@ KERNELS_OF_FAMILY = {"assemble": ["k_assemble"], "id": ["k_compress_fused", "k_c
                      "sweep_up": ["k_sweep_up_mfma", "k_sweep_seg", "k_wide_gather",
                                   "k_wide_gemm"],
                      "sweep_down": ["k_sweep_down_mfma"],
-                     "permute": ["k_permute_in", "k_permute_out", "k_permute_seg"]}
+                     "permute": ["k_permute_in", "k_permute_out", "k_permute_seg",
+                                 "k_permute_tiled"]}
 
 
 def measured_traffic(family, launches_per_step):
