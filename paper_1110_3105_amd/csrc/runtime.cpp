@@ -585,31 +585,17 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       }
     }
     RS_HIP_CHECK(hipEventRecord(S.ev_comp, st));   // ranks, order and pool of this level
-    std::vector<int32_t> ranks(cnt), order(order_total);
-    RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), Dranks.p, cnt * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, st));
-    if (order_total)
-      RS_HIP_CHECK(hipMemcpyAsync(order.data(), Dorder.p, order_total * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, st));
-    {
-      auto tw = Clock::now();
-      RS_HIP_CHECK(hipStreamSynchronize(st));
-      wait_ms += ms_since(tw);
-    }
-    prev_stage = Staging();        // the previous level's uploads have completed
-    auto tp2 = Clock::now();
-    // record skeletons; build the factor descriptors
+    // The box factorizations need this level's ranks and orders only on the device (the
+    // kernel reads them by slot), so their descriptors are built now and the launch is
+    // queued on the side stream behind the compression, before the host waits for it.
     const int err_base = (int)all_items.size();
     all_items.insert(all_items.end(), items.begin(), items.end());
-    std::vector<FacBox> &fac = cur_stage.fac;
-    fac.assign(cnt, FacBox{});
-    // descriptors first (the factor launch waits on them); bookkeeping after the launch
+    std::vector<FacBox> fac(cnt);
     int64_t woff = 0;
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
       const CompBox &cb = comp[i];
-      P.h->box_k[b] = ranks[i];
       FacBox &fb = fac[i];
       std::memset(&fb, 0, sizeof(fb));
       fb.prob = P.pidx;
@@ -648,11 +634,25 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     }
     RS_HIP_CHECK(hipEventRecord(S.ev_diag[par], side));
     diag_pending[par] = true;
+    std::vector<int32_t> ranks(cnt), order(order_total);
+    RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), Dranks.p, cnt * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+    if (order_total)
+      RS_HIP_CHECK(hipMemcpyAsync(order.data(), Dorder.p, order_total * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
+    {
+      auto tw = Clock::now();
+      RS_HIP_CHECK(hipStreamSynchronize(st));
+      wait_ms += ms_since(tw);
+    }
+    prev_stage = Staging();        // the previous level's uploads have completed
+    auto tp2 = Clock::now();
     // skeleton lists (the next level's active sets) and profiler work counts
     Work w_asm, w_id, w_fac;
     for (int i = 0; i < cnt; ++i) {
       const CompBox &cb = comp[i];
       const int k = ranks[i];
+      items[i].ps->h->box_k[items[i].box] = k;
       if (i < nf) {
         w_id += work_fused(cb.m, cb.n, k);
       } else {
