@@ -1988,6 +1988,8 @@ bool fused_class(bool cplx, int n, int m) { return !cplx && n <= kFusedMaxN && m
 // a box takes the first whose column (NW * CPW) and row (64 RT) capacity covers it.
 // Fewer waves per box mean less per-step overhead and more boxes resident per CU; the
 // arithmetic of a box is the same in every variant.
+bool fused_small(int n, int m) { return n <= 32 && m <= 512; }
+
 int fused_variant_of(int n, int m) {
   if (n <= 24 && m <= 320) return 0;     // <256, 5, 6>
   if (n <= 32 && m <= 512) return 1;     // <256, 8, 8>

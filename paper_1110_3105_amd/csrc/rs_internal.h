@@ -132,6 +132,7 @@ constexpr int kFusedMaxN = 80;
 constexpr int kFusedMaxM = 512;
 bool fused_class(bool cplx, int n, int m);
 int fused_variant_of(int n, int m);     // register-resident variant of a launch's largest box
+bool fused_small(int n, int m);         // fits the 256-thread variants
 void launch_compress_fused(const CompBox *boxes, int first, int count, const ProbDev *probs,
                            const int32_t *pool, double *Rarena, int32_t *order_pool,
                            int32_t *ranks, int max_n, int max_m, int max_npx, hipStream_t st);

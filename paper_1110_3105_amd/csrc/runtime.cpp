@@ -134,13 +134,15 @@ struct Scratch {
   PinnedBuf hfac[2];
   hipStream_t side = nullptr;                 // box factorizations of compressed levels
   hipStream_t aux = nullptr;                  // the direct compression class of a level
+  hipStream_t aux2 = nullptr;                 // the small fused boxes of a level
   hipEvent_t ev_comp = nullptr, ev_side = nullptr, ev_diag[2] = {nullptr, nullptr};
-  hipEvent_t ev_up = nullptr, ev_aux = nullptr;
+  hipEvent_t ev_up = nullptr, ev_aux = nullptr, ev_aux2 = nullptr;
   void init_streams() {
     if (side) return;
     RS_HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     RS_HIP_CHECK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
-    for (hipEvent_t *e : {&ev_comp, &ev_side, &ev_diag[0], &ev_diag[1], &ev_up, &ev_aux})
+    RS_HIP_CHECK(hipStreamCreateWithFlags(&aux2, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&ev_comp, &ev_side, &ev_diag[0], &ev_diag[1], &ev_up, &ev_aux, &ev_aux2})
       RS_HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }
 };
@@ -390,7 +392,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   struct SideSync {      // no side- or aux-stream work outlives this call (also on errors)
     hipStream_t s;
     ~SideSync() { (void)hipStreamSynchronize(s); }
-  } side_sync{side}, aux_sync{S.aux};
+  } side_sync{side}, aux_sync{S.aux}, aux2_sync{S.aux2};
   std::vector<ProbDev> probs(np);
   int max_npx = 0, max_depth = 0;
   for (int p = 0; p < np; ++p) {
@@ -448,37 +450,37 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         for (auto &v : nr) near_all[idx++] = std::move(v);
       }
     }
-    // boxes of the fused (register-resident) compression class first, so that each
+    // boxes of the fused (register-resident) compression class first -- the ones that
+    // fit the 256-thread variants, then the others -- then the direct class, so that each
     // class is one contiguous range of the launch (stable order)
-    int nf = 0;
+    int nf = 0, nfs = 0;
     {
       std::vector<char> fz(cnt);
       for (int i = 0; i < cnt; ++i) {
         const ProbState &P = *items[i].ps;
         const int n = (int)P.J[items[i].box].size();
         const int m = 2 * (int)near_all[i].size() + 2 * P.npx + (P.log_kernel ? 2 : 0);
-        fz[i] = fused_class(cplx, n, m) ? 1 : 0;
-        nf += fz[i];
+        fz[i] = fused_class(cplx, n, m) ? (fused_small(n, m) ? 2 : 1) : 0;
+        nf += fz[i] > 0;
+        nfs += fz[i] == 2;
       }
-      if (nf > 0 && nf < cnt) {
-        std::vector<StepBox> it2;
-        std::vector<std::vector<int32_t>> nr2;
-        it2.reserve(cnt);
-        nr2.reserve(cnt);
-        for (int pass = 1; pass >= 0; --pass)
-          for (int i = 0; i < cnt; ++i)
-            if (fz[i] == pass) {
-              it2.push_back(items[i]);
-              nr2.push_back(std::move(near_all[i]));
-            }
-        items.swap(it2);
-        near_all.swap(nr2);
-      }
+      std::vector<StepBox> it2;
+      std::vector<std::vector<int32_t>> nr2;
+      it2.reserve(cnt);
+      nr2.reserve(cnt);
+      for (int pass = 2; pass >= 0; --pass)
+        for (int i = 0; i < cnt; ++i)
+          if (fz[i] == pass) {
+            it2.push_back(items[i]);
+            nr2.push_back(std::move(near_all[i]));
+          }
+      items.swap(it2);
+      near_all.swap(nr2);
     }
     std::vector<CompBox> comp(cnt);
     int64_t M_total = 0, order_total = 0, work_total = 0, pool_total = 0;
     int max_n = 0, max_m_step = 0;
-    int max_n_f = 0, max_m_f = 0, max_n_d = 0, max_m_d = 0;
+    int max_n_f = 0, max_m_f = 0, max_n_s = 0, max_m_s = 0, max_n_d = 0, max_m_d = 0;
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
@@ -495,7 +497,10 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       cb.M_off = M_total;
       // fused boxes keep only the first k rows of R (k <= n): n x n scalars
       M_total += (int64_t)(i < nf ? cb.n : cb.m) * cb.n;
-      if (i < nf) {
+      if (i < nfs) {
+        max_n_s = std::max(max_n_s, cb.n);
+        max_m_s = std::max(max_m_s, cb.m);
+      } else if (i < nf) {
         max_n_f = std::max(max_n_f, cb.n);
         max_m_f = std::max(max_m_f, cb.m);
       } else {
@@ -555,19 +560,27 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                        Dranks.as<int32_t>(), comp[i].n, comp[i].m, st);
       }
     } else {
-      // the two classes touch disjoint boxes: with both present, the direct class runs
-      // on the auxiliary stream beside the fused one
-      const bool both = nf > 0 && nf < cnt;
-      hipStream_t dst = both ? S.aux : st;
+      // the classes touch disjoint boxes: with more than one present, the small fused
+      // boxes and the direct class run on auxiliary streams beside the other fused boxes
+      const int nclass = (nfs > 0) + (nf > nfs) + (nf < cnt);
+      const bool both = nclass > 1;
+      hipStream_t dst = both ? S.aux : st, sst = both ? S.aux2 : st;
       if (both) {
         RS_HIP_CHECK(hipEventRecord(S.ev_up, st));
         RS_HIP_CHECK(hipStreamWaitEvent(S.aux, S.ev_up, 0));
+        RS_HIP_CHECK(hipStreamWaitEvent(S.aux2, S.ev_up, 0));
       }
-      if (nf > 0) {
+      if (nfs > 0) {
+        ProfScope ps_(RS_K_ID, sst);
+        launch_compress_fused(d_comp, 0, nfs, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
+                              Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_s, max_m_s,
+                              max_npx, sst);
+      }
+      if (nf > nfs) {
         ProfScope ps_(RS_K_ID, st);
-        launch_compress_fused(d_comp, 0, nf, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
-                              Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_f, max_m_f,
-                              max_npx, st);
+        launch_compress_fused(d_comp, nfs, nf - nfs, d_probs, Dpool.as<int32_t>(),
+                              S.M.as<double>(), Dorder.as<int32_t>(), Dranks.as<int32_t>(),
+                              max_n_f, max_m_f, max_npx, st);
       }
       if (nf < cnt) {
         {
@@ -582,6 +595,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       if (both) {
         RS_HIP_CHECK(hipEventRecord(S.ev_aux, S.aux));
         RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_aux, 0));
+        RS_HIP_CHECK(hipEventRecord(S.ev_aux2, S.aux2));
+        RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_aux2, 0));
       }
     }
     RS_HIP_CHECK(hipEventRecord(S.ev_comp, st));   // ranks, order and pool of this level

@@ -21,7 +21,7 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   n = n_;
   leaf_size = leaf;
   // bounding box: per-chunk extremes, combined in chunk order (min / max are exact)
-  constexpr int64_t kPtsChunk = 16384;
+  constexpr int64_t kPtsChunk = 4096;
   const int nck = (int)std::max<int64_t>(1, (n + kPtsChunk - 1) / kPtsChunk);
   std::vector<std::array<double, 6>> ext(nck);
   parallel_for(nck, [&](int ci) {
