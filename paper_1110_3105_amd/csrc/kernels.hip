@@ -471,6 +471,70 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const CompBox *__restrict
 }
 
 
+// Chunked assembly of large blocks: blockIdx.x = box * CH + chunk; each chunk writes
+// every CH-th group of kThreads entries of its box (column-major, rows fastest) and the
+// largest proxy-row magnitude it saw into partials[box * CH + chunk]; k_assemble_tail
+// then adds the two rows of the log kernels.  The entries and both maxima equal those
+// of k_assemble.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_assemble_chunks(const CompBox *__restrict__ boxes,
+                                                              int first, int CH,
+                                                              const ProbDev *__restrict__ probs,
+                                                              const int32_t *__restrict__ pool,
+                                                              S *__restrict__ Marena,
+                                                              double *__restrict__ partials) {
+  extern __shared__ double sh_u[];   // npx * 3 proxy unit vectors
+  __shared__ double red[kWaves];
+  const int bi = blockIdx.x / CH, ch = blockIdx.x - bi * CH;
+  const CompBox &B = boxes[first + bi];
+  const ProbDev &P = probs[B.prob];
+  const int n = B.n, nn = B.nn, m = B.m, npx = P.npx, dim = P.dim;
+  if (n == 0) return;
+  const int32_t *J = pool + B.J_off;
+  const int32_t *N = pool + B.N_off;
+  S *M = Marena + B.M_off;
+  for (int p = threadIdx.x; p < npx; p += kThreads) proxy_unit(dim, p, npx, sh_u + 3 * p);
+  __syncthreads();
+  const double wG = dim == 2 ? 2.0 * kPi * B.rho / npx : 4.0 * kPi * B.rho * B.rho / npx;
+  const int rows = 2 * nn + 2 * npx;
+  double pmax = 0.0;
+  const int64_t total = (int64_t)rows * n;
+  for (int64_t e = (int64_t)ch * kThreads + threadIdx.x; e < total; e += (int64_t)CH * kThreads) {
+    const int j = (int)(e / rows), i = (int)(e - (int64_t)j * rows);
+    const S v = comp_entry<S>(P, B, J, N, sh_u, wG, i, j);
+    if (i >= 2 * nn) pmax = fmax(pmax, mag(v));
+    M[(int64_t)j * m + i] = v;
+  }
+  pmax = block_max(pmax, red);
+  if (threadIdx.x == 0) partials[(int64_t)bi * CH + ch] = pmax;
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_assemble_tail(const CompBox *__restrict__ boxes,
+                                                            int first, int CH,
+                                                            const ProbDev *__restrict__ probs,
+                                                            const int32_t *__restrict__ pool,
+                                                            S *__restrict__ Marena,
+                                                            const double *__restrict__ partials) {
+  __shared__ double red[kWaves];
+  const CompBox &B = boxes[first + blockIdx.x];
+  const ProbDev &P = probs[B.prob];
+  const int n = B.n, m = B.m;
+  if (n == 0 || !P.log_kernel) return;
+  const int32_t *J = pool + B.J_off;
+  S *M = Marena + B.M_off;
+  double wmax = 0.0;
+  for (int j = threadIdx.x; j < n; j += kThreads) wmax = fmax(wmax, P.w[J[j]]);
+  wmax = block_max(wmax, red);
+  double pmax = 0.0;
+  for (int c = 0; c < CH; ++c) pmax = fmax(pmax, partials[(int64_t)blockIdx.x * CH + c]);
+  const int rows = 2 * B.nn + 2 * P.npx;
+  for (int j = threadIdx.x; j < n; j += kThreads) {
+    M[(int64_t)j * m + rows] = S(pmax * P.w[J[j]] / wmax);
+    M[(int64_t)j * m + rows + 1] = S(pmax);
+  }
+}
+
 // --------------------------------------------------------------------------
 // Fused compression of small boxes (real data, n <= 16 CPW, m <= 64 RT): M_B is evaluated
 // into registers and factored there by column-pivoted Householder QR with the same rules
@@ -1970,16 +2034,34 @@ bool sweep_nt_valid(bool mfma, int nt, int max_n, int es) {
 
 int mfma_max_n(bool cplx) { return cplx ? kMfmaMaxNComplex : kMfmaMaxN; }
 
+int assemble_chunks(int max_n, int max_m) {
+  const int64_t e = (int64_t)max_n * max_m;
+  return (int)std::min<int64_t>(std::max<int64_t>((e + kThreads * 16 - 1) / (kThreads * 16), 1),
+                                kAssembleMaxChunks);
+}
+
 void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
-                     const int32_t *pool, double *Marena, int max_npx, hipStream_t st) {
+                     const int32_t *pool, double *Marena, int max_npx, int max_n, int max_m,
+                     double *partials, hipStream_t st) {
   if (count <= 0) return;
+  const int CH = assemble_chunks(max_n, max_m);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
-    hipLaunchKernelGGL(k_assemble<S>, dim3(count), dim3(kThreads),
-                       (size_t)max_npx * 3 * sizeof(double), st, boxes, first, probs, pool,
-                       reinterpret_cast<S *>(Marena));
+    if (CH == 1) {
+      hipLaunchKernelGGL(k_assemble<S>, dim3(count), dim3(kThreads),
+                         (size_t)max_npx * 3 * sizeof(double), st, boxes, first, probs, pool,
+                         reinterpret_cast<S *>(Marena));
+      check_launch("k_assemble");
+      return;
+    }
+    hipLaunchKernelGGL(k_assemble_chunks<S>, dim3(count * CH), dim3(kThreads),
+                       (size_t)max_npx * 3 * sizeof(double), st, boxes, first, CH, probs, pool,
+                       reinterpret_cast<S *>(Marena), partials);
+    check_launch("k_assemble_chunks");
+    hipLaunchKernelGGL(k_assemble_tail<S>, dim3(count), dim3(kThreads), 0, st, boxes, first, CH,
+                       probs, pool, reinterpret_cast<S *>(Marena), partials);
+    check_launch("k_assemble_tail");
   });
-  check_launch("k_assemble");
 }
 
 bool fused_class(bool cplx, int n, int m) { return !cplx && n <= kFusedMaxN && m <= kFusedMaxM; }

@@ -115,8 +115,14 @@ __host__ __device__ inline int64_t slot_bound(int n) { return (5 * (int64_t)n * 
 // All launchers enqueue on `st`; grid = one workgroup per box in [first, first+count).
 // `cplx` selects the scalar type of the arrays behind the double pointers: binary64, or
 // complex128 (re/im pairs) for the Helmholtz kernel.
+// Blocks with more than kThreads * 16 entries are assembled by several workgroups per
+// box (assemble_chunks(max_n, max_m) of them; `partials` holds count * chunks doubles);
+// smaller ones by one workgroup per box.  The entries are the same either way.
+constexpr int kAssembleMaxChunks = 1024;
+int assemble_chunks(int max_n, int max_m);
 void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
-                     const int32_t *pool, double *Marena, int max_npx, hipStream_t st);
+                     const int32_t *pool, double *Marena, int max_npx, int max_n, int max_m,
+                     double *partials, hipStream_t st);
 void launch_cpqr_id(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
                     double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                     hipStream_t st);

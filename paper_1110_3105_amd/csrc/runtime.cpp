@@ -129,7 +129,7 @@ struct PinnedBuf {
 // in two sets used by alternate levels: the factorization of one level runs on a second
 // stream while the next level is compressed.
 struct Scratch {
-  DevBuf pool, comp, fac, M, order, ranks, work, err, probs;
+  DevBuf pool, comp, fac, M, order, ranks, work, err, probs, partials;
   DevBuf pool2[2], order2[2], ranks2[2], fac2[2];
   PinnedBuf hfac[2];
   hipStream_t side = nullptr;                 // box factorizations of compressed levels
@@ -540,6 +540,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     Dorder.ensure(std::max<int64_t>(order_total, 1) * sizeof(int32_t));
     Dranks.ensure(std::max(cnt, 1) * sizeof(int32_t));
     S.work.ensure(std::max<int64_t>(work_total, 1) * sizeof(double) * es);
+    S.partials.ensure((size_t)std::max(cnt - nf, 1) * assemble_chunks(max_n_d, max_m_d) *
+                      sizeof(double));
     const CompBox *d_comp = S.comp.as<CompBox>();
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
@@ -553,7 +555,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         {
           ProfScope ps_(RS_K_ASSEMBLE, st);
           launch_assemble(cplx, d_comp, i, 1, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
-                          max_npx, st);
+                          max_npx, comp[i].n, comp[i].m, S.partials.as<double>(), st);
         }
         ProfScope ps_(RS_K_ID, st);
         launch_cpqr_id(cplx, d_comp, i, 1, d_probs, S.M.as<double>(), Dorder.as<int32_t>(),
@@ -586,7 +588,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         {
           ProfScope ps_(RS_K_ASSEMBLE, dst);
           launch_assemble(cplx, d_comp, nf, cnt - nf, d_probs, Dpool.as<int32_t>(),
-                          S.M.as<double>(), max_npx, dst);
+                          S.M.as<double>(), max_npx, max_n_d, max_m_d, S.partials.as<double>(),
+                          dst);
         }
         ProfScope ps_(RS_K_ID, dst);
         launch_cpqr_id(cplx, d_comp, nf, cnt - nf, d_probs, S.M.as<double>(),
