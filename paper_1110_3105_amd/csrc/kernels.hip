@@ -780,20 +780,18 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
     rk[c] = r;
   }
   __syncthreads();
+  // one thread per redundant column: back substitution over the rows of R11 (pivot
+  // order), x_l kept in the output column itself (sorted skeleton position rk[piv[l]])
   double *T = B.T;
-  double *buf = wbuf + wave * n;
-  for (int c = wave; c < n; c += NW) {
+  for (int c = tid; c < n; c += NTH) {
     if (done[c]) continue;
     const double *col = R + (int64_t)c * k;
-    for (int i = lane; i < k; i += 64) buf[i] = col[i];
-    for (int i = k - 1; i >= 0; --i) {
-      const double *ri = R + (int64_t)piv[i] * k;
-      const double xi = buf[i] / ri[i];
-      for (int l = lane; l < i; l += 64) buf[l] -= xi * ri[l];
-      if (lane == 0) buf[i] = xi;
-    }
     double *Tc = T + (int64_t)k * rk[c];
-    for (int i = lane; i < k; i += 64) Tc[rk[piv[i]]] = buf[i];
+    for (int i = k - 1; i >= 0; --i) {
+      double s = col[i];
+      for (int l = i + 1; l < k; ++l) s -= R[(int64_t)piv[l] * k + i] * Tc[rk[piv[l]]];
+      Tc[rk[piv[i]]] = s / R[(int64_t)piv[i] * k + i];
+    }
   }
   if (tid == 0) ranks[B.kslot] = k;
 }
