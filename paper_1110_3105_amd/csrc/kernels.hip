@@ -1232,24 +1232,32 @@ __device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
       const int ci = lane & 15, kq = lane >> 4;
       for (int tile = wave; tile < tr * tq; tile += NW) {
         const int ti = tile / tq, tc = tile - ti * tq;
-        Acc<S> acc;
         const int i = ti * 16 + ci;
         const int cc = tc * 16 + ci;
+        const int q = q0 + cc;
+        const bool colok = cc < qc && !(q >= p0 && q < p0 + pb);
+        // the tile's current values are loaded before the products, so their latency
+        // overlaps the MFMA steps
+        S cur[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ti * 16 + kq + 4 * v;
+          cur[v] = (colok && row < r) ? A[q * lda + row] : S(0.0);
+        }
+        Acc<S> acc;
         for (int k0 = 0; k0 < pb; k0 += 4) {
           const int kk = k0 + kq;
           const S av = (i < r && kk < pb) ? PN[i + kk * ldp] : S(0.0);
           const S bv = (kk < pb && cc < qc) ? Wt[kk * kQC + cc] : S(0.0);
           acc.mma(av, bv);
         }
-        const int q = q0 + cc;
-        if (cc < qc && !(q >= p0 && q < p0 + pb)) {
+        if (colok) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = ti * 16 + kq + 4 * v;
             if (row < r) {
               const int us = ustep[row];
-              S *ap = A + q * lda + row;
-              *ap = ((us >= p0 && us < p0 + pb) ? S(0.0) : *ap) + acc.get(v);
+              A[q * lda + row] = ((us >= p0 && us < p0 + pb) ? S(0.0) : cur[v]) + acc.get(v);
             }
           }
         }
