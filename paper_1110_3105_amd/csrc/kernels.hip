@@ -906,6 +906,77 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
     const S *vg = M + (int64_t)j * m;
     auto vload = [&](int i) -> S { return i == j ? S(1.0) : (VLDS ? sv[i] : vg[i]); };
     const int rows = m - j;
+    // Pipelined rounds of CBP columns: the next round's columns are loaded while the
+    // current one is reduced and written (software pipelining over the L2 latency), the
+    // reflector once per step; register budget: two rounds plus the reflector in at most
+    // 48 doubles per lane (half that with 1024 threads).  Per column the arithmetic is
+    // that of the plain rounds: one fused multiply-add per real term.  Complex data keeps
+    // the plain rounds, so that each complex product is contracted the same way in every
+    // variant a box can be launched with.
+    constexpr int ES = (int)(sizeof(S) / sizeof(double));
+    constexpr bool PIPE = ES == 1 && RT * (NTH >= 1024 ? 2 : 1) <= 16;
+    constexpr int CBP0 = RT * ES >= 16 ? 1 : 16 / (RT * ES);
+    constexpr int CBP = CBP0 < CB ? CBP0 : CB;
+    if (PIPE && rows <= 64 * RT) {
+      S vi[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int i = j + lane + 64 * t;
+        vi[t] = i < m ? vload(i) : S(0.0);
+      }
+      S nxt[CBP][RT];
+      auto load_round = [&](int c0) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = j + lane + 64 * t;
+#pragma unroll
+          for (int cb = 0; cb < CBP; ++cb) {
+            const int c = c0 + cb;
+            nxt[cb][t] = (i < m && c < n) ? M[(int64_t)c * m + i] : S(0.0);
+          }
+        }
+      };
+      const int c_first = j + 1 + wave * CBP;
+      if (c_first < n) load_round(c_first);
+      for (int c0 = c_first; c0 < n; c0 += NW * CBP) {
+        S val[CBP][RT];
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) val[cb][t] = nxt[cb][t];
+        if (c0 + NW * CBP < n) load_round(c0 + NW * CBP);
+        S dot[CBP];
+        double nrm[CBP];
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb) { dot[cb] = S(0.0); nrm[cb] = 0.0; }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int cb = 0; cb < CBP; ++cb) dot[cb] += conjg(vi[t]) * val[cb][t];
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb) dot[cb] = wave_sum(dot[cb]) * ctau;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = j + lane + 64 * t;
+          if (i < m) {
+#pragma unroll
+            for (int cb = 0; cb < CBP; ++cb) {
+              const int c = c0 + cb;
+              if (c < n) {
+                const S nv = val[cb][t] - dot[cb] * vi[t];
+                M[(int64_t)c * m + i] = nv;
+                if (i > j) nrm[cb] += abs2(nv);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb) {
+          const double sn = wave_sum(nrm[cb]);
+          if (lane == 0 && c0 + cb < n) norms[c0 + cb] = sqrt(sn);
+        }
+      }
+    } else
     for (int c0 = j + 1 + wave * CB; c0 < n; c0 += NW * CB) {
       S dot[CB];
       double nrm[CB];
