@@ -417,13 +417,85 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   // Every factored box gets a global index; a singular pivot reports the first one,
   // checked once after the root (no host wait per level).
   std::vector<StepBox> all_items;
-  // Host staging of the uploads enqueued after a level's rank readback: kept until the
-  // next synchronization, so the asynchronous copies never read released memory.
-  struct Staging {
-    std::vector<FacBox> fac;
-    std::vector<std::vector<int32_t>> idx;
+  // A level's solve data (index lists, sweep descriptors) is not needed to plan the next
+  // level, so it is built while the next level compresses (`deferred`).  Host arrays of
+  // its uploads stay in `keep_alive` until the next synchronization of the stream.
+  struct Deferred {
+    std::vector<StepBox> items;
+    std::vector<CompBox> comp;
+    std::vector<int32_t> ranks, order;
+    bool pending = false;
+  } dfr;
+  std::vector<std::vector<int32_t>> keep_alive;
+  auto run_deferred = [&]() {
+    if (!dfr.pending) return;
+    dfr.pending = false;
+    const std::vector<StepBox> &items = dfr.items;
+    const std::vector<CompBox> &comp = dfr.comp;
+    const std::vector<int32_t> &ranks = dfr.ranks, &order = dfr.order;
+    const int cnt = (int)items.size();
+    // persistent solve data: index lists (skeletons then redundant, tree positions),
+    // one contiguous block and one upload per problem and level
+    std::vector<std::vector<int32_t>> idx_keep(np);
+    std::vector<int32_t *> d_idx_base(np, nullptr);
+    std::vector<int64_t> idx_fill(np, 0);
+    for (int i = 0; i < cnt; ++i) idx_fill[items[i].ps->pidx] += comp[i].n;
+    for (int p = 0; p < np; ++p) {
+      if (idx_fill[p] == 0) continue;
+      d_idx_base[p] = ps[p].h->arena.alloc_n<int32_t>(idx_fill[p]);
+      idx_keep[p].resize(idx_fill[p]);
+      idx_fill[p] = 0;
+    }
+    std::vector<int64_t> idx_at(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      const int pi = items[i].ps->pidx;
+      idx_at[i] = idx_fill[pi];
+      idx_fill[pi] += comp[i].n;
+    }
+    parallel_for(cnt, [&](int i) {
+      ProbState &P = *items[i].ps;
+      const int32_t *ord = order.data() + comp[i].order_off;
+      int32_t *idx = idx_keep[P.pidx].data() + idx_at[i];
+      const std::vector<int32_t> &J = P.J[items[i].box];
+      for (int a = 0; a < comp[i].n; ++a) idx[a] = J[ord[a]];
+    }, 64);
+    for (int i = 0; i < cnt; ++i) {
+      ProbState &P = *items[i].ps;
+      const int b = items[i].box;
+      const int k = ranks[i], n = comp[i].n;
+      int32_t *d_idx = d_idx_base[P.pidx] + idx_at[i];
+      SweepBox sb;
+      sb.k = k;
+      sb.r = n - k;
+      sb.idx = d_idx;
+      double *slot = comp[i].T;
+      sb.T = slot + slot_T(k, n - k) * es;
+      sb.G = slot + slot_G(k, n - k) * es;
+      sb.E = slot + slot_E(k, n - k) * es;
+      sb.F = slot + slot_F(k, n - k) * es;
+      rs_factor_s *h = P.h;
+      const int d = P.t->depth[b];
+      if (h->levels.empty() || h->levels.back().depth != d) {
+        h->levels.emplace_back();
+        h->levels.back().depth = d;
+      }
+      LevelRec &lv = h->levels.back();
+      lv.boxes.push_back(b);
+      lv.sweep.push_back(sb);
+      lv.max_n = std::max(lv.max_n, n);
+      h->stats.total_skeletons += k;
+      h->stats.factor_doubles += (slot_size(k, n - k) - (int64_t)k * k) * es;
+      h->stats.max_box_n = std::max<int64_t>(h->stats.max_box_n, n);
+      h->stats.max_box_m = std::max<int64_t>(h->stats.max_box_m, comp[i].m);
+    }
+    for (int p = 0; p < np; ++p)
+      if (!idx_keep[p].empty()) {
+        RS_HIP_CHECK(hipMemcpyAsync(d_idx_base[p], idx_keep[p].data(),
+                                    idx_keep[p].size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    st));
+        keep_alive.push_back(std::move(idx_keep[p]));
+      }
   };
-  Staging prev_stage, cur_stage;
 
   // ---- compressed levels, aligned at the finest depth of every problem
   for (int step = 0; step < max_depth; ++step) {
@@ -652,6 +724,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     }
     RS_HIP_CHECK(hipEventRecord(S.ev_diag[par], side));
     diag_pending[par] = true;
+    run_deferred();        // the previous level's solve data, while this level compresses
     std::vector<int32_t> ranks(cnt), order(order_total);
     RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), Dranks.p, cnt * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, st));
@@ -663,7 +736,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       RS_HIP_CHECK(hipStreamSynchronize(st));
       wait_ms += ms_since(tw);
     }
-    prev_stage = Staging();        // the previous level's uploads have completed
+    keep_alive.clear();            // the uploads queued before this wait have completed
     auto tp2 = Clock::now();
     // skeleton lists (the next level's active sets) and profiler work counts
     Work w_asm, w_id, w_fac;
@@ -691,70 +764,15 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     prof_add_work(RS_K_ASSEMBLE, w_asm);
     prof_add_work(RS_K_ID, w_id);
     prof_add_work(RS_K_FACTOR, w_fac);
-    // persistent solve data: index lists (skeletons then redundant, tree positions),
-    // one contiguous block and one upload per problem and level
-    std::vector<std::vector<int32_t>> &idx_keep = cur_stage.idx;
-    idx_keep.assign(np, {});
-    std::vector<int32_t *> d_idx_base(np, nullptr);
-    std::vector<int64_t> idx_fill(np, 0);
-    for (int i = 0; i < cnt; ++i) idx_fill[items[i].ps->pidx] += comp[i].n;
-    for (int p = 0; p < np; ++p) {
-      if (idx_fill[p] == 0) continue;
-      d_idx_base[p] = ps[p].h->arena.alloc_n<int32_t>(idx_fill[p]);
-      idx_keep[p].resize(idx_fill[p]);
-      idx_fill[p] = 0;
-    }
-    std::vector<int64_t> idx_at(cnt);
-    for (int i = 0; i < cnt; ++i) {
-      const int pi = items[i].ps->pidx;
-      idx_at[i] = idx_fill[pi];
-      idx_fill[pi] += comp[i].n;
-    }
-    parallel_for(cnt, [&](int i) {
-      ProbState &P = *items[i].ps;
-      const int32_t *ord = order.data() + comp[i].order_off;
-      int32_t *idx = idx_keep[P.pidx].data() + idx_at[i];
-      const std::vector<int32_t> &J = P.J[items[i].box];
-      for (int a = 0; a < comp[i].n; ++a) idx[a] = J[ord[a]];
-    }, 64);
-    for (int i = 0; i < cnt; ++i) {
-      ProbState &P = *items[i].ps;
-      const int b = items[i].box;
-      const int k = ranks[i], n = comp[i].n;
-      int32_t *d_idx = d_idx_base[P.pidx] + idx_at[i];
-      SweepBox sb;
-      sb.k = k;
-      sb.r = n - k;
-      sb.idx = d_idx;
-      double *slot = comp[i].T;
-      sb.T = slot + slot_T(k, n - k) * es;
-      sb.G = slot + slot_G(k, n - k) * es;
-      sb.E = slot + slot_E(k, n - k) * es;
-      sb.F = slot + slot_F(k, n - k) * es;
-      rs_factor_s *h = P.h;
-      const int d = P.t->depth[b];
-      if (h->levels.empty() || h->levels.back().depth != d) {
-        h->levels.emplace_back();
-        h->levels.back().depth = d;
-      }
-      LevelRec &lv = h->levels.back();
-      lv.boxes.push_back(b);
-      lv.sweep.push_back(sb);
-      lv.max_n = std::max(lv.max_n, n);
-      h->stats.total_skeletons += k;
-      h->stats.factor_doubles += (slot_size(k, n - k) - (int64_t)k * k) * es;
-      h->stats.max_box_n = std::max<int64_t>(h->stats.max_box_n, n);
-      h->stats.max_box_m = std::max<int64_t>(h->stats.max_box_m, comp[i].m);
-    }
-    for (int p = 0; p < np; ++p)
-      if (!idx_keep[p].empty())
-        RS_HIP_CHECK(hipMemcpyAsync(d_idx_base[p], idx_keep[p].data(),
-                                    idx_keep[p].size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                    st));
-    std::swap(prev_stage, cur_stage);   // released after the next level's readback
+    dfr.items = std::move(items);
+    dfr.comp = std::move(comp);
+    dfr.ranks = std::move(ranks);
+    dfr.order = std::move(order);
+    dfr.pending = true;
     plan_ms += ms_since(tp2);
   }
 
+  run_deferred();
   // ---- roots: the dense block of the surviving skeletons, fully eliminated (on st,
   // after every box factorization of the side stream)
   RS_HIP_CHECK(hipEventRecord(S.ev_side, side));
@@ -816,7 +834,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       check_err(S.err, st, all_items, "factorization");
       wait_ms += ms_since(tw);
     }
-    prev_stage = Staging();
+    keep_alive.clear();
     for (int p = 0; p < np; ++p) {
       ProbState &P = ps[p];
       const std::vector<int32_t> &J = P.J[0];
