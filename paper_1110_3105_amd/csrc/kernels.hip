@@ -884,16 +884,44 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
     if (wave == 0) {   // Householder reflector of column j, rows j..m-1
       S *cj = M + (int64_t)j * m;
       double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) s += abs2(cj[i]);
+      // real data with at most 512 threads: the column's rows j + lane + 64 t are held
+      // in registers between the norm and the scaling, when they fit
+      constexpr bool kHhRegs = sizeof(S) == sizeof(double) && NTH <= 512;
+      const bool in_regs = kHhRegs && m - j <= 64 * RT;
+      S xv[RT];
+      if (in_regs) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = j + lane + 64 * t;
+          xv[t] = i < m ? cj[i] : S(0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+          if (j + lane + 64 * t < m) s += abs2(xv[t]);
+      } else {
+        for (int i = j + lane; i < m; i += 64) s += abs2(cj[i]);
+      }
       s = wave_sum(s);
       const double alpha = sqrt(s);
       const S x0 = cj[j];
       const double beta = re_part(x0) >= 0.0 ? -alpha : alpha;
       const S scale = recip(x0 - S(beta));
-      for (int i = j + 1 + lane; i < m; i += 64) {
-        const S v = cj[i] * scale;
-        cj[i] = v;
-        if (VLDS) sv[i] = v;
+      if (in_regs) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = j + lane + 64 * t;
+          if (i > j && i < m) {
+            const S v = xv[t] * scale;
+            cj[i] = v;
+            if (VLDS) sv[i] = v;
+          }
+        }
+      } else {
+        for (int i = j + 1 + lane; i < m; i += 64) {
+          const S v = cj[i] * scale;
+          cj[i] = v;
+          if (VLDS) sv[i] = v;
+        }
       }
       if (lane == 0) {
         s_ctau = conjg(sdiv(S(beta) - x0, beta));
@@ -1139,31 +1167,37 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // One non-pivot row of a panel step: A(i, c) <- A(i, c) - f prow[c] (c != jj) and
-// A(i, jj) <- -f inv with f = A(i, jj).  The row's entries are loaded in groups of 8
-// before any store, so the loads are in flight together.
+// A(i, jj) <- -f inv with f = A(i, jj).  The row's entries and those of prow are loaded
+// in groups (8 real, 4 complex) before any store, so the loads are in flight together.
 template <class S>
 __device__ __forceinline__ void gj_row_update(S *row, int ldp, int pb, int jj, S inv,
                                               const S *prow) {
+  constexpr int G = sizeof(S) == sizeof(double) ? 8 : 4;
   const S f = row[jj * ldp];
 #pragma unroll
-  for (int h = 0; h < kPB; h += 8) {
-    S v[8];
+  for (int h = 0; h < kPB; h += G) {
+    S v[G], pv[G];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = h + c < pb ? row[(h + c) * ldp] : S(0.0);
+    for (int c = 0; c < G; ++c) {
+      v[c] = h + c < pb ? row[(h + c) * ldp] : S(0.0);
+      pv[c] = h + c < pb ? prow[h + c] : S(0.0);
+    }
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if (h + c < pb) row[(h + c) * ldp] = h + c == jj ? S(0.0) - f * inv : v[c] - f * prow[h + c];
+    for (int c = 0; c < G; ++c)
+      if (h + c < pb) row[(h + c) * ldp] = h + c == jj ? S(0.0) - f * inv : v[c] - f * pv[c];
   }
 }
 
 // All rows i = i0, i0 + stride, ... < r of one panel step: the pivot row pr becomes
 // prow, every other row gets gj_row_update's values.  Full panels (pb = kPB) take a
-// branch-free path with the row's entries loaded before any store.
+// branch-free path: each group of a row's entries is loaded together with the matching
+// entries of prow before any store (a store to a row could alias prow, so a prow read
+// after a store would wait for it: one LDS round trip per entry).
 template <class S>
 __device__ __forceinline__ void gj_step_rows(S *PN, int ldp, int r, int i0, int stride, int pr,
                                              int pb, int jj, S inv, const S *prow) {
   if (pb == kPB) {
-    constexpr int G = sizeof(S) == sizeof(double) ? kPB : kPB / 2;
+    constexpr int G = sizeof(S) == sizeof(double) ? kPB / 2 : kPB / 4;
     for (int i = i0; i < r; i += stride) {
       S *row = PN + i;
       if (i == pr) {
@@ -1174,12 +1208,15 @@ __device__ __forceinline__ void gj_step_rows(S *PN, int ldp, int r, int i0, int 
         const S fj = S(0.0) - f * inv;
 #pragma unroll
         for (int h = 0; h < kPB; h += G) {
-          S v[G];
-#pragma unroll
-          for (int c = 0; c < G; ++c) v[c] = row[(h + c) * ldp];
+          S v[G], pv[G];
 #pragma unroll
           for (int c = 0; c < G; ++c) {
-            const S u = v[c] - f * prow[h + c];
+            v[c] = row[(h + c) * ldp];
+            pv[c] = prow[h + c];
+          }
+#pragma unroll
+          for (int c = 0; c < G; ++c) {
+            const S u = v[c] - f * pv[c];
             row[(h + c) * ldp] = h + c == jj ? fj : u;
           }
         }
@@ -1223,17 +1260,86 @@ __device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
 
   // Steps p0 .. p0 + pb - 1 on the panel PN (ld ldp; in LDS when pn_on_chip).  Returns
   // false on a bad pivot (uniform over the workgroup).
+  // Real data: panels of at most NTH rows are held in registers (complex rows would
+  // need twice the registers; they keep the LDS paths).
+  constexpr bool kRegPanel = sizeof(S) == sizeof(double);
   auto panel = [&](S *PN, int ldp, int p0, int pb, bool pn_on_chip) -> bool {
-    if (r <= kWavePanelMaxR && pn_on_chip) {
+    if (kRegPanel && r <= NTH) {
+      // One panel row per thread, held in registers through the pb steps: per step a
+      // block-wide argmax (two barriers) and a register update of every row, the same
+      // operations as gj_step_rows.
+      const int i = tid;
+      const bool own = i < r;
+      S rowv[kPB];
+#pragma unroll
+      for (int c = 0; c < kPB; ++c) rowv[c] = (own && c < pb) ? PN[i + c * ldp] : S(0.0);
+      bool used = !own || ustep[i] >= 0;
+      for (int jj = 0; jj < pb; ++jj) {
+        const int j = p0 + jj;
+        S x = rowv[0];
+#pragma unroll
+        for (int c = 1; c < kPB; ++c)
+          if (c == jj) x = rowv[c];
+        const double mv = mag(x);
+        const bool cand = !used && mv > -1.0;          // NaN rows are never chosen
+        const ArgMax am = wave_argmax(cand ? mv : -1.0, cand ? i : INT_MAX, 0);
+        if (lane == 0) { red_v[wave] = am.v; red_i[wave] = am.key; }
+        __syncthreads();
+        const ArgMax g = wave_argmax(lane < NW ? red_v[lane] : -1.0,
+                                     lane < NW ? red_i[lane] : INT_MAX, 0);
+        if (!(g.v > 0.0) || !isfinite(g.v)) return false;
+        const int pr = g.key;
+        if (i == pr) {
+          const S inv = recip(x);
+#pragma unroll
+          for (int c = 0; c < kPB; ++c)
+            if (c < pb) prow[c] = c == jj ? inv : rowv[c] * inv;
+          ustep[pr] = j;
+          piv[j] = pr;
+          used = true;
+        }
+        __syncthreads();
+        if (i == pr) {
+#pragma unroll
+          for (int c = 0; c < kPB; ++c)
+            if (c < pb) rowv[c] = prow[c];
+        } else if (own) {
+          const S inv = prow[jj];
+          const S fj = S(0.0) - x * inv;
+#pragma unroll
+          for (int c = 0; c < kPB; ++c)
+            if (c < pb) rowv[c] = c == jj ? fj : rowv[c] - x * prow[c];
+        }
+      }
+      if (own) {
+#pragma unroll
+        for (int c = 0; c < kPB; ++c)
+          if (c < pb) PN[i + c * ldp] = rowv[c];
+      }
+      __syncthreads();
+      return true;
+    }
+    if ((!kRegPanel || NTH < kWavePanelMaxR) && r <= kWavePanelMaxR && pn_on_chip) {
       if (wave == 0) {
         for (int jj = 0; jj < pb; ++jj) {
           const int j = p0 + jj;
           double lb = -1.0;
           int li = INT_MAX;
-          for (int i = lane; i < r; i += 64) {
-            if (ustep[i] >= 0) continue;
-            const double v = mag(PN[i + jj * ldp]);
-            if (v > lb || (v == lb && i < li)) { lb = v; li = i; }
+          // rows in groups of 4 per lane, loaded before they are compared (r <= 512)
+          for (int i0 = lane; i0 < r; i0 += 256) {
+            int us[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int i = i0 + 64 * u;
+              us[u] = i < r ? ustep[i] : 0;
+              v[u] = i < r ? mag(PN[i + jj * ldp]) : -1.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int i = i0 + 64 * u;
+              if (us[u] < 0 && (v[u] > lb || (v[u] == lb && i < li))) { lb = v[u]; li = i; }
+            }
           }
           const ArgMax am = wave_argmax(lb, li, li);
           if (!(am.v > 0.0) || !isfinite(am.v)) {
