@@ -1559,29 +1559,76 @@ __global__ __launch_bounds__(NTH, 4) void k_diag_factor(const FacBox *__restrict
   S *X = INLDS ? sh : workbase + B.work_off;                 // n x n, (s, r) order
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  // D in (s, r) order.
-  for (int b = wave; b < n; b += NW) {
-    const int lj = ord ? ord[b] : b;
-    int cb = 0;
-    if (!B.leaf)
-      for (int c = 1; c < B.nchild; ++c) cb += lj >= B.child_lo[c];
-    S *Xb = X + (int64_t)b * n;
-    for (int a = lane; a < n; a += 64) {
-      const int li = ord ? ord[a] : a;
-      S v;
-      if (B.leaf) {
-        v = entry<S>(P, J[li], J[lj]);
-      } else {
-        int ca = 0;
-        for (int c = 1; c < B.nchild; ++c) ca += li >= B.child_lo[c];
-        if (ca == cb) {
-          v = reinterpret_cast<const S *>(B.child_lam[ca])[(li - B.child_lo[ca]) +
-              (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
-        } else {
+  // D in (s, r) order.  Real data: a lane takes its rows four at a time; their indices,
+  // child and target point are loaded once and reused for every column of the wave, and
+  // the four entries of a column are formed before they are stored.  Complex data (whose
+  // kernel is an out-of-line call) takes one entry at a time.  Either way each entry is
+  // entry()'s value, or the child's Lambda entry.
+  if constexpr (sizeof(S) != sizeof(double)) {
+    for (int b = wave; b < n; b += NW) {
+      const int lj = ord ? ord[b] : b;
+      int cb = 0;
+      if (!B.leaf)
+        for (int c = 1; c < B.nchild; ++c) cb += lj >= B.child_lo[c];
+      S *Xb = X + (int64_t)b * n;
+      for (int a = lane; a < n; a += 64) {
+        const int li = ord ? ord[a] : a;
+        S v;
+        if (B.leaf) {
           v = entry<S>(P, J[li], J[lj]);
+        } else {
+          int ca = 0;
+          for (int c = 1; c < B.nchild; ++c) ca += li >= B.child_lo[c];
+          if (ca == cb) {
+            v = reinterpret_cast<const S *>(B.child_lam[ca])[(li - B.child_lo[ca]) +
+                (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
+          } else {
+            v = entry<S>(P, J[li], J[lj]);
+          }
+        }
+        Xb[a] = v;
+      }
+    }
+  } else
+  for (int a0 = lane; a0 < n; a0 += 256) {
+    int li[4], gi[4], ca[4];
+    double tx[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = min(a0 + 64 * u, n - 1);
+      li[u] = ord ? ord[a] : a;
+      gi[u] = J[li[u]];
+      ca[u] = 0;
+      if (!B.leaf)
+        for (int c = 1; c < B.nchild; ++c) ca[u] += li[u] >= B.child_lo[c];
+      load_pt(P, gi[u], tx[u]);
+    }
+    for (int b = wave; b < n; b += NW) {
+      const int lj = ord ? ord[b] : b;
+      int cb = 0;
+      if (!B.leaf)
+        for (int c = 1; c < B.nchild; ++c) cb += lj >= B.child_lo[c];
+      const int gj = J[lj];
+      double sx[3], ns[3];
+      load_pt(P, gj, sx);
+      load_nrm(P, gj, ns);
+      const double wj = P.w[gj];
+      S v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!B.leaf && ca[u] == cb) {
+          v[u] = reinterpret_cast<const S *>(B.child_lam[cb])[(li[u] - B.child_lo[cb]) +
+                 (int64_t)B.child_k[cb] * (lj - B.child_lo[cb])];
+        } else if (gi[u] == gj) {
+          v[u] = diag_entry<S>(P, gj);
+        } else {
+          v[u] = kernel_val<S>(P, tx[u], sx, ns) * wj;
         }
       }
-      Xb[a] = v;
+      S *Xb = X + (int64_t)b * n;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (a0 + 64 * u < n) Xb[a0 + 64 * u] = v[u];
     }
   }
   __syncthreads();
