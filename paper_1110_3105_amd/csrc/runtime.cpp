@@ -495,6 +495,20 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                                     st));
         keep_alive.push_back(std::move(idx_keep[p]));
       }
+    // a step holds every box of one depth of each problem in it: those levels are
+    // complete, and their sweep descriptors go to the device now (the handle keeps the
+    // host copies)
+    std::vector<char> stepped(np, 0);
+    for (int i = 0; i < cnt; ++i) stepped[items[i].ps->pidx] = 1;
+    for (int p = 0; p < np; ++p) {
+      if (!stepped[p]) continue;
+      rs_factor_s *h = ps[p].h;
+      LevelRec &lv = h->levels.back();
+      lv.partition_classes(mfma_max_n(cplx));
+      lv.d_sweep = h->arena.alloc_n<SweepBox>((int64_t)lv.sweep.size());
+      RS_HIP_CHECK(hipMemcpyAsync(lv.d_sweep, lv.sweep.data(), lv.sweep.size() * sizeof(SweepBox),
+                                  hipMemcpyHostToDevice, st));
+    }
   };
 
   // ---- compressed levels, aligned at the finest depth of every problem
@@ -536,16 +550,31 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         nf += fz[i] > 0;
         nfs += fz[i] == 2;
       }
+      // Within the 512-thread fused class (one workgroup per CU, several rounds per
+      // launch on wide levels) the largest blocks go first, so that the last round holds
+      // short boxes; a box's arithmetic does not depend on its place in the launch.
+      std::vector<int64_t> cost(cnt);
+      for (int i = 0; i < cnt; ++i) {
+        const ProbState &P = *items[i].ps;
+        const int64_t n = (int64_t)P.J[items[i].box].size();
+        cost[i] = n * (2 * (int64_t)near_all[i].size() + 2 * P.npx);
+      }
       std::vector<StepBox> it2;
       std::vector<std::vector<int32_t>> nr2;
       it2.reserve(cnt);
       nr2.reserve(cnt);
-      for (int pass = 2; pass >= 0; --pass)
+      for (int pass = 2; pass >= 0; --pass) {
+        std::vector<int> sel;
         for (int i = 0; i < cnt; ++i)
-          if (fz[i] == pass) {
-            it2.push_back(items[i]);
-            nr2.push_back(std::move(near_all[i]));
-          }
+          if (fz[i] == pass) sel.push_back(i);
+        if (pass == 1)
+          std::stable_sort(sel.begin(), sel.end(),
+                           [&](int x, int y) { return cost[x] > cost[y]; });
+        for (int i : sel) {
+          it2.push_back(items[i]);
+          nr2.push_back(std::move(near_all[i]));
+        }
+      }
       items.swap(it2);
       near_all.swap(nr2);
     }
@@ -861,6 +890,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   for (int p = 0; p < np; ++p) {
     rs_factor_s *h = handles[p].get();
     for (LevelRec &lv : h->levels) {
+      if (lv.d_sweep) continue;                 // uploaded when its step completed
       lv.partition_classes(mfma_max_n(cplx));
       lv.d_sweep = h->arena.alloc_n<SweepBox>((int64_t)lv.sweep.size());
       RS_HIP_CHECK(hipMemcpyAsync(lv.d_sweep, lv.sweep.data(), lv.sweep.size() * sizeof(SweepBox),
