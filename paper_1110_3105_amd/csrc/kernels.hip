@@ -1712,7 +1712,21 @@ __device__ __forceinline__ Acc<S> tile_gemm(AF a, const S *Bs, int ldb, int K, i
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
   Acc<S> acc;
   const bool rowok = r0 + i < M;
-  for (int k0 = 0; k0 < K; k0 += 4) {
+  int k0 = 0;
+  // four K steps' operands are loaded before their products (the same products in the
+  // same order), so the operand loads are in flight together
+  for (; k0 + 16 <= K; k0 += 16) {
+    S av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + 4 * u + kq;
+      av[u] = rowok ? a(r0 + i, kk) : S(0.0);
+      bv[u] = Bs[kk * ldb + c0 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc.mma(av[u], bv[u]);
+  }
+  for (; k0 < K; k0 += 4) {
     const int kk = k0 + kq;
     const bool kok = kk < K;
     const S av = (rowok && kok) ? a(r0 + i, kk) : S(0.0);
@@ -1720,6 +1734,28 @@ __device__ __forceinline__ Acc<S> tile_gemm(AF a, const S *Bs, int ldb, int K, i
     acc.mma(av, bv);
   }
   return acc;
+}
+
+// The box's rows of W (columns col0 .. col0 + nt, zero beyond) into LDS, row-major with
+// NT columns; four elements per thread are loaded before they are stored.
+template <class S, int NT>
+__device__ __forceinline__ void sweep_gather(const S *__restrict__ W, int nrhs, int col0, int nt,
+                                             const int32_t *idx, int rows, S *sh) {
+  const int total = rows * NT;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 4 * kThreads) {
+    S v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kThreads;
+      const int i = e / NT, c = e - i * NT;
+      v[u] = (e < total && c < nt) ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < total) sh[e] = v[u];
+    }
+  }
 }
 
 template <class S, int NT>
@@ -1733,10 +1769,7 @@ __device__ __forceinline__ void sweep_up_box_mfma(const SweepBox &B, S *__restri
   S *bs = sh;              // k x NT
   S *t = sh + k * NT;      // r x NT
   const int32_t *idx = B.idx;
-  for (int e = threadIdx.x; e < (k + r) * NT; e += kThreads) {
-    const int i = e / NT, c = e - i * NT;
-    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
-  }
+  sweep_gather<S, NT>(W, nrhs, col0, nt, idx, k + r, sh);
   __syncthreads();
   const S *T = O.T;
   const int tm_r = (r + 15) >> 4, tm_k = (k + 15) >> 4;
@@ -1791,10 +1824,7 @@ __device__ __forceinline__ void sweep_down_box_mfma(const SweepBox &B, S *__rest
   S *z = sh;              // k x NT
   S *u = sh + k * NT;     // r x NT
   const int32_t *idx = B.idx;
-  for (int e = threadIdx.x; e < (k + r) * NT; e += kThreads) {
-    const int i = e / NT, c = e - i * NT;
-    sh[e] = c < nt ? W[(int64_t)idx[i] * nrhs + col0 + c] : S(0.0);
-  }
+  sweep_gather<S, NT>(W, nrhs, col0, nt, idx, k + r, sh);
   __syncthreads();
   const int tm_r = (r + 15) >> 4, tm_k = (k + 15) >> 4;
   const S *F = O.F;
