@@ -1422,11 +1422,24 @@ __device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
           cur[v] = (colok && row < r) ? A[q * lda + row] : S(0.0);
         }
         Acc<S> acc;
-        for (int k0 = 0; k0 < pb; k0 += 4) {
-          const int kk = k0 + kq;
-          const S av = (i < r && kk < pb) ? PN[i + kk * ldp] : S(0.0);
-          const S bv = (kk < pb && cc < qc) ? Wt[kk * kQC + cc] : S(0.0);
-          acc.mma(av, bv);
+        if (sizeof(S) == sizeof(double) && pb == kPB) {   // real full panel: the four
+                                                           // steps' operands first
+          S av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kk = 4 * u + kq;
+            av[u] = i < r ? PN[i + kk * ldp] : S(0.0);
+            bv[u] = cc < qc ? Wt[kk * kQC + cc] : S(0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc.mma(av[u], bv[u]);
+        } else {
+          for (int k0 = 0; k0 < pb; k0 += 4) {
+            const int kk = k0 + kq;
+            const S av = (i < r && kk < pb) ? PN[i + kk * ldp] : S(0.0);
+            const S bv = (kk < pb && cc < qc) ? Wt[kk * kQC + cc] : S(0.0);
+            acc.mma(av, bv);
+          }
         }
         if (colok) {
 #pragma unroll
@@ -1503,7 +1516,22 @@ __device__ __forceinline__ void block_gemm(int M, int N, int K, FA a, FB b, FO o
     const int ti = tile / tn, tj = tile - ti * tn;
     const int i = ti * 16 + ci, j = tj * 16 + ci;
     Acc<S> acc;
-    for (int k0 = 0; k0 < K; k0 += 4) {
+    int k0 = 0;
+    if constexpr (sizeof(S) == sizeof(double)) {
+      // real data: four K steps' operands loaded before their products (same order)
+      for (; k0 + 16 <= K; k0 += 16) {
+        S av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = k0 + 4 * u + kq;
+          av[u] = i < M ? a(i, kk) : S(0.0);
+          bv[u] = j < N ? b(kk, j) : S(0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc.mma(av[u], bv[u]);
+      }
+    }
+    for (; k0 < K; k0 += 4) {
       const int kk = k0 + kq;
       const S av = (i < M && kk < K) ? a(i, kk) : S(0.0);
       const S bv = (kk < K && j < N) ? b(kk, j) : S(0.0);
