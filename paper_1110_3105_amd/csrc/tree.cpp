@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <stdexcept>
 
 #include "pool.h"
@@ -15,6 +16,56 @@
 namespace rs {
 
 static constexpr int kMaxDepth = 40;
+
+namespace {
+// A few large per-point arrays kept between builds (a process builds trees of similar
+// sizes again and again).  take() returns a cached array of sufficient capacity, or an
+// empty one; give() keeps arrays of at least kMinCached elements, up to kCacheSlots.
+constexpr size_t kMinCached = size_t(1) << 14;
+constexpr size_t kCacheSlots = 4;
+template <class T>
+struct BufCache {
+  std::mutex mu;
+  std::vector<std::vector<T>> bufs;
+  std::vector<T> take(size_t n) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (size_t i = 0; i < bufs.size(); ++i)
+      if (bufs[i].capacity() >= n) {
+        std::vector<T> v = std::move(bufs[i]);
+        bufs.erase(bufs.begin() + (std::ptrdiff_t)i);
+        return v;
+      }
+    return {};
+  }
+  void give(std::vector<T> &v) {
+    if (v.capacity() < kMinCached) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (bufs.size() >= kCacheSlots) bufs.erase(bufs.begin());   // keep the newest
+    bufs.push_back(std::move(v));
+    v = std::vector<T>();
+  }
+};
+template <class T>
+BufCache<T> &buf_cache() {
+  static BufCache<T> *c = new BufCache<T>();   // never destroyed: trees may outlive main
+  return *c;
+}
+// Sized to n, contents unspecified (every element is written before it is read).
+template <class T>
+void take_sized(std::vector<T> &v, size_t n) {
+  if (v.capacity() < n) {
+    std::vector<T> c = buf_cache<T>().take(n);
+    if (c.capacity() >= n) v.swap(c);
+    buf_cache<T>().give(c);
+  }
+  v.resize(n);
+}
+}  // namespace
+
+Tree::~Tree() {
+  buf_cache<int64_t>().give(perm);
+  buf_cache<double>().give(coords);
+}
 
 void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   dim = dim_;
@@ -50,7 +101,7 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
     c0[a] = (lo[a] + hi[a]) * 0.5;
     s0 = std::max(s0, hi[a] - lo[a]);
   }
-  perm.resize(n);
+  take_sized(perm, (size_t)n);
   parallel_for(nck, [&](int ci) {
     for (int64_t i = ci * kPtsChunk; i < std::min(n, (ci + 1) * kPtsChunk); ++i) perm[i] = i;
   }, 1);
@@ -74,8 +125,10 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   // Level by level: the boxes of one depth partition their (disjoint) index ranges in
   // parallel, then their children are numbered in box order -- the same breadth-first
   // numbering and stable order as splitting the boxes one after another.
-  std::vector<int64_t> tmp(n);
-  std::vector<int> code(n);
+  std::vector<int64_t> tmp;
+  std::vector<int> code;
+  take_sized(tmp, (size_t)n);
+  take_sized(code, (size_t)n);
   std::vector<int> cur = {0};
   // A box with more than kPartChunk points is partitioned by several tasks (consecutive
   // chunks of its range): each counts its codes, the counts are prefix-summed in chunk
@@ -186,8 +239,10 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   for (int d : depth) maxdepth = std::max(maxdepth, d);
   levels.assign(maxdepth + 1, {});
   for (int bx = 0; bx < (int)side.size(); ++bx) levels[depth[bx]].push_back(bx);
-  // tree-order coordinates (structure of arrays)
-  coords.assign((size_t)dim * n, 0.0);
+  buf_cache<int64_t>().give(tmp);
+  buf_cache<int>().give(code);
+  // tree-order coordinates (structure of arrays; every entry is written below)
+  take_sized(coords, (size_t)dim * n);
   parallel_for(nck, [&](int ci) {
     const int64_t i0 = ci * kPtsChunk, i1 = std::min(n, i0 + kPtsChunk);
     for (int64_t i = i0; i < i1; ++i)

@@ -25,6 +25,15 @@ struct Tree {
   int nbox() const { return (int)side.size(); }
   bool is_leaf(int b) const { return nchild[b] == 0; }
   void build(int dim, int64_t n, const double *points, int leaf_size);
+
+  Tree() = default;
+  Tree(const Tree &) = default;
+  Tree(Tree &&) = default;
+  Tree &operator=(const Tree &) = default;
+  Tree &operator=(Tree &&) = default;
+  // The per-point arrays go back to a process-wide cache for the next build (their
+  // pages are already mapped: first-touch faults on fresh arrays were most of a build).
+  ~Tree();
 };
 
 }  // namespace rs
