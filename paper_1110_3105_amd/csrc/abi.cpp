@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, error translation, object lifetime.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -38,8 +39,14 @@ rs_status guarded(F &&f) {
 [[noreturn]] void fail(rs_status code, const std::string &msg) { throw UserError{code, msg}; }
 
 bool all_finite(const double *p, int64_t n) {
-  for (int64_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) return false;
+  // branch-free over blocks (the compiler vectorizes the inner loop), early out per block
+  constexpr int64_t kBlock = 4096;
+  for (int64_t i0 = 0; i0 < n; i0 += kBlock) {
+    const int64_t i1 = std::min(n, i0 + kBlock);
+    bool ok = true;
+    for (int64_t i = i0; i < i1; ++i) ok &= std::isfinite(p[i]);
+    if (!ok) return false;
+  }
   return true;
 }
 
