@@ -404,10 +404,12 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     def step(mode="level"):
+        # the right-hand side is reset first: the device copy runs while the host builds
+        # the tree (stream order puts it before the factor's and the solve's kernels)
+        B.copy_(B0)
         t = rs.build_tree(g.points, LEAF)
         h = rs.factor("lap2d_sl", t, g.points, g.weights, EPS, proxy_points=NPX,
                       launch_mode=mode, stream=stream)
-        B.copy_(B0)
         h.solve(B, stream=stream, launch_mode=mode)
         torch.cuda.synchronize()
         st = h.stats()
