@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "librs.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
-                      "(run `python -m paper_1110_3105_amd.build`)")
+                      "(run `python paper_1110_3105_amd/build.py`)")
 
 # PyTorch ships its own HIP runtime with the same soname (libamdhip64.so.7).  Loading
 # torch first makes the library bind to that copy, so that the process holds one HIP

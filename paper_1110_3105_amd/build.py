@@ -1,6 +1,6 @@
 """Builds the HIP library (gfx950) in-tree: paper_1110_3105_amd/lib/librs.so.
 
-Usage: python -m paper_1110_3105_amd.build   (or __graft_entry__.build()).
+Usage: python paper_1110_3105_amd/build.py   (or __graft_entry__.build()).
 Always recompiles every source.
 """
 from __future__ import annotations

@@ -160,3 +160,34 @@ def test_cfie_diagonal_rule_sign_and_coupling():
     const = 0.25j - (np.log(ks / 2) + 0.57721566490153286) / (2 * np.pi)
     W_ = np.tile(g.weights, (n, 1))
     assert np.abs(Sk - const * W_ - S0).max() < 1e-7
+
+
+@pytest.mark.parametrize("kind,chunk", [("lap2d_sl", 1000), ("lap2d_sl", 701),
+                                        ("lap2d_dl", 3000), ("lap2d_dl", 4096),
+                                        ("helm2d_cfie", 512), ("helm2d_cfie", 999)])
+def test_matvec_rows_equals_dense_rows(kind, chunk):
+    # The chunked row matvec (used for residuals where A does not fit) against rows of the
+    # assembled matrix, with chunk sizes that divide N, do not divide it, equal it and
+    # exceed it.
+    from oracle import dense
+    n = 3000
+    g = W.star_curve(n)
+    if kind == "lap2d_sl":
+        p = Problem(kind, g.points, g.weights)
+    elif kind == "lap2d_dl":
+        p = Problem(kind, g.points, g.weights, g.normals, g.curvature, identity=-0.5)
+    else:
+        k = W.helmholtz_wavenumber(g, 4.0)
+        p = Problem(kind, g.points, g.weights, g.normals, g.curvature, identity=0.5,
+                    wavenumber=k, eta=k)
+    A = dense.matrix(p)
+    rng = np.random.default_rng(4)
+    rows = np.sort(rng.choice(n, 37, replace=False))
+    rows = np.concatenate([rows, [0, n - 1]])      # first and last rows, unsorted tail
+    for x in (rng.standard_normal(n), rng.standard_normal((n, 3))):
+        if kind == "helm2d_cfie":
+            x = x + 1j * rng.standard_normal(x.shape)
+        ref = A[rows] @ x
+        got = dense.matvec_rows(p, rows, x, chunk=chunk)
+        assert got.shape == ref.shape
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(A[rows]).sum(axis=1).max() * np.abs(x).max()

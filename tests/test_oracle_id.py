@@ -111,3 +111,40 @@ def test_complex_id():
     assert idr.k == 10
     res = A[:, idr.redund] - A[:, idr.skel] @ idr.T
     assert np.abs(res).max() < 1e-13 * np.abs(A).max()
+
+
+def _orthogonal_columns(m, norms, seed):
+    """m x n matrix whose columns are orthogonal with the given 2-norms: column-pivoted QR
+    takes them in order of decreasing norm and |R_jj| equals the j-th largest norm (up to
+    rounding)."""
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((m, len(norms))))
+    return Q * np.asarray(norms)[None, :]
+
+
+@pytest.mark.parametrize("rel,expect_k,expect_near", [
+    (1e-12, 4, True),      # |R_33| just above eps |R_00|: kept, but within 1e-10
+    (-1e-12, 3, True),     # just below: dropped, and the stopping value is within 1e-10
+    (1e-9, 4, False),      # outside the 1e-10 band on either side
+    (-1e-9, 3, False),
+])
+def test_near_threshold_flag(rel, expect_k, expect_near):
+    # The rank rule keeps pivots with |R_jj| > eps |R_00|; a decision taken within a
+    # relative 1e-10 of the threshold is flagged, since rounding may take it either way.
+    eps = 1e-6
+    norms = [1.0, 0.5, 0.25, eps * (1.0 + rel), 1e-9, 1e-10]
+    M = _orthogonal_columns(40, norms, 5)
+    idr = cpqr_id(M, eps)
+    assert idr.k == expect_k
+    assert idr.near_threshold is expect_near
+    assert list(idr.pivots[:4]) == [0, 1, 2, 3]
+    assert abs(idr.rdiag[3] - norms[3]) <= 1e-15
+
+
+def test_near_threshold_clear_when_rank_gap_is_wide():
+    # |R_kk| two orders of magnitude on either side of eps |R_00|: no flag.
+    eps = 1e-3
+    norms = [1.0, 0.9, 1e-1, 1e-5, 1e-7]
+    M = _orthogonal_columns(30, norms, 9)
+    idr = cpqr_id(M, eps)
+    assert idr.k == 3
+    assert idr.near_threshold is False

@@ -34,9 +34,8 @@ def sph_prob(g):
 
 def helm_prob(g, wavelengths=5.0):
     # exterior combined-field equation (1/2 I + D - i k S) sigma = f, k giving the stated
-    # number of wavelengths across the curve
-    diam = np.ptp(g.points[:, 0])
-    k = 2 * np.pi * wavelengths / diam
+    # number of wavelengths across the domain's diameter
+    k = W.helmholtz_wavenumber(g, wavelengths)
     return Problem("helm2d_cfie", g.points, g.weights, g.normals, g.curvature, identity=0.5,
                    wavenumber=k, eta=k)
 

@@ -164,12 +164,30 @@ def random_curve_problem(p: int):
     return random_curve(n, amps, phases), b
 
 
+def diameter(points: np.ndarray) -> float:
+    """Largest distance between two nodes (the diameter of the discretized boundary).
+
+    The farthest pair of a point set lies on its convex hull, so only hull vertices are
+    compared pairwise."""
+    from scipy.spatial import ConvexHull
+    pts = np.asarray(points, dtype=np.float64)
+    if pts.shape[0] < pts.shape[1] + 2:
+        cand = pts
+    else:
+        cand = pts[ConvexHull(pts).vertices]
+    best = 0.0
+    for lo in range(0, cand.shape[0], 1024):
+        d = cand[lo:lo + 1024, None, :] - cand[None, :, :]
+        best = max(best, float(np.sqrt((d * d).sum(axis=2)).max()))
+    return best
+
+
 def helmholtz_wavenumber(g: Geometry, wavelengths: float) -> float:
-    """Wavenumber k with the given number of wavelengths across the curve, the width
-    taken as the diameter of the smallest origin-centred disc holding the nodes
-    (2 max|x_i|; 2.6 for the star curve): k = 2 pi wavelengths / width."""
-    width = 2.0 * float(np.sqrt((g.points ** 2).sum(axis=1)).max())
-    return 2.0 * np.pi * wavelengths / width
+    """Wavenumber k with the given number of wavelengths across the domain: the width is
+    the domain's diameter (the largest node-to-node distance; 2.4919 for the star
+    curve), so k = 2 pi wavelengths / diameter (Section 6.1 counts wavelengths as
+    k diam / (2 pi))."""
+    return 2.0 * np.pi * wavelengths / diameter(g.points)
 
 
 # Named workloads (sizes of the benchmark and parity configurations).
