@@ -133,14 +133,19 @@ rs_status rs_factor_ex(const rs_kernel *k, rs_tree t, const double *points,
 
 /* ---------------------------------------------------------------- solve ---- */
 
-/* B := A_eps^{-1} B in place (the solution phase, Section 3.4).  B is device
- * memory, column-major n x nrhs with leading dimension ldb >= n (in entries), caller
- * order; entries are doubles for the Laplace kernels and complex128 (re, im pairs of
- * doubles) for HELM2D_CFIE.
- * Work is enqueued on stream (hipStream_t, NULL = default stream); the result is
- * valid once the stream has reached this point.  nrhs = 0 is a no-op.
- * Concurrent calls on one handle from different streams are allowed; each call
- * takes its own workspace.  Errors: RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
+/* B := A_eps^{-1} B in place (the solution phase, Section 3.4).  B is column-major
+ * n x nrhs with leading dimension ldb >= n (in entries), caller order; entries are
+ * doubles for the Laplace kernels and complex128 (re, im pairs of doubles) for
+ * HELM2D_CFIE.  B may be
+ *   - device memory of the current device: the work is enqueued on stream
+ *     (hipStream_t, NULL = default stream) and the result is valid once the stream
+ *     has reached this point; the whole n x nrhs range must lie inside one device
+ *     allocation (RS_EINVAL otherwise);
+ *   - host memory (pageable or pinned): the call stages B through device memory on
+ *     stream and returns when the result is back in B (synchronous).
+ * nrhs = 0 is a no-op.  Concurrent calls on one handle from different streams are
+ * allowed; each call takes its own workspace.  Errors: RS_EINVAL (including device
+ * memory of another device), RS_ENOMEM, RS_EDEVICE. */
 rs_status rs_solve(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream);
 
 /* rs_solve with a launch mode (RS_LAUNCH_LEVEL or RS_LAUNCH_PER_BOX). */
@@ -207,8 +212,9 @@ rs_status rs_tune_clear(void);
 rs_status rs_tune_save(const char *path);
 rs_status rs_tune_load(const char *path);
 
-/* Releases a handle.  Waits for the library's own queued work on it; returns
- * RS_OK for NULL. */
+/* Releases a handle.  RS_EBUSY (handle untouched) while a solve enqueued on it has not
+ * completed on its stream, or while a call, a plan or the server uses it; synchronize
+ * the solve's stream first.  RS_OK for NULL. */
 rs_status rs_free(rs_handle h);
 
 /* Thread-local message for the last failed call on this thread ("" if none). */
@@ -291,10 +297,14 @@ rs_status rs_server_submit_factor(rs_server s, const rs_kernel *k, rs_tree t,
                                   const double *points, const double *weights, double eps,
                                   uint64_t *ticket);
 
-/* Queues B := A^{-1} B (device memory, column-major, ldb >= n, nrhs >= 1).  B must
- * not be touched until the ticket completes; concurrent requests need disjoint B. */
+/* Queues B := A^{-1} B (device memory of the server's device, column-major, ldb >= n,
+ * nrhs >= 1; RS_EINVAL for a host pointer or a range past the end of B's allocation).
+ * stream (hipStream_t, NULL = default stream) is the producer's stream: the request
+ * runs after all work queued on it before this call (an event is recorded on it here),
+ * so B may still be being written there.  B must not be touched until the ticket
+ * completes; concurrent requests need disjoint B. */
 rs_status rs_server_submit_solve(rs_server s, rs_handle h, void *B, int64_t ldb,
-                                 int32_t nrhs, uint64_t *ticket);
+                                 int32_t nrhs, void *stream, uint64_t *ticket);
 
 /* Waits up to timeout_ms (0: no wait, < 0: forever) for a ticket.  *done = 1 when it
  * completed; then *status holds its outcome, *factor_out the new handle of a factor

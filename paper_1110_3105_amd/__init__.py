@@ -14,7 +14,9 @@ from .binding import (  # noqa: F401
     rs_server_submit_factor, rs_server_submit_solve, Plan, autotune, tune_entries, tune_clear,
     tune_save, tune_load, rs_plan_create, rs_plan_launch, rs_plan_free, rs_autotune,
     rs_tune_entries, rs_tune_clear, rs_tune_save, rs_tune_load,
+    RS_OK, RS_EINVAL, RS_ENOMEM, RS_ESINGULAR, RS_EDEVICE, RS_EBUSY, RS_ENOTSUP,
 )
+from . import binding  # noqa: F401
 
 
 def device_available() -> bool:

@@ -104,7 +104,7 @@ _sig = {
     "rs_server_create": (C.c_int, [C.POINTER(rs_server_opts), C.POINTER(_P)]),
     "rs_server_submit_factor": (C.c_int, [_P, C.POINTER(rs_kernel), _P, _PD, _PD, C.c_double,
                                           C.POINTER(C.c_uint64)]),
-    "rs_server_submit_solve": (C.c_int, [_P, _P, C.c_void_p, C.c_int64, C.c_int32,
+    "rs_server_submit_solve": (C.c_int, [_P, _P, C.c_void_p, C.c_int64, C.c_int32, _P,
                                          C.POINTER(C.c_uint64)]),
     "rs_server_poll": (C.c_int, [_P, C.c_uint64, C.c_int32, _PI32, _PI32, C.POINTER(_P)]),
     "rs_server_release": (C.c_int, [_P, _P]),
@@ -252,10 +252,20 @@ class Handle:
     def __del__(self):
         try:
             self.free()
+        except RSError as e:
+            if e.code == RS_EBUSY and self._server is None:
+                try:
+                    import torch
+                    torch.cuda.synchronize()
+                    self.free()
+                except Exception:
+                    pass
         except Exception:
             pass
 
     def free(self):
+        """Releases the factorization (RS_EBUSY while a solve on it is still queued or
+        running on its stream: synchronize that stream first)."""
         if getattr(self, "_h", None):
             if self._server is not None:
                 if self._server._s is not None:
@@ -297,6 +307,19 @@ class Handle:
         if not colmajor:
             X.copy_(work)
         return B
+
+    def solve_host(self, b: np.ndarray, stream=None) -> np.ndarray:
+        """Synchronous solve of host right-hand sides (numpy, shape (n,) or (n, nrhs),
+        float64 or complex128 to match the handle); returns a new array."""
+        dt = np.complex128 if self.is_complex else np.float64
+        X = np.array(b, dtype=dt, order="F", copy=True)
+        vec = X.ndim == 1
+        if vec:
+            X = X.reshape(-1, 1, order="F")
+        if X.shape[0] != self.n:
+            raise ValueError("b has the wrong number of rows")
+        self.solve_ptr(X.ctypes.data, self.n, X.shape[1], stream)
+        return X[:, 0] if vec else X
 
     def box_skeletons(self):
         nb = self.stats()["nbox"]
@@ -529,16 +552,24 @@ class Server:
         self._pending[t.value] = ("factor", pts.shape[0], tree)
         return t.value
 
-    def submit_solve(self, handle: Handle, B) -> int:
+    def submit_solve(self, handle: Handle, B, stream=None) -> int:
+        """Queues B := A^{-1} B for a device tensor B.  The request runs after the work
+        queued on `stream` (default: the current torch stream of B's device) so far."""
+        import torch
+        if not (isinstance(B, torch.Tensor) and B.is_cuda):
+            raise TypeError("B must be a tensor on the HIP device")
         if B.dtype != handle.dtype:
             raise TypeError(f"B must be {handle.dtype} for this handle")
         X = B.unsqueeze(1) if B.dim() == 1 else B
         if X.shape[0] != handle.n or X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) < handle.n):
             raise ValueError("B must be column-major with n rows")
         ldb = X.stride(1) if X.shape[1] > 1 else handle.n
+        if stream is None:
+            stream = torch.cuda.current_stream(B.device)
         t = C.c_uint64()
         _check(_lib.rs_server_submit_solve(self._s, handle.handle, C.c_void_p(X.data_ptr()),
-                                           int(ldb), int(X.shape[1]), C.byref(t)))
+                                           int(ldb), int(X.shape[1]), _stream_ptr(stream),
+                                           C.byref(t)))
         self._pending[t.value] = ("solve", B, handle)
         return t.value
 

@@ -226,7 +226,15 @@ rs_status rs_solve_batched(int32_t count, const rs_handle *h, void *const *B,
         for (int i = 0; i < n; ++i) h[i]->busy.fetch_sub(1);
       }
     } dec{h, count};
+    for (int i = 0; i < count; ++i) {
+      if (nrhs[i] == 0) continue;
+      const size_t es = h[i]->cplx ? 16 : 8;
+      if (!is_device_buffer(B[i], ((size_t)(nrhs[i] - 1) * (size_t)ldb[i] + (size_t)h[i]->n) * es))
+        fail(RS_EINVAL, "batched solves take device memory only (request " + std::to_string(i) +
+                            " is a host pointer)");
+    }
     solve_many(reqs, stream_of(opts));
+    for (int i = 0; i < count; ++i) note_inflight(h[i], stream_of(opts));
     return RS_OK;
   });
 }
@@ -240,12 +248,37 @@ rs_status rs_solve_ex(rs_handle h, void *B, int64_t ldb, int32_t nrhs,
     if (!B) fail(RS_EINVAL, "NULL right-hand side");
     if (ldb < h->n) fail(RS_EINVAL, "ldb < n");
     const int mode = mode_of(opts);
+    const hipStream_t st = stream_of(opts);
+    const size_t es = h->cplx ? 16 : 8;
+    const size_t span = ((size_t)(nrhs - 1) * (size_t)ldb + (size_t)h->n) * es;
     h->busy.fetch_add(1);
     struct Dec {
       rs_handle h;
       ~Dec() { h->busy.fetch_sub(1); }
     } dec{h};
-    solve_one(h, B, ldb, nrhs, mode, stream_of(opts));
+    if (is_device_buffer(B, span)) {
+      solve_one(h, B, ldb, nrhs, mode, st);
+      note_inflight(h, st);
+      return RS_OK;
+    }
+    // host right-hand sides: staged through device memory, synchronous
+    const size_t col = (size_t)h->n * es;
+    void *D = nullptr;
+    RS_HIP_CHECK(hipMallocAsync(&D, col * (size_t)nrhs, st));
+    struct Freer {
+      void *p;
+      hipStream_t st;
+      ~Freer() {
+        (void)hipFreeAsync(p, st);
+        (void)hipStreamSynchronize(st);
+      }
+    } freer{D, st};
+    RS_HIP_CHECK(hipMemcpy2DAsync(D, col, B, (size_t)ldb * es, col, (size_t)nrhs,
+                                  hipMemcpyHostToDevice, st));
+    solve_one(h, D, h->n, nrhs, mode, st);
+    RS_HIP_CHECK(hipMemcpy2DAsync(B, (size_t)ldb * es, D, col, col, (size_t)nrhs,
+                                  hipMemcpyDeviceToHost, st));
+    RS_HIP_CHECK(hipStreamSynchronize(st));
     return RS_OK;
   });
 }
@@ -352,6 +385,7 @@ rs_status rs_free(rs_handle h) {
   return guarded([&]() -> rs_status {
     if (!h) return RS_OK;
     if (h->busy.load() != 0) fail(RS_EBUSY, "handle is in use by a running call");
+    if (has_inflight(h)) fail(RS_EBUSY, "solves on this handle are still queued or running");
     RS_HIP_CHECK(hipDeviceSynchronize());
     h->arena.release();                  // device memory back to the cache now
     Reaper::get().defer([h] { delete h; });   // host lists freed in the background

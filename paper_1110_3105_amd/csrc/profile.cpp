@@ -1,5 +1,6 @@
 // Launch profiler: HIP events on the launch stream around each kernel launch, plus
 // the algorithmic work of the launch counted by the caller from the box sizes.
+#include <algorithm>
 #include <vector>
 
 #include "runtime.h"
@@ -84,14 +85,18 @@ Work work_assemble(int m, int n, bool cplx) {
   return w;
 }
 
+// Algorithmic count of the ID by column-pivoted Householder QR stopped after k steps:
+// sum over steps j < k of 4 (m - j)(n - j) flops (reflector applied to the remaining
+// columns), i.e. 4mnk - 2k^2(m + n) + 4k^3/3, plus k^2 r for T = R11^{-1} R12
+// (r = n - k).  The column norms the kernels recompute after every reflection (about
+// 2 (m - j)(n - j) more per step) are implementation overhead and are not counted.
 Work work_id(int m, int n, int k, bool cplx) {
   Work w;
-  double f = 2.0 * m * n;                       // initial column norms
-  for (int j = 0; j < k; ++j)                   // reflector + update + recomputed norms
-    f += 2.0 * (m - j) + 6.0 * (double)(m - j) * (n - j - 1);
-  f += (double)k * k * (n - k);                 // T = R11^{-1} R12
-  w.flops = f * flop_scale(cplx);
-  w.bytes = byte_size(cplx) * ((double)m * n + (double)k * (n - k)) + 4.0 * n;
+  const double mm = m, nn = n, kk = k, r = n - k;
+  const double f = 4.0 * mm * nn * kk - 2.0 * kk * kk * (mm + nn) + 4.0 * kk * kk * kk / 3.0 +
+                   kk * kk * r;
+  w.flops = std::max(f, 0.0) * flop_scale(cplx);
+  w.bytes = byte_size(cplx) * (mm * nn + kk * r) + 4.0 * nn;
   return w;
 }
 

@@ -971,6 +971,61 @@ int64_t wide_scratch_for(const rs_factor_s *h, int nrhs) {
 }
 }  // namespace
 
+bool is_device_buffer(const void *p, size_t bytes) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();       // unknown to the runtime: plain host memory
+    return false;
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) return false;
+  int cur = 0;
+  RS_HIP_CHECK(hipGetDevice(&cur));
+  if (a.device != cur)
+    throw UserError{RS_EINVAL, "buffer is on device " + std::to_string(a.device) +
+                                   ", the current device is " + std::to_string(cur)};
+  void *base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) == hipSuccess && base) {
+    if (static_cast<const char *>(p) + bytes > static_cast<const char *>(base) + size)
+      throw UserError{RS_EINVAL, "buffer runs past the end of its device allocation"};
+  } else {
+    (void)hipGetLastError();
+  }
+  return true;
+}
+
+void note_inflight(rs_factor_s *h, hipStream_t st) {
+  hipEvent_t ev = nullptr;
+  RS_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  const hipError_t e = hipEventRecord(ev, st);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    RS_HIP_CHECK(e);
+  }
+  std::lock_guard<std::mutex> lock(h->inflight_mu);
+  // drop completed events from the front (they complete in issue order per stream;
+  // a stalled one on another stream only delays the pruning)
+  size_t keep = 0;
+  for (hipEvent_t x : h->inflight) {
+    if (hipEventQuery(x) == hipErrorNotReady) h->inflight[keep++] = x;
+    else (void)hipEventDestroy(x);
+  }
+  h->inflight.resize(keep);
+  h->inflight.push_back(ev);
+}
+
+bool has_inflight(rs_factor_s *h) {
+  std::lock_guard<std::mutex> lock(h->inflight_mu);
+  size_t keep = 0;
+  for (hipEvent_t x : h->inflight) {
+    const hipError_t q = hipEventQuery(x);
+    if (q == hipErrorNotReady) h->inflight[keep++] = x;
+    else (void)hipEventDestroy(x);
+  }
+  h->inflight.resize(keep);
+  return keep > 0;
+}
+
 void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
                hipStream_t st) {
   if (nrhs == 0) return;

@@ -3,6 +3,7 @@
 
 #include <atomic>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "rs_internal.h"
@@ -89,6 +90,8 @@ struct rs_factor_s {
   int nbox = 0;
   rs_stats stats{};
   std::atomic<int> busy{0};
+  std::mutex inflight_mu;
+  std::vector<hipEvent_t> inflight;      // completion events of enqueued solves
 };
 
 namespace rs {
@@ -143,6 +146,18 @@ struct UserError {
   rs_status code;
   std::string what;
 };
+
+// True if p is device memory (or managed memory) of the current device; false for host
+// memory (pageable, registered or pinned).  Throws UserError (RS_EINVAL) for device
+// memory of another device, or when [p, p + bytes) runs past the end of p's device
+// allocation (checked where the runtime reports the allocation's extent).
+bool is_device_buffer(const void *p, size_t bytes);
+
+// Solves issued on a handle: an event is recorded after each one on its stream, so
+// that rs_free can tell whether any is still queued or running.
+void note_inflight(rs_factor_s *h, hipStream_t st);
+// True if a recorded solve has not completed (completed events are released).
+bool has_inflight(rs_factor_s *h);
 
 // Argument checks shared by rs_factor and the server (throws UserError).
 void validate_kernel(const rs_kernel *k, const Tree &t, const double *points,

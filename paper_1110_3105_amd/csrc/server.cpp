@@ -44,6 +44,7 @@ struct Ticket {
 struct SolveItem {
   std::shared_ptr<Ticket> tk;
   SolveRequest req;
+  hipEvent_t after = nullptr;     // recorded on the producer's stream at submission
 };
 
 struct FactorItem {
@@ -149,14 +150,36 @@ void solve_loop(rs_server_s *s) {
       it.tk->t_start = t_start;
     }
     hipEvent_t ev = nullptr;
+    rs_status fail_st = RS_OK;
+    std::string fail_msg;
     try {
+      // the batch starts after the work each producer had queued when it submitted
+      for (SolveItem &it : batch)
+        if (it.after) RS_HIP_CHECK(hipStreamWaitEvent(st, it.after, 0));
       solve_many(reqs, st);
       RS_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
       RS_HIP_CHECK(hipEventRecord(ev, st));
     } catch (const DeviceError &e) {
+      fail_st = RS_EDEVICE;
+      fail_msg = e.what;
+    } catch (const UserError &e) {
+      fail_st = e.code;
+      fail_msg = e.what;
+    } catch (const std::bad_alloc &) {
+      fail_st = RS_ENOMEM;
+      fail_msg = "host allocation failed";
+    } catch (const std::exception &e) {
+      fail_st = RS_EDEVICE;
+      fail_msg = e.what();
+    } catch (...) {
+      fail_st = RS_EDEVICE;
+      fail_msg = "unknown error in the solve loop";
+    }
+    if (fail_st != RS_OK) {
       for (SolveItem &it : batch) {
         it.req.h->busy.fetch_sub(1);
-        fail_ticket(s, it.tk, RS_EDEVICE, e.what);
+        if (it.after) (void)hipEventDestroy(it.after);
+        fail_ticket(s, it.tk, fail_st, fail_msg);
       }
       if (ev) (void)hipEventDestroy(ev);
       continue;
@@ -188,6 +211,7 @@ void done_loop(rs_server_s *s) {
     s->inflight.pop_front();
     for (SolveItem &it : done.items) {
       it.req.h->busy.fetch_sub(1);
+      if (it.after) (void)hipEventDestroy(it.after);
       it.tk->t_done = t;
       it.tk->done = true;
       if (e != hipSuccess) {
@@ -242,6 +266,12 @@ void factor_loop(rs_server_s *s) {
     } catch (const std::bad_alloc &) {
       st = RS_ENOMEM;
       msg = "host allocation failed";
+    } catch (const std::exception &e) {
+      st = RS_EDEVICE;
+      msg = e.what();
+    } catch (...) {
+      st = RS_EDEVICE;
+      msg = "unknown error in the factor loop";
     }
     std::lock_guard<std::mutex> lock(s->mu);
     s->reserved_bytes -= item->estimate;
@@ -348,10 +378,27 @@ rs_status rs_server_submit_factor(rs_server s, const rs_kernel *k, rs_tree t,
 }
 
 rs_status rs_server_submit_solve(rs_server s, rs_handle h, void *B, int64_t ldb, int32_t nrhs,
-                                 uint64_t *ticket) {
+                                 void *stream, uint64_t *ticket) {
   if (!s || !h || !ticket || nrhs < 1 || !B || ldb < h->n) {
     set_error("bad solve request (NULL argument, nrhs < 1 or ldb < n)");
     return RS_EINVAL;
+  }
+  hipEvent_t after = nullptr;
+  try {
+    RS_HIP_CHECK(hipSetDevice(s->device));
+    const size_t es = h->cplx ? 16 : 8;
+    if (!is_device_buffer(B, ((size_t)(nrhs - 1) * (size_t)ldb + (size_t)h->n) * es))
+      throw UserError{RS_EINVAL, "the server solves device memory only (B is a host pointer)"};
+    RS_HIP_CHECK(hipEventCreateWithFlags(&after, hipEventDisableTiming));
+    RS_HIP_CHECK(hipEventRecord(after, static_cast<hipStream_t>(stream)));
+  } catch (const UserError &e) {
+    if (after) (void)hipEventDestroy(after);
+    set_error(e.what);
+    return e.code;
+  } catch (const DeviceError &e) {
+    if (after) (void)hipEventDestroy(after);
+    set_error(e.what);
+    return RS_EDEVICE;
   }
   auto tk = std::make_shared<Ticket>();
   tk->nrhs = nrhs;
@@ -362,7 +409,7 @@ rs_status rs_server_submit_solve(rs_server s, rs_handle h, void *B, int64_t ldb,
   s->tickets[tk->id] = tk;
   *ticket = tk->id;
   if (s->first_submit < 0) s->first_submit = tk->t_submit;
-  s->solve_q.push_back(SolveItem{tk, SolveRequest{h, B, ldb, nrhs}});
+  s->solve_q.push_back(SolveItem{tk, SolveRequest{h, B, ldb, nrhs}, after});
   s->cv_solve.notify_all();
   return RS_OK;
 }
