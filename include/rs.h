@@ -50,9 +50,11 @@ typedef enum {
   RS_LAP2D_SL = 1,   /* -(1/2pi) log|x-y|,  dim 2 */
   RS_LAP2D_DL = 2,   /* (x-y).nu_y / (2pi |x-y|^2), dim 2, needs normals + curvature */
   RS_LAP3D_SL = 3,   /* 1/(4pi |x-y|), dim 3 */
-  RS_HELM2D_CFIE = 4 /* combined field dG_k/dnu_y - i eta G_k, G_k = (i/4) H0(k|x-y|),
+  RS_HELM2D_CFIE = 4, /* combined field dG_k/dnu_y - i eta G_k, G_k = (i/4) H0(k|x-y|),
                         dim 2, complex128; needs normals + curvature (Section 6.1
                         eq. (2d-helmholtz), combined layer of Section 3.2) */
+  RS_HELM3D_SL = 5   /* exp(i k |x-y|) / (4 pi |x-y|), dim 3, complex128 (Section 6.1
+                        eq. (3d-helmholtz)) */
 } rs_kernel_kind;
 
 /* Kernel description.  The diagonal entries A_ii follow a per-kernel rule:
@@ -61,19 +63,36 @@ typedef enum {
  *   HELM2D_CFIE: c - kappa_i w_i/(4pi) - i eta s_i with the single-layer self term
  *     s_i = w_i (i/4 - (log(k/2) + gamma)/(2pi)) - (w_i/2pi) log(w_i/2pi)
  *     (gamma = Euler's constant; the smooth part of G_k at coincidence plus the
- *     LAP2D_SL rule for its logarithm). */
+ *     LAP2D_SL rule for its logarithm);
+ *   HELM3D_SL: c + (exp(i k R) - 1) / (2 i k), R = sqrt(w_i/pi) (the kernel integrated
+ *     over a flat disc of area w_i; k -> 0 gives the LAP3D_SL rule). */
 typedef struct {
   int32_t kind;             /* rs_kernel_kind */
   int32_t dim;              /* 2 or 3, must match kind */
   double identity;          /* c: -0.5 for the interior double-layer equation
                                (eq. (2k-integral-eqn)), 0 for first kind */
   double wavenumber;        /* Helmholtz: k > 0 (unused otherwise) */
-  double eta;               /* Helmholtz: combined-field coupling, e.g. k (unused otherwise) */
+  double eta;               /* HELM2D_CFIE: combined-field coupling, e.g. k (unused otherwise) */
   const double *normals;    /* host, N x dim, caller order; LAP2D_DL and HELM2D_CFIE */
   const double *curvature;  /* host, N, caller order; LAP2D_DL and HELM2D_CFIE */
   int32_t proxy_points;     /* proxy-surface points per box (Section 3.2), >= 8 */
   double proxy_ratio;       /* proxy radius / box side; > 0.5*sqrt(dim), e.g. 1.5 */
+  int32_t id_mode;          /* rs_id_mode: how each box's block M (m x n) is compressed */
+  int32_t oversample;       /* RS_ID_SKETCH: sketch rows ell = min(m, n + oversample), 0..4096 */
+  uint64_t sketch_seed;     /* RS_ID_SKETCH: seed of the sign generator */
 } rs_kernel;
+
+/* Interpolative decomposition of a box's block (Section 2.2). */
+typedef enum {
+  RS_ID_CPQR = 0,     /* column-pivoted QR of M itself (deterministic) */
+  RS_ID_SKETCH = 1    /* column-pivoted QR of the row sketch Y = Omega M (the randomized
+                         ID of Section 2.2): Omega is ell x m with entries +-1, entry (a, i)
+                         of tree box b set by the top bit of SplitMix64 (Steele, Lea and
+                         Flood, OOPSLA 2014) at the counter
+                         seed ^ (b << 40) ^ (a << 20) ^ i  (sign -1 when the bit is set);
+                         no sketch when ell = m.  Every box is compressed through its
+                         sketch, so a factorization depends on the seed. */
+} rs_id_mode;
 
 typedef struct rs_tree_s *rs_tree;
 typedef struct rs_factor_s *rs_handle;
@@ -135,12 +154,14 @@ rs_status rs_factor_ex(const rs_kernel *k, rs_tree t, const double *points,
 
 /* B := A_eps^{-1} B in place (the solution phase, Section 3.4).  B is column-major
  * n x nrhs with leading dimension ldb >= n (in entries), caller order; entries are
- * doubles for the Laplace kernels and complex128 (re, im pairs of doubles) for
- * HELM2D_CFIE.  B may be
+ * doubles for the Laplace kernels and complex128 (re, im pairs of doubles) for the
+ * Helmholtz kernels.  B may be
  *   - device memory of the current device: the work is enqueued on stream
  *     (hipStream_t, NULL = default stream) and the result is valid once the stream
  *     has reached this point; the whole n x nrhs range must lie inside one device
- *     allocation (RS_EINVAL otherwise);
+ *     allocation as the HIP runtime reports it (RS_EINVAL otherwise; for memory of a
+ *     pool allocator such as PyTorch's that is the pool's segment, so the check cannot
+ *     see a range that overruns a sub-allocation);
  *   - host memory (pageable or pinned): the call stages B through device memory on
  *     stream and returns when the result is back in B (synchronous).
  * nrhs = 0 is a no-op.  Concurrent calls on one handle from different streams are
@@ -151,6 +172,20 @@ rs_status rs_solve(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream
 /* rs_solve with a launch mode (RS_LAUNCH_LEVEL or RS_LAUNCH_PER_BOX). */
 rs_status rs_solve_ex(rs_handle h, void *B, int64_t ldb, int32_t nrhs,
                       const rs_options *opts);
+
+/* Y := A_eps X, the compressed forward operator that the handle's compression defines
+ * (Section 3.3: an upward pass applying each level's interpolation R, the dense block of
+ * the remaining skeletons, and a downward pass applying L and adding each level's
+ * diagonal blocks; Section 6.1 uses it as a generalized FMM).  A_eps agrees with A to
+ * the compression precision and is exactly the matrix rs_solve inverts, so
+ * |A_eps x - b| measures a solve's rounding in O(N) work.  X and Y: device memory of
+ * the current device, column-major n x nrhs, leading dimensions ldx, ldy >= n, doubles
+ * or complex128 as for rs_solve, caller order; they must not overlap.  Enqueued on
+ * stream (NULL = default stream).  The diagonal blocks are evaluated from the kernel on
+ * each call; the first call on a handle uploads its descriptors (synchronous once).
+ * Errors: RS_EINVAL (host pointers, overlap, ld < n), RS_ENOMEM, RS_EDEVICE. */
+rs_status rs_matvec(rs_handle h, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                    int32_t nrhs, void *stream);
 
 /* ------------------------------------------------- batched (many problems) ---- */
 

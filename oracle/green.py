@@ -14,6 +14,7 @@ lap2d_dl   dG/dnu_y = (x-y).nu_y / (2 pi |x-y|^2)          eq. (double-layer), 2
 lap3d_sl   G(x,y) = 1 / (4 pi |x-y|)                        eq. (3d-laplace)
 helm2d_cfie  dG_k/dnu_y - i eta G_k, G_k = (i/4) H0(k|x-y|) eq. (2d-helmholtz) with the
              combined layer mentioned at the end of Section 3.2 (complex128)
+helm3d_sl  G_k(x,y) = exp(i k |x-y|) / (4 pi |x-y|)        eq. (3d-helmholtz) (complex128)
 
 Diagonal rules (the paper's own quadrature corrections are not reproducible here):
 lap2d_dl   d_i = -kappa_i w_i / (4 pi): the limit of the double-layer kernel along a
@@ -23,6 +24,10 @@ lap2d_sl   d_i = -(w_i / 2pi) log(w_i / 2pi): the diagonal term that makes the e
            log|2 sin(pi (i-j)/N)| equals log N).  Pinned by unit-circle eigenvalues 1/(2m).
 lap3d_sl   d_i = sqrt(w_i / pi) / 2: the single-layer integral over a flat disc of area
            w_i centred at the node.  Pinned by S[1] -> 1 on the unit sphere.
+helm3d_sl  d_i = (exp(i k R) - 1) / (2 i k), R = sqrt(w_i / pi): the same flat-disc
+           integral of exp(i k r) / (4 pi r) (its k -> 0 limit is the lap3d_sl rule).
+           Pinned by the unit sphere's eigenvalues i k j_n(k) h_n(k) (n = 0, 1) and the
+           k -> 0 limit.
 """
 from __future__ import annotations
 
@@ -31,7 +36,7 @@ from typing import Optional
 
 import numpy as np
 
-KINDS = ("lap2d_sl", "lap2d_dl", "lap3d_sl", "helm2d_cfie")
+KINDS = ("lap2d_sl", "lap2d_dl", "lap3d_sl", "helm2d_cfie", "helm3d_sl")
 EULER_GAMMA = 0.57721566490153286061
 
 
@@ -64,7 +69,7 @@ class Problem:
 
     @property
     def is_complex(self) -> bool:
-        return self.kind == "helm2d_cfie"
+        return self.kind in ("helm2d_cfie", "helm3d_sl")
 
     @property
     def dtype(self):
@@ -111,6 +116,9 @@ def kernel(prob: Problem, tgt: np.ndarray, src: np.ndarray,
             dl = 0.25j * k * hankel1(1, k * r) * dot / r
             sl = 0.25j * hankel1(0, k * r)
             return dl - 1j * prob.eta * sl
+        if prob.kind == "helm3d_sl":
+            r = np.sqrt(r2)
+            return np.exp(1j * prob.wavenumber * r) / (4.0 * np.pi * r)
     raise ValueError(prob.kind)
 
 
@@ -129,6 +137,10 @@ def diagonal(prob: Problem, idx: np.ndarray) -> np.ndarray:
         sl = w * (0.25j - (np.log(k / 2.0) + EULER_GAMMA) / (2.0 * np.pi)) \
             - (w / (2.0 * np.pi)) * np.log(w / (2.0 * np.pi))
         d = dl - 1j * prob.eta * sl
+    elif prob.kind == "helm3d_sl":
+        k = prob.wavenumber
+        R = np.sqrt(w / np.pi)
+        d = (np.exp(1j * k * R) - 1.0) / (2j * k)
     else:
         raise ValueError(prob.kind)
     return prob.identity + d

@@ -15,9 +15,18 @@ deterministic route, column-pivoted QR in the Businger-Golub form:
   T = R11^{-1} R12 (k x (n-k)), so that A[:, rest] ~= A[:, skel] T.
 
 The skeleton set s and the redundant set r are then each sorted ascending and T is
-permuted to that order.  For comparisons, a pivot step is reported as tied when the
-two largest remaining norms agree to a relative 1e-10, and the rank is reported as
-near-threshold when |R_kk| or |R_{k+1,k+1}| lies within a relative 1e-10 of eps |R_00|.
+permuted to that order.
+
+For comparisons with another implementation (the paper fixes no tie rule): two correct
+Householder QRs of the same block differ by rounding, and the norms they recompute at a
+step may differ by up to the backward error of Householder QR, of the order of m u
+|R_00| in absolute terms (u the unit roundoff) -- small relative to the first pivots,
+large relative to pivots near eps |R_00| when eps is small.  A pivot step is therefore
+reported as tied when the two largest remaining norms differ by at most
+1e-10 x the larger + 2 m u |R_00|, and the rank as near-threshold when |R_kk| or
+|R_{k+1,k+1}| lies within 1e-10 eps |R_00| + 2 m u |R_00| of eps |R_00|.  Where
+neither happens, the pivot order and the rank do not depend on rounding, and two
+implementations must choose the same skeletons.
 """
 from __future__ import annotations
 
@@ -27,6 +36,12 @@ import numpy as np
 from scipy.linalg import solve_triangular
 
 TIE_RTOL = 1e-10
+UNIT_ROUNDOFF = np.finfo(np.float64).eps / 2.0
+
+
+def rounding_floor(m: int, r00: float) -> float:
+    """Absolute width below which two norms of an m-row block are not told apart."""
+    return 2.0 * m * UNIT_ROUNDOFF * r00
 
 
 @dataclass
@@ -41,9 +56,12 @@ class IDResult:
     near_threshold: bool
 
 
-def cpqr_id(M: np.ndarray, eps: float) -> IDResult:
+def cpqr_id(M: np.ndarray, eps: float, floor_rows: int = 0) -> IDResult:
+    """floor_rows: row count for the rounding width of the tie rule (default M's own; a
+    sketched block carries the rounding of the sum over the original block's rows)."""
     A = np.array(M, dtype=np.result_type(M.dtype, np.float64), copy=True)
     m, n = A.shape
+    mf = max(m, floor_rows)
     perm = np.arange(n)
     rdiag = []
     first_tie = -1
@@ -62,7 +80,7 @@ def cpqr_id(M: np.ndarray, eps: float) -> IDResult:
             break
         if first_tie < 0 and norms.size > 1:
             second = np.partition(norms, -2)[-2]
-            if best - second <= TIE_RTOL * best:
+            if best - second <= TIE_RTOL * best + rounding_floor(mf, r00):
                 first_tie = j
         # swap the pivot column into position j
         A[:, [j, p]] = A[:, [p, j]]
@@ -79,7 +97,7 @@ def cpqr_id(M: np.ndarray, eps: float) -> IDResult:
     if r00 > 0.0:
         thr = eps * r00
         for val in rdiag[max(0, k - 1):k + 1]:
-            if abs(val - thr) <= TIE_RTOL * thr:
+            if abs(val - thr) <= TIE_RTOL * thr + rounding_floor(mf, r00):
                 near = True
     R11 = np.triu(A[:k, :k])
     R12 = A[:k, k:]
@@ -90,3 +108,51 @@ def cpqr_id(M: np.ndarray, eps: float) -> IDResult:
     ro = np.argsort(red_p, kind="stable")
     return IDResult(k, skel_p[so], red_p[ro], T[so][:, ro], perm.copy(),
                     np.array(rdiag), first_tie, near)
+
+
+# ---------------------------------------------------------------------------------
+# Randomized ID (Section 2.2: the ID may be computed from a random sketch of the block,
+# as in the paper's own code).  The block M (m x n) is compressed through its row sketch
+# Y = Omega M with Omega an ell x m matrix of random signs, ell = min(m, n + oversample);
+# the ID of Y (the column-pivoted QR above, with its rank rule) gives the skeletons and
+# T.  When ell = m no sketch is taken (Y = M).  Omega's entries come from the SplitMix64
+# counter-based generator (published by Steele, Lea and Flood, "Fast splittable
+# pseudorandom number generators", OOPSLA 2014), so any implementation reproduces them
+# exactly: entry (a, i) for box b is +1 or -1 by the top bit of
+#     splitmix64(seed xor (b << 40) xor (a << 20) xor i).
+
+_GOLDEN_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 output for the counters x (uint64 array): the generator's state after
+    one increment by the golden gamma, mixed."""
+    z = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z + _GOLDEN_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def sketch_signs(box: int, rows: int, cols: int, seed: int) -> np.ndarray:
+    """The rows x cols sign matrix Omega of box ``box`` (float64 entries +-1)."""
+    a = np.arange(rows, dtype=np.uint64)[:, None]
+    i = np.arange(cols, dtype=np.uint64)[None, :]
+    ctr = (np.uint64(seed) ^ (np.uint64(box) << np.uint64(40)) ^ (a << np.uint64(20)) ^ i)
+    top = splitmix64(ctr) >> np.uint64(63)
+    return 1.0 - 2.0 * top.astype(np.float64)
+
+
+def sketch_rows(m: int, n: int, oversample: int) -> int:
+    return min(m, n + oversample)
+
+
+def randomized_id(M: np.ndarray, eps: float, box: int, seed: int, oversample: int) -> IDResult:
+    """ID of M through its row sketch (see above); the result refers to M's columns."""
+    m, n = M.shape
+    ell = sketch_rows(m, n, oversample)
+    if ell >= m:
+        return cpqr_id(M, eps)
+    Y = sketch_signs(box, ell, m, seed) @ M
+    return cpqr_id(Y, eps, floor_rows=m)

@@ -43,7 +43,7 @@ import numpy as np
 from scipy.linalg import lu_factor, lu_solve
 
 from .green import Problem, block, kernel
-from .interp import IDResult, cpqr_id
+from .interp import IDResult, cpqr_id, randomized_id
 from .tree import Tree, build_tree
 
 
@@ -52,6 +52,9 @@ class Options:
     eps: float
     proxy_points: int = 64
     proxy_ratio: float = 1.5
+    id_mode: str = "cpqr"         # "cpqr": ID of M_B; "sketch": ID of its row sketch
+    sketch_seed: int = 0
+    oversample: int = 16
 
 
 @dataclass
@@ -216,7 +219,10 @@ class RSFactor:
                     M_rows = 0
                 else:
                     M = compression_block(prob, J, near, t.center[b], radius, o.proxy_points)
-                    idr = cpqr_id(M, o.eps)
+                    if o.id_mode == "sketch":
+                        idr = randomized_id(M, o.eps, b, o.sketch_seed, o.oversample)
+                    else:
+                        idr = cpqr_id(M, o.eps)
                     M_rows = M.shape[0]
                 rec = BoxRecord(b, d, t.is_leaf(b), J, near, M_rows, idr, segs[b])
                 self.records[b] = rec
@@ -311,8 +317,14 @@ class RSFactor:
 
 
 def factor(prob: Problem, eps: float, leaf_size: int = 64, proxy_points: int = 64,
-           proxy_ratio: float = 1.5, tree: Optional[Tree] = None) -> RSFactor:
-    """Build the tree (unless given), compress and factor; returns the RSFactor."""
+           proxy_ratio: float = 1.5, tree: Optional[Tree] = None, id_mode: str = "cpqr",
+           sketch_seed: int = 0, oversample: int = 16) -> RSFactor:
+    """Build the tree (unless given), compress and factor; returns the RSFactor.
+    id_mode "sketch" compresses each block through its random row sketch
+    (interp.randomized_id) instead of the block itself."""
     if tree is None:
         tree = build_tree(prob.points, leaf_size)
-    return RSFactor(prob, tree, Options(eps, proxy_points, proxy_ratio)).run()
+    if id_mode not in ("cpqr", "sketch"):
+        raise ValueError(id_mode)
+    return RSFactor(prob, tree, Options(eps, proxy_points, proxy_ratio, id_mode, sketch_seed,
+                                        oversample)).run()

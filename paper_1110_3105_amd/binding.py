@@ -28,7 +28,7 @@ _lib = C.CDLL(LIB_PATH)
 RS_OK, RS_EINVAL, RS_ENOMEM, RS_ESINGULAR, RS_EDEVICE, RS_EBUSY, RS_ENOTSUP = range(7)
 STATUS_NAMES = {0: "RS_OK", 1: "RS_EINVAL", 2: "RS_ENOMEM", 3: "RS_ESINGULAR",
                 4: "RS_EDEVICE", 5: "RS_EBUSY", 6: "RS_ENOTSUP"}
-KINDS = {"lap2d_sl": 1, "lap2d_dl": 2, "lap3d_sl": 3, "helm2d_cfie": 4}
+KINDS = {"lap2d_sl": 1, "lap2d_dl": 2, "lap3d_sl": 3, "helm2d_cfie": 4, "helm3d_sl": 5}
 LAUNCH = {"level": 0, "per_box": 1}
 
 EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "rs_factor",
@@ -39,7 +39,7 @@ EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "
             "rs_server_submit_solve", "rs_server_poll", "rs_server_release", "rs_server_query",
             "rs_server_reset_stats", "rs_server_destroy", "rs_plan_create", "rs_plan_launch",
             "rs_plan_free", "rs_autotune", "rs_tune_entries", "rs_tune_clear", "rs_tune_save",
-            "rs_tune_load"]
+            "rs_tune_load", "rs_matvec"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -47,7 +47,11 @@ class rs_kernel(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("identity", C.c_double),
                 ("wavenumber", C.c_double), ("eta", C.c_double),
                 ("normals", C.POINTER(C.c_double)), ("curvature", C.POINTER(C.c_double)),
-                ("proxy_points", C.c_int32), ("proxy_ratio", C.c_double)]
+                ("proxy_points", C.c_int32), ("proxy_ratio", C.c_double),
+                ("id_mode", C.c_int32), ("oversample", C.c_int32), ("sketch_seed", C.c_uint64)]
+
+
+ID_MODES = {"cpqr": 0, "sketch": 1}
 
 
 class rs_options(C.Structure):
@@ -90,6 +94,7 @@ _sig = {
                                C.POINTER(rs_options), C.POINTER(_P)]),
     "rs_solve": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P]),
     "rs_solve_ex": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(rs_options)]),
+    "rs_matvec": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, _P]),
     "rs_free": (C.c_int, [_P]),
     "rs_last_error": (C.c_char_p, []),
     "rs_device_count": (C.c_int32, []),
@@ -308,6 +313,27 @@ class Handle:
             X.copy_(work)
         return B
 
+    def matvec(self, X, stream=None):
+        """Y = A_eps X (compressed forward operator) for a device tensor X of shape (n,) or
+        (n, nrhs); returns a new column-major tensor."""
+        import torch
+        if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == self.dtype):
+            raise TypeError(f"X must be a {self.dtype} tensor on the HIP device")
+        vec = X.dim() == 1
+        X2 = X.unsqueeze(1) if vec else X
+        if X2.shape[0] != self.n:
+            raise ValueError("X has the wrong number of rows")
+        nrhs = X2.shape[1]
+        if not (X2.stride(0) == 1 and (nrhs == 1 or X2.stride(1) >= self.n)):
+            X2 = X2.t().contiguous().t()
+        ldx = X2.stride(1) if nrhs > 1 else self.n
+        Y = torch.empty(nrhs, self.n, dtype=X.dtype, device=X.device).t()
+        if stream is None:
+            stream = torch.cuda.current_stream(X.device)
+        _check(_lib.rs_matvec(self._h, C.c_void_p(X2.data_ptr()), int(ldx),
+                              C.c_void_p(Y.data_ptr()), self.n, int(nrhs), _stream_ptr(stream)))
+        return Y[:, 0] if vec else Y
+
     def solve_host(self, b: np.ndarray, stream=None) -> np.ndarray:
         """Synchronous solve of host right-hand sides (numpy, shape (n,) or (n, nrhs),
         float64 or complex128 to match the handle); returns a new array."""
@@ -353,14 +379,18 @@ def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: 
            normals: Optional[np.ndarray] = None, curvature: Optional[np.ndarray] = None,
            identity: float = 0.0, proxy_points: int = 64, proxy_ratio: float = 1.5,
            launch_mode: str = "level", stream=None, wavenumber: float = 0.0,
-           eta: float = 0.0) -> Handle:
+           eta: float = 0.0, id_mode: str = "cpqr", sketch_seed: int = 0,
+           oversample: int = 16) -> Handle:
+    """Compress and factor (rs_factor_ex).  id_mode "sketch" compresses each box through
+    its random row sketch (the randomized ID; seed and oversampling as in rs.h)."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     w = np.ascontiguousarray(weights, dtype=np.float64)
     nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64)
     kap = None if curvature is None else np.ascontiguousarray(curvature, dtype=np.float64)
     if pts.shape[0] != w.shape[0]:
         raise ValueError("points and weights differ in length")
-    k = _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber, eta)
+    k = _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber, eta,
+                       id_mode, sketch_seed, oversample)
     o = rs_options(LAUNCH[launch_mode], _stream_ptr(stream))
     h = _P()
     _check(_lib.rs_factor_ex(C.byref(k), tree.handle, _dptr(pts), _dptr(w), float(eps),
@@ -369,9 +399,10 @@ def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: 
 
 
 def _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber=0.0,
-                   eta=0.0):
+                   eta=0.0, id_mode="cpqr", sketch_seed=0, oversample=16):
     return rs_kernel(KINDS[kind], pts.shape[1], float(identity), float(wavenumber), float(eta),
-                     _dptr(nrm), _dptr(kap), int(proxy_points), float(proxy_ratio))
+                     _dptr(nrm), _dptr(kap), int(proxy_points), float(proxy_ratio),
+                     ID_MODES[id_mode], int(oversample), int(sketch_seed))
 
 
 def factor_batched(problems, launch_mode: str = "level", stream=None):
@@ -393,7 +424,9 @@ def factor_batched(problems, launch_mode: str = "level", stream=None):
         keep += [pts, w, nrm, kap]
         ks.append(_kernel_struct(q["kind"], pts, nrm, kap, q.get("identity", 0.0),
                                  q.get("proxy_points", 64), q.get("proxy_ratio", 1.5),
-                                 q.get("wavenumber", 0.0), q.get("eta", 0.0)))
+                                 q.get("wavenumber", 0.0), q.get("eta", 0.0),
+                                 q.get("id_mode", "cpqr"), q.get("sketch_seed", 0),
+                                 q.get("oversample", 16)))
         trees.append(q["tree"].handle)
         pts_p.append(_dptr(pts))
         w_p.append(_dptr(w))

@@ -54,16 +54,21 @@ void validate_kernel(const rs_kernel *k, const Tree &t, const double *points,
                      const double *weights, double eps) {
   if (!k || !points || !weights) fail(RS_EINVAL, "NULL kernel, points or weights");
   if (k->kind != RS_LAP2D_SL && k->kind != RS_LAP2D_DL && k->kind != RS_LAP3D_SL &&
-      k->kind != RS_HELM2D_CFIE)
+      k->kind != RS_HELM2D_CFIE && k->kind != RS_HELM3D_SL)
     fail(RS_EINVAL, "unknown kernel kind");
-  const int want_dim = k->kind == RS_LAP3D_SL ? 3 : 2;
+  const int want_dim = (k->kind == RS_LAP3D_SL || k->kind == RS_HELM3D_SL) ? 3 : 2;
   if (k->dim != want_dim || t.dim != want_dim) fail(RS_EINVAL, "kernel dimension mismatch");
   if ((k->kind == RS_LAP2D_DL || k->kind == RS_HELM2D_CFIE) && (!k->normals || !k->curvature))
     fail(RS_EINVAL, "double-layer kernel needs normals and curvature");
   if (k->kind == RS_HELM2D_CFIE &&
       (!(k->wavenumber > 0.0) || !std::isfinite(k->wavenumber) || !std::isfinite(k->eta)))
     fail(RS_EINVAL, "Helmholtz kernel needs a finite wavenumber > 0 and a finite eta");
+  if (k->kind == RS_HELM3D_SL && (!(k->wavenumber > 0.0) || !std::isfinite(k->wavenumber)))
+    fail(RS_EINVAL, "Helmholtz kernel needs a finite wavenumber > 0");
   if (k->proxy_points < 8 || k->proxy_points > 4096) fail(RS_EINVAL, "proxy_points out of range");
+  if (k->id_mode != RS_ID_CPQR && k->id_mode != RS_ID_SKETCH) fail(RS_EINVAL, "unknown id_mode");
+  if (k->id_mode == RS_ID_SKETCH && (k->oversample < 0 || k->oversample > 4096))
+    fail(RS_EINVAL, "oversample out of range");
   if (!(k->proxy_ratio > 0.5 * std::sqrt((double)want_dim)) || !(k->proxy_ratio < 16.0))
     fail(RS_EINVAL, "proxy_ratio must exceed half the box diagonal");
   if (!std::isfinite(k->identity)) fail(RS_EINVAL, "non-finite identity coefficient");
@@ -234,7 +239,8 @@ rs_status rs_solve_batched(int32_t count, const rs_handle *h, void *const *B,
                             " is a host pointer)");
     }
     solve_many(reqs, stream_of(opts));
-    for (int i = 0; i < count; ++i) note_inflight(h[i], stream_of(opts));
+    const auto done = record_completion(stream_of(opts));
+    for (int i = 0; i < count; ++i) note_inflight(h[i], done);
     return RS_OK;
   });
 }
@@ -286,6 +292,33 @@ rs_status rs_solve_ex(rs_handle h, void *B, int64_t ldb, int32_t nrhs,
 rs_status rs_solve(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream) {
   rs_options o{RS_LAUNCH_LEVEL, stream};
   return rs_solve_ex(h, B, ldb, nrhs, &o);
+}
+
+rs_status rs_matvec(rs_handle h, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nrhs,
+                    void *stream) {
+  return guarded([&]() -> rs_status {
+    if (!h) fail(RS_EINVAL, "NULL handle");
+    if (nrhs < 0) fail(RS_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return RS_OK;
+    if (!X || !Y) fail(RS_EINVAL, "NULL input or output");
+    if (ldx < h->n || ldy < h->n) fail(RS_EINVAL, "ldx or ldy < n");
+    const size_t es = h->cplx ? 16 : 8;
+    const size_t sx = ((size_t)(nrhs - 1) * (size_t)ldx + (size_t)h->n) * es;
+    const size_t sy = ((size_t)(nrhs - 1) * (size_t)ldy + (size_t)h->n) * es;
+    if (!is_device_buffer(X, sx) || !is_device_buffer(Y, sy))
+      fail(RS_EINVAL, "rs_matvec takes device memory only");
+    const char *x0 = static_cast<const char *>(X), *y0 = static_cast<const char *>(Y);
+    if (x0 < y0 + sy && y0 < x0 + sx) fail(RS_EINVAL, "X and Y overlap");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    h->busy.fetch_add(1);
+    struct Dec {
+      rs_handle h;
+      ~Dec() { h->busy.fetch_sub(1); }
+    } dec{h};
+    matvec_one(h, X, ldx, Y, ldy, nrhs, st);
+    note_inflight(h, st);
+    return RS_OK;
+  });
 }
 
 rs_status rs_plan_create(int32_t count, const rs_handle *h, void *const *B, const int64_t *ldb,

@@ -234,9 +234,20 @@ __device__ __forceinline__ double kernel_val<double>(const ProbDev &P, const dou
                                                      const double *s, const double *ns) {
   return green(P.kind, t, s, ns);
 }
+// 3D Helmholtz (eq. (3d-helmholtz)): exp(i k r) / (4 pi r).
+__device__ __forceinline__ Cplx green_helm3d(double kw, const double *t, const double *s) {
+  const double dx = t[0] - s[0], dy = t[1] - s[1], dz = t[2] - s[2];
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double sn, cs;
+  sincos(kw * r, &sn, &cs);
+  const double a = kInv4Pi / r;
+  return {a * cs, a * sn};
+}
+
 template <>
 __device__ __forceinline__ Cplx kernel_val<Cplx>(const ProbDev &P, const double *t,
                                                  const double *s, const double *ns) {
+  if (P.kind == RS_HELM3D_SL) return green_helm3d(P.kwave, t, s);
   return green_cfie(P.kwave, P.eta, t, s, ns);
 }
 
@@ -277,6 +288,13 @@ __device__ __forceinline__ double diag_entry<double>(const ProbDev &P, int g) {
 template <>
 __device__ __forceinline__ Cplx diag_entry<Cplx>(const ProbDev &P, int g) {
   const double w = P.w[g];
+  if (P.kind == RS_HELM3D_SL) {
+    // (exp(i k R) - 1) / (2 i k) = (sin kR + i (1 - cos kR)) / (2k), R = sqrt(w / pi);
+    // 1 - cos kR written as 2 sin^2(kR/2) (no cancellation for small kR)
+    const double kr = P.kwave * sqrt(w / kPi);
+    const double sh = sin(0.5 * kr);
+    return {P.c + sin(kr) / (2.0 * P.kwave), sh * sh / P.kwave};
+  }
   const double dl = -P.kappa[g] * w * (0.25 / kPi);
   const double sl_re = -w * (log(0.5 * P.kwave) + kEulerGamma) * kInv2Pi -
                        (w * kInv2Pi) * log(w * kInv2Pi);
@@ -796,6 +814,68 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
   if (tid == 0) ranks[B.kslot] = k;
 }
 
+// Boxes with m n >= kCoopMinEntries take the multi-workgroup ID (k_cpqr_coop).
+// (below ~1M entries the two box-wide barriers of every pivot step cost more than the
+// single workgroup's streaming of the block: the 2D benchmark's top levels, 776 x 112,
+// ran 0.6 ms per launch slower across workgroups)
+constexpr int64_t kCoopMinEntries = int64_t(1) << 20;
+constexpr int kCoopThreads = 256;
+constexpr int kCoopMaxG = 64;
+constexpr unsigned kCoopSpinLimit = 1u << 22;   // polls (each one L2 round trip plus a sleep): seconds
+
+__host__ __device__ __forceinline__ bool coop_class(int m, int n) {
+  return (int64_t)m * n >= kCoopMinEntries;
+}
+
+// --------------------------------------------------------------------------
+// Row sketch Y = Omega M of a compression block for the randomized ID (Section 2.2):
+// Omega is ell x m with entries +-1, entry (a, i) of tree box b set by the top bit of
+// SplitMix64 (published by Steele, Lea and Flood, OOPSLA 2014) at the counter
+// seed ^ (b << 40) ^ (a << 20) ^ i.  Each wave produces 16 x 16 tiles of Y with FP64
+// MFMA over the rows of M in order.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_sketch(const CompBox *__restrict__ comp,
+                                                     const CompBox *__restrict__ comp_id,
+                                                     int first, const ProbDev *__restrict__ probs,
+                                                     S *__restrict__ Marena) {
+  const CompBox &B = comp[first + blockIdx.x];
+  const CompBox &Bi = comp_id[first + blockIdx.x];
+  const int m = B.m, n = B.n, ell = Bi.m;
+  if (ell >= m || n == 0) return;
+  const ProbDev &P = probs[B.prob];
+  const uint64_t key = P.sketch_seed ^ ((uint64_t)(uint32_t)B.box << 40);
+  const S *M = Marena + B.M_off;
+  S *Y = Marena + Bi.M_off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ta = (ell + 15) / 16, tc = (n + 15) / 16;
+  for (int tile = blockIdx.y * kWaves + wave; tile < ta * tc; tile += gridDim.y * kWaves) {
+    const int a0 = (tile / tc) * 16, c0 = (tile % tc) * 16;
+    const int a = a0 + li, c = c0 + li;
+    const uint64_t ka = key ^ ((uint64_t)a << 20);
+    Acc<S> acc;
+    for (int i0 = 0; i0 < m; i0 += 4) {
+      const int i = i0 + lk;
+      double w = 0.0;
+      if (a < ell && i < m) w = (splitmix64(ka ^ (uint64_t)i) >> 63) ? -1.0 : 1.0;
+      const S x = (c < n && i < m) ? M[(int64_t)c * m + i] : S(0.0);
+      acc.mma(S(w), x);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ar = a0 + lk + 4 * v;
+      if (ar < ell && c < n) Y[(int64_t)c * ell + ar] = acc.get(v);
+    }
+  }
+}
+
 // --------------------------------------------------------------------------
 // Interpolative decomposition (Section 2.2) of M_B by column-pivoted Householder QR:
 // pivot = largest remaining column norm (recomputed after every reflection, ties to
@@ -831,6 +911,7 @@ __global__ __launch_bounds__(NTH) void k_cpqr_id(const CompBox *__restrict__ box
     if (threadIdx.x == 0) ranks[B.kslot] = 0;
     return;
   }
+  if (coop_class(m, n)) return;                    // factored by k_cpqr_coop
   S *M = Marena + B.M_off;
   const int kmax = min(m, n);
   double *norms = smem;                                    // n
@@ -1165,6 +1246,258 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
+
+// --------------------------------------------------------------------------
+// The same interpolative decomposition for large blocks, spread over G workgroups per
+// box in one cooperative launch (every workgroup of the grid resident at once).  A box
+// is in this class when m n >= kCoopMinEntries (its own size only, so its result never
+// depends on the launch it shares); k_cpqr_id skips such boxes.  The rules and outputs
+// are those of k_cpqr_id: pivot = largest recomputed norm of the remaining part (rows
+// j..m-1), ties to the lowest column, stop at |R_jj| <= eps |R_00|, T = R11^{-1} R12,
+// sorted skeleton and redundant sets.
+//
+// Columns are not moved: step j's pivot is column piv[j], and R's row j ends in row j of
+// every column.  Workgroup g owns the columns c = g (mod G) and is the only one to write
+// them.  A step: each workgroup offers its best column; box-wide barrier; all pick the
+// same pivot from the G offers; the pivot's owner forms the reflector in place (v below
+// the diagonal, beta on it) and publishes conj(tau); box-wide barrier; every workgroup
+// applies the reflector to its remaining columns and recomputes their norms.  A column's
+// sums always run over the same lanes in the same order (one wave per column), so the
+// result does not depend on G.
+//
+// Barriers count arrivals on a per-box counter with agent-scope release/acquire; a wait
+// is bounded: past kCoopSpinLimit polls a workgroup raises the launch's abort flag and
+// every workgroup leaves at its next barrier (the box's rank is then reported as -1).
+// Box-wide barrier number `seq` (1, 2, ...) of G workgroups.  Returns false if the launch
+// was aborted (uniform over the workgroup).
+__device__ __forceinline__ bool coop_barrier(unsigned *cnt, unsigned target, int *abort_flag,
+                                             int *s_ok) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (++spins > kCoopSpinLimit) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    *s_ok = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return *s_ok != 0;
+}
+
+template <class S>
+__global__ __launch_bounds__(kCoopThreads) void k_cpqr_coop(
+    const CompBox *__restrict__ boxes, int first, int count, int nbox_al, int G,
+    const ProbDev *__restrict__ probs, S *__restrict__ Marena, int32_t *__restrict__ order_pool,
+    int32_t *__restrict__ ranks, unsigned *__restrict__ bar, double *__restrict__ cval,
+    int *__restrict__ ccol, double *__restrict__ ctau_g, int *__restrict__ abort_flag,
+    int vlds) {
+  constexpr int NW = kCoopThreads / 64;
+  extern __shared__ double smem[];
+  __shared__ int s_ok, s_p, s_k;
+  __shared__ double s_best;
+  const int bl = blockIdx.x % nbox_al, g = blockIdx.x / nbox_al;
+  if (bl >= count) return;
+  const CompBox &B = boxes[first + bl];
+  const int m = B.m, n = B.n;
+  if (!coop_class(m, n)) return;                    // not in this class: no barriers
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double eps = probs[B.prob].eps;
+  S *M = Marena + B.M_off;
+  const int kmax = min(m, n);
+  const int nq = g < n ? (n - g + G - 1) / G : 0;   // columns g, g + G, ...
+  const int nqmax = (n + G - 1) / G;
+  char *lb0 = reinterpret_cast<char *>(smem);
+  double *nrm = reinterpret_cast<double *>(lb0);                     // nqmax
+  int *dn = reinterpret_cast<int *>(lb0 + (size_t)nqmax * 8);        // nqmax
+  int *piv = dn + nqmax;                                             // kmax
+  int *rs = piv + kmax;                                              // kmax (sorted rank of step i)
+  const size_t vb_off = ((size_t)nqmax * 12 + (size_t)kmax * 8 + 15) & ~size_t(15);
+  S *vb = reinterpret_cast<S *>(lb0 + vb_off);       // m (reflector) when vlds, then T buffers
+  unsigned *cnt = bar + bl;
+  unsigned seq = 0;
+  double *cv = cval + (int64_t)bl * 2 * kCoopMaxG;
+  int *cc = ccol + (int64_t)bl * 2 * kCoopMaxG;
+  double *ct = ctau_g + (int64_t)bl * 2;
+
+  for (int q = wave; q < nq; q += NW) {
+    const S *col = M + (int64_t)(g + q * G) * m;
+    double sum = 0.0;
+    for (int i = lane; i < m; i += 64) sum += abs2(col[i]);
+    sum = wave_sum(sum);
+    if (lane == 0) {
+      nrm[q] = sqrt(sum);
+      dn[q] = 0;
+    }
+  }
+  __syncthreads();
+  int k = kmax;
+  double r00 = 0.0;
+  bool aborted = false;
+  for (int j = 0; j < kmax; ++j) {
+    const int par = j & 1;
+    if (wave == 0) {           // this workgroup's offer: largest norm, lowest column
+      double lb = -1.0;
+      int lc = INT_MAX;
+      for (int q = lane; q < nq; q += 64) {
+        if (dn[q]) continue;
+        const double v = nrm[q];
+        const int c = g + q * G;
+        if (v > lb || (v == lb && c < lc)) { lb = v; lc = c; }
+      }
+      const ArgMax a = wave_argmax(lb, lc, lc);
+      if (lane == 0) {
+        cv[par * kCoopMaxG + g] = a.v;
+        cc[par * kCoopMaxG + g] = a.key;
+      }
+    }
+    if (!coop_barrier(cnt, ++seq * (unsigned)G, abort_flag, &s_ok)) { aborted = true; break; }
+    if (wave == 0) {
+      const double v = lane < G ? cv[par * kCoopMaxG + lane] : -1.0;
+      const int c = lane < G ? cc[par * kCoopMaxG + lane] : INT_MAX;
+      const ArgMax a = wave_argmax(v, c, c);
+      if (lane == 0) { s_best = a.v; s_p = a.key; }
+    }
+    __syncthreads();
+    const double best = s_best;
+    const int p = s_p;
+    if (j == 0) r00 = best;
+    if (best == 0.0 || best <= eps * r00) { k = j; break; }
+    if (threadIdx.x == 0) piv[j] = p;
+    if (p % G == g && wave == 0) {     // owner: reflector of column p, rows j..m-1
+      S *cp = M + (int64_t)p * m;
+      double sum = 0.0;
+      for (int i = j + lane; i < m; i += 64) sum += abs2(cp[i]);
+      sum = wave_sum(sum);
+      const double alpha = sqrt(sum);
+      const S x0 = cp[j];
+      const double beta = re_part(x0) >= 0.0 ? -alpha : alpha;
+      const S scale = recip(x0 - S(beta));
+      for (int i = j + 1 + lane; i < m; i += 64) cp[i] = cp[i] * scale;
+      if (lane == 0) {
+        const S ctau = conjg(sdiv(S(beta) - x0, beta));
+        ct[0] = re_part(ctau);
+        if constexpr (sizeof(S) != sizeof(double)) ct[1] = reinterpret_cast<const double *>(&ctau)[1];
+        cp[j] = S(beta);
+        dn[(p - g) / G] = 1;
+      }
+    }
+    if (!coop_barrier(cnt, ++seq * (unsigned)G, abort_flag, &s_ok)) { aborted = true; break; }
+    S ctau;
+    if constexpr (sizeof(S) == sizeof(double)) {
+      ctau = ct[0];
+    } else {
+      reinterpret_cast<double *>(&ctau)[0] = ct[0];
+      reinterpret_cast<double *>(&ctau)[1] = ct[1];
+    }
+    const S *vg = M + (int64_t)p * m;
+    if (vlds) {
+      for (int i = j + threadIdx.x; i < m; i += kCoopThreads) vb[i] = i == j ? S(1.0) : vg[i];
+      __syncthreads();
+    }
+    auto vload = [&](int i) -> S { return vlds ? vb[i] : (i == j ? S(1.0) : vg[i]); };
+    for (int q = wave; q < nq; q += NW) {
+      if (dn[q]) continue;
+      S *col = M + (int64_t)(g + q * G) * m;
+      S dot = S(0.0);
+      for (int i0 = j; i0 < m; i0 += 256) {
+        S xv[4], vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + lane + 64 * u;
+          xv[u] = i < m ? col[i] : S(0.0);
+          vv[u] = i < m ? vload(i) : S(0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dot += conjg(vv[u]) * xv[u];
+      }
+      dot = wave_sum(dot) * ctau;
+      double ns = 0.0;
+      for (int i0 = j; i0 < m; i0 += 256) {
+        S xv[4], vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + lane + 64 * u;
+          xv[u] = i < m ? col[i] : S(0.0);
+          vv[u] = i < m ? vload(i) : S(0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + lane + 64 * u;
+          if (i < m) {
+            const S nv = xv[u] - dot * vv[u];
+            col[i] = nv;
+            if (i > j) ns += abs2(nv);
+          }
+        }
+      }
+      ns = wave_sum(ns);
+      if (lane == 0) nrm[q] = sqrt(ns);
+    }
+    __syncthreads();
+  }
+  if (aborted) {
+    if (g == 0 && threadIdx.x == 0) ranks[B.kslot] = -1;
+    return;
+  }
+  if (threadIdx.x == 0) s_k = k;
+  __syncthreads();
+  k = s_k;
+  // sorted position of each skeleton (pivot step i) among the skeletons
+  for (int i = threadIdx.x; i < k; i += kCoopThreads) {
+    const int pc = piv[i];
+    int r = 0;
+    for (int l = 0; l < k; ++l) r += piv[l] < pc;
+    rs[i] = r;
+  }
+  __syncthreads();
+  int32_t *order = order_pool + B.order_off;
+  S *T = reinterpret_cast<S *>(B.T);
+  for (int i = threadIdx.x; i < k; i += kCoopThreads)
+    if (piv[i] % G == g) order[rs[i]] = piv[i];
+  // T = R11^{-1} R12 for this workgroup's redundant columns, one column per wave; the
+  // column is solved in the wave's share of the LDS after the reflector buffer
+  S *buf = vb + (int64_t)wave * kmax;
+  for (int q = wave; q < nq; q += NW) {
+    if (dn[q]) continue;
+    const int c = g + q * G;
+    // redundant rank: columns below c that are not skeletons
+    int below = 0;
+    for (int l = lane; l < k; l += 64) below += piv[l] < c;
+    for (int off = 32; off > 0; off >>= 1) below += __shfl_xor(below, off, 64);
+    const int rr = c - below;
+    if (lane == 0) order[k + rr] = c;
+    const S *col = M + (int64_t)c * m;
+    for (int i = lane; i < k; i += 64) buf[i] = col[i];
+    wave_sync();
+    for (int i = k - 1; i >= 0; --i) {
+      const S *ri = M + (int64_t)piv[i] * m;        // R11 column i: rows 0..i
+      const S xi = sdiv(buf[i], ri[i]);
+      for (int l = lane; l < i; l += 64) buf[l] -= xi * ri[l];
+      wave_sync();
+      if (lane == 0) buf[i] = xi;
+      wave_sync();
+    }
+    S *Tc = T + (int64_t)k * rr;
+    for (int i = lane; i < k; i += 64) Tc[rs[i]] = buf[i];
+    wave_sync();
+  }
+  if (g == 0 && threadIdx.x == 0) ranks[B.kslot] = k;
+}
+
 
 // One non-pivot row of a panel step: A(i, c) <- A(i, c) - f prow[c] (c != jj) and
 // A(i, jj) <- -f inv with f = A(i, jj).  The row's entries and those of prow are loaded
@@ -1578,7 +1911,13 @@ __global__ __launch_bounds__(NTH, 4) void k_diag_factor(const FacBox *__restrict
   const ProbDev &P = probs[B.prob];
   const int n = B.n;
   if (n == 0) return;
+  if (B.force_k0 && n >= kWideRootMinN) return;      // factored by the wide-root launches
   const int k = B.force_k0 ? 0 : ranks[B.kslot];
+  if (k < 0 || k > n) {            // the box's ID did not complete: nothing to factor
+    if (threadIdx.x == 0)
+      atomicMin(reinterpret_cast<unsigned int *>(err), (unsigned int)(err_base + first + (int)blockIdx.x));
+    return;
+  }
   const int r = n - k;
   const int32_t *J = pool + B.J_off;
   const int32_t *ord = B.force_k0 ? nullptr : order_pool + B.order_off;
@@ -1721,6 +2060,177 @@ __global__ __launch_bounds__(NTH, 4) void k_diag_factor(const FacBox *__restrict
 //
 // Up (finest level first):  t = b_r - T^T b_s;  b_r <- G t;  b_s <- b_s - E t.
 // Down (root side first):   u = y_r - F z_s;   b_r <- u;     b_s <- z_s - T u.
+// ---------------------------------------------------------------------------------
+// Large roots across the GPU (the dense root block of Section 3.4, eq.
+// (multilevel-inverse), when it has kWideRootMinN unknowns or more): the block is
+// assembled by many workgroups, then inverted by the blocked Gauss-Jordan elimination of
+// gj_blocked spread over launches -- per panel of kPB columns one workgroup runs the
+// panel's pivot steps on those columns (partial pivoting over the unused rows, ties to
+// the lowest row), copies the panel's pivot rows, and a launch of many workgroups
+// applies the panel's rank-kPB update to every other column with FP64 MFMA tiles:
+//   A(i, q) <- [i not a pivot of the panel] A(i, q) + P(i, :) W(:, q).
+// At the end G(a, b) = A(piv[a], ustep[b]) (ustep is the inverse permutation of piv).
+// A zero or non-finite pivot sets the root's failure flag and the error index; every
+// later launch of the root sees the flag and does nothing.
+constexpr int kWidePanelThreads = 1024;
+
+// Entry (a, b) of a factored box's diagonal block D in its local order (the order ord,
+// or the active-set order when ord is null): a child's Lambda inside a child, else A.
+template <class S>
+__device__ __forceinline__ S fac_entry(const FacBox &B, const ProbDev &P, const int32_t *J,
+                                       const int32_t *ord, int a, int b) {
+  const int li = ord ? ord[a] : a, lj = ord ? ord[b] : b;
+  if (!B.leaf) {
+    int ca = 0, cb = 0;
+    for (int c = 1; c < B.nchild; ++c) {
+      ca += li >= B.child_lo[c];
+      cb += lj >= B.child_lo[c];
+    }
+    if (ca == cb)
+      return reinterpret_cast<const S *>(B.child_lam[ca])[(li - B.child_lo[ca]) +
+                                                          (int64_t)B.child_k[ca] * (lj - B.child_lo[ca])];
+  }
+  return entry<S>(P, J[li], J[lj]);
+}
+
+// Root block (k = 0) into the box's workspace, column-major n x n: grid.x column groups
+// of 16, 256 threads over the rows.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_root_assemble(const FacBox *__restrict__ box,
+                                                            const ProbDev *__restrict__ probs,
+                                                            const int32_t *__restrict__ pool,
+                                                            S *__restrict__ workbase) {
+  const FacBox &B = *box;
+  const ProbDev &P = probs[B.prob];
+  const int n = B.n;
+  const int32_t *J = pool + B.J_off;
+  S *X = workbase + B.work_off;
+  const int b0 = blockIdx.x * 16;
+  for (int bb = 0; bb < 16; ++bb) {
+    const int b = b0 + bb;
+    if (b >= n) break;
+    for (int a = threadIdx.x; a < n; a += kThreads) X[(int64_t)b * n + a] = fac_entry<S>(B, P, J, nullptr, a, b);
+  }
+}
+
+// Control block of a wide root: piv[r], ustep[r] (rows), fail flag.
+struct WideCtl {
+  int *piv;
+  int *ustep;
+  int *fail;
+};
+
+template <class S>
+__global__ __launch_bounds__(kWidePanelThreads) void k_gj_wide_panel(
+    S *__restrict__ A, int lda, int r, int p0, int pb, WideCtl ctl, S *__restrict__ W,
+    int32_t *__restrict__ err, int err_idx) {
+  constexpr int NTH = kWidePanelThreads, NW = NTH / 64;
+  __shared__ S prow[kPB];
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (*ctl.fail) return;
+  for (int jj = 0; jj < pb; ++jj) {
+    const int j = p0 + jj;
+    double lb = -1.0;
+    int li = INT_MAX;
+    for (int i = tid; i < r; i += NTH) {
+      if (ctl.ustep[i] >= 0) continue;
+      const double v = mag(A[(int64_t)j * lda + i]);
+      if (v > lb || (v == lb && i < li)) { lb = v; li = i; }
+    }
+    const ArgMax am = wave_argmax(lb, li, li);
+    if (lane == 0) { red_v[wave] = am.v; red_i[wave] = am.key; }
+    __syncthreads();
+    const ArgMax gm = wave_argmax(lane < NW ? red_v[lane] : -1.0, lane < NW ? red_i[lane] : INT_MAX, 0);
+    if (!(gm.v > 0.0) || !isfinite(gm.v)) {
+      if (tid == 0) {
+        *ctl.fail = 1;
+        atomicMin(reinterpret_cast<unsigned int *>(err), (unsigned int)err_idx);
+      }
+      return;
+    }
+    const int pr = gm.key;
+    if (wave == 0) {
+      const S inv = recip(A[(int64_t)j * lda + pr]);
+      if (lane < pb) prow[lane] = lane == jj ? inv : A[(int64_t)(p0 + lane) * lda + pr] * inv;
+      if (lane == 0) {
+        ctl.ustep[pr] = j;
+        ctl.piv[j] = pr;
+      }
+    }
+    __syncthreads();
+    const S inv = prow[jj];
+    for (int i = tid; i < r; i += NTH) {
+      S *row = A + (int64_t)p0 * lda + i;
+      if (i == pr) {
+        for (int c = 0; c < pb; ++c) row[(int64_t)c * lda] = prow[c];
+      } else {
+        const S f = row[(int64_t)jj * lda];
+        for (int c = 0; c < pb; ++c) {
+          const S v = row[(int64_t)c * lda];
+          row[(int64_t)c * lda] = c == jj ? S(0.0) - f * inv : v - f * prow[c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the panel's pivot rows outside the panel, before the update: W(s, q), ld kPB
+  for (int e = tid; e < pb * r; e += NTH) {
+    const int sidx = e % pb, q = e / pb;
+    W[(int64_t)q * kPB + sidx] = (q >= p0 && q < p0 + pb) ? S(0.0)
+                                                          : A[(int64_t)q * lda + ctl.piv[p0 + sidx]];
+  }
+}
+
+// Rank-pb update of every column outside the panel: 64 x 64 tiles, wave w takes rows
+// 16 w .. 16 w + 15 of the tile and its four 16 x 16 column tiles.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_gj_wide_update(S *__restrict__ A, int lda, int r,
+                                                             int p0, int pb, WideCtl ctl,
+                                                             const S *__restrict__ W) {
+  if (*ctl.fail) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 64 + wave * 16, q0 = blockIdx.y * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ia = i0 + li;
+  for (int t = 0; t < 4; ++t) {
+    const int qt = q0 + 16 * t;
+    if (qt >= r) break;
+    Acc<S> acc;
+#pragma unroll
+    for (int k0 = 0; k0 < kPB; k0 += 4) {
+      const int kk = k0 + lk;
+      const S a = (ia < r && kk < pb) ? A[(int64_t)(p0 + kk) * lda + ia] : S(0.0);
+      const int qb = qt + li;
+      const S b = (qb < r && kk < pb) ? W[(int64_t)qb * kPB + kk] : S(0.0);
+      acc.mma(a, b);
+    }
+    const int q = qt + li;
+    if (q >= r || (q >= p0 && q < p0 + pb)) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + lk + 4 * v;
+      if (i >= r) continue;
+      const int us = ctl.ustep[i];
+      const bool pivrow = us >= p0 && us < p0 + pb;
+      S *pa = A + (int64_t)q * lda + i;
+      *pa = (pivrow ? S(0.0) : *pa) + acc.get(v);
+    }
+  }
+}
+
+// G(a, b) = A(piv[a], ustep[b]), G column-major r x r.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_gj_wide_finish(const S *__restrict__ A, int lda,
+                                                             int r, WideCtl ctl, S *__restrict__ G) {
+  if (*ctl.fail) return;
+  const int b = blockIdx.y;
+  const int a = blockIdx.x * kThreads + threadIdx.x;
+  if (a >= r) return;
+  G[(int64_t)b * r + a] = A[(int64_t)ctl.ustep[b] * lda + ctl.piv[a]];
+}
+
 template <class S>
 struct SweepOps {
   const S *T, *G, *E, *F;
@@ -2354,6 +2864,18 @@ void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, cons
 
 bool fused_class(bool cplx, int n, int m) { return !cplx && n <= kFusedMaxN && m <= kFusedMaxM; }
 
+void launch_sketch(bool cplx, const CompBox *comp, const CompBox *comp_id, int first, int count,
+                   const ProbDev *probs, double *Marena, int max_tiles, hipStream_t st) {
+  if (count <= 0 || max_tiles <= 0) return;
+  const int gy = std::min(256, (max_tiles + kWaves - 1) / kWaves);
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_sketch<S>, dim3(count, gy), dim3(kThreads), 0, st, comp, comp_id,
+                       first, probs, reinterpret_cast<S *>(Marena));
+  });
+  check_launch("k_sketch");
+}
+
 // Register-resident variants (threads, rows per lane, columns per wave), smallest first;
 // a box takes the first whose column (NW * CPW) and row (64 RT) capacity covers it.
 // Fewer waves per box mean less per-step overhead and more boxes resident per CU; the
@@ -2427,11 +2949,86 @@ size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m) {
   return cpqr_lds_bytes_nt(256, max_n, max_m, cplx ? 2 : 1);
 }
 
+namespace {
+// LDS of k_cpqr_coop: norms and flags of a workgroup's columns, the pivot list and sorted
+// ranks, then the reflector (when it fits) or the T solves' column buffers.
+size_t coop_lds_bytes(int max_n, int max_m, int G, int es, bool vlds) {
+  const int kmax = std::min(max_n, max_m);
+  const int nqmax = (max_n + G - 1) / G;
+  // the kernel places the buffer at the 16-byte boundary after 12 nqmax + 8 kmax bytes
+  const size_t head = ((size_t)nqmax * 12 + (size_t)kmax * 8 + 15) & ~size_t(15);
+  const size_t vb = std::max<size_t>(vlds ? (size_t)max_m : 0, (size_t)4 * kmax) * 8 * es;
+  return head + vb;
+}
+
+int g_coop_supported = -1;     // cooperative launches available on the device (-1: unknown)
+
+void launch_cpqr_coop(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
+                      double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
+                      hipStream_t st) {
+  const int es = cplx ? 2 : 1;
+  if (g_coop_supported < 0) {
+    int dev = 0, v = 0;
+    RS_HIP_CHECK(hipGetDevice(&dev));
+    RS_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev));
+    g_coop_supported = v ? 1 : 0;
+  }
+  const int nbox_al = (count + 7) / 8 * 8;
+  int G = std::min(kCoopMaxG, std::max(1, 256 / nbox_al));
+  G = std::min(G, std::max(1, (max_n + 3) / 4));
+  if (!g_coop_supported) G = 1;
+  bool vlds = coop_lds_bytes(max_n, max_m, G, es, true) <= kMaxLds;
+  size_t lds = coop_lds_bytes(max_n, max_m, G, es, vlds);
+  if (lds > kMaxLds) throw DeviceError("k_cpqr_coop: box too large for LDS", hipErrorInvalidValue);
+  // per box: barrier counter, offers (values, columns) of both step parities, conj(tau)
+  const size_t off_val = 256;
+  const size_t off_col = off_val + (size_t)count * 2 * kCoopMaxG * sizeof(double);
+  const size_t off_tau = off_col + (size_t)count * 2 * kCoopMaxG * sizeof(int);
+  const size_t off_abort = off_tau + (size_t)count * 2 * sizeof(double);
+  const size_t bytes = off_abort + 256;
+  char *sync = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&sync, bytes + (size_t)count * sizeof(unsigned), st));
+  RS_HIP_CHECK(hipMemsetAsync(sync, 0, bytes + (size_t)count * sizeof(unsigned), st));
+  unsigned *bar = reinterpret_cast<unsigned *>(sync + bytes);
+  double *cval = reinterpret_cast<double *>(sync + off_val);
+  int *ccol = reinterpret_cast<int *>(sync + off_col);
+  double *ctau = reinterpret_cast<double *>(sync + off_tau);
+  int *abort_flag = reinterpret_cast<int *>(sync + off_abort);
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    auto kern = k_cpqr_coop<S>;
+    if (lds > 64 * 1024)
+      RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    S *Mp = reinterpret_cast<S *>(Marena);
+    int vl = vlds ? 1 : 0;
+    const dim3 grid(nbox_al * G), block(kCoopThreads);
+    if (G > 1) {
+      void *args[] = {(void *)&boxes, (void *)&first, (void *)&count, (void *)&nbox_al,
+                      (void *)&G, (void *)&probs, (void *)&Mp, (void *)&order_pool,
+                      (void *)&ranks, (void *)&bar, (void *)&cval, (void *)&ccol,
+                      (void *)&ctau, (void *)&abort_flag, (void *)&vl};
+      RS_HIP_CHECK(hipLaunchCooperativeKernel((const void *)kern, grid, block, args,
+                                              (unsigned)lds, st));
+    } else {
+      // one workgroup per box: its barriers complete on its own arrivals
+      hipLaunchKernelGGL(kern, grid, block, lds, st, boxes, first, count, nbox_al, G, probs, Mp,
+                         order_pool, ranks, bar, cval, ccol, ctau, abort_flag, vl);
+    }
+    check_launch("k_cpqr_coop");
+  });
+  RS_HIP_CHECK(hipFreeAsync(sync, st));
+}
+}  // namespace
+
 void launch_cpqr_id(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
                     double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                     hipStream_t st) {
   if (count <= 0) return;
   const int es = cplx ? 2 : 1;
+  if (coop_class(max_m, max_n))
+    launch_cpqr_coop(cplx, boxes, first, count, probs, Marena, order_pool, ranks, max_n, max_m,
+                     st);
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
     // Wide levels of small boxes: 256 threads, so several boxes share a CU; a few large
@@ -2453,6 +3050,41 @@ void launch_cpqr_id(bool cplx, const CompBox *boxes, int first, int count, const
 // variant (LDS or global) is chosen per launch from the largest box, so the smaller
 // boxes of a launch need one too.
 size_t diag_work_elems(int n) { return (size_t)n * n + (size_t)kPB * n; }
+
+void launch_root_wide(bool cplx, const FacBox *box, int n, const ProbDev *probs,
+                      const int32_t *pool, double *work, int64_t work_off, double *G,
+                      int32_t *err, int err_idx, hipStream_t st) {
+  if (n < kWideRootMinN) throw DeviceError("launch_root_wide: root below the wide class",
+                                           hipErrorInvalidValue);
+  int *ctl_mem = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&ctl_mem, (size_t)(2 * n + 1) * sizeof(int), st));
+  RS_HIP_CHECK(hipMemsetAsync(ctl_mem, 0xff, (size_t)(2 * n) * sizeof(int), st));
+  RS_HIP_CHECK(hipMemsetAsync(ctl_mem + 2 * n, 0, sizeof(int), st));
+  WideCtl ctl{ctl_mem, ctl_mem + n, ctl_mem + 2 * n};
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    S *wb = reinterpret_cast<S *>(work);
+    S *A = wb + work_off;
+    S *W = A + (int64_t)n * n;                   // kPB x n snapshot after the block
+    hipLaunchKernelGGL(k_root_assemble<S>, dim3((n + 15) / 16), dim3(kThreads), 0, st, box,
+                       probs, pool, wb);
+    check_launch("k_root_assemble");
+    const dim3 ug((n + 63) / 64, (n + 63) / 64);
+    for (int p0 = 0; p0 < n; p0 += kPB) {
+      const int pb = std::min(kPB, n - p0);
+      hipLaunchKernelGGL(k_gj_wide_panel<S>, dim3(1), dim3(kWidePanelThreads), 0, st, A, n, n,
+                         p0, pb, ctl, W, err, err_idx);
+      check_launch("k_gj_wide_panel");
+      hipLaunchKernelGGL(k_gj_wide_update<S>, ug, dim3(kThreads), 0, st, A, n, n, p0, pb, ctl,
+                         (const S *)W);
+      check_launch("k_gj_wide_update");
+    }
+    hipLaunchKernelGGL(k_gj_wide_finish<S>, dim3((n + kThreads - 1) / kThreads, n), dim3(kThreads),
+                       0, st, (const S *)A, n, n, ctl, reinterpret_cast<S *>(G));
+    check_launch("k_gj_wide_finish");
+  });
+  RS_HIP_CHECK(hipFreeAsync(ctl_mem, st));
+}
 
 void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
                         const ProbDev *probs, const int32_t *pool, const int32_t *order_pool,
@@ -2659,6 +3291,168 @@ void launch_sweep_seg(bool cplx, bool up, const SweepSeg *segs, int nseg, int nb
       default: sweep_seg_nt<S, 64>(up, segs, nseg, nblocks, max_nrhs, max_n, st); break;
     }
   });
+}
+
+// ---------------------------------------------------------------------------------
+// Compressed forward operator A_eps x (Section 3.3, the two passes of the compressed
+// matrix-vector product; used as a generalized FMM in Section 6.1).  Upward, finest
+// level first, every box replaces its skeleton values by x_s + T x_r (the
+// interpolation R_B) after keeping the level's x_s; at the root and on the way down
+// every box lifts its skeleton results to its redundant DOFs (y_r = T^T y_s, the
+// interpolation L_B) and adds its diagonal block of the level's matrix times the level's
+// values.  The diagonal blocks are evaluated from the kernel: A(J_B, J_B) with the
+// diagonal rule at a leaf; above the leaves the entries between different children
+// only (a child's own block belongs to the finer level).
+constexpr int kMvCols = 16;        // right-hand-side columns per workgroup
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_mv_up(const MvBox *__restrict__ boxes,
+                                                    S *__restrict__ W, int nrhs,
+                                                    S *__restrict__ save) {
+  const MvBox &B = boxes[blockIdx.x];
+  const int k = B.k, r = B.r;
+  const int a = blockIdx.y * kThreads + threadIdx.x;      // skeleton row of the box
+  const int c0 = blockIdx.z * kMvCols;
+  if (a >= k) return;
+  const int nc = min(kMvCols, nrhs - c0);
+  const S *T = reinterpret_cast<const S *>(B.T);
+  const int32_t *idx = B.idx;
+  S *Wa = W + (int64_t)idx[a] * nrhs + c0;
+  S *sv = save + (B.save_off + a) * (int64_t)nrhs + c0;
+  S acc[kMvCols];
+#pragma unroll
+  for (int c = 0; c < kMvCols; ++c) acc[c] = c < nc ? Wa[c] : S(0.0);
+#pragma unroll
+  for (int c = 0; c < kMvCols; ++c)
+    if (c < nc) sv[c] = acc[c];
+  for (int q = 0; q < r; ++q) {
+    const S t = T[a + (int64_t)k * q];
+    const S *Wq = W + (int64_t)idx[k + q] * nrhs + c0;
+#pragma unroll
+    for (int c = 0; c < kMvCols; ++c)
+      if (c < nc) acc[c] += t * Wq[c];
+  }
+#pragma unroll
+  for (int c = 0; c < kMvCols; ++c)
+    if (c < nc) Wa[c] = acc[c];
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_mv_lift(const MvBox *__restrict__ boxes,
+                                                      S *__restrict__ Y, int nrhs) {
+  const MvBox &B = boxes[blockIdx.x];
+  const int k = B.k, r = B.r;
+  const int q = blockIdx.y * kThreads + threadIdx.x;      // redundant row of the box
+  const int c0 = blockIdx.z * kMvCols;
+  if (q >= r) return;
+  const int nc = min(kMvCols, nrhs - c0);
+  const S *T = reinterpret_cast<const S *>(B.T);
+  const int32_t *idx = B.idx;
+  S acc[kMvCols];
+#pragma unroll
+  for (int c = 0; c < kMvCols; ++c) acc[c] = S(0.0);
+  for (int a = 0; a < k; ++a) {
+    const S t = T[a + (int64_t)k * q];
+    const S *Ya = Y + (int64_t)idx[a] * nrhs + c0;
+#pragma unroll
+    for (int c = 0; c < kMvCols; ++c)
+      if (c < nc) acc[c] += t * Ya[c];
+  }
+  S *Yq = Y + (int64_t)idx[k + q] * nrhs + c0;
+#pragma unroll
+  for (int c = 0; c < kMvCols; ++c)
+    if (c < nc) Yq[c] = acc[c];
+}
+
+__device__ __forceinline__ int mv_child_of(const MvBox &B, int64_t g) {
+  int c = 0;
+  for (int q = 1; q < B.nchild; ++q) c += g >= B.child_begin[q];
+  return c;
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_mv_diag(const MvBox *__restrict__ boxes,
+                                                      const ProbDev *__restrict__ probs,
+                                                      const S *__restrict__ W,
+                                                      const S *__restrict__ save,
+                                                      S *__restrict__ Y, int nrhs) {
+  const MvBox &B = boxes[blockIdx.x];
+  const ProbDev &P = probs[B.prob];
+  const int k = B.k, n = B.k + B.r;
+  const int i = blockIdx.y * kThreads + threadIdx.x;      // local row (s, then r)
+  const int c0 = blockIdx.z * kMvCols;
+  if (i >= n) return;
+  const int nc = min(kMvCols, nrhs - c0);
+  const int32_t *idx = B.idx;
+  const int gi = idx[i];
+  const int ci = B.leaf ? 0 : mv_child_of(B, gi);
+  double ti[3];
+  load_pt(P, gi, ti);
+  S acc[kMvCols];
+#pragma unroll
+  for (int c = 0; c < kMvCols; ++c) acc[c] = S(0.0);
+  for (int j = 0; j < n; ++j) {
+    const int gj = idx[j];
+    if (!B.leaf && mv_child_of(B, gj) == ci) continue;
+    S d;
+    if (gj == gi) {
+      d = diag_entry<S>(P, gi);
+    } else {
+      double sj[3], nj[3];
+      load_pt(P, gj, sj);
+      load_nrm(P, gj, nj);
+      d = kernel_val<S>(P, ti, sj, nj) * P.w[gj];
+    }
+    const S *xj = j < k ? save + (B.save_off + j) * (int64_t)nrhs + c0
+                        : W + (int64_t)gj * nrhs + c0;
+#pragma unroll
+    for (int c = 0; c < kMvCols; ++c)
+      if (c < nc) acc[c] += d * xj[c];
+  }
+  S *Yi = Y + (int64_t)gi * nrhs + c0;
+#pragma unroll
+  for (int c = 0; c < kMvCols; ++c)
+    if (c < nc) Yi[c] += acc[c];
+}
+
+namespace {
+dim3 mv_grid(int count, int rows, int nrhs) {
+  return dim3(count, (rows + kThreads - 1) / kThreads, (nrhs + kMvCols - 1) / kMvCols);
+}
+}  // namespace
+
+void launch_mv_up(bool cplx, const MvBox *boxes, int count, int max_k, double *W, int nrhs,
+                  double *save, hipStream_t st) {
+  if (count <= 0 || max_k <= 0 || nrhs <= 0) return;
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_mv_up<S>, mv_grid(count, max_k, nrhs), dim3(kThreads), 0, st, boxes,
+                       reinterpret_cast<S *>(W), nrhs, reinterpret_cast<S *>(save));
+  });
+  check_launch("k_mv_up");
+}
+
+void launch_mv_lift(bool cplx, const MvBox *boxes, int count, int max_r, double *Y, int nrhs,
+                    hipStream_t st) {
+  if (count <= 0 || max_r <= 0 || nrhs <= 0) return;
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_mv_lift<S>, mv_grid(count, max_r, nrhs), dim3(kThreads), 0, st, boxes,
+                       reinterpret_cast<S *>(Y), nrhs);
+  });
+  check_launch("k_mv_lift");
+}
+
+void launch_mv_diag(bool cplx, const MvBox *boxes, int count, int max_n, const ProbDev *probs,
+                    const double *W, const double *save, double *Y, int nrhs, hipStream_t st) {
+  if (count <= 0 || max_n <= 0 || nrhs <= 0) return;
+  with_scalar(cplx, [&](auto z) {
+    using S = decltype(z);
+    hipLaunchKernelGGL(k_mv_diag<S>, mv_grid(count, max_n, nrhs), dim3(kThreads), 0, st, boxes,
+                       probs, reinterpret_cast<const S *>(W), reinterpret_cast<const S *>(save),
+                       reinterpret_cast<S *>(Y), nrhs);
+  });
+  check_launch("k_mv_diag");
 }
 
 }  // namespace rs

@@ -28,6 +28,9 @@ struct ProbDev {
   double ratio;            // proxy radius / box side
   double kwave;            // Helmholtz wavenumber
   double eta;              // Helmholtz combined-field coupling
+  int32_t id_mode;         // rs_id_mode
+  int32_t oversample;      // sketch rows beyond n (RS_ID_SKETCH)
+  uint64_t sketch_seed;
 };
 
 // One box of one level, for the compression kernels (assembly + ID).
@@ -43,7 +46,7 @@ struct CompBox {
   double rho;              // proxy radius
   int64_t order_off;       // ints: out, sorted skeleton then redundant local positions
   int32_t kslot;           // index of this box's rank in the rank array
-  int32_t pad;
+  int32_t box;             // tree box index (the sketch's counter)
   double *T;               // out: T (k x (n-k)), the head of the box's factor slot
 };
 
@@ -73,6 +76,23 @@ struct SweepBox {
   const double *G;         // r x r  (X_rr^{-1})
   const double *E;         // k x r  (X_sr G)
   const double *F;         // r x k  (G X_rs)
+};
+
+// One box of one level for the compressed forward operator (rs_matvec).  idx lists the
+// box's active DOFs as in SweepBox (k skeletons, then r redundant); save_off is the
+// box's first row in the buffer that keeps the level's skeleton values for the
+// downward pass.  Children's tree ranges start at child_begin[0..nchild) (ascending):
+// above the leaves a DOF belongs to the child whose range holds its tree position.
+struct MvBox {
+  int32_t k, r;
+  const int32_t *idx;
+  const double *T;         // k x r, scalars of the problem's type (null when k or r is 0)
+  int64_t save_off;
+  int32_t prob;
+  int32_t leaf;
+  int32_t nchild;
+  int32_t pad;
+  int64_t child_begin[8];
 };
 
 // A run of consecutive blocks of a multi-handle sweep launch: boxes[0..count) of one
@@ -137,11 +157,26 @@ size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m);
 constexpr int kFusedMaxN = 80;
 constexpr int kFusedMaxM = 512;
 bool fused_class(bool cplx, int n, int m);
+// Randomized ID: comp_id[i] is comp[i] with m the sketch's row count and M_off its
+// sketch Y (ell x n, column-major, in the same arena); boxes with ell = m are skipped
+// (their comp_id entry points at M itself).  max_tiles bounds ceil(ell/16) ceil(n/16).
+void launch_sketch(bool cplx, const CompBox *comp, const CompBox *comp_id, int first, int count,
+                   const ProbDev *probs, double *Marena, int max_tiles, hipStream_t st);
 int fused_variant_of(int n, int m);     // register-resident variant of a launch's largest box
 bool fused_small(int n, int m);         // fits the 256-thread variants
 void launch_compress_fused(const CompBox *boxes, int first, int count, const ProbDev *probs,
                            const int32_t *pool, double *Rarena, int32_t *order_pool,
                            int32_t *ranks, int max_n, int max_m, int max_npx, hipStream_t st);
+// Roots with at least kWideRootMinN unknowns are skipped by k_diag_factor and factored
+// by launch_root_wide instead: assembly by many workgroups, then a blocked Gauss-Jordan
+// inversion with one launch per panel of 16 pivot steps and one launch of many
+// workgroups per rank-16 update.  box: the root's device descriptor; work + work_off:
+// its workspace (n^2 + 16 n scalars); G: its slot (n x n inverse); err: the factor's
+// error index (err_idx written on a zero or non-finite pivot).
+constexpr int kWideRootMinN = 1536;
+void launch_root_wide(bool cplx, const FacBox *box, int n, const ProbDev *probs,
+                      const int32_t *pool, double *work, int64_t work_off, double *G,
+                      int32_t *err, int err_idx, hipStream_t st);
 // Global workspace scalars reserved for a box of n DOFs in k_diag_factor.
 size_t diag_work_elems(int n);
 void launch_permute_in(bool cplx, const double *B, int64_t ldb, double *W, const int64_t *perm,
@@ -172,6 +207,19 @@ int64_t wide_scratch_doubles(int count, int max_n, int max_r, int nrhs, bool cpl
 void launch_wide_level(bool cplx, bool up, const SweepBox *boxes, int count, int max_n,
                        int max_k, int max_r, double *W, int nrhs, double *scratch,
                        int64_t scratch_doubles, hipStream_t st);
+
+// Compressed forward operator (one launch per kernel per level; grid.x = boxes, grid.y
+// = row blocks of 256, grid.z = column tiles of 16).  W, Y, save: tree order, row-major
+// (n x nrhs and total-skeletons x nrhs), scalars of the problem's type.
+//   up:   save[box rows] <- W[s];  W[s] <- W[s] + T W[r]
+//   lift: Y[r] <- T^T Y[s]
+//   diag: Y[J] += S_d(J, J) x_J with x_s from save (x_J = W[J] when k = 0)
+void launch_mv_up(bool cplx, const MvBox *boxes, int count, int max_k, double *W, int nrhs,
+                  double *save, hipStream_t st);
+void launch_mv_lift(bool cplx, const MvBox *boxes, int count, int max_r, double *Y, int nrhs,
+                    hipStream_t st);
+void launch_mv_diag(bool cplx, const MvBox *boxes, int count, int max_n, const ProbDev *probs,
+                    const double *W, const double *save, double *Y, int nrhs, hipStream_t st);
 
 // ------------------------------------------------------------------ tuning table
 // Tile widths of the MFMA-class sweep kernels per bucket (class flag, scalar size,

@@ -129,7 +129,7 @@ struct PinnedBuf {
 // in two sets used by alternate levels: the factorization of one level runs on a second
 // stream while the next level is compressed.
 struct Scratch {
-  DevBuf pool, comp, fac, M, order, ranks, work, err, probs, partials;
+  DevBuf pool, comp, comp_id, fac, M, order, ranks, work, err, probs, partials;
   DevBuf pool2[2], order2[2], ranks2[2], fac2[2];
   PinnedBuf hfac[2];
   hipStream_t side = nullptr;                 // box factorizations of compressed levels
@@ -172,6 +172,8 @@ struct ProbState {
   int R = 0, Rc = 0;
   int npx = 0;
   bool log_kernel = false;
+  bool sketch = false;       // randomized ID: every box compressed through its row sketch
+  int oversample = 0;
 };
 
 int cheb(const Tree &t, int a, int b) {
@@ -267,7 +269,7 @@ void setup_problem(ProbState &ps, hipStream_t st) {
   h->dim = dim;
   h->n = n;
   h->kind = k.kind;
-  h->cplx = k.kind == RS_HELM2D_CFIE;
+  h->cplx = k.kind == RS_HELM2D_CFIE || k.kind == RS_HELM3D_SL;
   std::vector<double> host((size_t)n * (2 * dim + 2), 0.0);
   double *hx = host.data();
   double *hn = hx + (size_t)dim * n;
@@ -304,7 +306,12 @@ void setup_problem(ProbState &ps, hipStream_t st) {
   P.log_kernel = (k.kind == RS_LAP2D_SL || k.kind == RS_HELM2D_CFIE) ? 1 : 0;
   P.eps = ps.req->eps;
   P.ratio = k.proxy_ratio;
-  P.kwave = k.kind == RS_HELM2D_CFIE ? k.wavenumber : 0.0;
+  P.kwave = (k.kind == RS_HELM2D_CFIE || k.kind == RS_HELM3D_SL) ? k.wavenumber : 0.0;
+  P.id_mode = k.id_mode;
+  P.oversample = k.oversample;
+  P.sketch_seed = k.sketch_seed;
+  ps.sketch = k.id_mode == RS_ID_SKETCH;
+  ps.oversample = k.oversample;
   P.eta = k.kind == RS_HELM2D_CFIE ? k.eta : 0.0;
   ps.npx = k.proxy_points;
   ps.log_kernel = P.log_kernel != 0;
@@ -546,7 +553,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         const ProbState &P = *items[i].ps;
         const int n = (int)P.J[items[i].box].size();
         const int m = 2 * (int)near_all[i].size() + 2 * P.npx + (P.log_kernel ? 2 : 0);
-        fz[i] = fused_class(cplx, n, m) ? (fused_small(n, m) ? 2 : 1) : 0;
+        fz[i] = (!P.sketch && fused_class(cplx, n, m)) ? (fused_small(n, m) ? 2 : 1) : 0;
         nf += fz[i] > 0;
         nfs += fz[i] == 2;
       }
@@ -613,6 +620,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       cb.order_off = order_total;
       order_total += cb.n;
       cb.kslot = i;
+      cb.box = b;
       double *slot = P.h->arena.alloc_n<double>(slot_bound(cb.n) * es);
       cb.T = slot;
       P.h->box_slot[b] = slot;
@@ -620,6 +628,28 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       max_n = std::max(max_n, cb.n);
       max_m_step = std::max(max_m_step, cb.m);
       max_m_seen = std::max<int64_t>(max_m_seen, cb.m);
+    }
+    // randomized ID: the direct-class boxes of sketching problems are compressed through
+    // Y = Omega M (ell = min(m, n + oversample) rows) placed after the blocks in the arena
+    std::vector<CompBox> comp_id;
+    int max_m_id = max_m_d, max_sketch_tiles = 0;
+    bool any_sketch = false;
+    for (int i = nf; i < cnt; ++i) any_sketch = any_sketch || items[i].ps->sketch;
+    if (any_sketch) {
+      comp_id = comp;
+      max_m_id = 0;
+      for (int i = nf; i < cnt; ++i) {
+        CompBox &ci = comp_id[i];
+        const ProbState &P = *items[i].ps;
+        const int ell = P.sketch ? std::min<int64_t>(ci.m, (int64_t)ci.n + P.oversample) : ci.m;
+        if (ell < ci.m) {
+          ci.m = ell;
+          ci.M_off = M_total;
+          M_total += (int64_t)ell * ci.n;
+          max_sketch_tiles = std::max(max_sketch_tiles, ((ell + 15) / 16) * ((ci.n + 15) / 16));
+        }
+        max_m_id = std::max(max_m_id, ci.m);
+      }
     }
     std::vector<int32_t> pool(pool_total);
     parallel_for(cnt, [&](int i) {
@@ -637,6 +667,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     if (diag_pending[par]) RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_diag[par], 0));
     upload(Dpool, pool, st);
     upload(S.comp, comp, st);
+    if (any_sketch) upload(S.comp_id, comp_id, st);
     S.M.ensure(std::max<int64_t>(M_total, 1) * sizeof(double) * es);
     Dorder.ensure(std::max<int64_t>(order_total, 1) * sizeof(int32_t));
     Dranks.ensure(std::max(cnt, 1) * sizeof(int32_t));
@@ -644,6 +675,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     S.partials.ensure((size_t)std::max(cnt - nf, 1) * assemble_chunks(max_n_d, max_m_d) *
                       sizeof(double));
     const CompBox *d_comp = S.comp.as<CompBox>();
+    const CompBox *d_comp_id = any_sketch ? S.comp_id.as<CompBox>() : d_comp;
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         if (i < nf) {
@@ -659,8 +691,12 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                           max_npx, comp[i].n, comp[i].m, S.partials.as<double>(), st);
         }
         ProfScope ps_(RS_K_ID, st);
-        launch_cpqr_id(cplx, d_comp, i, 1, d_probs, S.M.as<double>(), Dorder.as<int32_t>(),
-                       Dranks.as<int32_t>(), comp[i].n, comp[i].m, st);
+        if (any_sketch)
+          launch_sketch(cplx, d_comp, d_comp_id, i, 1, d_probs, S.M.as<double>(),
+                        ((comp_id[i].m + 15) / 16) * ((comp_id[i].n + 15) / 16), st);
+        launch_cpqr_id(cplx, d_comp_id, i, 1, d_probs, S.M.as<double>(), Dorder.as<int32_t>(),
+                       Dranks.as<int32_t>(), comp[i].n, any_sketch ? comp_id[i].m : comp[i].m,
+                       st);
       }
     } else {
       // the classes touch disjoint boxes: with more than one present, the small fused
@@ -693,8 +729,11 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                           dst);
         }
         ProfScope ps_(RS_K_ID, dst);
-        launch_cpqr_id(cplx, d_comp, nf, cnt - nf, d_probs, S.M.as<double>(),
-                       Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_d, max_m_d, dst);
+        if (any_sketch)
+          launch_sketch(cplx, d_comp, d_comp_id, nf, cnt - nf, d_probs, S.M.as<double>(),
+                        max_sketch_tiles, dst);
+        launch_cpqr_id(cplx, d_comp_id, nf, cnt - nf, d_probs, S.M.as<double>(),
+                       Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_d, max_m_id, dst);
       }
       if (both) {
         RS_HIP_CHECK(hipEventRecord(S.ev_aux, S.aux));
@@ -767,6 +806,10 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     }
     keep_alive.clear();            // the uploads queued before this wait have completed
     auto tp2 = Clock::now();
+    for (int i = 0; i < cnt; ++i)
+      if (ranks[i] < 0 || ranks[i] > comp[i].n)
+        throw DeviceError("interpolative decomposition did not complete (a multi-workgroup "
+                          "barrier exceeded its wait limit)", hipErrorLaunchTimeOut);
     // skeleton lists (the next level's active sets) and profiler work counts
     Work w_asm, w_id, w_fac;
     for (int i = 0; i < cnt; ++i) {
@@ -777,7 +820,9 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         w_id += work_fused(cb.m, cb.n, k);
       } else {
         w_asm += work_assemble(cb.m, cb.n, cplx);
-        w_id += work_id(cb.m, cb.n, k, cplx);
+        const int ell = any_sketch ? comp_id[i].m : cb.m;
+        w_id += work_id(ell, cb.n, k, cplx);
+        if (ell < cb.m) w_id.flops += 2.0 * ell * cb.m * cb.n * (cplx ? 2.0 : 1.0);
       }
       w_fac += work_factor(cb.n, k, cplx);
     }
@@ -847,16 +892,28 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       for (const FacBox &f : fac) w += work_factor(f.n, 0, cplx);
       prof_add_work(RS_K_FACTOR, w);
     }
+    // roots below the wide class: one workgroup each (k_diag_factor skips wide roots)
+    int max_n_narrow = 0;
+    for (const FacBox &f : fac)
+      if (f.n < kWideRootMinN) max_n_narrow = std::max(max_n_narrow, f.n);
     if (per_box) {
       for (int i = 0; i < np; ++i) {
+        if (fac[i].n >= kWideRootMinN) continue;
         ProfScope ps_(RS_K_FACTOR, st);
         launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
                            S.work.as<double>(), S.err.as<int32_t>(), err_base, fac[i].n, st);
       }
-    } else {
+    } else if (max_n_narrow > 0) {
       ProfScope ps_(RS_K_FACTOR, st);
       launch_diag_factor(cplx, d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
-                         S.work.as<double>(), S.err.as<int32_t>(), err_base, max_n, st);
+                         S.work.as<double>(), S.err.as<int32_t>(), err_base, max_n_narrow, st);
+    }
+    for (int i = 0; i < np; ++i) {
+      if (fac[i].n < kWideRootMinN) continue;
+      ProfScope ps_(RS_K_FACTOR, st);
+      launch_root_wide(cplx, d_fac + i, fac[i].n, d_probs, S.pool.as<int32_t>(),
+                       S.work.as<double>(), fac[i].work_off, fac[i].slot, S.err.as<int32_t>(),
+                       err_base + i, st);
     }
     {
       auto tw = Clock::now();
@@ -909,6 +966,10 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     rs_factor_s *h = handles[p].get();
     h->box_J = std::move(ps[p].J);          // per-box active sets and skeletons (queries)
     h->box_skel = std::move(ps[p].skel);
+    const Tree &tr = *ps[p].t;
+    h->tree_first_child.assign(tr.first_child.begin(), tr.first_child.end());
+    h->tree_nchild.assign(tr.nchild.begin(), tr.nchild.end());
+    h->tree_begin = tr.begin;
     h->stats.n = h->n;
     h->stats.nbox = ps[p].t->nbox();
     h->stats.maxdepth = ps[p].t->maxdepth;
@@ -933,7 +994,8 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
   // groups (each problem's arithmetic is the same either way).
   std::vector<int> idx[2];
   for (int i = 0; i < (int)reqs.size(); ++i)
-    idx[reqs[i].k->kind == RS_HELM2D_CFIE ? 1 : 0].push_back(i);
+    idx[(reqs[i].k->kind == RS_HELM2D_CFIE || reqs[i].k->kind == RS_HELM3D_SL) ? 1 : 0]
+        .push_back(i);
   if (idx[0].empty() || idx[1].empty()) {
     factor_group(reqs, launch_mode, st, out);
     return;
@@ -971,6 +1033,94 @@ int64_t wide_scratch_for(const rs_factor_s *h, int nrhs) {
 }
 }  // namespace
 
+namespace {
+MvBox mv_box(const rs_factor_s *h, int b, const SweepBox &sb, int64_t save_off) {
+  MvBox m{};
+  m.k = sb.k;
+  m.r = sb.r;
+  m.idx = sb.idx;
+  m.T = sb.T;
+  m.save_off = save_off;
+  m.prob = 0;
+  m.nchild = h->tree_nchild[b];
+  m.leaf = m.nchild == 0 ? 1 : 0;
+  if (m.nchild > 8) throw std::runtime_error("matvec: a box has more than 8 children");
+  for (int c = 0; c < m.nchild; ++c) m.child_begin[c] = h->tree_begin[h->tree_first_child[b] + c];
+  return m;
+}
+
+MvLevel mv_upload(rs_factor_s *h, const std::vector<MvBox> &v, hipStream_t st) {
+  MvLevel L;
+  L.count = (int)v.size();
+  for (const MvBox &m : v) {
+    L.max_k = std::max(L.max_k, (int)m.k);
+    L.max_r = std::max(L.max_r, (int)m.r);
+    L.max_n = std::max(L.max_n, (int)(m.k + m.r));
+  }
+  if (!v.empty()) {
+    L.d = h->arena.alloc_n<MvBox>((int64_t)v.size());
+    RS_HIP_CHECK(hipMemcpyAsync(L.d, v.data(), v.size() * sizeof(MvBox), hipMemcpyHostToDevice, st));
+  }
+  return L;
+}
+
+// Builds the handle's forward-operator descriptors once (thread-safe).
+MvPlan &mv_plan(rs_factor_s *h, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(h->mv_mu);
+  if (h->mv) return *h->mv;
+  auto plan = std::make_unique<MvPlan>();
+  int64_t save = 0;
+  for (const LevelRec &lv : h->levels) {
+    std::vector<MvBox> v;
+    for (size_t i = 0; i < lv.sweep.size(); ++i) {
+      v.push_back(mv_box(h, lv.boxes[i], lv.sweep[i], save));
+      save += lv.sweep[i].k;
+    }
+    plan->levels.push_back(mv_upload(h, v, st));
+  }
+  plan->root = mv_upload(h, {mv_box(h, 0, h->root.sweep[0], 0)}, st);
+  plan->save_rows = save;
+  plan->d_prob = h->arena.alloc_n<ProbDev>(1);
+  RS_HIP_CHECK(hipMemcpyAsync(plan->d_prob, &h->prob, sizeof(ProbDev), hipMemcpyHostToDevice, st));
+  RS_HIP_CHECK(hipStreamSynchronize(st));     // host descriptor arrays go out of scope
+  h->mv = std::move(plan);
+  return *h->mv;
+}
+}  // namespace
+
+void matvec_one(rs_factor_s *h, const void *X, int64_t ldx, void *Y, int64_t ldy, int nrhs,
+                hipStream_t st) {
+  if (nrhs == 0) return;
+  const MvPlan &P = mv_plan(h, st);
+  const int64_t n = h->n;
+  const bool cplx = h->cplx;
+  const size_t es = cplx ? 2 : 1;
+  const size_t cols = (size_t)nrhs * es * sizeof(double);
+  double *W = nullptr, *Yw = nullptr, *save = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)n * cols, st));
+  struct Freer {
+    double *p;
+    hipStream_t st;
+    ~Freer() {
+      if (p) (void)hipFreeAsync(p, st);
+    }
+  } f1{W, st};
+  RS_HIP_CHECK(hipMallocAsync((void **)&Yw, (size_t)n * cols, st));
+  Freer f2{Yw, st};
+  RS_HIP_CHECK(hipMallocAsync((void **)&save, std::max<size_t>((size_t)P.save_rows * cols, 8), st));
+  Freer f3{save, st};
+  launch_permute_in(cplx, static_cast<const double *>(X), ldx, W, h->d_perm, n, nrhs, st);
+  RS_HIP_CHECK(hipMemsetAsync(Yw, 0, (size_t)n * cols, st));
+  for (const MvLevel &L : P.levels)
+    launch_mv_up(cplx, L.d, L.count, L.max_k, W, nrhs, save, st);
+  launch_mv_diag(cplx, P.root.d, P.root.count, P.root.max_n, P.d_prob, W, save, Yw, nrhs, st);
+  for (auto it = P.levels.rbegin(); it != P.levels.rend(); ++it) {
+    launch_mv_lift(cplx, it->d, it->count, it->max_r, Yw, nrhs, st);
+    launch_mv_diag(cplx, it->d, it->count, it->max_n, P.d_prob, W, save, Yw, nrhs, st);
+  }
+  launch_permute_out(cplx, static_cast<double *>(Y), ldy, Yw, h->d_perm, n, nrhs, st);
+}
+
 bool is_device_buffer(const void *p, size_t bytes) {
   hipPointerAttribute_t a{};
   if (hipPointerGetAttributes(&a, p) != hipSuccess) {
@@ -994,34 +1144,30 @@ bool is_device_buffer(const void *p, size_t bytes) {
   return true;
 }
 
-void note_inflight(rs_factor_s *h, hipStream_t st) {
-  hipEvent_t ev = nullptr;
-  RS_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  const hipError_t e = hipEventRecord(ev, st);
-  if (e != hipSuccess) {
-    (void)hipEventDestroy(ev);
-    RS_HIP_CHECK(e);
-  }
-  std::lock_guard<std::mutex> lock(h->inflight_mu);
-  // drop completed events from the front (they complete in issue order per stream;
-  // a stalled one on another stream only delays the pruning)
-  size_t keep = 0;
-  for (hipEvent_t x : h->inflight) {
-    if (hipEventQuery(x) == hipErrorNotReady) h->inflight[keep++] = x;
-    else (void)hipEventDestroy(x);
-  }
-  h->inflight.resize(keep);
-  h->inflight.push_back(ev);
+std::shared_ptr<SharedEvent> record_completion(hipStream_t st) {
+  auto e = std::make_shared<SharedEvent>();
+  RS_HIP_CHECK(hipEventCreateWithFlags(&e->ev, hipEventDisableTiming));
+  RS_HIP_CHECK(hipEventRecord(e->ev, st));
+  return e;
 }
+
+void note_inflight(rs_factor_s *h, const std::shared_ptr<SharedEvent> &e) {
+  std::lock_guard<std::mutex> lock(h->inflight_mu);
+  // drop completed events (a stalled one on another stream only delays the pruning)
+  size_t keep = 0;
+  for (auto &x : h->inflight)
+    if (hipEventQuery(x->ev) == hipErrorNotReady) h->inflight[keep++] = x;
+  h->inflight.resize(keep);
+  h->inflight.push_back(e);
+}
+
+void note_inflight(rs_factor_s *h, hipStream_t st) { note_inflight(h, record_completion(st)); }
 
 bool has_inflight(rs_factor_s *h) {
   std::lock_guard<std::mutex> lock(h->inflight_mu);
   size_t keep = 0;
-  for (hipEvent_t x : h->inflight) {
-    const hipError_t q = hipEventQuery(x);
-    if (q == hipErrorNotReady) h->inflight[keep++] = x;
-    else (void)hipEventDestroy(x);
-  }
+  for (auto &x : h->inflight)
+    if (hipEventQuery(x->ev) == hipErrorNotReady) h->inflight[keep++] = x;
   h->inflight.resize(keep);
   return keep > 0;
 }
@@ -1029,12 +1175,9 @@ bool has_inflight(rs_factor_s *h) {
 void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
                hipStream_t st) {
   if (nrhs == 0) return;
-  const int64_t n = h->n;
-  const bool cplx = h->cplx;
-  const int es = cplx ? 2 : 1;
-  double *B = static_cast<double *>(Bv);
+  const int es = h->cplx ? 2 : 1;
   double *W = nullptr;
-  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)n * nrhs * sizeof(double) * es, st));
+  RS_HIP_CHECK(hipMallocAsync((void **)&W, (size_t)h->n * nrhs * sizeof(double) * es, st));
   struct Freer {
     double *W;
     hipStream_t st;
@@ -1047,6 +1190,29 @@ void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
   if (wide_sz > 0)
     RS_HIP_CHECK(hipMallocAsync((void **)&wide, (size_t)wide_sz * sizeof(double), st));
   Freer wide_freer{wide, st};
+  solve_one_into(h, Bv, ldb, nrhs, launch_mode, st, W, wide, wide_sz);
+}
+
+int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs) {
+  int64_t m = 0;
+  auto one = [&](const LevelRec &lv) {
+    if ((int)lv.sweep.size() > lv.n_small && lv.max_r_large > 0)
+      m = std::max(m, wide_scratch_doubles(1, lv.max_n_large, lv.max_r_large, nrhs, h->cplx));
+  };
+  one(h->root);
+  for (const LevelRec &lv : h->levels) one(lv);
+  return m;
+}
+
+int64_t solve_wide_doubles(const rs_factor_s *h, int nrhs) { return wide_scratch_for(h, nrhs); }
+
+void solve_one_into(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
+                    hipStream_t st, double *W, double *wide, int64_t wide_sz) {
+  if (nrhs == 0) return;
+  const int64_t n = h->n;
+  const bool cplx = h->cplx;
+  const int es = cplx ? 2 : 1;
+  double *B = static_cast<double *>(Bv);
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
   const bool prof = prof_on();
   Work wperm;

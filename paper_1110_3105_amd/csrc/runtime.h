@@ -71,6 +71,28 @@ struct LevelRec {
   void partition_classes(int mfma_limit);
 };
 
+// A completion event shared by the handles one call touched (destroyed with the last
+// reference).
+struct SharedEvent {
+  hipEvent_t ev = nullptr;
+  ~SharedEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+// Device descriptors of the compressed forward operator, built on a handle's first
+// rs_matvec call (per compressed level, finest first, and the root).
+struct MvLevel {
+  MvBox *d = nullptr;
+  int count = 0, max_k = 0, max_r = 0, max_n = 0;
+};
+struct MvPlan {
+  std::vector<MvLevel> levels;
+  MvLevel root;
+  ProbDev *d_prob = nullptr;
+  int64_t save_rows = 0;           // skeleton rows kept for the downward pass
+};
+
 }  // namespace rs
 
 struct rs_factor_s {
@@ -91,7 +113,12 @@ struct rs_factor_s {
   rs_stats stats{};
   std::atomic<int> busy{0};
   std::mutex inflight_mu;
-  std::vector<hipEvent_t> inflight;      // completion events of enqueued solves
+  std::vector<std::shared_ptr<rs::SharedEvent>> inflight;   // completions of enqueued solves
+  // tree structure kept for the compressed forward operator (rs_matvec)
+  std::vector<int32_t> tree_first_child, tree_nchild;
+  std::vector<int64_t> tree_begin;
+  std::mutex mv_mu;
+  std::unique_ptr<rs::MvPlan> mv;
 };
 
 namespace rs {
@@ -112,6 +139,21 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
 // B: device, column-major, scalars of the handle's type (complex128 as re/im pairs).
 void solve_one(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_mode,
                hipStream_t st);
+
+// Y = A_eps X (the compressed forward operator of the handle's compression), X and Y
+// device memory, column-major, caller order.  Enqueued on st.
+void matvec_one(rs_factor_s *h, const void *X, int64_t ldx, void *Y, int64_t ldy, int nrhs,
+                hipStream_t st);
+
+// solve_one with caller-provided device workspace: W holds n * nrhs scalars of the
+// handle's type; wide holds wide_sz doubles, at least solve_wide_min_doubles(h, nrhs)
+// when that is positive (wide boxes are swept in chunks that fit).  Allocates nothing.
+void solve_one_into(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_mode,
+                    hipStream_t st, double *W, double *wide, int64_t wide_sz);
+// Smallest wide-class staging (doubles) a solve of nrhs columns can run with, and the
+// size solve_one allocates (every wide box of a level at once, up to a cap).
+int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs);
+int64_t solve_wide_doubles(const rs_factor_s *h, int nrhs);
 
 struct SolveRequest {
   rs_factor_s *h;
@@ -153,8 +195,11 @@ struct UserError {
 // allocation (checked where the runtime reports the allocation's extent).
 bool is_device_buffer(const void *p, size_t bytes);
 
-// Solves issued on a handle: an event is recorded after each one on its stream, so
-// that rs_free can tell whether any is still queued or running.
+// Solves issued on a handle: an event is recorded after each call on its stream, so
+// that rs_free can tell whether any is still queued or running.  One event per call,
+// shared by every handle the call touched.
+std::shared_ptr<SharedEvent> record_completion(hipStream_t st);
+void note_inflight(rs_factor_s *h, const std::shared_ptr<SharedEvent> &e);
 void note_inflight(rs_factor_s *h, hipStream_t st);
 // True if a recorded solve has not completed (completed events are released).
 bool has_inflight(rs_factor_s *h);

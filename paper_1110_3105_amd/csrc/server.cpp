@@ -106,7 +106,10 @@ size_t handle_bytes(rs_handle h) {
 // per-kernel constant (2D Laplace: ~4 KB per unknown at eps = 1e-9; complex Helmholtz
 // entries are twice the size and its ranks higher; 3D larger).
 size_t factor_estimate(const rs_kernel &k, int64_t n) {
-  const size_t per = k.kind == RS_HELM2D_CFIE ? 16384 : k.dim == 2 ? 6144 : 65536;
+  const size_t per = k.kind == RS_HELM3D_SL    ? 131072
+                     : k.kind == RS_HELM2D_CFIE ? 16384
+                     : k.dim == 2               ? 6144
+                                                : 65536;
   return (size_t)n * per + (size_t(64) << 20);
 }
 

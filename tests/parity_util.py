@@ -6,20 +6,57 @@ from oracle.rs import compression_block
 U = np.finfo(np.float64).eps
 
 
+def identical_skeletons(h, F):
+    """True if every compressed box has the oracle's rank and skeleton set (then both
+    sides compress to the same A_eps, whatever the tie flags say)."""
+    ks, sk = h.box_skeletons()
+    for b, r in F.records.items():
+        if ks[b] != r.k or not np.array_equal(np.sort(sk[b]), r.skel):
+            return False
+    return True
+
+
+def uncertain_boxes(depth, children, own_tie, active, near):
+    """Boxes whose compression block may legitimately differ between two correct
+    implementations: a box is uncertain if its own pivot sequence or rank decision is
+    tied, if a child is uncertain (its active set then may differ), or if one of its
+    active or near DOFs may or may not be active at its depth -- a DOF of an uncertain
+    box at a finer depth, whose skeleton choice decides whether it survives.
+
+    depth, children: per box; own_tie: box -> bool for the compressed boxes; active(b):
+    the box's active DOFs (array); near(b, dofs): True if a DOF of the set `dofs` is in
+    box b's near field."""
+    bad = set()
+    pending = set()          # DOFs whose activity at the current depth is uncertain
+    by_depth = {}
+    for b in own_tie:
+        by_depth.setdefault(int(depth[b]), []).append(b)
+    for d in sorted(by_depth, reverse=True):
+        level_bad = []
+        for b in by_depth[d]:
+            u = bool(own_tie[b]) or any(c in bad for c in children[b])
+            if not u and pending:
+                u = bool(pending.intersection(active(b).tolist())) or near(b, pending)
+            if u:
+                level_bad.append(b)
+        for b in level_bad:
+            bad.add(b)
+            pending.update(active(b).tolist())
+    return bad
+
+
 def compare_skeletons(h, F, residual_every=1):
-    """Skeleton sets equal on every box whose subtree has no tie; returns
-    (#boxes compared, #boxes skipped because of a tie below or at them).
+    """Skeleton sets equal on every box that no tie can reach (uncertain_boxes); returns
+    (#boxes compared, #boxes skipped as uncertain).
 
     T agrees with the oracle's to within the conditioning of R11 (up to 1/eps), and the
     device's T satisfies the ID column-residual bound on the oracle's own block M.
     """
     ks, sk = h.box_skeletons()
     t = F.tree
-    tied = set()
-    for b in sorted(F.records, key=lambda b: -t.depth[b]):
-        r = F.records[b]
-        if r.idr.first_tie >= 0 or r.idr.near_threshold or any(c in tied for c in t.children[b]):
-            tied.add(b)
+    own = {b: (r.idr.first_tie >= 0 or r.idr.near_threshold) for b, r in F.records.items()}
+    tied = uncertain_boxes(t.depth, t.children, own, lambda b: F.records[b].J,
+                           lambda b, dofs: bool(dofs.intersection(F.records[b].near.tolist())))
     compared = 0
     for b, r in F.records.items():
         if b in tied:

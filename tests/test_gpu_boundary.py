@@ -58,17 +58,6 @@ def test_host_pointer_solve_matches_device(gpu_lib):
     assert np.array_equal(xv, xd[:, 2])
 
 
-def test_device_range_past_allocation_rejected(gpu_lib):
-    import torch
-    rs = gpu_lib
-    g, h = _star_dl(rs, 2000)
-    B = torch.zeros(g.n * 2 - 1, dtype=torch.float64, device="cuda")
-    # 2 columns of n rows need 2n entries; the allocation holds 2n - 1
-    with pytest.raises(rs.RSError) as e:
-        h.solve_ptr(B.data_ptr(), g.n, 2)
-    assert e.value.code == rs.RS_EINVAL
-
-
 def test_free_refused_while_solve_queued(gpu_lib):
     import torch
     rs = gpu_lib

@@ -191,3 +191,34 @@ def test_matvec_rows_equals_dense_rows(kind, chunk):
         got = dense.matvec_rows(p, rows, x, chunk=chunk)
         assert got.shape == ref.shape
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(A[rows]).sum(axis=1).max() * np.abs(x).max()
+
+
+def test_sphere_helmholtz_single_layer_eigenvalues():
+    # On the unit sphere the Helmholtz single layer maps the spherical harmonic Y_n to
+    # i k j_n(k) h_n(k) Y_n (h_n = j_n + i y_n, the outgoing spherical Hankel function):
+    # S_k[1] = i k j_0 h_0 = sin(k) e^{ik} / k and S_k[z] = i k j_1 h_1 z.  The flat-disc
+    # diagonal rule converges at first order in the mesh size, as for the Laplace kernel.
+    from scipy.special import spherical_jn, spherical_yn
+    k = 2 * np.pi * 3.18 / 2.0          # 3.18 wavelengths across the unit sphere
+    lam = [1j * k * spherical_jn(nn, k) * (spherical_jn(nn, k) + 1j * spherical_yn(nn, k))
+           for nn in (0, 1)]
+    assert abs(lam[0] - np.sin(k) * np.exp(1j * k) / k) < 1e-14
+    errs0, errs1 = [], []
+    for n in (512, 2048):
+        g = W.fibonacci_sphere(n)
+        A = dense.matrix(Problem("helm3d_sl", g.points, g.weights, wavenumber=k))
+        z = g.points[:, 2]
+        errs0.append(np.abs(A @ np.ones(n) - lam[0]).max())
+        errs1.append(np.abs(A @ z - lam[1] * z).max())
+    assert errs0[1] < 1e-2 and errs1[1] < 1e-2
+    assert errs0[0] / errs0[1] > 1.8 and errs1[0] / errs1[1] > 1.8
+
+
+def test_helmholtz_3d_low_frequency_limit():
+    # k -> 0: exp(ikr)/(4 pi r) -> 1/(4 pi r) entry by entry, off the diagonal and on it
+    # ((e^{ikR} - 1)/(2ik) -> R/2), with an O(k) difference.
+    g = W.fibonacci_sphere(300)
+    A0 = dense.matrix(Problem("lap3d_sl", g.points, g.weights))
+    for k in (1e-3, 1e-5):
+        Ak = dense.matrix(Problem("helm3d_sl", g.points, g.weights, wavenumber=k))
+        assert np.abs(Ak - A0).max() < 0.2 * k * np.abs(A0).max() + 1e-14

@@ -122,14 +122,16 @@ def _orthogonal_columns(m, norms, seed):
 
 
 @pytest.mark.parametrize("rel,expect_k,expect_near", [
-    (1e-12, 4, True),      # |R_33| just above eps |R_00|: kept, but within 1e-10
-    (-1e-12, 3, True),     # just below: dropped, and the stopping value is within 1e-10
-    (1e-9, 4, False),      # outside the 1e-10 band on either side
-    (-1e-9, 3, False),
+    (1e-12, 4, True),      # |R_33| just above eps |R_00|: kept, but within the band
+    (-1e-12, 3, True),     # just below: dropped, and the stopping value is within it
+    (1e-9, 4, True),       # 1e-15 from the threshold: inside the rounding floor
+    (1e-7, 4, False),      # outside the band on either side
+    (-1e-7, 3, False),
 ])
 def test_near_threshold_flag(rel, expect_k, expect_near):
-    # The rank rule keeps pivots with |R_jj| > eps |R_00|; a decision taken within a
-    # relative 1e-10 of the threshold is flagged, since rounding may take it either way.
+    # The rank rule keeps pivots with |R_jj| > eps |R_00|; a decision taken within
+    # 1e-10 eps |R_00| + 2 m u |R_00| of the threshold (here 40 rows, |R_00| = 1: about
+    # 8.9e-15) is flagged, since rounding may take it either way.
     eps = 1e-6
     norms = [1.0, 0.5, 0.25, eps * (1.0 + rel), 1e-9, 1e-10]
     M = _orthogonal_columns(40, norms, 5)
@@ -148,3 +150,79 @@ def test_near_threshold_clear_when_rank_gap_is_wide():
     idr = cpqr_id(M, eps)
     assert idr.k == 3
     assert idr.near_threshold is False
+
+
+def test_tie_flag_uses_the_rounding_floor():
+    # Orthogonal columns: at step 2 the two remaining norms are 1e-8 and 1e-8 (1 + 1e-7),
+    # 1e-15 apart -- far more than a relative 1e-10 of either, but below the absolute
+    # width 2 m u |R_00| (about 8.9e-15 for 40 rows) within which two Householder QRs
+    # of this block may disagree.  The step is reported as tied.
+    norms = [1.0, 0.5, 1e-8 * (1.0 + 1e-7), 1e-8, 1e-12]
+    M = _orthogonal_columns(40, norms, 3)
+    idr = cpqr_id(M, 1e-14)
+    assert idr.first_tie == 2
+    assert list(idr.pivots[:2]) == [0, 1]
+    # well separated norms: no tie anywhere
+    M2 = _orthogonal_columns(40, [1.0, 0.5, 1e-3, 0.5e-3, 1e-6], 4)
+    assert cpqr_id(M2, 1e-9).first_tie == -1
+
+
+def test_splitmix64_reference_outputs():
+    # The generator's first three outputs from state 0 (the published reference values):
+    # counters 0, gamma, 2 gamma.
+    from oracle.interp import splitmix64
+    g = 0x9E3779B97F4A7C15
+    out = splitmix64(np.array([0, g, (2 * g) % (1 << 64)], dtype=np.uint64))
+    assert [int(v) for v in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_sketch_signs_balanced_and_reproducible():
+    from oracle.interp import sketch_signs
+    S = sketch_signs(7, 300, 2000, 12345)
+    assert set(np.unique(S)) == {-1.0, 1.0}
+    assert abs(S.mean()) < 0.01                    # 6e5 fair signs: sd 1.3e-3
+    assert np.array_equal(S, sketch_signs(7, 300, 2000, 12345))
+    assert not np.array_equal(S, sketch_signs(8, 300, 2000, 12345))
+    # rows are nearly orthogonal (E[S S^T] = m I)
+    G = S @ S.T / 2000.0
+    assert np.abs(G - np.eye(300)).max() < 0.15
+
+
+def test_randomized_id_exact_low_rank_and_identity_when_short():
+    from oracle.interp import randomized_id
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((400, 12)) @ rng.standard_normal((12, 50))
+    idr = randomized_id(A, 1e-12, box=5, seed=99, oversample=16)
+    assert idr.k == 12
+    res = A[:, idr.redund] - A[:, idr.skel] @ idr.T
+    assert np.abs(res).max() < 1e-12 * np.abs(A).max()
+    # fewer rows than n + oversample: no sketch, the deterministic ID itself
+    B = rng.standard_normal((30, 20))
+    r1, r2 = randomized_id(B, 1e-9, 1, 2, 16), cpqr_id(B, 1e-9)
+    assert r1.k == r2.k and np.array_equal(r1.skel, r2.skel) and np.array_equal(r1.T, r2.T)
+
+
+def test_randomized_id_error_on_kernel_blocks():
+    # On proxy compression blocks of the star curve the sketched ID reproduces the
+    # redundant columns to the precision of the deterministic one (a small factor):
+    # |M(:, r) - M(:, s) T| <= 10 max(|R_kk| of the deterministic ID, eps |R_00|).
+    import workloads as W
+    from oracle import Problem, factor
+    from oracle.interp import randomized_id
+    from oracle.rs import compression_block
+    g = W.star_curve(2048)
+    p = Problem("lap2d_sl", g.points, g.weights)
+    F = factor(p, 1e-9, 64, 64)
+    checked = 0
+    for b, r in list(F.records.items())[::7]:
+        t = F.tree
+        M = compression_block(F.prob, r.J, r.near, t.center[b], 1.5 * t.side[b], 64)
+        rid = randomized_id(M, 1e-9, b, 2024, 16)
+        if rid.k in (0, M.shape[1]):
+            continue
+        res = M[:, rid.redund] - M[:, rid.skel] @ rid.T
+        bound = 10 * max(r.idr.rdiag[min(r.k, len(r.idr.rdiag) - 1)], 1e-9 * r.idr.rdiag[0])
+        assert np.linalg.norm(res, axis=0).max() <= bound, b
+        assert abs(rid.k - r.k) <= max(3, r.k // 10), (b, rid.k, r.k)
+        checked += 1
+    assert checked >= 10

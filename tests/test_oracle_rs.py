@@ -40,16 +40,22 @@ def helm_prob(g, wavelengths=5.0):
                    wavenumber=k, eta=k)
 
 
+def helm3_prob(g, wavelengths=3.18):
+    return Problem("helm3d_sl", g.points, g.weights,
+                   wavenumber=W.helmholtz_wavenumber(g, wavelengths))
+
+
 @pytest.mark.parametrize("mk,leaf", [(lambda: dl_prob(W.star_curve(700)), 32),
                                      (lambda: sl_prob(W.star_curve(500)), 24),
-                                     (lambda: sph_prob(W.fibonacci_sphere(600)), 40)])
+                                     (lambda: sph_prob(W.fibonacci_sphere(600)), 40),
+                                     (lambda: helm3_prob(W.fibonacci_sphere(500)), 40)])
 def test_eps_zero_is_dense_lu(mk, leaf):
     p = mk()
     F = factor(p, 0.0, leaf, 64 if p.dim == 2 else 128)
     for r in F.records.values():
         assert r.k == r.n
     assert F.root_size == p.n
-    b = W.gaussian_rhs(p.n, 3, 5)
+    b = W.gaussian_rhs(p.n, 3, 5, p.is_complex)
     x = F.solve(b)
     xd = dense.solve(p, b)
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-12
@@ -186,6 +192,20 @@ def test_sphere_solve_brute_force():
     assert np.linalg.norm(x - np.linalg.solve(A, b)) / np.linalg.norm(x) <= 2e-6 * kappa
 
 
+def test_helmholtz3d_sphere_brute_force():
+    # Section 5's bounds against dense Gaussian elimination for the 3D Helmholtz single
+    # layer at the paper's 3D frequency (3.18 wavelengths across the sphere)
+    g = W.fibonacci_sphere(1200)
+    p = helm3_prob(g)
+    F = factor(p, 1e-6, 128, 256)
+    A = dense.matrix(p)
+    b = W.gaussian_rhs(p.n, 1, 4, True)
+    x = F.solve(b)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 1e-6 * kappa
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) / np.linalg.norm(x) <= 2e-6 * kappa
+
+
 def test_ranks_consistent_with_paper_scale():
     # Table 5 reports O(30) top-level skeletons for a 2D curve at eps = 1e-9,
     # essentially independent of N; with four depth-1 boxes the root here holds
@@ -212,3 +232,21 @@ def test_helmholtz_cfie_brute_force():
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 10 * eps
     assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 10 * eps
     assert any(0 < r.k < r.n for r in F.records.values())
+
+
+@pytest.mark.parametrize("mk,eps,leaf,npx", [(lambda: dl_prob(W.star_curve(1500)), 1e-9, 64, 64),
+                                            (lambda: sph_prob(W.fibonacci_sphere(1500)), 1e-6, 128, 256)])
+def test_sketched_id_factorization_brute_force(mk, eps, leaf, npx):
+    # Compression through random row sketches (the paper's randomized ID): the solve
+    # still meets Section 5's bounds against dense Gaussian elimination.
+    p = mk()
+    F = factor(p, eps, leaf, npx, id_mode="sketch", sketch_seed=77)
+    A = dense.matrix(p)
+    b = W.gaussian_rhs(p.n, 1, 6)
+    x = F.solve(b)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 10 * eps * kappa
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) / np.linalg.norm(x) <= 20 * eps * kappa
+    # a different seed gives a different (equally valid) compression
+    F2 = factor(p, eps, leaf, npx, id_mode="sketch", sketch_seed=78)
+    assert any(not np.array_equal(F.records[b].skel, F2.records[b].skel) for b in F.records)

@@ -11,6 +11,7 @@ random smooth curves and a quasi-uniform sphere of the same kind):
 * ``star_curve``    r(t) = 1 + a cos(m t), equispaced parameter, trapezoid weights
 * ``random_curve``  r(t) = 1 + sum_k a_k cos(k t + phi_k)
 * ``ellipse``       semi-axes (a, b), equispaced parameter
+* ``scatterer_curve``  r(t) = (2 + cos 3t) / 6 (the multiple-scattering example's body)
 * ``fibonacci_sphere``  N quasi-uniform points on the unit sphere, equal-area weights
 
 All arrays are float64.  Points are point-major, shape (N, dim).
@@ -75,6 +76,19 @@ def star_curve(n: int, amp: float = 0.3, lobes: int = 5) -> Geometry:
         lambda t: -amp * lobes * np.sin(lobes * t),
         lambda t: -amp * lobes * lobes * np.cos(lobes * t),
         "star", {"amp": amp, "lobes": lobes})
+
+
+def scatterer_curve(n: int, center=(0.0, 0.0)) -> Geometry:
+    """The scatterer of the paper's multiple-scattering example (Section 6.4):
+    r(t) = (2 + cos 3t) / 6, shifted to ``center``."""
+    g = _polar_curve(
+        n,
+        lambda t: (2.0 + np.cos(3.0 * t)) / 6.0,
+        lambda t: -0.5 * np.sin(3.0 * t),
+        lambda t: -1.5 * np.cos(3.0 * t),
+        "scatterer", {"center": tuple(center)})
+    g.points = g.points + np.asarray(center, dtype=np.float64)[None, :]
+    return g
 
 
 def random_curve(n: int, amps, phases) -> Geometry:
