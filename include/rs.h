@@ -187,6 +187,24 @@ rs_status rs_solve_ex(rs_handle h, void *B, int64_t ldb, int32_t nrhs,
 rs_status rs_matvec(rs_handle h, const void *X, int64_t ldx, void *Y, int64_t ldy,
                     int32_t nrhs, void *stream);
 
+/* rs_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve,
+ * bitwise equal to rs_solve, with its workspace (the tree-ordered copy of B and the
+ * staging of large boxes) in a fixed 64 MiB scratch array that each device holds
+ * from the library's first such call until the process ends.  No hipMalloc, hipFree
+ * or other allocating call is made, and no profiler events are recorded.
+ * B: device memory of the current device, column-major n x nrhs, ldb >= n, doubles or
+ * complex128 as for rs_solve; enqueued on stream (NULL = default stream).
+ * Limit: n * nrhs scalars (times 2 for complex128) plus the staging of the largest
+ * box must fit 64 MiB; larger requests fail with RS_EINVAL and a message giving the
+ * size needed (split the columns over several calls).
+ * Every call on a device shares that device's scratch: calls that overlap on one
+ * device (different streams, or host threads) race and give wrong results; order
+ * them on one stream or synchronize between them.
+ * Errors: RS_EINVAL (host pointer, range past the allocation, size over the limit),
+ * RS_EDEVICE. */
+rs_status rs_solve_noalloc(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream);
+
 /* ------------------------------------------------- batched (many problems) ---- */
 
 /* Factors `count` independent problems together (arrays of length count): every

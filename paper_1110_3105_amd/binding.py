@@ -39,7 +39,7 @@ EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "
             "rs_server_submit_solve", "rs_server_poll", "rs_server_release", "rs_server_query",
             "rs_server_reset_stats", "rs_server_destroy", "rs_plan_create", "rs_plan_launch",
             "rs_plan_free", "rs_autotune", "rs_tune_entries", "rs_tune_clear", "rs_tune_save",
-            "rs_tune_load", "rs_matvec"]
+            "rs_tune_load", "rs_solve_noalloc", "rs_matvec"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -94,6 +94,7 @@ _sig = {
                                C.POINTER(rs_options), C.POINTER(_P)]),
     "rs_solve": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P]),
     "rs_solve_ex": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(rs_options)]),
+    "rs_solve_noalloc": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P]),
     "rs_matvec": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, _P]),
     "rs_free": (C.c_int, [_P]),
     "rs_last_error": (C.c_char_p, []),
@@ -333,6 +334,22 @@ class Handle:
         _check(_lib.rs_matvec(self._h, C.c_void_p(X2.data_ptr()), int(ldx),
                               C.c_void_p(Y.data_ptr()), self.n, int(nrhs), _stream_ptr(stream)))
         return Y[:, 0] if vec else Y
+
+    def solve_noalloc(self, B, stream=None):
+        """In-place solve through rs_solve_noalloc (workspace in the library's fixed
+        per-device scratch; no device allocation).  B: column-major device tensor."""
+        import torch
+        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == self.dtype):
+            raise TypeError(f"B must be a {self.dtype} tensor on the HIP device")
+        X = B.unsqueeze(1) if B.dim() == 1 else B
+        if X.shape[0] != self.n or X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) < self.n):
+            raise ValueError("B must be column-major with n rows")
+        ldb = X.stride(1) if X.shape[1] > 1 else self.n
+        if stream is None:
+            stream = torch.cuda.current_stream(B.device)
+        _check(_lib.rs_solve_noalloc(self._h, C.c_void_p(X.data_ptr()), int(ldb),
+                                     int(X.shape[1]), _stream_ptr(stream)))
+        return B
 
     def solve_host(self, b: np.ndarray, stream=None) -> np.ndarray:
         """Synchronous solve of host right-hand sides (numpy, shape (n,) or (n, nrhs),

@@ -321,6 +321,48 @@ rs_status rs_matvec(rs_handle h, const void *X, int64_t ldx, void *Y, int64_t ld
   });
 }
 
+rs_status rs_solve_noalloc(rs_handle h, void *B, int64_t ldb, int32_t nrhs, void *stream) {
+  return guarded([&]() -> rs_status {
+    if (!h) fail(RS_EINVAL, "NULL handle");
+    if (nrhs < 0) fail(RS_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return RS_OK;
+    if (!B) fail(RS_EINVAL, "NULL right-hand side");
+    if (ldb < h->n) fail(RS_EINVAL, "ldb < n");
+    const size_t es = h->cplx ? 2 : 1;
+    if (!is_device_buffer(B, ((size_t)(nrhs - 1) * (size_t)ldb + (size_t)h->n) * es * 8))
+      fail(RS_EINVAL, "rs_solve_noalloc takes device memory only");
+    // workspace layout in the scratch array: W (n * nrhs scalars), then the wide-box
+    // staging starting at the next 256-byte boundary
+    const size_t cap = noalloc_scratch_bytes() / sizeof(double);
+    const size_t w_doubles = (size_t)h->n * (size_t)nrhs * es;
+    const size_t wide_off = (w_doubles + 31) & ~size_t(31);
+    const int64_t wide_min = solve_wide_min_doubles(h, nrhs);
+    const size_t need = wide_min > 0 ? wide_off + (size_t)wide_min : w_doubles;
+    if (need > cap)
+      fail(RS_EINVAL, "solve needs " + std::to_string(need * sizeof(double)) +
+                          " bytes of scratch; rs_solve_noalloc is limited to " +
+                          std::to_string(noalloc_scratch_bytes()) + " bytes per call");
+    double *base = noalloc_scratch();
+    const int64_t wide_sz =
+        wide_min > 0 ? std::min<int64_t>(solve_wide_doubles(h, nrhs), (int64_t)(cap - wide_off)) : 0;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    h->busy.fetch_add(1);
+    struct Dec {
+      rs_handle h;
+      ~Dec() { h->busy.fetch_sub(1); }
+    } dec{h};
+    {
+      CaptureScope no_profiler_events;
+      solve_one_into(h, B, ldb, nrhs, RS_LAUNCH_LEVEL, st, base, wide_sz > 0 ? base + wide_off : nullptr,
+                     wide_sz);
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    RS_HIP_CHECK(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusNone) note_inflight(h, st);
+    return RS_OK;
+  });
+}
+
 rs_status rs_plan_create(int32_t count, const rs_handle *h, void *const *B, const int64_t *ldb,
                          const int32_t *nrhs, rs_plan *out) {
   return guarded([&]() -> rs_status {

@@ -3455,4 +3455,36 @@ void launch_mv_diag(bool cplx, const MvBox *boxes, int count, int max_n, const P
   check_launch("k_mv_diag");
 }
 
+// ------------------------------------------------------ allocation-free solve scratch
+// Device scratch of the allocation-free solve entry point: the tree-ordered workspace
+// and the wide-box staging of one solve, 64 MiB per device (every device the library
+// runs on holds its own copy until the process ends).  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device address): the
+// device address comes from hipGetSymbolAddress, looked up once per device with that
+// device current, and only that pointer is used afterwards.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_ptr;     // per device id
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
+double *noalloc_scratch() {
+  int dev = 0;
+  RS_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    RS_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw DeviceError("hipGetSymbolAddress returned no address for the scratch array",
+                                hipErrorInvalidSymbol);
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace rs

@@ -155,6 +155,11 @@ void solve_one_into(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_m
 int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs);
 int64_t solve_wide_doubles(const rs_factor_s *h, int nrhs);
 
+// The allocation-free solve's device scratch (kernels.hip): a fixed array per device.
+// noalloc_scratch() returns the current device's copy, looked up once per device.
+size_t noalloc_scratch_bytes();
+double *noalloc_scratch();
+
 struct SolveRequest {
   rs_factor_s *h;
   void *B;
