@@ -297,6 +297,29 @@ typedef struct {
 
 rs_status rs_query(rs_handle h, rs_stats *out);
 
+/* Per level of a factorization (compressed levels finest first, then the root). */
+typedef struct {
+  int32_t depth;            /* tree depth (0 = the root) */
+  int32_t boxes;            /* boxes factored at this level */
+  int64_t n_total;          /* sum over the boxes of the active DOFs n */
+  int64_t k_total;          /* sum of the ranks k (skeletons passed to the parent; 0 at the root) */
+  int32_t max_n;            /* largest active set */
+  int32_t max_m;            /* largest compression block (rows; 0 at the root) */
+  int64_t factor_doubles;   /* doubles stored for the level's compressed inverse (2 per complex) */
+  double device_ms;         /* compressed levels: device time of the level's compression
+                               launches (assembly, sketch, ID; from the first launch to the
+                               join of its streams); root: its factorization */
+  double plan_ms;           /* host planning time of the level (active sets, near lists,
+                               descriptors).  A batched factorization processes the same
+                               level step of all its problems together: both times are then
+                               those of the step, shared by the problems */
+} rs_level_stats;
+
+/* Copies up to cap level records into out (finest level first, the root last) and sets
+ * *count to the number of levels.  out may be NULL with cap = 0 to query the count.
+ * Errors: RS_EINVAL. */
+rs_status rs_query_levels(rs_handle h, rs_level_stats *out, int32_t cap, int32_t *count);
+
 /* Per-box ranks and skeletons (tree positions, ascending per box), for
  * inspection and testing.  k_out[nbox] receives k per box (-1 for boxes with no
  * compression step, i.e. the root); skel_out receives the concatenation of all

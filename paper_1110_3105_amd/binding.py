@@ -39,7 +39,7 @@ EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "
             "rs_server_submit_solve", "rs_server_poll", "rs_server_release", "rs_server_query",
             "rs_server_reset_stats", "rs_server_destroy", "rs_plan_create", "rs_plan_launch",
             "rs_plan_free", "rs_autotune", "rs_tune_entries", "rs_tune_clear", "rs_tune_save",
-            "rs_tune_load", "rs_solve_noalloc", "rs_matvec"]
+            "rs_tune_load", "rs_solve_noalloc", "rs_matvec", "rs_query_levels"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -64,6 +64,12 @@ class rs_stats(C.Structure):
                 ("factor_doubles", C.c_int64), ("max_box_n", C.c_int64),
                 ("max_box_m", C.c_int64), ("factor_ms", C.c_double), ("plan_ms", C.c_double),
                 ("wait_ms", C.c_double), ("complex_values", C.c_int32), ("pad", C.c_int32)]
+
+
+class rs_level_stats(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("boxes", C.c_int32), ("n_total", C.c_int64),
+                ("k_total", C.c_int64), ("max_n", C.c_int32), ("max_m", C.c_int32),
+                ("factor_doubles", C.c_int64), ("device_ms", C.c_double), ("plan_ms", C.c_double)]
 
 
 class rs_server_opts(C.Structure):
@@ -100,6 +106,8 @@ _sig = {
     "rs_last_error": (C.c_char_p, []),
     "rs_device_count": (C.c_int32, []),
     "rs_query": (C.c_int, [_P, C.POINTER(rs_stats)]),
+    "rs_query_levels": (C.c_int, [_P, C.POINTER(rs_level_stats), C.c_int32,
+                                  C.POINTER(C.c_int32)]),
     "rs_box_skeletons": (C.c_int, [_P, _PI32, _PI64, C.c_int64, _PI64]),
     "rs_box_export": (C.c_int, [_P, C.c_int64, _PI32, _PI32, _PI64, _PD]),
     "rs_factor_batched": (C.c_int, [C.c_int32, C.POINTER(rs_kernel), C.POINTER(_P),
@@ -288,6 +296,15 @@ class Handle:
         s = rs_stats()
         _check(_lib.rs_query(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in rs_stats._fields_}
+
+    def levels(self) -> list:
+        """Per-level records of the factorization, finest level first and the root last."""
+        cnt = C.c_int32(0)
+        _check(_lib.rs_query_levels(self._h, None, 0, C.byref(cnt)))
+        arr = (rs_level_stats * max(cnt.value, 1))()
+        _check(_lib.rs_query_levels(self._h, arr, cnt.value, C.byref(cnt)))
+        return [{f: getattr(arr[i], f) for f, _ in rs_level_stats._fields_}
+                for i in range(cnt.value)]
 
     def solve_ptr(self, ptr: int, ldb: int, nrhs: int, stream=None, launch_mode: str = "level"):
         o = rs_options(LAUNCH[launch_mode], _stream_ptr(stream))

@@ -476,6 +476,16 @@ rs_status rs_query(rs_handle h, rs_stats *out) {
   });
 }
 
+rs_status rs_query_levels(rs_handle h, rs_level_stats *out, int32_t cap, int32_t *count) {
+  return guarded([&]() -> rs_status {
+    if (!h || !count) fail(RS_EINVAL, "NULL argument");
+    if (cap < 0 || (cap > 0 && !out)) fail(RS_EINVAL, "bad output buffer");
+    *count = (int32_t)h->level_stats.size();
+    for (int32_t i = 0; i < cap && i < *count; ++i) out[i] = h->level_stats[i];
+    return RS_OK;
+  });
+}
+
 rs_status rs_box_skeletons(rs_handle h, int32_t *k_out, int64_t *skel_out, int64_t cap,
                            int64_t *total) {
   return guarded([&]() -> rs_status {

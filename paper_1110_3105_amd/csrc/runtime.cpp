@@ -420,6 +420,31 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   S.err.ensure(sizeof(int32_t));
   RS_HIP_CHECK(hipMemsetAsync(S.err.p, 0xff, sizeof(int32_t), st));
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
+  // per-level statistics: device time of each step's compression (timing events on st)
+  // and host planning time; filled into the handles after the final synchronization
+  struct StepTiming {
+    hipEvent_t a = nullptr, b = nullptr;
+    double plan_ms = 0;
+  };
+  std::vector<StepTiming> step_t(max_depth + 1);
+  struct TimingRelease {
+    std::vector<StepTiming> *v;
+    ~TimingRelease() {
+      for (StepTiming &x : *v) {
+        if (x.a) (void)hipEventDestroy(x.a);
+        if (x.b) (void)hipEventDestroy(x.b);
+      }
+    }
+  } timing_release{&step_t};
+  auto level_entry = [&](rs_factor_s *h, int depth) -> rs_level_stats & {
+    for (rs_level_stats &e : h->level_stats)
+      if (e.depth == depth) return e;
+    h->level_stats.emplace_back();
+    rs_level_stats &e = h->level_stats.back();
+    std::memset(&e, 0, sizeof(e));
+    e.depth = depth;
+    return e;
+  };
   int64_t max_m_seen = 0;
   // Every factored box gets a global index; a singular pivot reports the first one,
   // checked once after the root (no host wait per level).
@@ -494,6 +519,13 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       h->stats.factor_doubles += (slot_size(k, n - k) - (int64_t)k * k) * es;
       h->stats.max_box_n = std::max<int64_t>(h->stats.max_box_n, n);
       h->stats.max_box_m = std::max<int64_t>(h->stats.max_box_m, comp[i].m);
+      rs_level_stats &ls = level_entry(h, d);
+      ls.boxes++;
+      ls.n_total += n;
+      ls.k_total += k;
+      ls.max_n = std::max(ls.max_n, n);
+      ls.max_m = std::max(ls.max_m, (int32_t)comp[i].m);
+      ls.factor_doubles += (slot_size(k, n - k) - (int64_t)k * k) * es;
     }
     for (int p = 0; p < np; ++p)
       if (!idx_keep[p].empty()) {
@@ -658,6 +690,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       std::copy(near_all[i].begin(), near_all[i].end(), pool.begin() + comp[i].N_off);
     }, 64);
     plan_ms += ms_since(tp);
+    step_t[step].plan_ms += ms_since(tp);
     if (cpqr_lds_bytes(cplx, max_n, 1 << 30) > 160 * 1024)
       throw UserError{RS_ENOTSUP, "a box's active set exceeds the on-chip ID limit"};
     // this level's buffer set was last read by the box factorization two levels back
@@ -676,6 +709,9 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                       sizeof(double));
     const CompBox *d_comp = S.comp.as<CompBox>();
     const CompBox *d_comp_id = any_sketch ? S.comp_id.as<CompBox>() : d_comp;
+    RS_HIP_CHECK(hipEventCreate(&step_t[step].a));
+    RS_HIP_CHECK(hipEventCreate(&step_t[step].b));
+    RS_HIP_CHECK(hipEventRecord(step_t[step].a, st));
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
         if (i < nf) {
@@ -742,6 +778,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_aux2, 0));
       }
     }
+    RS_HIP_CHECK(hipEventRecord(step_t[step].b, st));
     RS_HIP_CHECK(hipEventRecord(S.ev_comp, st));   // ranks, order and pool of this level
     // The box factorizations need this level's ranks and orders only on the device (the
     // kernel reads them by slot), so their descriptors are built now and the launch is
@@ -844,6 +881,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     dfr.order = std::move(order);
     dfr.pending = true;
     plan_ms += ms_since(tp2);
+    step_t[step].plan_ms += ms_since(tp2);
   }
 
   run_deferred();
@@ -892,6 +930,9 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       for (const FacBox &f : fac) w += work_factor(f.n, 0, cplx);
       prof_add_work(RS_K_FACTOR, w);
     }
+    RS_HIP_CHECK(hipEventCreate(&step_t[max_depth].a));
+    RS_HIP_CHECK(hipEventCreate(&step_t[max_depth].b));
+    RS_HIP_CHECK(hipEventRecord(step_t[max_depth].a, st));
     // roots below the wide class: one workgroup each (k_diag_factor skips wide roots)
     int max_n_narrow = 0;
     for (const FacBox &f : fac)
@@ -915,6 +956,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                        S.work.as<double>(), fac[i].work_off, fac[i].slot, S.err.as<int32_t>(),
                        err_base + i, st);
     }
+    RS_HIP_CHECK(hipEventRecord(step_t[max_depth].b, st));
     {
       auto tw = Clock::now();
       check_err(S.err, st, all_items, "factorization");
@@ -961,6 +1003,32 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   RS_HIP_CHECK(hipStreamSynchronize(st));
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  // per-level device times: step s held depth maxdepth - s of each problem; the root last
+  for (int p = 0; p < np; ++p) {
+    rs_factor_s *h = handles[p].get();
+    for (int step = 0; step < max_depth; ++step) {
+      const int d = ps[p].t->maxdepth - step;
+      if (d < 1 || !step_t[step].a) continue;
+      float el = 0.f;
+      RS_HIP_CHECK(hipEventElapsedTime(&el, step_t[step].a, step_t[step].b));
+      rs_level_stats &e = level_entry(h, d);
+      e.device_ms = el;
+      e.plan_ms = step_t[step].plan_ms;
+    }
+    rs_level_stats &r = level_entry(h, 0);
+    r.boxes = 1;
+    r.n_total = r.max_n = (int32_t)h->stats.root_size;
+    r.factor_doubles = (int64_t)h->stats.root_size * h->stats.root_size * es;
+    if (step_t[max_depth].a) {
+      float el = 0.f;
+      RS_HIP_CHECK(hipEventElapsedTime(&el, step_t[max_depth].a, step_t[max_depth].b));
+      r.device_ms = el;
+    }
+    std::stable_sort(h->level_stats.begin(), h->level_stats.end(),
+                     [](const rs_level_stats &x, const rs_level_stats &y) {
+                       return (x.depth == 0 ? -1 : x.depth) > (y.depth == 0 ? -1 : y.depth);
+                     });
+  }
   out.resize(np);
   for (int p = 0; p < np; ++p) {
     rs_factor_s *h = handles[p].get();

@@ -111,6 +111,7 @@ struct rs_factor_s {
   std::vector<double *> box_slot;        // factor slot per box (scalars of the handle's type)
   int nbox = 0;
   rs_stats stats{};
+  std::vector<rs_level_stats> level_stats;   // finest level first, the root last
   std::atomic<int> busy{0};
   std::mutex inflight_mu;
   std::vector<std::shared_ptr<rs::SharedEvent>> inflight;   // completions of enqueued solves

@@ -112,3 +112,33 @@ def test_batched_argument_errors(gpu_lib):
         rs.factor_batched([dict(kind="lap2d_sl", tree=rs.build_tree(g.points, 64),
                                 points=g.points, weights=g.weights, eps=-1.0)])
     assert ei.value.code == 1
+
+
+def test_many_problem_family_parity_on_16(gpu_lib):
+    """Members 0..15 of the benchmark's 256-curve family (N ~ U{1024..16384}, interior
+    double layer, eps = 1e-9, leaf 64, 64 proxies), factored in one batch: each against
+    its own oracle run (skeletons where no tie reaches a box; the solution to 10 eps when
+    all skeletons agree), and its residual against the compressed operator the batch
+    inverted (rs_matvec over all rows)."""
+    import torch
+    from parity_util import compare_skeletons, identical_skeletons, to_device
+    rs = gpu_lib
+    eps = 1e-9
+    fam = [W.random_curve_problem(p) for p in range(16)]
+    specs = [_spec(rs, g, "lap2d_dl", eps, 64, 64) for g, _ in fam]
+    hb = rs.factor_batched(specs)
+    Bs = [to_device(b) for _, b in fam]
+    rs.solve_batched(hb, Bs)
+    torch.cuda.synchronize()
+    for (g, b), h, B in zip(fam, hb, Bs):
+        p = Problem("lap2d_dl", g.points, g.weights, g.normals, g.curvature, identity=-0.5)
+        F = ofactor(p, eps, 64, 64)
+        compared, _ = compare_skeletons(h, F, residual_every=5)
+        assert compared >= 0.9 * len(F.records)
+        x = B.cpu().numpy()
+        if identical_skeletons(h, F):
+            xo = F.solve(b)
+            assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 10 * eps
+        Y = h.matvec(B)
+        torch.cuda.synchronize()
+        assert np.linalg.norm(Y.cpu().numpy() - b) / np.linalg.norm(b) <= 1e-12
