@@ -84,6 +84,12 @@ __device__ __forceinline__ double dpp_f64(double v) {
   const int hi = dpp_i32<CTRL>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -561,9 +567,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble_tail(const CompBox *__res
 // (q < CPW), lane l rows l + 64 t (t < RT); a column's reductions stay inside its wave,
 // so a pivot step needs two workgroup barriers (reflector ready, norms ready) and
 // touches no global memory.  Columns are not moved: piv[j] is the column of pivot step
-// j.  The first k rows of R go to the box's scratch (k x n) for T = R11^{-1} R12.  The
-// arithmetic of a box does not depend on NTH, RT or CPW (a column's sums run over its
-// rows in the same lanes and order; rows and columns beyond the box are zeros).
+// j.  The first k rows of R are then staged in LDS and T = R11^{-1} R12 is solved by one wave
+// per redundant column.  The arithmetic of a box does not depend on NTH, RT or CPW (a
+// column's sums run over its rows in the same lanes and order; rows and columns beyond
+// the box are zeros).
 template <int NW>
 __device__ __forceinline__ double block_max_w(double v, double *red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -576,11 +583,17 @@ __device__ __forceinline__ double block_max_w(double v, double *red) {
   return r;
 }
 
+// LDS doubles of the staging region: the assembly tiles, then rows < k <= min(m, n) of R
+__host__ __device__ __forceinline__ int fused_tile_doubles(int nw, int n, int m) {
+  const int kmax = n < m ? n : m;
+  return nw * m > n * kmax ? nw * m : n * kmax;
+}
+
 template <int NTH, int RT, int CPW>
 __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
     const CompBox *__restrict__ boxes, int first, const ProbDev *__restrict__ probs,
-    const int32_t *__restrict__ pool, double *__restrict__ Rarena,
-    int32_t *__restrict__ order_pool, int32_t *__restrict__ ranks) {
+    const int32_t *__restrict__ pool, int32_t *__restrict__ order_pool,
+    int32_t *__restrict__ ranks) {
   constexpr int NW = NTH / 64;
   extern __shared__ double smem[];
   __shared__ double red[NW];
@@ -599,8 +612,8 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
   double *norms = sh_u + 3 * npx;                      // n
   double *sv = norms + n;                              // m
   double *wbuf = sv + m;                               // NW * n
-  double *tile = wbuf + NW * n;                        // NW * m (assembly staging)
-  double *pts = tile + NW * m;                         // 7 (n + nn): staged points
+  double *tile = wbuf + NW * n;   // NW m (assembly staging), later k n (rows < k of R)
+  double *pts = tile + fused_tile_doubles(NW, n, m);   // 7 (n + nn): staged points
   int *piv = reinterpret_cast<int *>(pts + 7 * (n + nn));   // n
   int *rk = piv + n;                                   // n
   int *done = rk + n;                                  // n
@@ -616,13 +629,38 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
   const int rows = 2 * nn + 2 * npx;
   double pmax = 0.0;
   double val[CPW][RT];
-  // each wave evaluates its own columns; a lane stages exactly the rows it keeps (its
-  // slice of the wave's LDS column), so no barrier is needed
+  // each wave evaluates its own columns into its LDS column, then every lane takes its
+  // rows.  Symmetric kernels (the single layers, K(x, y) = K(y, x) bit for bit: the
+  // distance is formed from squared differences) evaluate each point pair once for both
+  // of its rows: near row i and its transpose nn + i, proxy row 2 nn + p and 2 nn + npx + p.
   double *mytile = tile + wave * m;
+  const bool sym = P.kind == RS_LAP2D_SL || P.kind == RS_LAP3D_SL;
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
     const int c = wave + NW * q;
-    if (c < n) {
+    if (c < n && sym) {
+      double xs[3], ns[3];
+      Jp.load(dim, c, xs, ns);
+      const double wc = Jp.w[c];
+      for (int i = lane; i < nn; i += 64) {
+        double xq[3], nq[3];
+        Np.load(dim, i, xq, nq);
+        const double g = kernel_val<double>(P, xq, xs, ns);
+        mytile[i] = g * wc;
+        mytile[nn + i] = g * Np.w[i];
+      }
+      for (int p = lane; p < npx; p += 64) {
+        const double *u = sh_u + 3 * p;
+        const double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1],
+                             B.cen[2] + B.rho * u[2]};
+        const double g = kernel_val<double>(P, y, xs, ns);
+        const double a = g * wc, b = g * wG;
+        pmax = fmax(pmax, fmax(fabs(a), fabs(b)));
+        mytile[2 * nn + p] = a;
+        mytile[2 * nn + npx + p] = b;
+      }
+      wave_sync();     // rows were written by other lanes of the wave
+    } else if (c < n) {
       for (int i = lane; i < rows; i += 64) {
         const double v = comp_entry_staged<double>(P, B, Jp, Np, sh_u, wG, i, c);
         if (i >= 2 * nn) pmax = fmax(pmax, fabs(v));
@@ -661,7 +699,8 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
       double s = 0.0;
       if (q < CPW) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) s += val[q][t] * val[q][t];
+        for (int t = 0; t < RT; ++t)
+          if (64 * t < m) s += val[q][t] * val[q][t];
       }
       x[qq] = s;
     }
@@ -691,19 +730,17 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
     if (best == 0.0 || best <= eps * r00) { k = j; break; }
     const int p = bc, pw = p & (NW - 1), pq = p / NW;
     if (wave == pw) {   // reflector of column p, rows j..m-1
-      double s = 0.0, mine = 0.0;
+      // its norm over rows j..m-1 is the pivot search's value (recomputed after the
+      // previous step over exactly these rows)
+      double mine = 0.0;
 #pragma unroll
       for (int q = 0; q < CPW; ++q)
         if (q == pq)
 #pragma unroll
-          for (int t = 0; t < RT; ++t) {
-            const int i = lane + 64 * t;
-            if (i >= j) s += val[q][t] * val[q][t];
+          for (int t = 0; t < RT; ++t)
             if (t == (j >> 6)) mine = val[q][t];
-          }
-      s = wave_sum(s);
-      const double alpha = sqrt(s);
-      const double x0 = __shfl(mine, j & 63, 64);
+      const double alpha = best;
+      const double x0 = readlane_f64(mine, j & 63);
       const double beta = x0 >= 0.0 ? -alpha : alpha;
       const double scale = 1.0 / (x0 - beta);
 #pragma unroll
@@ -711,6 +748,7 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
         if (q == pq)
 #pragma unroll
           for (int t = 0; t < RT; ++t) {
+            if (64 * t >= m) continue;
             const int i = lane + 64 * t;
             if (i > j && i < m) {
               val[q][t] *= scale;
@@ -773,42 +811,96 @@ __global__ __launch_bounds__(NTH, 2) void k_compress_fused(
     __syncthreads();
   }
 
-  // ---- R rows < k to the box scratch (k x n, column c at c k), then T = R11^{-1} R12
-  double *R = Rarena + B.M_off;
+  // every wave has left the pivot search (the loop ends at a break without a barrier)
+  // before its norms' space is reused
+  __syncthreads();
+  // ---- rows < k of R to LDS (column c at c k; the assembly staging is free now), and
+  // the sorted positions of the columns within their class (skeleton or redundant)
+  double *Rl = tile;
+  int *ordl = reinterpret_cast<int *>(norms);          // n ints (the norms are done)
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
     const int c = wave + NW * q;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int i = lane + 64 * t;
-      if (c < n && i < k) R[(int64_t)c * k + i] = val[q][t];
+      if (c < n && i < k) Rl[c * k + i] = val[q][t];
+    }
+  }
+  if (wave == 0) {
+    // n <= 128: two 64-column masks of the skeleton columns
+    const bool s0 = lane < n && done[lane] != 0;
+    const bool s1 = lane + 64 < n && done[lane + 64] != 0;
+    const uint64_t m0 = __ballot(s0), m1 = __ballot(s1);
+    const uint64_t v0 = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    const uint64_t v1 = n >= 128 ? ~0ull : (n > 64 ? ((1ull << (n - 64)) - 1ull) : 0ull);
+    const uint64_t below = (1ull << lane) - 1ull;
+    int32_t *order = order_pool + B.order_off;
+    if (lane < n) {
+      const int c = lane;
+      const int r = s0 ? __popcll(m0 & below) : __popcll(~m0 & v0 & below);
+      const int pos = s0 ? r : k + r;
+      order[pos] = c;
+      ordl[pos] = c;
+      rk[c] = r;
+    }
+    if (lane + 64 < n) {
+      const int c = lane + 64;
+      const int r = s1 ? __popcll(m0) + __popcll(m1 & below)
+                       : __popcll(~m0 & v0) + __popcll(~m1 & v1 & below);
+      const int pos = s1 ? r : k + r;
+      order[pos] = c;
+      ordl[pos] = c;
+      rk[c] = r;
     }
   }
   __syncthreads();
-  int32_t *order = order_pool + B.order_off;
-  for (int c = tid; c < n; c += NTH) {
-    int r = 0;
-    if (done[c]) {
-      for (int b = 0; b < k; ++b) r += piv[b] < c;
-      order[r] = c;
-    } else {
-      for (int c2 = 0; c2 < c; ++c2) r += !done[c2];
-      order[k + r] = c;
-    }
-    rk[c] = r;
-  }
-  __syncthreads();
-  // one thread per redundant column: back substitution over the rows of R11 (pivot
-  // order), x_l kept in the output column itself (sorted skeleton position rk[piv[l]])
+  // T = R11^{-1} R12, one wave per redundant column (two at a time): lane l keeps rows l
+  // and l + 64 of the column; for i = k-1 down to 0, x_i = b_i / R(i, piv_i), then
+  // b_l -= R(l, piv_i) x_i for l < i.  x_l goes to T(rk[piv_l], r) (skeletons sorted).
   double *T = B.T;
-  for (int c = tid; c < n; c += NTH) {
-    if (done[c]) continue;
-    const double *col = R + (int64_t)c * k;
-    double *Tc = T + (int64_t)k * rk[c];
+  const int nr = n - k;
+  const int pv0 = lane < k ? piv[lane] : 0, pv1 = lane + 64 < k ? piv[lane + 64] : 0;
+  for (int r0 = wave; r0 < nr; r0 += 2 * NW) {
+    const int r1 = r0 + NW;
+    const bool two = r1 < nr;
+    const int ca = ordl[k + r0], cb = two ? ordl[k + r1] : ca;
+    double a0 = lane < k ? Rl[ca * k + lane] : 0.0;
+    double a1 = lane + 64 < k ? Rl[ca * k + lane + 64] : 0.0;
+    double b0 = lane < k ? Rl[cb * k + lane] : 0.0;
+    double b1 = lane + 64 < k ? Rl[cb * k + lane + 64] : 0.0;
     for (int i = k - 1; i >= 0; --i) {
-      double s = col[i];
-      for (int l = i + 1; l < k; ++l) s -= R[(int64_t)piv[l] * k + i] * Tc[rk[piv[l]]];
-      Tc[rk[piv[i]]] = s / R[(int64_t)piv[i] * k + i];
+      const int pi = i < 64 ? __builtin_amdgcn_readlane(pv0, i) : __builtin_amdgcn_readlane(pv1, i - 64);
+      const double *Rc = Rl + pi * k;
+      const double rii = Rc[i];
+      const double ra0 = lane < k ? Rc[lane] : 0.0;
+      const double ra1 = lane + 64 < k ? Rc[lane + 64] : 0.0;
+      const double xa = (i < 64 ? readlane_f64(a0, i) : readlane_f64(a1, i - 64)) / rii;
+      const double xb = (i < 64 ? readlane_f64(b0, i) : readlane_f64(b1, i - 64)) / rii;
+      if (lane < i) {
+        a0 -= ra0 * xa;
+        b0 -= ra0 * xb;
+      } else if (lane == i) {
+        a0 = xa;
+        b0 = xb;
+      }
+      if (lane + 64 < i) {
+        a1 -= ra1 * xa;
+        b1 -= ra1 * xb;
+      } else if (lane + 64 == i) {
+        a1 = xa;
+        b1 = xb;
+      }
+    }
+    double *Ta = T + (int64_t)k * r0;
+    double *Tb = T + (int64_t)k * r1;
+    if (lane < k) {
+      Ta[rk[pv0]] = a0;
+      if (two) Tb[rk[pv0]] = b0;
+    }
+    if (lane + 64 < k) {
+      Ta[rk[pv1]] = a1;
+      if (two) Tb[rk[pv1]] = b1;
     }
   }
   if (tid == 0) ranks[B.kslot] = k;
@@ -1241,11 +1333,6 @@ __host__ __device__ inline size_t gj_blocked_lds(int r, int nw, bool a_in_lds) {
 }
 
 // Orders the memory operations of the lanes of one wave (no workgroup barrier).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // --------------------------------------------------------------------------
 // The same interpolative decomposition for large blocks, spread over G workgroups per
@@ -2894,13 +2981,14 @@ size_t fused_lds_bytes(int nth, int max_n, int max_m, int max_npx) {
   const int nw = nth / 64;
   const size_t max_nn = (size_t)max_m / 2;       // m >= 2 nn
   return sizeof(double) * ((size_t)3 * max_npx + max_n + max_m + (size_t)nw * max_n +
-                           (size_t)nw * max_m + 7 * ((size_t)max_n + max_nn)) +
+                           (size_t)fused_tile_doubles(nw, max_n, max_m) +
+                           7 * ((size_t)max_n + max_nn)) +
          sizeof(int) * (size_t)3 * max_n;
 }
 
 template <int NTH, int RT, int CPW>
 void fused_variant(const CompBox *boxes, int first, int count, const ProbDev *probs,
-                   const int32_t *pool, double *Rarena, int32_t *order_pool, int32_t *ranks,
+                   const int32_t *pool, int32_t *order_pool, int32_t *ranks,
                    int max_n, int max_m, int max_npx, hipStream_t st) {
   static_assert(CPW <= 32, "column mask");
   if (max_n > (NTH / 64) * CPW || max_m > 64 * RT)
@@ -2911,37 +2999,37 @@ void fused_variant(const CompBox *boxes, int first, int count, const ProbDev *pr
   if (lds > 64 * 1024)
     RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool, Rarena,
+  hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool,
                      order_pool, ranks);
   check_launch("k_compress_fused");
 }
 
 void launch_compress_fused(const CompBox *boxes, int first, int count, const ProbDev *probs,
-                           const int32_t *pool, double *Rarena, int32_t *order_pool,
-                           int32_t *ranks, int max_n, int max_m, int max_npx, hipStream_t st) {
+                           const int32_t *pool, int32_t *order_pool, int32_t *ranks, int max_n,
+                           int max_m, int max_npx, hipStream_t st) {
   if (count <= 0) return;
   if (max_n > kFusedMaxN || max_m > kFusedMaxM)
     throw DeviceError("k_compress_fused: box outside the fused class", hipErrorInvalidValue);
   switch (fused_variant_of(max_n, max_m)) {
     case 0:
-      fused_variant<256, 5, 6>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
-                               max_n, max_m, max_npx, st);
+      fused_variant<256, 5, 6>(boxes, first, count, probs, pool, order_pool, ranks, max_n,
+                               max_m, max_npx, st);
       break;
     case 1:
-      fused_variant<256, 8, 8>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
-                               max_n, max_m, max_npx, st);
+      fused_variant<256, 8, 8>(boxes, first, count, probs, pool, order_pool, ranks, max_n,
+                               max_m, max_npx, st);
       break;
     case 2:
-      fused_variant<512, 5, 6>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
-                               max_n, max_m, max_npx, st);
+      fused_variant<512, 5, 6>(boxes, first, count, probs, pool, order_pool, ranks, max_n,
+                               max_m, max_npx, st);
       break;
     case 3:
-      fused_variant<512, 7, 8>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
-                               max_n, max_m, max_npx, st);
+      fused_variant<512, 7, 8>(boxes, first, count, probs, pool, order_pool, ranks, max_n,
+                               max_m, max_npx, st);
       break;
     default:
-      fused_variant<512, 8, 10>(boxes, first, count, probs, pool, Rarena, order_pool, ranks,
-                                max_n, max_m, max_npx, st);
+      fused_variant<512, 8, 10>(boxes, first, count, probs, pool, order_pool, ranks, max_n,
+                                max_m, max_npx, st);
   }
 }
 

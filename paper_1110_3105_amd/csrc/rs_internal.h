@@ -165,8 +165,8 @@ void launch_sketch(bool cplx, const CompBox *comp, const CompBox *comp_id, int f
 int fused_variant_of(int n, int m);     // register-resident variant of a launch's largest box
 bool fused_small(int n, int m);         // fits the 256-thread variants
 void launch_compress_fused(const CompBox *boxes, int first, int count, const ProbDev *probs,
-                           const int32_t *pool, double *Rarena, int32_t *order_pool,
-                           int32_t *ranks, int max_n, int max_m, int max_npx, hipStream_t st);
+                           const int32_t *pool, int32_t *order_pool, int32_t *ranks, int max_n,
+                           int max_m, int max_npx, hipStream_t st);
 // Roots with at least kWideRootMinN unknowns are skipped by k_diag_factor and factored
 // by launch_root_wide instead: assembly by many workgroups, then a blocked Gauss-Jordan
 // inversion with one launch per panel of 16 pivot steps and one launch of many

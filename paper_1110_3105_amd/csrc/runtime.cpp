@@ -635,8 +635,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       cb.N_off = pool_total + cb.n;
       pool_total += cb.n + cb.nn;
       cb.M_off = M_total;
-      // fused boxes keep only the first k rows of R (k <= n): n x n scalars
-      M_total += (int64_t)(i < nf ? cb.n : cb.m) * cb.n;
+      // fused boxes keep their block in registers and LDS: no arena space
+      if (i >= nf) M_total += (int64_t)cb.m * cb.n;
       if (i < nfs) {
         max_n_s = std::max(max_n_s, cb.n);
         max_m_s = std::max(max_m_s, cb.m);
@@ -716,9 +716,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       for (int i = 0; i < cnt; ++i) {
         if (i < nf) {
           ProfScope ps_(RS_K_ID, st);
-          launch_compress_fused(d_comp, i, 1, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
-                                Dorder.as<int32_t>(), Dranks.as<int32_t>(), comp[i].n,
-                                comp[i].m, max_npx, st);
+          launch_compress_fused(d_comp, i, 1, d_probs, Dpool.as<int32_t>(), Dorder.as<int32_t>(),
+                                Dranks.as<int32_t>(), comp[i].n, comp[i].m, max_npx, st);
           continue;
         }
         {
@@ -747,15 +746,14 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       }
       if (nfs > 0) {
         ProfScope ps_(RS_K_ID, sst);
-        launch_compress_fused(d_comp, 0, nfs, d_probs, Dpool.as<int32_t>(), S.M.as<double>(),
-                              Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_s, max_m_s,
-                              max_npx, sst);
+        launch_compress_fused(d_comp, 0, nfs, d_probs, Dpool.as<int32_t>(), Dorder.as<int32_t>(),
+                              Dranks.as<int32_t>(), max_n_s, max_m_s, max_npx, sst);
       }
       if (nf > nfs) {
         ProfScope ps_(RS_K_ID, st);
         launch_compress_fused(d_comp, nfs, nf - nfs, d_probs, Dpool.as<int32_t>(),
-                              S.M.as<double>(), Dorder.as<int32_t>(), Dranks.as<int32_t>(),
-                              max_n_f, max_m_f, max_npx, st);
+                              Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_f, max_m_f,
+                              max_npx, st);
       }
       if (nf < cnt) {
         {
