@@ -919,6 +919,420 @@ __host__ __device__ __forceinline__ bool coop_class(int m, int n) {
   return (int64_t)m * n >= kCoopMinEntries;
 }
 
+// ---------------------------------------------------------------------------------
+// Register-resident ID of blocks beyond one workgroup's registers (the top levels' boxes,
+// up to 64 RT rows and kSplitMaxN columns), spread over G workgroups per box in one
+// cooperative launch.  Workgroup g of a box holds the columns c = g + G (w + 8 q) (wave
+// w, slot q) in the layout of k_compress_fused (lane l: rows l + 64 t) and assembles them
+// itself.  Per pivot step every workgroup offers its best column (norm, index and rows
+// j..m-1) in the box's exchange area -- agent-coherent stores, then its step count --
+// and, once all G offers are in, takes the same winner (largest norm, ties to the lowest
+// column), forms the same Householder reflector from the offered column and updates its
+// own columns.  After the last step the pivot columns' rows < k are exchanged the same
+// way and each workgroup solves T = R11^{-1} R12 for its redundant columns from LDS.  A
+// box's arithmetic does not depend on the launch (G follows from n).  Waits are bounded:
+// past kCoopSpinLimit polls the launch's abort flag is raised, every workgroup stops and
+// the box's rank is left at -1 for the host to report.
+constexpr int kSplitRT = 13, kSplitCPW = 6, kSplitThreads = 512;
+constexpr int kSplitCols = (kSplitThreads / 64) * kSplitCPW;      // columns per workgroup
+constexpr int kSplitMaxN = 112;      // k <= 112: R11 fits LDS, rows < k in two registers
+constexpr int kSplitMaxG = (kSplitMaxN + kSplitCols - 1) / kSplitCols;
+constexpr int kSplitWideG = 8;       // workgroups per box on levels of few boxes
+
+__host__ __device__ __forceinline__ int split_groups(int n) {
+  return (n + kSplitCols - 1) / kSplitCols;
+}
+// exchange area of one box (doubles): step counts (one per 64-byte line), offers of both
+// step parities (value, column), the proxy-row maxima, the offered columns of both
+// parities, then R11 (k x k, in pivot order)
+__host__ __device__ __forceinline__ int64_t split_xarea(int G) {
+  const int64_t mp = 64 * kSplitRT;
+  return 8 * G + 4 * G + G + 2 * G * mp + (int64_t)kSplitMaxN * kSplitMaxN + 8;
+}
+
+__device__ __forceinline__ void xstore(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xload(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publishes the workgroup's stores of the exchange (all of them completed first), then
+// waits until every workgroup of the box has published `seq`: lane h of wave 0 polls
+// workgroup h's count, so one poll is one round trip whatever G (G <= 64).  False on
+// abort.
+__device__ __forceinline__ bool split_exchange(unsigned *cnt, int g, int G, unsigned seq,
+                                               int *abort_flag, int *s_ok) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(cnt + 16 * g, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool ready = lane >= G;
+    bool ok = true;
+    unsigned spins = 0;
+    while (true) {
+      if (!ready)
+        ready = __hip_atomic_load(cnt + 16 * lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= seq;
+      if (__all(ready)) break;
+      const bool ab = lane == 0 &&
+          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      if (__any(ab) || ++spins > kCoopSpinLimit) {
+        if (lane == 0) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) *s_ok = ok ? 1 : 0;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+template <int RT, int CPW>
+__global__ __launch_bounds__(kSplitThreads) void k_compress_split(
+    const CompBox *__restrict__ boxes, int first, int G, const ProbDev *__restrict__ probs,
+    const int32_t *__restrict__ pool, int32_t *__restrict__ order_pool,
+    int32_t *__restrict__ ranks, double *__restrict__ xbase, int *__restrict__ abort_flag) {
+  constexpr int NTH = kSplitThreads, NW = NTH / 64;
+  extern __shared__ double smem[];
+  __shared__ double red[NW];
+  __shared__ int s_ok;
+  __shared__ double s_best;
+  __shared__ int s_bc, s_gw;
+  const int bi = blockIdx.x / G, g = blockIdx.x - bi * G;
+  const CompBox &B = boxes[first + bi];
+  const ProbDev &P = probs[B.prob];
+  const int n = B.n, nn = B.nn, m = B.m, npx = P.npx, dim = P.dim;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double *X = xbase + split_xarea(G) * bi;
+  unsigned *cnt = reinterpret_cast<unsigned *>(X);
+  double *offer = X + 8 * G;                 // [parity][h]: value, column
+  double *xpmax = offer + 4 * G;             // [h]
+  double *xcol = xpmax + G;                  // [parity][h][64 RT]
+  double *xR = xcol + 2 * G * 64 * RT;       // k x k
+  if (n == 0) {
+    if (g == 0 && tid == 0) ranks[B.kslot] = 0;
+    return;
+  }
+  const int32_t *J = pool + B.J_off;
+  const int32_t *N = pool + B.N_off;
+  // LDS: proxy vectors, then the assembly region (staged points and per-wave column
+  // tiles) which the T solve later reuses for R11, then the column state
+  double *sh_u = smem;                                        // 3 npx
+  double *reg = sh_u + 3 * npx;
+  const int assemble_d = 7 * (n + nn) + NW * m;
+  const int kmax = min(m, n);
+  double *pts = reg;                                          // 7 (n + nn)
+  double *tile = pts + 7 * (n + nn);                          // NW m
+  double *Rl = reg;                                           // kmax^2 (T solve)
+  double *norms = reg + max(assemble_d, kmax * kmax);         // NW CPW (own columns)
+  int *gdone = reinterpret_cast<int *>(norms + NW * CPW);     // n: pivoted, any group
+  int *piv = gdone + n;                                       // kmax: column of step j
+  int *stepof = piv + kmax;                                   // n: step of a pivot column
+  int *rk = stepof + n;                                       // n: sorted class position
+
+  // ---- assembly of this group's columns (as in k_compress_fused)
+  for (int p = tid; p < npx; p += NTH) proxy_unit(dim, p, npx, sh_u + 3 * p);
+  const StagedPts Jp = stage_points(P, J, n, pts, NTH);
+  const StagedPts Np = stage_points(P, N, nn, pts + 7 * n, NTH);
+  for (int c = tid; c < n; c += NTH) gdone[c] = 0;
+  double wmax = 0.0;
+  for (int j = tid; j < n; j += NTH) wmax = fmax(wmax, P.w[J[j]]);
+  wmax = block_max_w<NW>(wmax, red);
+  const double wG = dim == 2 ? 2.0 * kPi * B.rho / npx : 4.0 * kPi * B.rho * B.rho / npx;
+  const int rows = 2 * nn + 2 * npx;
+  double pmax = 0.0;
+  double val[CPW][RT];
+  double *mytile = tile + wave * m;
+  const bool sym = P.kind == RS_LAP2D_SL || P.kind == RS_LAP3D_SL;
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = g + G * (wave + NW * q);
+    if (c < n && sym) {
+      double xs[3], ns[3];
+      Jp.load(dim, c, xs, ns);
+      const double wc = Jp.w[c];
+      for (int i = lane; i < nn; i += 64) {
+        double xq[3], nq[3];
+        Np.load(dim, i, xq, nq);
+        const double gv = kernel_val<double>(P, xq, xs, ns);
+        mytile[i] = gv * wc;
+        mytile[nn + i] = gv * Np.w[i];
+      }
+      for (int p = lane; p < npx; p += 64) {
+        const double *u = sh_u + 3 * p;
+        const double y[3] = {B.cen[0] + B.rho * u[0], B.cen[1] + B.rho * u[1],
+                             B.cen[2] + B.rho * u[2]};
+        const double gv = kernel_val<double>(P, y, xs, ns);
+        const double a = gv * wc, b = gv * wG;
+        pmax = fmax(pmax, fmax(fabs(a), fabs(b)));
+        mytile[2 * nn + p] = a;
+        mytile[2 * nn + npx + p] = b;
+      }
+      wave_sync();
+    } else if (c < n) {
+      for (int i = lane; i < rows; i += 64) {
+        const double v = comp_entry_staged<double>(P, B, Jp, Np, sh_u, wG, i, c);
+        if (i >= 2 * nn) pmax = fmax(pmax, fabs(v));
+        mytile[i] = v;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      val[q][t] = (c < n && i < rows) ? mytile[i] : 0.0;
+    }
+  }
+  unsigned seq = 0;
+  if (P.log_kernel) {
+    // the proxy-row maximum over the whole box, through the exchange
+    pmax = block_max_w<NW>(pmax, red);
+    if (tid == 0) xstore(xpmax + g, pmax);
+    if (!split_exchange(cnt, g, G, ++seq, abort_flag, &s_ok)) {
+      if (g == 0 && tid == 0) ranks[B.kslot] = -1;
+      return;
+    }
+    pmax = wave_max(lane < G ? xload(xpmax + lane) : 0.0);
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const int c = g + G * (wave + NW * q);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int i = lane + 64 * t;
+        if (c < n && i == rows) val[q][t] = pmax * P.w[J[c]] / wmax;
+        if (c < n && i == rows + 1) val[q][t] = pmax;
+      }
+    }
+  }
+  // ---- initial column norms (one wave_sum8 group: CPW <= 8)
+  static_assert(CPW <= 8, "one reduction group per wave");
+  {
+    double x[8];
+#pragma unroll
+    for (int qq = 0; qq < 8; ++qq) {
+      double s = 0.0;
+      if (qq < CPW) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) s += val[qq][t] * val[qq][t];
+      }
+      x[qq] = s;
+    }
+    const double tot = wave_sum8(x);
+    const int q = lane >> 3;
+    if ((lane & 7) == 0 && q < CPW) norms[wave + NW * q] = sqrt(tot);
+  }
+  __syncthreads();
+
+  // ---- pivot steps
+  const double eps = P.eps;
+  int k = kmax;
+  double r00 = 0.0;
+  unsigned mine_done = 0;
+  bool aborted = false;
+  for (int j = 0; j < kmax; ++j) {
+    const int par = j & 1;
+    // this group's best column (every wave scans the group's norms)
+    double lbest = -1.0;
+    int lbc = INT_MAX;
+    for (int cl = lane; cl < NW * CPW; cl += 64) {
+      const int c = g + G * cl;
+      if (c >= n || gdone[c]) continue;
+      const double v = norms[cl];
+      if (v > lbest || (v == lbest && c < lbc)) { lbest = v; lbc = c; }
+    }
+    const ArgMax am = wave_argmax(lbest, lbc, lbc);
+    // offer it: value and column, and its rows j..m-1
+    if (am.key != INT_MAX) {
+      const int cl = (am.key - g) / G, ow = cl % NW, oq = cl / NW;
+      if (wave == ow) {
+#pragma unroll
+        for (int q = 0; q < CPW; ++q)
+          if (q == oq)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+              const int i = lane + 64 * t;
+              if (i >= j && i < m) xstore(xcol + ((int64_t)(par * G + g) * RT * 64) + i, val[q][t]);
+            }
+      }
+    }
+    if (tid == 0) {
+      xstore(offer + 2 * (par * G + g), am.v);
+      xstore(offer + 2 * (par * G + g) + 1, (double)am.key);
+    }
+    if (!split_exchange(cnt, g, G, ++seq, abort_flag, &s_ok)) {
+      aborted = true;      // leaves the loop (returning from inside it costs registers)
+      break;
+    }
+    if (wave == 0) {       // the offers, one lane each: largest norm, ties to the lowest column
+      const double v = lane < G ? xload(offer + 2 * (par * G + lane)) : -2.0;
+      const int c = lane < G ? (int)xload(offer + 2 * (par * G + lane) + 1) : INT_MAX;
+      const ArgMax w = wave_argmax(v, c, lane);
+      if (lane == 0) {
+        s_best = w.v;
+        s_bc = w.key;
+        s_gw = w.val;
+      }
+    }
+    __syncthreads();
+    const double best = s_best;
+    const int bc = s_bc, gw = s_gw;
+    if (j == 0) r00 = best;
+    if (best <= 0.0 || best <= eps * r00) { k = j; break; }
+    // the reflector of the winning column, rows j..m-1, formed by every wave
+    const double *xc = xcol + (int64_t)(par * G + gw) * RT * 64;
+    double vi[RT];
+    double xj = 0.0;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      vi[t] = (i >= j && i < m) ? xload(xc + i) : 0.0;
+      if (t == (j >> 6)) xj = vi[t];
+    }
+    const double alpha = best;
+    const double x0 = readlane_f64(xj, j & 63);
+    const double beta = x0 >= 0.0 ? -alpha : alpha;
+    const double scale = 1.0 / (x0 - beta);
+    const double ctau = (beta - x0) / beta;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int i = lane + 64 * t;
+      vi[t] = i > j ? vi[t] * scale : (i == j ? 1.0 : 0.0);
+    }
+    if (tid == 0) {
+      gdone[bc] = 1;
+      piv[j] = bc;
+      stepof[bc] = j;
+    }
+    // the winning column itself (its group): R(j, bc) = beta, Householder vector below
+    if (gw == g) {
+      const int cl = (bc - g) / G, ow = cl % NW, oq = cl / NW;
+      if (wave == ow) {
+#pragma unroll
+        for (int q = 0; q < CPW; ++q)
+          if (q == oq) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+              const int i = lane + 64 * t;
+              if (i == j) val[q][t] = beta;
+              else if (i > j && i < m) val[q][t] = vi[t];
+            }
+          }
+        mine_done |= 1u << oq;
+      }
+    }
+    // update of the group's other columns and their norms over rows > j
+    {
+      double x[8];
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) {
+        double dot = 0.0;
+        if (qq < CPW && g + G * (wave + NW * qq) < n && !((mine_done >> qq) & 1u)) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t) dot += vi[t] * val[qq][t];
+        }
+        x[qq] = dot;
+      }
+      const double dots = wave_sum8(x);
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) {
+        double nr = 0.0;
+        if (qq < CPW && g + G * (wave + NW * qq) < n && !((mine_done >> qq) & 1u)) {
+          const double dot = readlane_f64(dots, 8 * qq) * ctau;
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int i = lane + 64 * t;
+            const double nv = val[qq][t] - dot * vi[t];
+            val[qq][t] = nv;
+            if (i > j) nr += nv * nv;
+          }
+        }
+        x[qq] = nr;
+      }
+      const double nrs = wave_sum8(x);
+      const int q = lane >> 3;
+      if ((lane & 7) == 0 && q < CPW && g + G * (wave + NW * q) < n && !((mine_done >> q) & 1u))
+        norms[wave + NW * q] = sqrt(nrs);
+    }
+    __syncthreads();
+  }
+  if (aborted) {
+    if (g == 0 && tid == 0) ranks[B.kslot] = -1;
+    return;
+  }
+  __syncthreads();
+  // ---- rows < k of the group's pivot columns to the exchange (R11 in pivot order)
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = g + G * (wave + NW * q);
+    if (c < n && ((mine_done >> q) & 1u)) {
+      const int s = stepof[c];
+      if (s < k) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = lane + 64 * t;
+          if (i < k) xstore(xR + i + (int64_t)k * s, val[q][t]);
+        }
+      }
+    }
+  }
+  if (!split_exchange(cnt, g, G, ++seq, abort_flag, &s_ok)) {
+    if (g == 0 && tid == 0) ranks[B.kslot] = -1;
+    return;
+  }
+  for (int e = tid; e < k * k; e += NTH) Rl[e] = xload(xR + e);
+  // sorted positions of the columns within their class (n <= 128: two masks)
+  if (wave == 0) {
+    const bool s0 = lane < n && gdone[lane] != 0 && stepof[lane] < k;
+    const bool s1 = lane + 64 < n && gdone[lane + 64] != 0 && stepof[lane + 64] < k;
+    const uint64_t m0 = __ballot(s0), m1 = __ballot(s1);
+    const uint64_t v0 = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    const uint64_t v1 = n >= 128 ? ~0ull : (n > 64 ? ((1ull << (n - 64)) - 1ull) : 0ull);
+    const uint64_t below = (1ull << lane) - 1ull;
+    int32_t *order = order_pool + B.order_off;
+    if (lane < n) {
+      const int r = s0 ? __popcll(m0 & below) : __popcll(~m0 & v0 & below);
+      if (g == 0) order[s0 ? r : k + r] = lane;
+      rk[lane] = r;
+    }
+    if (lane + 64 < n) {
+      const int r = s1 ? __popcll(m0) + __popcll(m1 & below)
+                       : __popcll(~m0 & v0) + __popcll(~m1 & v1 & below);
+      if (g == 0) order[s1 ? r : k + r] = lane + 64;
+      rk[lane + 64] = r;
+    }
+  }
+  __syncthreads();
+  // ---- T = R11^{-1} R12 for this group's redundant columns: one wave per column,
+  // right-looking substitution as in k_compress_fused (k <= 128: rows l and l + 64)
+  double *T = B.T;
+  const int pv0 = lane < k ? piv[lane] : 0, pv1 = lane + 64 < k ? piv[lane + 64] : 0;
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = g + G * (wave + NW * q);
+    if (c >= n || (gdone[c] && stepof[c] < k)) continue;
+    double b0 = lane < k ? val[q][0] : 0.0;
+    double b1 = lane + 64 < k ? val[q][1] : 0.0;
+    for (int i = k - 1; i >= 0; --i) {
+      const double *Rc = Rl + (int64_t)k * i;        // R11 column of step i
+      const double rii = Rc[i];
+      const double ra0 = lane < k ? Rc[lane] : 0.0;
+      const double ra1 = lane + 64 < k ? Rc[lane + 64] : 0.0;
+      const double x = (i < 64 ? readlane_f64(b0, i) : readlane_f64(b1, i - 64)) / rii;
+      if (lane < i) b0 -= ra0 * x;
+      else if (lane == i) b0 = x;
+      if (lane + 64 < i) b1 -= ra1 * x;
+      else if (lane + 64 == i) b1 = x;
+    }
+    double *Tc = T + (int64_t)k * rk[c];
+    if (lane < k) Tc[rk[pv0]] = b0;
+    if (lane + 64 < k) Tc[rk[pv1]] = b1;
+  }
+  if (g == 0 && tid == 0) ranks[B.kslot] = k;
+}
+
 // --------------------------------------------------------------------------
 // Row sketch Y = Omega M of a compression block for the randomized ID (Section 2.2):
 // Omega is ell x m with entries +-1, entry (a, i) of tree box b set by the top bit of
@@ -3033,6 +3447,83 @@ void launch_compress_fused(const CompBox *boxes, int first, int count, const Pro
   }
 }
 
+namespace {
+int g_coop_supported = -1;     // cooperative launches available on the device (-1: unknown)
+}  // namespace
+
+bool split_class(bool cplx, int n, int m) {
+  return !cplx && !fused_class(cplx, n, m) && n <= kSplitMaxN && m <= 64 * kSplitRT;
+}
+
+size_t split_lds_bytes(int max_n, int max_m, int max_npx) {
+  const int nw = kSplitThreads / 64;
+  const size_t max_nn = (size_t)max_m / 2;
+  const size_t kmax = (size_t)std::min(max_n, max_m);
+  const size_t assemble = 7 * ((size_t)max_n + max_nn) + (size_t)nw * max_m;
+  return sizeof(double) * (3 * (size_t)max_npx + std::max(assemble, kmax * kmax) +
+                           (size_t)nw * kSplitCPW) +
+         sizeof(int) * (3 * (size_t)max_n + kmax);
+}
+
+void launch_compress_split(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                           const int32_t *pool, int32_t *order_pool, int32_t *ranks, int max_n,
+                           int max_m, int max_npx, hipStream_t st) {
+  if (count <= 0) return;
+  if (max_n > kSplitMaxN || max_m > 64 * kSplitRT)
+    throw DeviceError("k_compress_split: box outside the split class", hipErrorInvalidValue);
+  if (g_coop_supported < 0) {
+    int dev = 0, v = 0;
+    RS_HIP_CHECK(hipGetDevice(&dev));
+    RS_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev));
+    g_coop_supported = v ? 1 : 0;
+  }
+  // at least enough workgroups for the columns; more (up to kSplitWideG) when the level
+  // has few boxes -- a box's arithmetic does not depend on G
+  const int G = std::max(split_groups(max_n), std::min(kSplitWideG, 256 / std::max(count, 1)));
+  if (G > 1 && !g_coop_supported)
+    throw DeviceError("k_compress_split: cooperative launches unavailable", hipErrorNotSupported);
+  const size_t lds = split_lds_bytes(max_n, max_m, max_npx);
+  if (lds > kMaxLds) throw DeviceError("k_compress_split: LDS", hipErrorInvalidValue);
+  auto kern = k_compress_split<kSplitRT, kSplitCPW>;
+  if (lds > 64 * 1024)
+    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  // boxes per launch: every workgroup of a launch resident at once
+  int per_cu = 0, dev = 0, ncu = 0;
+  RS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern,
+                                                            kSplitThreads, lds));
+  RS_HIP_CHECK(hipGetDevice(&dev));
+  RS_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int chunk = std::max(1, (per_cu * ncu) / G);
+  if (per_cu * ncu < G)
+    throw DeviceError("k_compress_split: a box's workgroups cannot be resident together",
+                      hipErrorInvalidValue);
+  // exchange areas (step counts zeroed) and the abort flag
+  const int per_launch = std::min(count, chunk);
+  const size_t xbytes = (size_t)per_launch * (size_t)split_xarea(G) * sizeof(double);
+  char *mem = nullptr;
+  RS_HIP_CHECK(hipMallocAsync((void **)&mem, xbytes + 256, st));
+  for (int b0 = 0; b0 < count; b0 += chunk) {
+    const int nb = std::min(chunk, count - b0);
+    RS_HIP_CHECK(hipMemsetAsync(mem, 0, xbytes + 256, st));
+    double *xb = reinterpret_cast<double *>(mem);
+    int *abort_flag = reinterpret_cast<int *>(mem + xbytes);
+    int f = first + b0, gg = G;
+    const dim3 grid(nb * G), block(kSplitThreads);
+    if (G > 1) {
+      void *args[] = {(void *)&boxes, (void *)&f, (void *)&gg, (void *)&probs, (void *)&pool,
+                      (void *)&order_pool, (void *)&ranks, (void *)&xb, (void *)&abort_flag};
+      RS_HIP_CHECK(hipLaunchCooperativeKernel((const void *)kern, grid, block, args,
+                                              (unsigned)lds, st));
+    } else {
+      hipLaunchKernelGGL(kern, grid, block, lds, st, boxes, f, gg, probs, pool, order_pool,
+                         ranks, xb, abort_flag);
+    }
+    check_launch("k_compress_split");
+  }
+  RS_HIP_CHECK(hipFreeAsync(mem, st));
+}
+
 size_t cpqr_lds_bytes(bool cplx, int max_n, int max_m) {
   return cpqr_lds_bytes_nt(256, max_n, max_m, cplx ? 2 : 1);
 }
@@ -3048,8 +3539,6 @@ size_t coop_lds_bytes(int max_n, int max_m, int G, int es, bool vlds) {
   const size_t vb = std::max<size_t>(vlds ? (size_t)max_m : 0, (size_t)4 * kmax) * 8 * es;
   return head + vb;
 }
-
-int g_coop_supported = -1;     // cooperative launches available on the device (-1: unknown)
 
 void launch_cpqr_coop(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
                       double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,

@@ -23,7 +23,8 @@ namespace rs {
 // word, so a worker still finishing one job can never take a chunk of the next.  Idle
 // workers spin for kSpinUs before sleeping on a condition variable (a planner issues
 // its parallel loops in bursts a few hundred microseconds apart; waking sleeping
-// threads costs tens of microseconds per loop).
+// threads costs tens of microseconds per loop, while longer spins take the host's cores
+// from the GPU runtime's own threads).
 constexpr int kPlanThreads = 16;
 constexpr int kSpinUs = 300;
 class PlanPool {

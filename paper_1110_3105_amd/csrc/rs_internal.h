@@ -167,6 +167,14 @@ bool fused_small(int n, int m);         // fits the 256-thread variants
 void launch_compress_fused(const CompBox *boxes, int first, int count, const ProbDev *probs,
                            const int32_t *pool, int32_t *order_pool, int32_t *ranks, int max_n,
                            int max_m, int max_npx, hipStream_t st);
+// Real boxes beyond the fused class up to 832 rows and 112 columns are assembled and
+// compressed in the registers of ceil(n / 48) workgroups per box that exchange each pivot
+// step's offers through device memory (k_compress_split); same outputs as the fused
+// class.
+bool split_class(bool cplx, int n, int m);
+void launch_compress_split(const CompBox *boxes, int first, int count, const ProbDev *probs,
+                           const int32_t *pool, int32_t *order_pool, int32_t *ranks, int max_n,
+                           int max_m, int max_npx, hipStream_t st);
 // Roots with at least kWideRootMinN unknowns are skipped by k_diag_factor and factored
 // by launch_root_wide instead: assembly by many workgroups, then a blocked Gauss-Jordan
 // inversion with one launch per panel of 16 pivot steps and one launch of many

@@ -132,18 +132,55 @@ struct Scratch {
   DevBuf pool, comp, comp_id, fac, M, order, ranks, work, err, probs, partials;
   DevBuf pool2[2], order2[2], ranks2[2], fac2[2];
   PinnedBuf hfac[2];
+  // Pinned staging of the factor's host-to-device uploads: stage() hands out space after
+  // the previous staging (its copies may still be queued); stage_reset() returns all of
+  // it once the stream that carries the copies has been synchronized.  A grow waits for
+  // the device first, so queued copies never read freed memory.
+  PinnedBuf hup;
+  size_t hup_used = 0;
+  void *stage(size_t bytes) {
+    size_t off = (hup_used + 255) & ~size_t(255);
+    if (off + bytes > hup.bytes) {
+      hup.ensure(std::max(off + bytes, 2 * hup.bytes));
+      off = 0;
+    }
+    hup_used = off + bytes;
+    return static_cast<char *>(hup.p) + off;
+  }
+  void stage_reset() { hup_used = 0; }
+  template <class T>
+  void upload(DevBuf &buf, const std::vector<T> &v, hipStream_t st) {
+    const size_t bytes = v.size() * sizeof(T);
+    buf.ensure(std::max<size_t>(bytes, 8));
+    if (!bytes) return;
+    void *h = stage(bytes);
+    std::memcpy(h, v.data(), bytes);
+    RS_HIP_CHECK(hipMemcpyAsync(buf.p, h, bytes, hipMemcpyHostToDevice, st));
+  }
   hipStream_t side = nullptr;                 // box factorizations of compressed levels
   hipStream_t aux = nullptr;                  // the direct compression class of a level
   hipStream_t aux2 = nullptr;                 // the small fused boxes of a level
   hipEvent_t ev_comp = nullptr, ev_side = nullptr, ev_diag[2] = {nullptr, nullptr};
-  hipEvent_t ev_up = nullptr, ev_aux = nullptr, ev_aux2 = nullptr;
+  hipEvent_t ev_up = nullptr, ev_aux = nullptr, ev_aux2 = nullptr, ev_wait = nullptr;
   void init_streams() {
     if (side) return;
     RS_HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     RS_HIP_CHECK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
     RS_HIP_CHECK(hipStreamCreateWithFlags(&aux2, hipStreamNonBlocking));
-    for (hipEvent_t *e : {&ev_comp, &ev_side, &ev_diag[0], &ev_diag[1], &ev_up, &ev_aux, &ev_aux2})
+    for (hipEvent_t *e : {&ev_comp, &ev_side, &ev_diag[0], &ev_diag[1], &ev_up, &ev_aux, &ev_aux2,
+                          &ev_wait})
       RS_HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
+  // Waits for the work queued on st by polling an event: the level loop waits for each
+  // level's ranks, and a blocking wait adds the thread's wake-up to every level.
+  void wait_stream(hipStream_t st) {
+    RS_HIP_CHECK(hipEventRecord(ev_wait, st));
+    while (true) {
+      const hipError_t e = hipEventQuery(ev_wait);
+      if (e == hipSuccess) return;
+      if (e != hipErrorNotReady) RS_HIP_CHECK(e);
+      __builtin_ia32_pause();
+    }
   }
 };
 
@@ -153,12 +190,6 @@ Scratch &scratch() {
   return *s;
 }
 
-template <class T>
-void upload(DevBuf &buf, const std::vector<T> &v, hipStream_t st) {
-  buf.ensure(std::max<size_t>(v.size() * sizeof(T), 8));
-  if (!v.empty())
-    RS_HIP_CHECK(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
-}
 
 struct ProbState {
   const FactorRequest *req = nullptr;
@@ -260,7 +291,7 @@ void plan_near(ProbState &ps, int d, std::vector<std::vector<int32_t>> &near) {
 }
 
 // Copies the geometry of one request to device memory in tree order.
-void setup_problem(ProbState &ps, hipStream_t st) {
+void setup_problem(ProbState &ps, Scratch &S, hipStream_t st) {
   const rs_kernel &k = *ps.req->k;
   const Tree &t = *ps.t;
   rs_factor_s *h = ps.h;
@@ -270,27 +301,31 @@ void setup_problem(ProbState &ps, hipStream_t st) {
   h->n = n;
   h->kind = k.kind;
   h->cplx = k.kind == RS_HELM2D_CFIE || k.kind == RS_HELM3D_SL;
-  std::vector<double> host((size_t)n * (2 * dim + 2), 0.0);
-  double *hx = host.data();
+  // points, normals, weights and curvature in tree order, then the permutation, through
+  // the pinned staging (no wait: the staging is reused after the stream's next wait)
+  const size_t nd = (size_t)n * (2 * dim + 2);
+  double *hx = static_cast<double *>(S.stage(nd * sizeof(double) + (size_t)n * sizeof(int64_t)));
   double *hn = hx + (size_t)dim * n;
   double *hw = hn + (size_t)dim * n;
   double *hk = hw + n;
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t g = t.perm[i];
-    for (int a = 0; a < dim; ++a) {
-      hx[(size_t)a * n + i] = ps.req->points[g * dim + a];
-      if (k.normals) hn[(size_t)a * n + i] = k.normals[g * dim + a];
+  int64_t *hp = reinterpret_cast<int64_t *>(hx + nd);
+  const int64_t chunk = 4096;
+  parallel_for((int)((n + chunk - 1) / chunk), [&](int ci) {
+    for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
+      const int64_t g = t.perm[i];
+      for (int a = 0; a < dim; ++a) {
+        hx[(size_t)a * n + i] = ps.req->points[g * dim + a];
+        hn[(size_t)a * n + i] = k.normals ? k.normals[g * dim + a] : 0.0;
+      }
+      hw[i] = ps.req->weights[g];
+      hk[i] = k.curvature ? k.curvature[g] : 0.0;
+      hp[i] = g;
     }
-    hw[i] = ps.req->weights[g];
-    hk[i] = k.curvature ? k.curvature[g] : 0.0;
-  }
-  double *d = h->arena.alloc_n<double>((int64_t)host.size());
-  RS_HIP_CHECK(hipMemcpyAsync(d, host.data(), host.size() * sizeof(double),
-                              hipMemcpyHostToDevice, st));
+  }, 1);
+  double *d = h->arena.alloc_n<double>((int64_t)nd);
+  RS_HIP_CHECK(hipMemcpyAsync(d, hx, nd * sizeof(double), hipMemcpyHostToDevice, st));
   h->d_perm = h->arena.alloc_n<int64_t>(n);
-  RS_HIP_CHECK(hipMemcpyAsync(h->d_perm, t.perm.data(), n * sizeof(int64_t),
-                              hipMemcpyHostToDevice, st));
-  RS_HIP_CHECK(hipStreamSynchronize(st));   // `host` is released on return
+  RS_HIP_CHECK(hipMemcpyAsync(h->d_perm, hp, n * sizeof(int64_t), hipMemcpyHostToDevice, st));
   ProbDev &P = h->prob;
   std::memset(&P, 0, sizeof(P));
   for (int a = 0; a < dim; ++a) {
@@ -408,12 +443,12 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     ps[p].h = handles[p].get();
     ps[p].t = reqs[p].tree;
     ps[p].pidx = p;
-    setup_problem(ps[p], st);
+    setup_problem(ps[p], S, st);
     probs[p] = handles[p]->prob;
     max_npx = std::max(max_npx, ps[p].npx);
     max_depth = std::max(max_depth, ps[p].t->maxdepth);
   }
-  upload(S.probs, probs, st);
+  S.upload(S.probs, probs, st);
   const ProbDev *d_probs = S.probs.as<ProbDev>();
   const bool cplx = np > 0 && handles[0]->cplx;
   const int es = cplx ? 2 : 1;                 // doubles per scalar
@@ -576,18 +611,22 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       }
     }
     // boxes of the fused (register-resident) compression class first -- the ones that
-    // fit the 256-thread variants, then the others -- then the direct class, so that each
-    // class is one contiguous range of the launch (stable order)
-    int nf = 0, nfs = 0;
+    // fit the 256-thread variants, then the others -- then the split class (registers of
+    // two workgroups), then the direct class, so that each class is one contiguous range
+    // of the launch (stable order)
+    int nf = 0, nfs = 0, nsp = 0;
     {
       std::vector<char> fz(cnt);
       for (int i = 0; i < cnt; ++i) {
         const ProbState &P = *items[i].ps;
         const int n = (int)P.J[items[i].box].size();
         const int m = 2 * (int)near_all[i].size() + 2 * P.npx + (P.log_kernel ? 2 : 0);
-        fz[i] = (!P.sketch && fused_class(cplx, n, m)) ? (fused_small(n, m) ? 2 : 1) : 0;
-        nf += fz[i] > 0;
+        fz[i] = P.sketch ? 0
+                : fused_class(cplx, n, m) ? (fused_small(n, m) ? 2 : 1)
+                : split_class(cplx, n, m) ? 3 : 0;
+        nf += fz[i] == 1 || fz[i] == 2;
         nfs += fz[i] == 2;
+        nsp += fz[i] == 3;
       }
       // Within the 512-thread fused class (one workgroup per CU, several rounds per
       // launch on wide levels) the largest blocks go first, so that the last round holds
@@ -602,7 +641,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       std::vector<std::vector<int32_t>> nr2;
       it2.reserve(cnt);
       nr2.reserve(cnt);
-      for (int pass = 2; pass >= 0; --pass) {
+      for (int pass : {2, 1, 3, 0}) {
         std::vector<int> sel;
         for (int i = 0; i < cnt; ++i)
           if (fz[i] == pass) sel.push_back(i);
@@ -617,10 +656,12 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       items.swap(it2);
       near_all.swap(nr2);
     }
+    const int nd0 = nf + nsp;        // first box of the direct class
     std::vector<CompBox> comp(cnt);
     int64_t M_total = 0, order_total = 0, work_total = 0, pool_total = 0;
     int max_n = 0, max_m_step = 0;
     int max_n_f = 0, max_m_f = 0, max_n_s = 0, max_m_s = 0, max_n_d = 0, max_m_d = 0;
+    int max_n_sp = 0, max_m_sp = 0;
     for (int i = 0; i < cnt; ++i) {
       ProbState &P = *items[i].ps;
       const int b = items[i].box;
@@ -635,14 +676,17 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       cb.N_off = pool_total + cb.n;
       pool_total += cb.n + cb.nn;
       cb.M_off = M_total;
-      // fused boxes keep their block in registers and LDS: no arena space
-      if (i >= nf) M_total += (int64_t)cb.m * cb.n;
+      // fused and split boxes keep their block in registers and LDS: no arena space
+      if (i >= nd0) M_total += (int64_t)cb.m * cb.n;
       if (i < nfs) {
         max_n_s = std::max(max_n_s, cb.n);
         max_m_s = std::max(max_m_s, cb.m);
       } else if (i < nf) {
         max_n_f = std::max(max_n_f, cb.n);
         max_m_f = std::max(max_m_f, cb.m);
+      } else if (i < nd0) {
+        max_n_sp = std::max(max_n_sp, cb.n);
+        max_m_sp = std::max(max_m_sp, cb.m);
       } else {
         max_n_d = std::max(max_n_d, cb.n);
         max_m_d = std::max(max_m_d, cb.m);
@@ -666,11 +710,11 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     std::vector<CompBox> comp_id;
     int max_m_id = max_m_d, max_sketch_tiles = 0;
     bool any_sketch = false;
-    for (int i = nf; i < cnt; ++i) any_sketch = any_sketch || items[i].ps->sketch;
+    for (int i = nd0; i < cnt; ++i) any_sketch = any_sketch || items[i].ps->sketch;
     if (any_sketch) {
       comp_id = comp;
       max_m_id = 0;
-      for (int i = nf; i < cnt; ++i) {
+      for (int i = nd0; i < cnt; ++i) {
         CompBox &ci = comp_id[i];
         const ProbState &P = *items[i].ps;
         const int ell = P.sketch ? std::min<int64_t>(ci.m, (int64_t)ci.n + P.oversample) : ci.m;
@@ -698,14 +742,14 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     DevBuf &Dpool = S.pool2[par], &Dorder = S.order2[par], &Dranks = S.ranks2[par];
     DevBuf &Dfac = S.fac2[par];
     if (diag_pending[par]) RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_diag[par], 0));
-    upload(Dpool, pool, st);
-    upload(S.comp, comp, st);
-    if (any_sketch) upload(S.comp_id, comp_id, st);
+    S.upload(Dpool, pool, st);
+    S.upload(S.comp, comp, st);
+    if (any_sketch) S.upload(S.comp_id, comp_id, st);
     S.M.ensure(std::max<int64_t>(M_total, 1) * sizeof(double) * es);
     Dorder.ensure(std::max<int64_t>(order_total, 1) * sizeof(int32_t));
     Dranks.ensure(std::max(cnt, 1) * sizeof(int32_t));
     S.work.ensure(std::max<int64_t>(work_total, 1) * sizeof(double) * es);
-    S.partials.ensure((size_t)std::max(cnt - nf, 1) * assemble_chunks(max_n_d, max_m_d) *
+    S.partials.ensure((size_t)std::max(cnt - nd0, 1) * assemble_chunks(max_n_d, max_m_d) *
                       sizeof(double));
     const CompBox *d_comp = S.comp.as<CompBox>();
     const CompBox *d_comp_id = any_sketch ? S.comp_id.as<CompBox>() : d_comp;
@@ -717,6 +761,12 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
         if (i < nf) {
           ProfScope ps_(RS_K_ID, st);
           launch_compress_fused(d_comp, i, 1, d_probs, Dpool.as<int32_t>(), Dorder.as<int32_t>(),
+                                Dranks.as<int32_t>(), comp[i].n, comp[i].m, max_npx, st);
+          continue;
+        }
+        if (i < nd0) {
+          ProfScope ps_(RS_K_ID, st);
+          launch_compress_split(d_comp, i, 1, d_probs, Dpool.as<int32_t>(), Dorder.as<int32_t>(),
                                 Dranks.as<int32_t>(), comp[i].n, comp[i].m, max_npx, st);
           continue;
         }
@@ -735,7 +785,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       }
     } else {
       // the classes touch disjoint boxes: with more than one present, the small fused
-      // boxes and the direct class run on auxiliary streams beside the other fused boxes
+      // boxes and the split and direct classes run on auxiliary streams beside the other
+      // fused boxes
       const int nclass = (nfs > 0) + (nf > nfs) + (nf < cnt);
       const bool both = nclass > 1;
       hipStream_t dst = both ? S.aux : st, sst = both ? S.aux2 : st;
@@ -755,18 +806,23 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                               Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_f, max_m_f,
                               max_npx, st);
       }
-      if (nf < cnt) {
+      if (nsp > 0) {
+        ProfScope ps_(RS_K_ID, dst);
+        launch_compress_split(d_comp, nf, nsp, d_probs, Dpool.as<int32_t>(), Dorder.as<int32_t>(),
+                              Dranks.as<int32_t>(), max_n_sp, max_m_sp, max_npx, dst);
+      }
+      if (nd0 < cnt) {
         {
           ProfScope ps_(RS_K_ASSEMBLE, dst);
-          launch_assemble(cplx, d_comp, nf, cnt - nf, d_probs, Dpool.as<int32_t>(),
+          launch_assemble(cplx, d_comp, nd0, cnt - nd0, d_probs, Dpool.as<int32_t>(),
                           S.M.as<double>(), max_npx, max_n_d, max_m_d, S.partials.as<double>(),
                           dst);
         }
         ProfScope ps_(RS_K_ID, dst);
         if (any_sketch)
-          launch_sketch(cplx, d_comp, d_comp_id, nf, cnt - nf, d_probs, S.M.as<double>(),
+          launch_sketch(cplx, d_comp, d_comp_id, nd0, cnt - nd0, d_probs, S.M.as<double>(),
                         max_sketch_tiles, dst);
-        launch_cpqr_id(cplx, d_comp_id, nf, cnt - nf, d_probs, S.M.as<double>(),
+        launch_cpqr_id(cplx, d_comp_id, nd0, cnt - nd0, d_probs, S.M.as<double>(),
                        Dorder.as<int32_t>(), Dranks.as<int32_t>(), max_n_d, max_m_id, dst);
       }
       if (both) {
@@ -836,9 +892,10 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                                   hipMemcpyDeviceToHost, st));
     {
       auto tw = Clock::now();
-      RS_HIP_CHECK(hipStreamSynchronize(st));
+      S.wait_stream(st);
       wait_ms += ms_since(tw);
     }
+    S.stage_reset();
     keep_alive.clear();            // the uploads queued before this wait have completed
     auto tp2 = Clock::now();
     for (int i = 0; i < cnt; ++i)
@@ -851,7 +908,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       const CompBox &cb = comp[i];
       const int k = ranks[i];
       items[i].ps->h->box_k[items[i].box] = k;
-      if (i < nf) {
+      if (i < nd0) {
         w_id += work_fused(cb.m, cb.n, k);
       } else {
         w_asm += work_assemble(cb.m, cb.n, cplx);
@@ -917,8 +974,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       P.h->box_J[b] = J;
       P.h->box_slot[b] = fb.slot;
     }
-    upload(S.pool, pool, st);
-    upload(S.fac, fac, st);
+    S.upload(S.pool, pool, st);
+    S.upload(S.fac, fac, st);
     S.work.ensure(std::max<int64_t>(woff, 1) * sizeof(double) * es);
     const FacBox *d_fac = S.fac.as<FacBox>();
     const int err_base = (int)all_items.size();
@@ -999,6 +1056,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                                 hipMemcpyHostToDevice, st));
   }
   RS_HIP_CHECK(hipStreamSynchronize(st));
+  S.stage_reset();
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   // per-level device times: step s held depth maxdepth - s of each problem; the root last
