@@ -363,12 +363,25 @@ typedef struct {
   double window_ms;             /* first submission -> last completion */
 } rs_server_stats;
 
+/* Device footprint of rs_factor(k, t, points, weights, eps) before it runs, from the
+ * tree, the kernel and eps only (host computation; no device needed): a rank model
+ * (skeletons per box growing with the box's height and the decades of eps, never more
+ * than its active set), giving the bytes the handle keeps (*resident) and the bytes the
+ * factorization needs besides while it runs (*transient).  The server admits factor
+ * requests by resident * c + transient, where c >= 1 is the ratio of kept to predicted
+ * bytes of its earlier factorizations of the same kernel and decade of eps.
+ * Errors: RS_EINVAL. */
+rs_status rs_factor_estimate(const rs_kernel *k, rs_tree t, double eps, size_t *resident,
+                             size_t *transient);
+
 /* Creates a server on the current device.  Errors: RS_EINVAL, RS_EDEVICE. */
 rs_status rs_server_create(const rs_server_opts *opts, rs_server *out);
 
 /* Queues a factorization (arguments as rs_factor; inputs are copied, so they may be
- * freed on return).  A request whose estimated footprint exceeds the whole budget
- * completes at once with RS_ENOMEM.  *ticket identifies the request. */
+ * freed on return).  It is admitted when its estimated footprint (rs_factor_estimate,
+ * corrected as described there) fits the budget left by the resident factorizations and
+ * the admitted ones; a request whose estimate exceeds the whole budget completes at once
+ * with RS_ENOMEM.  *ticket identifies the request. */
 rs_status rs_server_submit_factor(rs_server s, const rs_kernel *k, rs_tree t,
                                   const double *points, const double *weights, double eps,
                                   uint64_t *ticket);

@@ -39,7 +39,8 @@ EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "
             "rs_server_submit_solve", "rs_server_poll", "rs_server_release", "rs_server_query",
             "rs_server_reset_stats", "rs_server_destroy", "rs_plan_create", "rs_plan_launch",
             "rs_plan_free", "rs_autotune", "rs_tune_entries", "rs_tune_clear", "rs_tune_save",
-            "rs_tune_load", "rs_solve_noalloc", "rs_matvec", "rs_query_levels"]
+            "rs_tune_load", "rs_solve_noalloc", "rs_matvec", "rs_query_levels",
+            "rs_factor_estimate"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -106,6 +107,8 @@ _sig = {
     "rs_last_error": (C.c_char_p, []),
     "rs_device_count": (C.c_int32, []),
     "rs_query": (C.c_int, [_P, C.POINTER(rs_stats)]),
+    "rs_factor_estimate": (C.c_int, [C.POINTER(rs_kernel), _P, C.c_double,
+                                     C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "rs_query_levels": (C.c_int, [_P, C.POINTER(rs_level_stats), C.c_int32,
                                   C.POINTER(C.c_int32)]),
     "rs_box_skeletons": (C.c_int, [_P, _PI32, _PI64, C.c_int64, _PI64]),
@@ -430,6 +433,18 @@ def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: 
     _check(_lib.rs_factor_ex(C.byref(k), tree.handle, _dptr(pts), _dptr(w), float(eps),
                              C.byref(o), C.byref(h)))
     return Handle(h, pts.shape[0], keep=(tree,))
+
+
+def factor_estimate(kind: str, tree: Tree, eps: float, proxy_points: int = 64,
+                    wavenumber: float = 0.0) -> dict:
+    """Device footprint of a factorization before it runs (rs_factor_estimate): bytes the
+    handle keeps and bytes needed besides while it is factored."""
+    pts = np.zeros((1, tree.dim), dtype=np.float64)
+    k = _kernel_struct(kind, pts, None, None, 0.0, proxy_points, 1.5, wavenumber, 0.0)
+    res, tr = C.c_size_t(), C.c_size_t()
+    _check(_lib.rs_factor_estimate(C.byref(k), tree.handle, float(eps), C.byref(res),
+                                   C.byref(tr)))
+    return {"resident": res.value, "transient": tr.value}
 
 
 def _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber=0.0,

@@ -476,6 +476,18 @@ rs_status rs_query(rs_handle h, rs_stats *out) {
   });
 }
 
+rs_status rs_factor_estimate(const rs_kernel *k, rs_tree t, double eps, size_t *resident,
+                             size_t *transient) {
+  return guarded([&]() -> rs_status {
+    if (!k || !t || !resident || !transient) fail(RS_EINVAL, "NULL argument");
+    if (!(eps >= 0.0)) fail(RS_EINVAL, "eps must be >= 0");
+    const FootprintEstimate e = factor_footprint(*k, t->t, eps);
+    *resident = e.resident;
+    *transient = e.transient;
+    return RS_OK;
+  });
+}
+
 rs_status rs_query_levels(rs_handle h, rs_level_stats *out, int32_t cap, int32_t *count) {
   return guarded([&]() -> rs_status {
     if (!h || !count) fail(RS_EINVAL, "NULL argument");

@@ -106,30 +106,47 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 }
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
 
-// Wave sums of eight per-lane values at once: afterwards every lane of the 8-lane group
-// g = lane >> 3 holds the total of value g.  Lane bits 5, 4 and 3 are folded by
-// exchanges in which each lane keeps half of its values and adds its partner's copy of
-// that half; bits 2..0 by DPP as in wave_sum_f64.  Every value is summed over the same
-// tree (addition commutes), so its rounding depends on its 64 inputs only -- not on
-// its slot or on the other values.
+// Eight sums over the wave at once: lane 8 g + 0..7 receive the sum of slot g.  Three
+// transposing stages halve the slots while pairing lanes across bit 5, bit 4 and bit 3
+// of the lane index -- gfx950's v_permlane32_swap and v_permlane16_swap exchange the
+// halves and rows in registers, DPP row_ror:8 the half rows -- then DPP adds over lane
+// bits 0-2.  Every slot is summed over the same pairing tree (and IEEE addition is
+// commutative), so a column's sum does not depend on its slot.
+constexpr int kDppRor8 = 0x128;
+__device__ __forceinline__ void permlane32_swap_f64(double &a, double &b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false,
+                                                   false);
+  a = __hiloint2double(hi[0], lo[0]);
+  b = __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ void permlane16_swap_f64(double &a, double &b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false,
+                                                   false);
+  a = __hiloint2double(hi[0], lo[0]);
+  b = __hiloint2double(hi[1], lo[1]);
+}
 __device__ __forceinline__ double wave_sum8(const double (&x)[8]) {
   const int lane = threadIdx.x & 63;
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  const bool b3 = lane & 8;
   double y[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const double keep = b5 ? x[j + 4] : x[j];
-    const double send = b5 ? x[j] : x[j + 4];
-    y[j] = keep + __shfl_xor(send, 32, 64);
+  for (int j = 0; j < 4; ++j) {      // lanes 0-31: slot j over lanes l, l+32; 32-63: slot j+4
+    double a = x[j], b = x[j + 4];
+    permlane32_swap_f64(a, b);
+    y[j] = a + b;
   }
   double z[2];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const double keep = b4 ? y[j + 2] : y[j];
-    const double send = b4 ? y[j] : y[j + 2];
-    z[j] = keep + __shfl_xor(send, 16, 64);
+  for (int j = 0; j < 2; ++j) {      // rows of 16: even rows keep slot j, odd rows slot j+2
+    double a = y[j], b = y[j + 2];
+    permlane16_swap_f64(a, b);
+    z[j] = a + b;
   }
-  double w = (b3 ? z[1] : z[0]) + __shfl_xor(b3 ? z[0] : z[1], 8, 64);
+  double w = (b3 ? z[1] : z[0]) + dpp_f64<kDppRor8>(b3 ? z[0] : z[1]);
   w += dpp_f64<kDppXor1>(w);
   w += dpp_f64<kDppXor2>(w);
   w += dpp_f64<kDppHalfMirror>(w);

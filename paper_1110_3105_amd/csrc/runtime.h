@@ -156,6 +156,14 @@ void solve_one_into(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_m
 int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs);
 int64_t solve_wide_doubles(const rs_factor_s *h, int nrhs);
 
+// Device footprint of a factorization before it runs, from the tree, the kernel and eps
+// (a rank model; the server corrects it by the bytes later factorizations kept).
+struct FootprintEstimate {
+  size_t resident = 0;     // bytes the handle keeps
+  size_t transient = 0;    // bytes needed besides while it is factored
+};
+FootprintEstimate factor_footprint(const rs_kernel &k, const Tree &t, double eps);
+
 // The allocation-free solve's device scratch (kernels.hip): a fixed array per device.
 // noalloc_scratch() returns the current device's copy, looked up once per device.
 size_t noalloc_scratch_bytes();

@@ -13,6 +13,8 @@
 //                     third stream.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
+#include <map>
 #include <condition_variable>
 #include <deque>
 #include <memory>
@@ -54,6 +56,8 @@ struct FactorItem {
   std::vector<double> points, weights, normals, curvature;
   double eps;
   size_t estimate;
+  FootprintEstimate model;
+  int corr_key = 0;
 };
 
 struct InFlight {
@@ -76,6 +80,9 @@ struct rs_server_s {
   std::deque<rs::InFlight> inflight;
   std::unordered_map<uint64_t, std::shared_ptr<rs::Ticket>> tickets;
   std::unordered_map<rs_handle, size_t> resident;      // handles created by the server
+  // footprint model corrections by (kernel, decades of eps): kept / predicted resident
+  // bytes of the factorizations done so far (never below 1)
+  std::map<int, double> footprint_corr;
   size_t resident_bytes = 0;
   size_t reserved_bytes = 0;
   uint64_t next_id = 1;
@@ -95,23 +102,70 @@ namespace rs {
 
 namespace {
 
+int footprint_key(const rs_kernel &k, double eps) {
+  return k.kind * 100 + (int)std::lround(std::max(0.0, -std::log10(std::max(eps, 1e-16))));
+}
+
+// (caller holds s->mu)
+size_t corrected_estimate(const rs_server_s *s, const FootprintEstimate &m, int key) {
+  auto it = s->footprint_corr.find(key);
+  const double c = it == s->footprint_corr.end() ? 1.0 : it->second;
+  return (size_t)((double)m.resident * c) + m.transient;
+}
+
 size_t handle_bytes(rs_handle h) {
   size_t b = 0;
   for (const auto &c : h->arena.chunks) b += c->bytes;
   return b;
 }
 
-// Device bytes a factorization needs while it runs: the resident factor plus the
-// transient compression blocks, workspaces and index pools.  Proportional to N with a
-// per-kernel constant (2D Laplace: ~4 KB per unknown at eps = 1e-9; complex Helmholtz
-// entries are twice the size and its ranks higher; 3D larger).
-size_t factor_estimate(const rs_kernel &k, int64_t n) {
-  const size_t per = k.kind == RS_HELM3D_SL    ? 131072
-                     : k.kind == RS_HELM2D_CFIE ? 16384
-                     : k.dim == 2               ? 6144
-                                                : 65536;
-  return (size_t)n * per + (size_t(64) << 20);
+}  // namespace
+
+// Rank model of a factorization's device footprint.  Prior ranks: a box at height
+// h = maxdepth - depth keeps about c d^p g^h skeletons (d = decades of eps; 2D curves
+// p = 1, g = 1.14; 3D surfaces p = 2, g = 2: a box's boundary grows like its side),
+// never more than its active set; complex (oscillatory) kernels 1.5 times more.  The
+// active set of a leaf is its points, of a parent its children's skeletons.  Resident:
+// each box's slot (slot_bound(n) scalars) and the root's inverse (n^2); transient: the
+// largest level's box workspaces (n^2 + 16 n scalars each) plus a fixed 64 MiB for the
+// index pools, descriptors and allocation granularity.
+FootprintEstimate factor_footprint(const rs_kernel &k, const Tree &t, double eps) {
+  const bool cplx = k.kind == RS_HELM2D_CFIE || k.kind == RS_HELM3D_SL;
+  const double es = cplx ? 2.0 : 1.0;
+  const double dec = std::max(1.0, -std::log10(std::max(eps, 1e-16)));
+  const bool d3 = t.dim == 3;
+  const double base = 1.7 * (d3 ? dec * dec : dec) * (cplx ? 1.5 : 1.0);
+  const double growth = d3 ? 2.0 : 1.14;
+  const int nb = t.nbox();
+  std::vector<double> kk(nb, 0.0);
+  std::vector<double> lvl_work(t.maxdepth + 1, 0.0);
+  double resident = 0.0;
+  for (int d = t.maxdepth; d >= 0; --d) {
+    for (int b : t.levels[d]) {
+      double n = 0.0;
+      if (t.is_leaf(b)) {
+        n = (double)(t.end[b] - t.begin[b]);
+      } else {
+        for (int c = t.first_child[b]; c < t.first_child[b] + t.nchild[b]; ++c) n += kk[c];
+      }
+      lvl_work[d] += n * n + 16.0 * n;
+      if (d == 0) {
+        resident += n * n;
+      } else {
+        kk[b] = std::min(n, base * std::pow(growth, (double)(t.maxdepth - d)));
+        resident += (double)slot_bound((int)std::ceil(n));
+      }
+    }
+  }
+  double transient = 0.0;
+  for (double w : lvl_work) transient = std::max(transient, w);
+  FootprintEstimate e;
+  e.resident = (size_t)(resident * es * sizeof(double));
+  e.transient = (size_t)(transient * es * sizeof(double)) + (size_t(64) << 20);
+  return e;
 }
+
+namespace {
 
 void fail_ticket(rs_server_s *s, const std::shared_ptr<Ticket> &tk, rs_status st,
                  const std::string &msg) {
@@ -289,6 +343,11 @@ void factor_loop(rs_server_s *s) {
       s->resident[out[0]] = b;
       s->resident_bytes += b;
       s->factors_done++;
+      // correct the model for later requests of the same kernel and eps decade
+      const double ratio = (double)b / std::max<double>(1.0, (double)item->model.resident);
+      auto it = s->footprint_corr.find(item->corr_key);
+      const double prev = it == s->footprint_corr.end() ? ratio : it->second;
+      s->footprint_corr[item->corr_key] = std::max(1.0, 0.5 * prev + 0.5 * ratio);
     }
     s->cv_done.notify_all();
     s->cv_factor.notify_all();
@@ -358,7 +417,12 @@ rs_status rs_server_submit_factor(rs_server s, const rs_kernel *k, rs_tree t,
   if (k->normals) item->normals.assign(k->normals, k->normals + n * dim);
   if (k->curvature) item->curvature.assign(k->curvature, k->curvature + n);
   item->eps = eps;
-  item->estimate = factor_estimate(*k, n);
+  item->model = factor_footprint(*k, t->t, eps);
+  item->corr_key = footprint_key(*k, eps);
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    item->estimate = corrected_estimate(s, item->model, item->corr_key);
+  }
   auto tk = std::make_shared<Ticket>();
   tk->is_factor = true;
   tk->t_submit = now_ms();

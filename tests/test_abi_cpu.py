@@ -118,3 +118,27 @@ def test_tree_builds_from_concurrent_threads():
         t.join(timeout=120)
     assert not any(t.is_alive() for t in threads)
     assert not errors, errors
+
+
+def test_factor_estimate_rank_model():
+    """rs_factor_estimate (host only): the footprint grows with N and with the decades of
+    eps, complex kernels need more than real ones, and the resident part stays below the
+    slots of every box at an active set of 128 (the largest ranks of this curve are below
+    64, so no box of the model comes near it)."""
+    import paper_1110_3105_amd as rs
+    est = {}
+    for n in (4096, 16384, 65536):
+        g = W.star_curve(n)
+        t = rs.build_tree(g.points, 64)
+        for eps in (1e-6, 1e-9, 1e-12):
+            est[n, eps] = rs.factor_estimate("lap2d_sl", t, eps)
+        e = est[n, 1e-9]
+        nb = t.info()[0]
+        assert e["resident"] <= 8 * nb * (5 * 128 * 128 // 4 + 128 + 8)
+        assert e["transient"] >= 64 << 20
+        ec = rs.factor_estimate("helm2d_cfie", t, 1e-9, wavenumber=20.0)
+        assert ec["resident"] > e["resident"]
+    for n in (4096, 16384, 65536):
+        assert est[n, 1e-6]["resident"] < est[n, 1e-9]["resident"] < est[n, 1e-12]["resident"]
+    for eps in (1e-6, 1e-9, 1e-12):
+        assert est[4096, eps]["resident"] < est[16384, eps]["resident"] < est[65536, eps]["resident"]

@@ -92,16 +92,25 @@ def test_admission_by_memory(gpu_lib):
     rs = gpu_lib
     g = W.star_curve(16384)
     t = rs.build_tree(g.points, 64)
-    # footprint estimate of this request: 6 KiB * N + 64 MiB = 160 MiB; the factor it
-    # leaves resident holds > 10 MiB, so a second one does not fit in 170 MiB
-    srv = rs.Server(170 << 20)
+    # the server admits a request by its footprint estimate (rank model; corrected upward
+    # only by what earlier factorizations kept): a budget 4 MiB above this request's
+    # estimate admits it alone, and the factor it leaves resident (>= one 8 MiB arena
+    # chunk) keeps a second one waiting
+    e = rs.factor_estimate("lap2d_sl", t, 1e-9)
+    est = e["resident"] + e["transient"]
+    srv = rs.Server(est + (4 << 20))
     big = W.star_curve(65536)
     tb = rs.build_tree(big.points, 64)
+    eb = rs.factor_estimate("lap2d_sl", tb, 1e-9)
+    assert eb["resident"] + eb["transient"] > est + (4 << 20)
     tk_big = srv.submit_factor("lap2d_sl", tb, big.points, big.weights, 1e-9)
     done, st, _ = srv.poll(tk_big, -1)
     assert done and st == rs.binding.RS_ENOMEM          # larger than the whole budget
     t1 = srv.submit_factor("lap2d_sl", t, g.points, g.weights, 1e-9)
     h1 = srv.wait(t1)
+    kept = srv.stats()["resident_bytes"]
+    # the model is of the right size: the kept factor is within a factor 2 of it
+    assert e["resident"] / 2 <= kept <= 2 * e["resident"] + (8 << 20), (kept, e)
     # the next request does not fit while h1 is resident ...
     t2 = srv.submit_factor("lap2d_sl", t, g.points, g.weights, 1e-9)
     time.sleep(0.5)
