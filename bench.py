@@ -56,7 +56,9 @@ def parse():
 
 
 # kernels (rocprofv3 names, template arguments dropped) of each profiler family
-KERNELS_OF_FAMILY = {"assemble": ["k_assemble", "k_assemble_chunks", "k_assemble_tail"], "id": ["k_compress_fused", "k_cpqr_id"],
+KERNELS_OF_FAMILY = {"assemble": ["k_assemble", "k_assemble_chunks", "k_assemble_tail"],
+                     "id": ["k_compress_fused", "k_compress_split", "k_cpqr_id", "k_cpqr_coop",
+                            "k_sketch"],
                      "factor": ["k_diag_factor"],
                      # k_sweep_seg / k_wide_* serve both directions; the workload timed
                      # here sweeps with the per-handle kernels and has no wide boxes
