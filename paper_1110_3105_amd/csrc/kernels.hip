@@ -2348,6 +2348,185 @@ __device__ __forceinline__ bool gj_blocked(S *__restrict__ A, int lda, int r,
 }
 
 // --------------------------------------------------------------------------
+// Unblocked Gauss-Jordan inversion with partial pivoting held in registers (real
+// blocks of up to RS * 64 rows and NW * CPL columns; the box inversions of Section 3.4).
+// Lane l of wave w holds rows s * 64 + l (s < RS) of columns cc * NW + w (cc < CPL).
+// Rows are kept unscaled: the array holds S(i, c) = A_j(i, c) d_i, where A_j is the
+// matrix after j steps and d_i = 1 until row i is a pivot, then the pivot value that
+// eliminated it.  Step j: the wave owning column j picks the pivot row p among the
+// unused rows (largest magnitude, ties to the lowest row; a NaN is never chosen) and
+// publishes the column and 1 / S(p, j) in LDS (two buffers, so one barrier per step
+// suffices); with x_i = S(i, j) / S(p, j) for i != p and x_p = 0 every wave then applies
+//   S(i, c) <- S(i, c) - x_i S(p, c)   (c != j),   S(i, j) <- -x_i,   S(p, j) <- 1,
+// the row of p reaching each wave through LDS.  The entry S(p, j) is held as S(p, j) - 1
+// (only later steps update it; nothing reads it), so that column j takes the common
+// update from zeroed registers.  At the end A^{-1}(ustep[i], piv[c]) = S(i, c) / d_i
+// (ustep[i]: the step at which row i was the pivot).  Each element sees the
+// same operations in every layout, so the result depends on the block alone.  The
+// inverse is written to G (ld r) and, when Ginv is given, to Ginv (ld ldi); A is read at
+// the start only, so Ginv may alias it.  Returns false (uniformly) on a zero or
+// non-finite pivot.  LDS: gj_regs_lds(RS, NW, CPL, r) bytes.
+__host__ __device__ constexpr size_t gj_regs_lds(int rs, int nw, int cpl, int r) {
+  return (size_t)(2 * (rs * 64 + 1) + nw * cpl + r) * sizeof(double) +
+         (size_t)(4 + 2 * r) * sizeof(int);
+}
+static_assert(gj_regs_lds(4, 8, (kGjRegRootMax + 7) / 8, kGjRegRootMax) <=
+                  (size_t)kPB * kQC * sizeof(double),
+              "the register inversion fits the LDS reserved for the blocked one");
+
+template <int NTH, int RS, int CPL>
+__device__ __forceinline__ bool gj_regs(const double *A, int lda, int r,
+                                        double *__restrict__ G, double *Ginv, int ldi,
+                                        char *lds) {
+  constexpr int NW = NTH / 64;
+  constexpr int CB = RS * 64 + 1;              // doubles per column buffer (column, 1/pivot)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double *colbuf = reinterpret_cast<double *>(lds);
+  double *prw = colbuf + 2 * CB + wave * CPL;  // this wave's columns of the pivot row
+  double *rinv = colbuf + 2 * CB + NW * CPL;   // 1 / d_i per row
+  int *pv = reinterpret_cast<int *>(rinv + r);  // pivot row per buffer (-1: failed)
+  int *piv = pv + 4;                            // pivot row of each step
+  int *ustep = piv + r;                         // step of each row (-1: not yet a pivot)
+  double a[RS][CPL];
+#pragma unroll
+  for (int s = 0; s < RS; ++s)
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int i = s * 64 + lane, c = cc * NW + wave;
+      a[s][cc] = (i < r && c < r) ? A[(int64_t)c * lda + i] : 0.0;
+    }
+  for (int i = threadIdx.x; i < r; i += NTH) ustep[i] = -1;
+  // Column j reaches its owner through LDS: column 0 from the start, column j + 1 from
+  // the wave that applies step j to it (so no register is indexed by j).
+  if (wave == 0) {
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      colbuf[s * 64 + lane] = a[s][0];
+      a[s][0] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    double *col = colbuf + (j & 1) * CB;
+    if (wave == j % NW) {
+      double x[RS];
+      double lb = -1.0;
+      int li = INT_MAX;
+#pragma unroll
+      for (int s = 0; s < RS; ++s) {
+        x[s] = col[s * 64 + lane];
+        const int i = s * 64 + lane;
+        const double v = fabs(x[s]);
+        if (i < r && ustep[i] < 0 && v > lb) { lb = v; li = i; }
+      }
+      const ArgMax am = wave_argmax(lb, li, li);
+      const bool ok = am.v > 0.0 && isfinite(am.v);
+      const int p = ok ? am.key : 0;
+      double xp = x[0];
+#pragma unroll
+      for (int s = 1; s < RS; ++s)
+        if ((p >> 6) == s) xp = x[s];
+      const double inv = recip(readlane_f64(xp, p & 63));
+      if (lane == 0) {
+        col[RS * 64] = inv;
+        pv[j & 1] = ok ? p : -1;
+        piv[j] = p;
+        ustep[p] = j;
+        rinv[p] = inv;
+      }
+    }
+    __syncthreads();
+    const int p = pv[j & 1];
+    if (p < 0) return false;
+    const double inv = col[RS * 64];
+    double xi[RS];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) xi[s] = s * 64 + lane == p ? 0.0 : col[s * 64 + lane] * inv;
+    // the pivot row's values of this wave's columns, from the lane that holds them (its
+    // slot p / 64 a constant of each copy of the branch); column j, whose registers
+    // were cleared when it went to LDS, takes the value 1, so that the common update
+    // below leaves -x_i in it and 0 in row p (the entry S(p, j) - 1)
+    const int jc = j % NW == wave ? j / NW : -1;
+    const int jn = (j + 1) % NW == wave && j + 1 < r ? (j + 1) / NW : -1;
+#pragma unroll
+    for (int ps = 0; ps < RS; ++ps)
+      if ((p >> 6) == ps && lane == (p & 63)) {
+#pragma unroll
+        for (int c2 = 0; c2 < CPL; ++c2) prw[c2] = a[ps][c2];
+      }
+    if (jc >= 0 && lane == 0) prw[jc] = 1.0;
+    wave_sync();
+    // one branch-free pass over the columns in groups of GC, the pivot-row values of the
+    // next group read from LDS while the current group is updated (two groups in
+    // registers)
+    constexpr int GC = CPL > 8 ? 5 : CPL, NG = (CPL + GC - 1) / GC;
+    double vb[2][GC];
+#pragma unroll
+    for (int u = 0; u < GC; ++u) vb[0][u] = u < CPL ? prw[u] : 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      if (g + 1 < NG) {
+#pragma unroll
+        for (int u = 0; u < GC; ++u)
+          vb[(g + 1) & 1][u] = (g + 1) * GC + u < CPL ? prw[(g + 1) * GC + u] : 0.0;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < GC; ++u) {
+        const int c2 = g * GC + u;
+        if (c2 < CPL) {
+#pragma unroll
+          for (int s = 0; s < RS; ++s) a[s][c2] = a[s][c2] - xi[s] * vb[g & 1][u];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // every updated value is complete here (keeps the products out of the branches below)
+#pragma unroll
+    for (int s = 0; s < RS; ++s)
+#pragma unroll
+      for (int c2 = 0; c2 < CPL; ++c2) asm volatile("" : "+v"(a[s][c2]));
+    // column j + 1 to its owner, its registers cleared
+    double *nxt = colbuf + ((j + 1) & 1) * CB;
+#pragma unroll
+    for (int c2 = 0; c2 < CPL; ++c2)
+      if (c2 == jn) {
+#pragma unroll
+        for (int s = 0; s < RS; ++s) {
+          nxt[s * 64 + lane] = a[s][c2];
+          a[s][c2] = 0.0;
+        }
+      }
+  }
+  __syncthreads();                   // piv, ustep and rinv complete
+  int us[RS];
+  double dinv[RS];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int i = min(s * 64 + lane, r - 1);
+    us[s] = ustep[i];
+    dinv[s] = rinv[i];
+  }
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int c = cc * NW + wave;
+    if (c >= r) continue;
+    const int b = piv[c];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int i = s * 64 + lane;
+      if (i < r) {
+        const double g = (c == us[s] ? a[s][cc] + 1.0 : a[s][cc]) * dinv[s];
+        G[(int64_t)b * r + us[s]] = g;
+        if (Ginv) Ginv[(int64_t)b * ldi + us[s]] = g;
+      }
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// --------------------------------------------------------------------------
 // Small dense products of a box factorization with FP64 MFMA tiles (16 x 16 per wave,
 // the full K loop in k order): out(i, j) = c0(i, j) - sum_l a(i, l) b(l, j) when
 // subtract (c0 defaults to out's current value), else the plain product.  Each output
@@ -2429,7 +2608,8 @@ __global__ __launch_bounds__(NTH, 4) void k_diag_factor(const FacBox *__restrict
   const ProbDev &P = probs[B.prob];
   const int n = B.n;
   if (n == 0) return;
-  if (B.force_k0 && n >= kWideRootMinN) return;      // factored by the wide-root launches
+  // roots factored by the wide-root or register-root launches
+  if (B.force_k0 && (n >= kWideRootMinN || root_in_regs(sizeof(S) != sizeof(double), n))) return;
   const int k = B.force_k0 ? 0 : ranks[B.kslot];
   if (k < 0 || k > n) {            // the box's ID did not complete: nothing to factor
     if (threadIdx.x == 0)
@@ -2538,15 +2718,30 @@ __global__ __launch_bounds__(NTH, 4) void k_diag_factor(const FacBox *__restrict
   int ldg = r;
   if (r > 0) {
     char *gl = INLDS ? reinterpret_cast<char *>(sh + (int64_t)n * n) : reinterpret_cast<char *>(sh_raw);
-    if (!gj_blocked<S, NTH>(A, n, r, G, gl, workbase + B.work_off + (int64_t)n * n, INLDS)) {
+    // Real blocks of up to 64 unknowns are inverted in registers, larger ones by the
+    // blocked elimination.  The choice depends on r alone, so a box's arithmetic is the
+    // same in every variant and launch mode.
+    bool ok, in_regs = false;
+    if constexpr (sizeof(S) == sizeof(double)) {
+      double *gd = reinterpret_cast<double *>(G);
+      double *ad = INLDS ? reinterpret_cast<double *>(A) : nullptr;
+      if (r <= 64) {
+        ok = gj_regs<NTH, 1, 64 / NW>(reinterpret_cast<const double *>(A), n, r, gd, ad, n, gl);
+        in_regs = true;
+      }
+    }
+    if (!in_regs) ok = gj_blocked<S, NTH>(A, n, r, G, gl, workbase + B.work_off + (int64_t)n * n, INLDS);
+    if (!ok) {
       if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned int *>(err),
                                       (unsigned int)(err_base + first + (int)blockIdx.x));
       return;
     }
     if (INLDS) {
-      for (int c = wave; c < r; c += NW)
-        for (int a = lane; a < r; a += 64) A[(int64_t)c * n + a] = G[(int64_t)c * r + a];
-      __syncthreads();
+      if (!in_regs) {
+        for (int c = wave; c < r; c += NW)
+          for (int a = lane; a < r; a += 64) A[(int64_t)c * n + a] = G[(int64_t)c * r + a];
+        __syncthreads();
+      }
       Gi = A;
       ldg = n;
     }
@@ -2629,6 +2824,19 @@ __global__ __launch_bounds__(kThreads) void k_root_assemble(const FacBox *__rest
     if (b >= n) break;
     for (int a = threadIdx.x; a < n; a += kThreads) X[(int64_t)b * n + a] = fac_entry<S>(B, P, J, nullptr, a, b);
   }
+}
+
+// Real roots of kRegRootMinN .. kGjRegRootMax unknowns: the block assembled in the
+// workspace by k_root_assemble is inverted in the registers of one 512-thread workgroup
+// (two waves per SIMD, up to 256 registers each), G = D^{-1} in the root's slot.
+template <int RS, int CPL>
+__global__ __launch_bounds__(512, 1) void k_root_regs(const double *__restrict__ X, int n,
+                                                       double *__restrict__ G,
+                                                       int32_t *__restrict__ err, int err_idx) {
+  extern __shared__ double sh_raw[];
+  if (!gj_regs<512, RS, CPL>(X, n, n, G, nullptr, 0, reinterpret_cast<char *>(sh_raw)) &&
+      threadIdx.x == 0)
+    atomicMin(reinterpret_cast<unsigned int *>(err), (unsigned int)err_idx);
 }
 
 // Control block of a wide root: piv[r], ustep[r] (rows), fail flag.
@@ -3189,6 +3397,22 @@ void check_launch(const char *what) {
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
+
+// Kernels using more than 64 KiB of dynamic LDS need the limit raised first; the call
+// costs a runtime round trip, so the largest value set so far is remembered per device
+// and kernel and the attribute is set again only when a launch needs more.
+void allow_lds(const void *kern, size_t lds) {
+  if (lds <= 64 * 1024) return;
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, size_t> set;
+  int dev = 0;
+  RS_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  size_t &cur = set[{dev, kern}];
+  if (lds <= cur) return;
+  RS_HIP_CHECK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  cur = lds;
+}
 // Dynamic LDS requested per workgroup.
 constexpr size_t kLdsLimit = 64 * 1024;
 
@@ -3253,9 +3477,7 @@ void cpqr_variant(const CompBox *boxes, int first, int count, const ProbDev *pro
                   double *Marena, int32_t *order_pool, int32_t *ranks, size_t lds,
                   hipStream_t st) {
   auto kern = k_cpqr_id<S, NTH, RT, CB, VLDS>;
-  if (lds > 64 * 1024)
-    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void *)kern, lds);
   hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs,
                      reinterpret_cast<S *>(Marena), order_pool, ranks);
   check_launch("k_cpqr_id");
@@ -3295,9 +3517,7 @@ void diag_factor_nt(const FacBox *boxes, int first, int count, const ProbDev *pr
                     const int32_t *pool, const int32_t *order_pool, const int32_t *ranks,
                     double *work, int32_t *err, int err_base, size_t lds, hipStream_t st) {
   auto kern = k_diag_factor<S, NTH, INLDS>;
-  if (lds > 64 * 1024)
-    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void *)kern, lds);
   hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool,
                      order_pool, ranks, reinterpret_cast<S *>(work), err, err_base);
   check_launch("k_diag_factor");
@@ -3427,9 +3647,7 @@ void fused_variant(const CompBox *boxes, int first, int count, const ProbDev *pr
   const size_t lds = fused_lds_bytes(NTH, max_n, max_m, max_npx);
   if (lds > kMaxLds) throw DeviceError("k_compress_fused: LDS", hipErrorInvalidValue);
   auto kern = k_compress_fused<NTH, RT, CPW>;
-  if (lds > 64 * 1024)
-    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void *)kern, lds);
   hipLaunchKernelGGL(kern, dim3(count), dim3(NTH), lds, st, boxes, first, probs, pool,
                      order_pool, ranks);
   check_launch("k_compress_fused");
@@ -3502,15 +3720,26 @@ void launch_compress_split(const CompBox *boxes, int first, int count, const Pro
   const size_t lds = split_lds_bytes(max_n, max_m, max_npx);
   if (lds > kMaxLds) throw DeviceError("k_compress_split: LDS", hipErrorInvalidValue);
   auto kern = k_compress_split<kSplitRT, kSplitCPW>;
-  if (lds > 64 * 1024)
-    RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  // boxes per launch: every workgroup of a launch resident at once
+  allow_lds((const void *)kern, lds);
+  // boxes per launch: every workgroup of a launch resident at once (the occupancy and CU
+  // count are queried once per device and LDS size)
   int per_cu = 0, dev = 0, ncu = 0;
-  RS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern,
-                                                            kSplitThreads, lds));
   RS_HIP_CHECK(hipGetDevice(&dev));
-  RS_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  {
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, std::pair<int, int>> known;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = known.find({dev, lds});
+    if (it == known.end()) {
+      RS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern,
+                                                                kSplitThreads, lds));
+      RS_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      known[{dev, lds}] = {per_cu, ncu};
+    } else {
+      per_cu = it->second.first;
+      ncu = it->second.second;
+    }
+  }
   const int chunk = std::max(1, (per_cu * ncu) / G);
   if (per_cu * ncu < G)
     throw DeviceError("k_compress_split: a box's workgroups cannot be resident together",
@@ -3591,9 +3820,7 @@ void launch_cpqr_coop(bool cplx, const CompBox *boxes, int first, int count, con
   with_scalar(cplx, [&](auto z) {
     using S = decltype(z);
     auto kern = k_cpqr_coop<S>;
-    if (lds > 64 * 1024)
-      RS_HIP_CHECK(hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    allow_lds((const void *)kern, lds);
     S *Mp = reinterpret_cast<S *>(Marena);
     int vl = vlds ? 1 : 0;
     const dim3 grid(nbox_al * G), block(kCoopThreads);
@@ -3678,6 +3905,21 @@ void launch_root_wide(bool cplx, const FacBox *box, int n, const ProbDev *probs,
     check_launch("k_gj_wide_finish");
   });
   RS_HIP_CHECK(hipFreeAsync(ctl_mem, st));
+}
+
+void launch_root_regs(const FacBox *box, int n, const ProbDev *probs, const int32_t *pool,
+                      double *work, int64_t work_off, double *G, int32_t *err, int err_idx,
+                      hipStream_t st) {
+  if (!root_in_regs(false, n))
+    throw DeviceError("launch_root_regs: root outside the register class", hipErrorInvalidValue);
+  hipLaunchKernelGGL(k_root_assemble<double>, dim3((n + 15) / 16), dim3(kThreads), 0, st, box,
+                     probs, pool, work);
+  check_launch("k_root_assemble");
+  constexpr int kRS = (kGjRegRootMax + 63) / 64, kCPL = (kGjRegRootMax + 7) / 8;
+  const size_t lds = gj_regs_lds(kRS, 8, kCPL, n);
+  hipLaunchKernelGGL((k_root_regs<kRS, kCPL>), dim3(1), dim3(512), lds, st, work + work_off, n,
+                     G, err, err_idx);
+  check_launch("k_root_regs");
 }
 
 void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,

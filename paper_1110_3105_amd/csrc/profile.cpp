@@ -1,6 +1,7 @@
 // Launch profiler: HIP events on the launch stream around each kernel launch, plus
 // the algorithmic work of the launch counted by the caller from the box sizes.
 #include <algorithm>
+#include <map>
 #include <vector>
 
 #include "runtime.h"
@@ -11,6 +12,7 @@ namespace {
 
 struct Pending {
   int family;
+  int device;
   hipEvent_t start, stop;
 };
 
@@ -23,6 +25,24 @@ std::mutex g_prof_mutex;
 std::atomic<bool> g_prof_on{false};
 std::vector<Pending> g_pending;
 Totals g_totals[RS_K_COUNT];
+// events read by drain_locked, kept per device for later launches (creating an event
+// allocates a signal: tens of microseconds per profiled launch otherwise)
+std::map<int, std::vector<hipEvent_t>> g_free_events;
+
+hipEvent_t take_event(int device) {
+  {
+    std::lock_guard<std::mutex> lock(g_prof_mutex);
+    std::vector<hipEvent_t> &f = g_free_events[device];
+    if (!f.empty()) {
+      hipEvent_t e = f.back();
+      f.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  RS_HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
 
 void drain_locked() {
   for (Pending &p : g_pending) {
@@ -33,8 +53,9 @@ void drain_locked() {
       t.launches += 1;
       t.ms += ms;
     }
-    (void)hipEventDestroy(p.start);
-    (void)hipEventDestroy(p.stop);
+    std::vector<hipEvent_t> &f = g_free_events[p.device];
+    f.push_back(p.start);
+    f.push_back(p.stop);
   }
   g_pending.clear();
 }
@@ -51,8 +72,9 @@ CaptureScope::~CaptureScope() { --t_capture_depth; }
 
 ProfScope::ProfScope(int family, hipStream_t st) : family_(family), st_(st) {
   if (!prof_on() || t_capture_depth > 0) return;
-  RS_HIP_CHECK(hipEventCreate(&start_));
-  RS_HIP_CHECK(hipEventCreate(&stop_));
+  RS_HIP_CHECK(hipGetDevice(&device_));
+  start_ = take_event(device_);
+  stop_ = take_event(device_);
   RS_HIP_CHECK(hipEventRecord(start_, st_));
   active_ = true;
 }
@@ -61,7 +83,7 @@ ProfScope::~ProfScope() {
   if (!active_) return;
   (void)hipEventRecord(stop_, st_);
   std::lock_guard<std::mutex> lock(g_prof_mutex);
-  g_pending.push_back({family_, start_, stop_});
+  g_pending.push_back({family_, device_, start_, stop_});
 }
 
 void prof_add_work(int family, const Work &w) {

@@ -146,6 +146,8 @@ void launch_assemble(bool cplx, const CompBox *boxes, int first, int count, cons
 void launch_cpqr_id(bool cplx, const CompBox *boxes, int first, int count, const ProbDev *probs,
                     double *Marena, int32_t *order_pool, int32_t *ranks, int max_n, int max_m,
                     hipStream_t st);
+// Box factorizations (one workgroup per box).  The roots' launches pass no order and no
+// ranks (force_k0 boxes).
 void launch_diag_factor(bool cplx, const FacBox *boxes, int first, int count,
                         const ProbDev *probs, const int32_t *pool, const int32_t *order_pool,
                         const int32_t *ranks, double *work, int32_t *err, int err_base,
@@ -185,6 +187,18 @@ constexpr int kWideRootMinN = 1536;
 void launch_root_wide(bool cplx, const FacBox *box, int n, const ProbDev *probs,
                       const int32_t *pool, double *work, int64_t work_off, double *G,
                       int32_t *err, int err_idx, hipStream_t st);
+// Real roots of kRegRootMinN .. kGjRegRootMax unknowns are skipped by k_diag_factor too and
+// factored by launch_root_regs: assembly by many workgroups into the workspace, then the
+// Gauss-Jordan inversion held in the registers of one 512-thread workgroup.  Arguments as
+// for launch_root_wide.
+constexpr int kRegRootMinN = 65;
+constexpr int kGjRegRootMax = 200;
+__host__ __device__ constexpr bool root_in_regs(bool cplx, int n) {
+  return !cplx && n >= kRegRootMinN && n <= kGjRegRootMax;
+}
+void launch_root_regs(const FacBox *box, int n, const ProbDev *probs, const int32_t *pool,
+                      double *work, int64_t work_off, double *G, int32_t *err, int err_idx,
+                      hipStream_t st);
 // Global workspace scalars reserved for a box of n DOFs in k_diag_factor.
 size_t diag_work_elems(int n);
 void launch_permute_in(bool cplx, const double *B, int64_t ldb, double *W, const int64_t *perm,

@@ -138,6 +138,15 @@ struct Scratch {
   // the device first, so queued copies never read freed memory.
   PinnedBuf hup;
   size_t hup_used = 0;
+  // timing events of the per-level statistics (two per level), created once
+  std::vector<hipEvent_t> timing_ev;
+  void timing_events(size_t count) {
+    while (timing_ev.size() < count) {
+      hipEvent_t e = nullptr;
+      RS_HIP_CHECK(hipEventCreate(&e));
+      timing_ev.push_back(e);
+    }
+  }
   void *stage(size_t bytes) {
     size_t off = (hup_used + 255) & ~size_t(255);
     if (off + bytes > hup.bytes) {
@@ -462,15 +471,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     double plan_ms = 0;
   };
   std::vector<StepTiming> step_t(max_depth + 1);
-  struct TimingRelease {
-    std::vector<StepTiming> *v;
-    ~TimingRelease() {
-      for (StepTiming &x : *v) {
-        if (x.a) (void)hipEventDestroy(x.a);
-        if (x.b) (void)hipEventDestroy(x.b);
-      }
-    }
-  } timing_release{&step_t};
+  S.timing_events(2 * (max_depth + 1));      // kept by the scratch and reused
   auto level_entry = [&](rs_factor_s *h, int depth) -> rs_level_stats & {
     for (rs_level_stats &e : h->level_stats)
       if (e.depth == depth) return e;
@@ -753,8 +754,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
                       sizeof(double));
     const CompBox *d_comp = S.comp.as<CompBox>();
     const CompBox *d_comp_id = any_sketch ? S.comp_id.as<CompBox>() : d_comp;
-    RS_HIP_CHECK(hipEventCreate(&step_t[step].a));
-    RS_HIP_CHECK(hipEventCreate(&step_t[step].b));
+    step_t[step].a = S.timing_ev[2 * step];
+    step_t[step].b = S.timing_ev[2 * step + 1];
     RS_HIP_CHECK(hipEventRecord(step_t[step].a, st));
     if (per_box) {
       for (int i = 0; i < cnt; ++i) {
@@ -985,16 +986,18 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       for (const FacBox &f : fac) w += work_factor(f.n, 0, cplx);
       prof_add_work(RS_K_FACTOR, w);
     }
-    RS_HIP_CHECK(hipEventCreate(&step_t[max_depth].a));
-    RS_HIP_CHECK(hipEventCreate(&step_t[max_depth].b));
+    step_t[max_depth].a = S.timing_ev[2 * max_depth];
+    step_t[max_depth].b = S.timing_ev[2 * max_depth + 1];
     RS_HIP_CHECK(hipEventRecord(step_t[max_depth].a, st));
-    // roots below the wide class: one workgroup each (k_diag_factor skips wide roots)
+    // roots below the register and wide classes: one workgroup each (k_diag_factor skips
+    // the others)
+    auto narrow = [&](int n) { return n < kWideRootMinN && !root_in_regs(cplx, n); };
     int max_n_narrow = 0;
     for (const FacBox &f : fac)
-      if (f.n < kWideRootMinN) max_n_narrow = std::max(max_n_narrow, f.n);
+      if (narrow(f.n)) max_n_narrow = std::max(max_n_narrow, f.n);
     if (per_box) {
       for (int i = 0; i < np; ++i) {
-        if (fac[i].n >= kWideRootMinN) continue;
+        if (!narrow(fac[i].n)) continue;
         ProfScope ps_(RS_K_FACTOR, st);
         launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
                            S.work.as<double>(), S.err.as<int32_t>(), err_base, fac[i].n, st);
@@ -1003,6 +1006,12 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       ProfScope ps_(RS_K_FACTOR, st);
       launch_diag_factor(cplx, d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
                          S.work.as<double>(), S.err.as<int32_t>(), err_base, max_n_narrow, st);
+    }
+    for (int i = 0; i < np; ++i) {
+      if (!root_in_regs(cplx, fac[i].n)) continue;
+      ProfScope ps_(RS_K_FACTOR, st);
+      launch_root_regs(d_fac + i, fac[i].n, d_probs, S.pool.as<int32_t>(), S.work.as<double>(),
+                       fac[i].work_off, fac[i].slot, S.err.as<int32_t>(), err_base + i, st);
     }
     for (int i = 0; i < np; ++i) {
       if (fac[i].n < kWideRootMinN) continue;

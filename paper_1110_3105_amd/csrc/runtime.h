@@ -256,6 +256,7 @@ class ProfScope {
   int family_;
   hipStream_t st_;
   hipEvent_t start_ = nullptr, stop_ = nullptr;
+  int device_ = 0;
   bool active_ = false;
 };
 
