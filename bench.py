@@ -59,7 +59,8 @@ def parse():
 KERNELS_OF_FAMILY = {"assemble": ["k_assemble", "k_assemble_chunks", "k_assemble_tail"],
                      "id": ["k_compress_fused", "k_compress_split", "k_cpqr_id", "k_cpqr_coop",
                             "k_sketch"],
-                     "factor": ["k_diag_factor"],
+                     "factor": ["k_diag_factor", "k_root_assemble", "k_root_regs",
+                                "k_gj_wide_panel", "k_gj_wide_update", "k_gj_wide_finish"],
                      # k_sweep_seg / k_wide_* serve both directions; the workload timed
                      # here sweeps with the per-handle kernels and has no wide boxes
                      "sweep_up": ["k_sweep_up_mfma", "k_sweep_seg", "k_wide_gather",
