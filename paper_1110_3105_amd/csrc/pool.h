@@ -34,6 +34,16 @@ class PlanPool {
     return *p;
   }
   int workers() const { return (int)th_.size(); }
+  // Wakes sleeping workers so that they spin again (for kSpinUs) without a job: a caller
+  // about to issue parallel loops after a pause calls it before its serial preamble, so
+  // the first loop does not wait for threads to be scheduled.
+  void wake() {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (sleepers_ > 0) {
+      wakes_.fetch_add(1, std::memory_order_relaxed);
+      cv_.notify_all();
+    }
+  }
   // Runs job(0..nchunks) on the caller plus the workers (nchunks < 2^20).  One job at a
   // time: a caller that finds the pool busy (another thread's job) runs all of its
   // chunks itself.
@@ -95,8 +105,13 @@ class PlanPool {
             std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinUs)) {
           std::unique_lock<std::mutex> lk(mu_);
           ++sleepers_;
-          cv_.wait(lk, [&] { return gen_of(slot_.load(std::memory_order_acquire)) != seen; });
+          const uint32_t w0 = wakes_.load(std::memory_order_relaxed);
+          cv_.wait(lk, [&] {
+            return gen_of(slot_.load(std::memory_order_acquire)) != seen ||
+                   wakes_.load(std::memory_order_relaxed) != w0;
+          });
           --sleepers_;
+          t0 = std::chrono::steady_clock::now();     // spin again before the next sleep
         } else {
           relax();
         }
@@ -119,6 +134,7 @@ class PlanPool {
   const std::function<void(int)> *job_ = nullptr;
   std::atomic<uint64_t> slot_{0};
   std::atomic<int> pending_{0};
+  std::atomic<uint32_t> wakes_{0};
 };
 
 // Background release of large host structures made of many small allocations (the

@@ -68,6 +68,7 @@ Tree::~Tree() {
 }
 
 void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
+  PlanPool::get().wake();
   dim = dim_;
   n = n_;
   leaf_size = leaf;
@@ -107,6 +108,13 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   }, 1);
   center.clear(); side.clear(); depth.clear(); parent.clear(); begin.clear(); end.clear();
   first_child.clear(); nchild.clear(); icoord.clear();
+  {
+    // about two boxes per leaf's worth of points
+    const size_t est = (size_t)(2 * n / std::max(1, leaf)) + 64;
+    center.reserve(3 * est); icoord.reserve(3 * est); side.reserve(est); depth.reserve(est);
+    parent.reserve(est); begin.reserve(est); end.reserve(est); first_child.reserve(est);
+    nchild.reserve(est);
+  }
 
   auto add = [&](const double *c, double s, int d, int p, int64_t b, int64_t e, int code) {
     for (int a = 0; a < 3; ++a)
@@ -134,20 +142,204 @@ void Tree::build(int dim_, int64_t n_, const double *pts, int leaf) {
   // chunks of its range): each counts its codes, the counts are prefix-summed in chunk
   // order, and each task scatters its points -- the same stable order as one pass.
   constexpr int64_t kPartChunk = 4096;
+  constexpr int64_t kSubtreeMax = 4096;
   struct Task {
     int bi;
     int64_t i0, i1;
     std::array<int64_t, 8> cnt, pos;
   };
+  auto splits = [&](int64_t b, int64_t e, int d, double sd) {
+    return e - b > leaf_size && d < kMaxDepth && sd > 0.0;
+  };
+  // One subtree per box of roots (those that split), then the merge.
+  auto build_subtrees = [&](const std::vector<int> &roots) {
+    struct LBox {
+      double c[3];
+      double s;
+      int depth, lparent, code;
+      int64_t b, e;
+    };
+    const int nr = (int)roots.size();
+    std::vector<std::vector<LBox>> sub(nr);
+    parallel_for(nr, [&](int ri) {
+      const int q = roots[ri];
+      if (!splits(begin[q], end[q], depth[q], side[q])) return;
+      std::vector<LBox> &L = sub[ri];
+      LBox r0;
+      for (int a = 0; a < 3; ++a) r0.c[a] = center[3 * q + a];
+      r0.s = side[q];
+      r0.depth = depth[q];
+      r0.lparent = -1;
+      r0.code = 0;
+      r0.b = begin[q];
+      r0.e = end[q];
+      L.push_back(r0);
+      for (size_t li = 0; li < L.size(); ++li) {
+        const LBox x = L[li];
+        if (!splits(x.b, x.e, x.depth, x.s)) continue;
+        int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t i = x.b; i < x.e; ++i) {
+          const int64_t g = perm[i];
+          int cc = 0;
+          for (int a = 0; a < dim; ++a) cc |= (pts[g * dim + a] >= x.c[a] ? 1 : 0) << a;
+          code[i] = cc;
+          cnt[cc]++;
+        }
+        int64_t pos[8], acc = x.b;
+        for (int cc = 0; cc < ncode; ++cc) {
+          pos[cc] = acc;
+          acc += cnt[cc];
+        }
+        for (int64_t i = x.b; i < x.e; ++i) tmp[pos[code[i]]++] = perm[i];
+        std::copy(tmp.begin() + x.b, tmp.begin() + x.e, perm.begin() + x.b);
+        int64_t off = x.b;
+        for (int cc = 0; cc < ncode; ++cc) {
+          if (cnt[cc] == 0) continue;
+          LBox ch;
+          for (int a = 0; a < 3; ++a)
+            ch.c[a] = a < dim ? (((cc >> a) & 1) ? x.c[a] + x.s * 0.25 : x.c[a] - x.s * 0.25) : 0.0;
+          ch.s = x.s * 0.5;
+          ch.depth = x.depth + 1;
+          ch.lparent = (int)li;
+          ch.code = cc;
+          ch.b = off;
+          ch.e = off + cnt[cc];
+          L.push_back(ch);
+          off += cnt[cc];
+        }
+      }
+    }, 1);
+    // merge: boxes of one depth are consecutive in each subtree's breadth-first list
+    std::vector<std::vector<int>> gid(nr);
+    std::vector<size_t> at(nr, 1);
+    for (int ri = 0; ri < nr; ++ri) {
+      gid[ri].assign(sub[ri].size(), -1);
+      if (!sub[ri].empty()) gid[ri][0] = roots[ri];
+    }
+    for (int d = depth[roots[0]] + 1;; ++d) {
+      bool any = false;
+      for (int ri = 0; ri < nr; ++ri) {
+        const std::vector<LBox> &L = sub[ri];
+        size_t &li = at[ri];
+        for (; li < L.size() && L[li].depth == d; ++li) {
+          const LBox &x = L[li];
+          const int pg = gid[ri][x.lparent];
+          const int id = (int)side.size();
+          if (first_child[pg] < 0) first_child[pg] = id;
+          nchild[pg]++;
+          add(x.c, x.s, d, pg, x.b, x.e, x.code);
+          gid[ri][li] = id;
+          any = true;
+        }
+      }
+      if (!any) break;
+    }
+  };
+  // The first kTop levels in one pass when the root splits: each point's cell kTop levels
+  // down (its quadrant codes along the centers its boxes will have, formed by the same
+  // operations as the boxes' own centers), then one stable counting sort by that cell --
+  // the order of kTop successive stable partitions.  A box that stops splitting above
+  // depth kTop gets its range back in caller order, the order its level left it in.
+  constexpr int kTop = 3;
+  if (splits(0, n, 0, s0)) {
+    const int nbk = 1 << (dim * kTop);
+    std::vector<int64_t> hist((size_t)nck * nbk, 0);
+    parallel_for(nck, [&](int ci) {
+      int64_t *hc = &hist[(size_t)ci * nbk];
+      for (int64_t i = ci * kPtsChunk; i < std::min(n, (ci + 1) * kPtsChunk); ++i) {
+        const double *x = pts + i * dim;
+        double c[3] = {c0[0], c0[1], c0[2]};
+        double sq = s0;
+        int key = 0;
+        for (int l = 0; l < kTop; ++l) {
+          int cc = 0;
+          for (int a = 0; a < dim; ++a) cc |= (x[a] >= c[a] ? 1 : 0) << a;
+          for (int a = 0; a < dim; ++a) c[a] = ((cc >> a) & 1) ? c[a] + sq * 0.25 : c[a] - sq * 0.25;
+          sq = sq * 0.5;
+          key = (key << dim) | cc;
+        }
+        code[i] = key;
+        hc[key]++;
+      }
+    }, 1);
+    std::vector<int64_t> kcount(nbk + 1, 0);      // kcount[key]: start of the key's run
+    {
+      int64_t acc = 0;
+      for (int key = 0; key < nbk; ++key) {
+        kcount[key] = acc;
+        for (int ci = 0; ci < nck; ++ci) {
+          int64_t &h = hist[(size_t)ci * nbk + key];
+          const int64_t c = h;
+          h = acc;                                  // the chunk's first slot for the key
+          acc += c;
+        }
+      }
+      kcount[nbk] = acc;
+    }
+    parallel_for(nck, [&](int ci) {
+      int64_t *hc = &hist[(size_t)ci * nbk];
+      for (int64_t i = ci * kPtsChunk; i < std::min(n, (ci + 1) * kPtsChunk); ++i)
+        perm[hc[code[i]]++] = i;
+    }, 1);
+    // boxes of depths 1..kTop from the runs of the cells (key ranges)
+    std::vector<int> lvl = {0};
+    std::vector<int> klo = {0};
+    for (int l = 1; l <= kTop; ++l) {
+      std::vector<int> next, nklo;
+      const int span = 1 << (dim * (kTop - l));     // keys per child cell
+      for (size_t qi = 0; qi < lvl.size(); ++qi) {
+        const int q = lvl[qi];
+        if (!splits(begin[q], end[q], depth[q], side[q])) {
+          std::sort(perm.begin() + begin[q], perm.begin() + end[q]);
+          continue;
+        }
+        const double c[3] = {center[3 * q], center[3 * q + 1], center[3 * q + 2]};
+        const double sq = side[q];
+        for (int cc = 0; cc < ncode; ++cc) {
+          const int k0 = klo[qi] + cc * span;
+          const int64_t b = kcount[k0], e = kcount[k0 + span];
+          if (e == b) continue;
+          double cch[3] = {0, 0, 0};
+          for (int a = 0; a < dim; ++a) cch[a] = ((cc >> a) & 1) ? c[a] + sq * 0.25 : c[a] - sq * 0.25;
+          const int id = (int)side.size();
+          if (first_child[q] < 0) first_child[q] = id;
+          nchild[q]++;
+          add(cch, sq * 0.5, depth[q] + 1, q, b, e, cc);
+          next.push_back(id);
+          nklo.push_back(k0);
+        }
+      }
+      lvl.swap(next);
+      klo.swap(nklo);
+    }
+    cur.swap(lvl);
+  }
   while (!cur.empty()) {
     const int nb = (int)cur.size();
+    // Once every box still to split holds at most kSubtreeMax points, each of them builds
+    // its whole subtree in one task (breadth first, on its own index range), and the
+    // subtrees are merged depth by depth in box order -- the numbering and the point
+    // order of splitting the levels one after another.
+    {
+      int nsplit = 0;
+      bool small = true;
+      for (int q : cur)
+        if (splits(begin[q], end[q], depth[q], side[q])) {
+          ++nsplit;
+          small = small && end[q] - begin[q] <= kSubtreeMax;
+        }
+      if (nsplit > 0 && small) {
+        build_subtrees(cur);
+        break;
+      }
+    }
     std::vector<std::array<int64_t, 8>> counts(nb);
     std::vector<char> split(nb, 0);
     std::vector<Task> tasks;
     for (int bi = 0; bi < nb; ++bi) {
       const int q = cur[bi];
       const int64_t b = begin[q], e = end[q];
-      if (!(e - b > leaf_size && depth[q] < kMaxDepth && side[q] > 0.0)) continue;
+      if (!splits(b, e, depth[q], side[q])) continue;
       split[bi] = 1;
       for (int64_t i0 = b; i0 < e; i0 += kPartChunk) {
         Task tk;

@@ -47,6 +47,29 @@ def test_host_tree_matches_oracle_tree(mk, leaf):
     assert np.array_equal(e["center"], o.center) and np.array_equal(e["side"], o.side)
 
 
+def test_host_tree_adaptive_cases_match_oracle_tree():
+    """Boxes that stop splitting above the top levels built in one pass (a dense cluster
+    with sparse outliers, a few points, collinear points, 3D clusters) keep the point
+    order of splitting level by level: the oracle's tree, array for array."""
+    import paper_1110_3105_amd as rs
+    rng = np.random.default_rng(11)
+    cases = [
+        (np.concatenate([rng.normal(0.0, 1e-3, (3000, 2)), rng.random((40, 2))]), 8),
+        (rng.random((7, 2)), 2),
+        (np.stack([np.linspace(0.0, 1.0, 900), np.zeros(900)], axis=1), 10),
+        (np.concatenate([rng.normal(0.0, 1e-2, (2000, 3)), 4.0 * rng.random((30, 3))]), 16),
+        (np.repeat(rng.random((20, 2)), 30, axis=0), 8),
+    ]
+    for pts, leaf in cases:
+        pts = np.ascontiguousarray(pts)
+        e = rs.build_tree(pts, leaf).export()
+        o = oracle_tree(pts, leaf)
+        assert np.array_equal(e["perm"], o.perm)
+        assert np.array_equal(e["depth"], o.depth) and np.array_equal(e["parent"], o.parent)
+        assert np.array_equal(e["begin"], o.begin) and np.array_equal(e["end"], o.end)
+        assert np.array_equal(e["center"], o.center) and np.array_equal(e["side"], o.side)
+
+
 def test_tree_argument_errors():
     import paper_1110_3105_amd as rs
     with pytest.raises(rs.RSError) as ei:
