@@ -265,6 +265,19 @@ rs_status rs_tune_clear(void);
 rs_status rs_tune_save(const char *path);
 rs_status rs_tune_load(const char *path);
 
+/* Factors one problem and solves one block of right-hand sides with the new factors in
+ * the same call (Sections 3.4 and 4: the factorization, then the multilevel inverse
+ * applied to B in place).  Arguments as rs_factor_ex, plus B: device memory,
+ * column-major n x nrhs with leading dimension ldb >= n, scalars of the operator's type
+ * (complex128 as interleaved pairs), overwritten with the solution.  The solve's
+ * permutation and upward sweeps through the compressed levels run while the root block
+ * is inverted; the results are those of rs_factor_ex followed by rs_solve_ex, bit for
+ * bit.  Returns when both are complete (errors of either, as those calls report them;
+ * on an error no handle is returned and B is unspecified).  The caller owns *out. */
+rs_status rs_factor_solve_ex(const rs_kernel *k, rs_tree t, const double *points,
+                             const double *weights, double eps, const rs_options *opts,
+                             void *B, int64_t ldb, int32_t nrhs, rs_handle *out);
+
 /* Releases a handle.  RS_EBUSY (handle untouched) while a solve enqueued on it has not
  * completed on its stream, or while a call, a plan or the server uses it; synchronize
  * the solve's stream first.  RS_OK for NULL. */

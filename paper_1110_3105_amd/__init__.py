@@ -7,7 +7,7 @@ from .binding import (  # noqa: F401
     EXPORTED, KINDS, LAUNCH, Handle, RSError, Tree, build_tree, device_count, factor,
     rs_box_export, rs_box_skeletons, rs_build_tree, rs_device_count, rs_factor, rs_factor_ex,
     rs_free, rs_last_error, rs_query, rs_query_levels, rs_solve, rs_solve_ex, rs_solve_noalloc,
-    rs_matvec, rs_factor_estimate, factor_estimate,
+    rs_matvec, rs_factor_estimate, factor_estimate, factor_solve, rs_factor_solve_ex,
     rs_tree_export,
     rs_tree_free,
     rs_tree_info, LIB_PATH, FAMILIES, profile_enable, profile_read, profile_reset,

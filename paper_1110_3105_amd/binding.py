@@ -40,7 +40,7 @@ EXPORTED = ["rs_build_tree", "rs_tree_info", "rs_tree_export", "rs_tree_free", "
             "rs_server_reset_stats", "rs_server_destroy", "rs_plan_create", "rs_plan_launch",
             "rs_plan_free", "rs_autotune", "rs_tune_entries", "rs_tune_clear", "rs_tune_save",
             "rs_tune_load", "rs_solve_noalloc", "rs_matvec", "rs_query_levels",
-            "rs_factor_estimate"]
+            "rs_factor_estimate", "rs_factor_solve_ex"]
 FAMILIES = ["assemble", "id", "factor", "sweep_up", "sweep_down", "permute"]
 
 
@@ -99,6 +99,9 @@ _sig = {
     "rs_factor": (C.c_int, [C.POINTER(rs_kernel), _P, _PD, _PD, C.c_double, C.POINTER(_P)]),
     "rs_factor_ex": (C.c_int, [C.POINTER(rs_kernel), _P, _PD, _PD, C.c_double,
                                C.POINTER(rs_options), C.POINTER(_P)]),
+    "rs_factor_solve_ex": (C.c_int, [C.POINTER(rs_kernel), _P, _PD, _PD, C.c_double,
+                                     C.POINTER(rs_options), _P, C.c_int64, C.c_int32,
+                                     C.POINTER(_P)]),
     "rs_solve": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P]),
     "rs_solve_ex": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(rs_options)]),
     "rs_solve_noalloc": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P]),
@@ -432,6 +435,46 @@ def factor(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: 
     h = _P()
     _check(_lib.rs_factor_ex(C.byref(k), tree.handle, _dptr(pts), _dptr(w), float(eps),
                              C.byref(o), C.byref(h)))
+    return Handle(h, pts.shape[0], keep=(tree,))
+
+
+def factor_solve(kind: str, tree: Tree, points: np.ndarray, weights: np.ndarray, eps: float,
+                 B, normals: Optional[np.ndarray] = None,
+                 curvature: Optional[np.ndarray] = None, identity: float = 0.0,
+                 proxy_points: int = 64, proxy_ratio: float = 1.5, launch_mode: str = "level",
+                 stream=None, wavenumber: float = 0.0, eta: float = 0.0, id_mode: str = "cpqr",
+                 sketch_seed: int = 0, oversample: int = 16) -> Handle:
+    """Factor and solve in one call (rs_factor_solve_ex): B (a device tensor of shape (n,)
+    or (n, nrhs), float64 or complex128 as the operator) is overwritten with the
+    solution; the same bits as factor() followed by Handle.solve()."""
+    import torch
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64)
+    kap = None if curvature is None else np.ascontiguousarray(curvature, dtype=np.float64)
+    if pts.shape[0] != w.shape[0]:
+        raise ValueError("points and weights differ in length")
+    dtype = torch.complex128 if kind in ("helm2d_cfie", "helm3d_sl") else torch.float64
+    if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == dtype):
+        raise TypeError(f"B must be a {dtype} tensor on the HIP device")
+    X = B.unsqueeze(1) if B.dim() == 1 else B
+    if X.shape[0] != pts.shape[0]:
+        raise ValueError("B has the wrong number of rows")
+    nrhs = X.shape[1]
+    colmajor = X.stride(0) == 1 and (nrhs == 1 or X.stride(1) >= pts.shape[0])
+    work = X if colmajor else X.t().contiguous().t()
+    ldb = work.stride(1) if nrhs > 1 else pts.shape[0]
+    if stream is None:
+        stream = torch.cuda.current_stream(B.device)
+    k = _kernel_struct(kind, pts, nrm, kap, identity, proxy_points, proxy_ratio, wavenumber, eta,
+                       id_mode, sketch_seed, oversample)
+    o = rs_options(LAUNCH[launch_mode], _stream_ptr(stream))
+    h = _P()
+    _check(_lib.rs_factor_solve_ex(C.byref(k), tree.handle, _dptr(pts), _dptr(w), float(eps),
+                                   C.byref(o), C.c_void_p(work.data_ptr()), int(ldb), int(nrhs),
+                                   C.byref(h)))
+    if not colmajor:
+        X.copy_(work)
     return Handle(h, pts.shape[0], keep=(tree,))
 
 

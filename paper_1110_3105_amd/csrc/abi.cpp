@@ -180,6 +180,33 @@ rs_status rs_factor_ex(const rs_kernel *k, rs_tree t, const double *points,
   });
 }
 
+rs_status rs_factor_solve_ex(const rs_kernel *k, rs_tree t, const double *points,
+                             const double *weights, double eps, const rs_options *opts,
+                             void *B, int64_t ldb, int32_t nrhs, rs_handle *out) {
+  return guarded([&]() -> rs_status {
+    if (!out || !t) fail(RS_EINVAL, "NULL argument");
+    validate_kernel(k, t->t, points, weights, eps);
+    if (nrhs < 0) fail(RS_EINVAL, "nrhs must be >= 0");
+    const int64_t n = t->t.n;
+    if (nrhs > 0 && !B) fail(RS_EINVAL, "NULL right-hand side");
+    if (nrhs > 0 && ldb < n) fail(RS_EINVAL, "ldb < n");
+    const bool cplx = k->kind == RS_HELM2D_CFIE || k->kind == RS_HELM3D_SL;
+    const size_t es = cplx ? 16 : 8;
+    if (nrhs > 0 && !is_device_buffer(B, ((size_t)(nrhs - 1) * (size_t)ldb + (size_t)n) * es))
+      fail(RS_EINVAL, "rs_factor_solve_ex takes device right-hand sides only");
+    const int mode = mode_of(opts);
+    require_device();
+    std::vector<FactorRequest> reqs{{k, &t->t, points, weights, eps}};
+    std::vector<rs_factor_s *> hs;
+    const AfterRoots solve = [&](rs_factor_s *h, hipStream_t st, hipEvent_t roots) {
+      if (nrhs > 0) solve_one(h, B, ldb, nrhs, mode, st, roots);
+    };
+    factor_many(reqs, mode, stream_of(opts), hs, &solve);
+    *out = hs[0];
+    return RS_OK;
+  });
+}
+
 rs_status rs_factor(const rs_kernel *k, rs_tree t, const double *points, const double *weights,
                     double eps, rs_handle *out) {
   return rs_factor_ex(k, t, points, weights, eps, nullptr, out);

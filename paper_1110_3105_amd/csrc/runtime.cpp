@@ -171,13 +171,14 @@ struct Scratch {
   hipStream_t aux2 = nullptr;                 // the small fused boxes of a level
   hipEvent_t ev_comp = nullptr, ev_side = nullptr, ev_diag[2] = {nullptr, nullptr};
   hipEvent_t ev_up = nullptr, ev_aux = nullptr, ev_aux2 = nullptr, ev_wait = nullptr;
+  hipEvent_t ev_root_in = nullptr, ev_root_done = nullptr;   // the roots' launches on aux
   void init_streams() {
     if (side) return;
     RS_HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     RS_HIP_CHECK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
     RS_HIP_CHECK(hipStreamCreateWithFlags(&aux2, hipStreamNonBlocking));
     for (hipEvent_t *e : {&ev_comp, &ev_side, &ev_diag[0], &ev_diag[1], &ev_up, &ev_aux, &ev_aux2,
-                          &ev_wait})
+                          &ev_wait, &ev_root_in, &ev_root_done})
       RS_HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }
   // Waits for the work queued on st by polling an event: the level loop waits for each
@@ -430,7 +431,7 @@ namespace {
 
 // Factors requests that share one scalar type (all real or all complex).
 void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
-                  std::vector<rs_factor_s *> &out) {
+                  std::vector<rs_factor_s *> &out, const AfterRoots *after_roots) {
   auto t0 = std::chrono::steady_clock::now();
   double plan_ms = 0.0, wait_ms = 0.0;
   const int np = (int)reqs.size();
@@ -986,9 +987,15 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       for (const FacBox &f : fac) w += work_factor(f.n, 0, cplx);
       prof_add_work(RS_K_FACTOR, w);
     }
+    // The roots run on the aux stream (after everything queued on st so far), so that
+    // work that does not need them -- a solve's permutation and upward sweeps through the
+    // compressed levels, when the caller asks for one -- can proceed on st meanwhile.
+    const hipStream_t rst = S.aux;
+    RS_HIP_CHECK(hipEventRecord(S.ev_root_in, st));
+    RS_HIP_CHECK(hipStreamWaitEvent(rst, S.ev_root_in, 0));
     step_t[max_depth].a = S.timing_ev[2 * max_depth];
     step_t[max_depth].b = S.timing_ev[2 * max_depth + 1];
-    RS_HIP_CHECK(hipEventRecord(step_t[max_depth].a, st));
+    RS_HIP_CHECK(hipEventRecord(step_t[max_depth].a, rst));
     // roots below the register and wide classes: one workgroup each (k_diag_factor skips
     // the others)
     auto narrow = [&](int n) { return n < kWideRootMinN && !root_in_regs(cplx, n); };
@@ -998,35 +1005,30 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     if (per_box) {
       for (int i = 0; i < np; ++i) {
         if (!narrow(fac[i].n)) continue;
-        ProfScope ps_(RS_K_FACTOR, st);
+        ProfScope ps_(RS_K_FACTOR, rst);
         launch_diag_factor(cplx, d_fac, i, 1, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
-                           S.work.as<double>(), S.err.as<int32_t>(), err_base, fac[i].n, st);
+                           S.work.as<double>(), S.err.as<int32_t>(), err_base, fac[i].n, rst);
       }
     } else if (max_n_narrow > 0) {
-      ProfScope ps_(RS_K_FACTOR, st);
+      ProfScope ps_(RS_K_FACTOR, rst);
       launch_diag_factor(cplx, d_fac, 0, np, d_probs, S.pool.as<int32_t>(), nullptr, nullptr,
-                         S.work.as<double>(), S.err.as<int32_t>(), err_base, max_n_narrow, st);
+                         S.work.as<double>(), S.err.as<int32_t>(), err_base, max_n_narrow, rst);
     }
     for (int i = 0; i < np; ++i) {
       if (!root_in_regs(cplx, fac[i].n)) continue;
-      ProfScope ps_(RS_K_FACTOR, st);
+      ProfScope ps_(RS_K_FACTOR, rst);
       launch_root_regs(d_fac + i, fac[i].n, d_probs, S.pool.as<int32_t>(), S.work.as<double>(),
-                       fac[i].work_off, fac[i].slot, S.err.as<int32_t>(), err_base + i, st);
+                       fac[i].work_off, fac[i].slot, S.err.as<int32_t>(), err_base + i, rst);
     }
     for (int i = 0; i < np; ++i) {
       if (fac[i].n < kWideRootMinN) continue;
-      ProfScope ps_(RS_K_FACTOR, st);
+      ProfScope ps_(RS_K_FACTOR, rst);
       launch_root_wide(cplx, d_fac + i, fac[i].n, d_probs, S.pool.as<int32_t>(),
                        S.work.as<double>(), fac[i].work_off, fac[i].slot, S.err.as<int32_t>(),
-                       err_base + i, st);
+                       err_base + i, rst);
     }
-    RS_HIP_CHECK(hipEventRecord(step_t[max_depth].b, st));
-    {
-      auto tw = Clock::now();
-      check_err(S.err, st, all_items, "factorization");
-      wait_ms += ms_since(tw);
-    }
-    keep_alive.clear();
+    RS_HIP_CHECK(hipEventRecord(step_t[max_depth].b, rst));
+    RS_HIP_CHECK(hipEventRecord(S.ev_root_done, rst));
     for (int p = 0; p < np; ++p) {
       ProbState &P = ps[p];
       const std::vector<int32_t> &J = P.J[0];
@@ -1064,6 +1066,16 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     RS_HIP_CHECK(hipMemcpyAsync(h->root.d_sweep, h->root.sweep.data(), sizeof(SweepBox),
                                 hipMemcpyHostToDevice, st));
   }
+  // work of the caller's that may overlap the roots (it waits for them itself), then the
+  // roots joined, the error index read back and checked
+  if (after_roots && np == 1) (*after_roots)(handles[0].get(), st, S.ev_root_done);
+  RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_root_done, 0));
+  {
+    auto tw = Clock::now();
+    check_err(S.err, st, all_items, "factorization");
+    wait_ms += ms_since(tw);
+  }
+  keep_alive.clear();
   RS_HIP_CHECK(hipStreamSynchronize(st));
   S.stage_reset();
   const double ms =
@@ -1121,7 +1133,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
 }  // namespace
 
 void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
-                 std::vector<rs_factor_s *> &out) {
+                 std::vector<rs_factor_s *> &out, const AfterRoots *after_roots) {
   std::lock_guard<std::mutex> lock(g_factor_mutex);
   // Launches are typed by the scalar: real and complex problems are factored in two
   // groups (each problem's arithmetic is the same either way).
@@ -1130,7 +1142,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     idx[(reqs[i].k->kind == RS_HELM2D_CFIE || reqs[i].k->kind == RS_HELM3D_SL) ? 1 : 0]
         .push_back(i);
   if (idx[0].empty() || idx[1].empty()) {
-    factor_group(reqs, launch_mode, st, out);
+    factor_group(reqs, launch_mode, st, out, after_roots);
     return;
   }
   out.assign(reqs.size(), nullptr);
@@ -1139,7 +1151,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
       std::vector<FactorRequest> sub;
       for (int i : idx[g]) sub.push_back(reqs[i]);
       std::vector<rs_factor_s *> o;
-      factor_group(sub, launch_mode, st, o);
+      factor_group(sub, launch_mode, st, o, nullptr);
       for (size_t j = 0; j < o.size(); ++j) out[idx[g][j]] = o[j];
     }
   } catch (...) {
@@ -1306,7 +1318,7 @@ bool has_inflight(rs_factor_s *h) {
 }
 
 void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
-               hipStream_t st) {
+               hipStream_t st, hipEvent_t roots_ready) {
   if (nrhs == 0) return;
   const int es = h->cplx ? 2 : 1;
   double *W = nullptr;
@@ -1323,7 +1335,7 @@ void solve_one(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
   if (wide_sz > 0)
     RS_HIP_CHECK(hipMallocAsync((void **)&wide, (size_t)wide_sz * sizeof(double), st));
   Freer wide_freer{wide, st};
-  solve_one_into(h, Bv, ldb, nrhs, launch_mode, st, W, wide, wide_sz);
+  solve_one_into(h, Bv, ldb, nrhs, launch_mode, st, W, wide, wide_sz, roots_ready);
 }
 
 int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs) {
@@ -1340,7 +1352,8 @@ int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs) {
 int64_t solve_wide_doubles(const rs_factor_s *h, int nrhs) { return wide_scratch_for(h, nrhs); }
 
 void solve_one_into(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
-                    hipStream_t st, double *W, double *wide, int64_t wide_sz) {
+                    hipStream_t st, double *W, double *wide, int64_t wide_sz,
+                    hipEvent_t roots_ready) {
   if (nrhs == 0) return;
   const int64_t n = h->n;
   const bool cplx = h->cplx;
@@ -1404,6 +1417,7 @@ void solve_one_into(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_
     }
   };
   for (const LevelRec &lv : h->levels) up(lv);
+  if (roots_ready) RS_HIP_CHECK(hipStreamWaitEvent(st, roots_ready, 0));
   up(h->root);
   for (auto it = h->levels.rbegin(); it != h->levels.rend(); ++it) down(*it);
   prof_add_work(RS_K_PERMUTE, wperm);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <atomic>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -132,14 +133,20 @@ struct FactorRequest {
   double eps;
 };
 
+// Work queued on the factor's stream once a single problem's levels are factored and
+// its roots launched (on another stream): it gets the handle, the stream and an event
+// that completes with the roots, and must wait for that event before it reads them.
+// The factorization then joins the roots and checks its errors.
+using AfterRoots = std::function<void(rs_factor_s *, hipStream_t, hipEvent_t)>;
+
 // Factors every request; shared per-level launches across requests.  On success
 // out[i] owns a new handle.  Throws on failure (all partial handles freed).
 void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
-                 std::vector<rs_factor_s *> &out);
+                 std::vector<rs_factor_s *> &out, const AfterRoots *after_roots = nullptr);
 
 // B: device, column-major, scalars of the handle's type (complex128 as re/im pairs).
 void solve_one(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_mode,
-               hipStream_t st);
+               hipStream_t st, hipEvent_t roots_ready = nullptr);
 
 // Y = A_eps X (the compressed forward operator of the handle's compression), X and Y
 // device memory, column-major, caller order.  Enqueued on st.
@@ -149,8 +156,10 @@ void matvec_one(rs_factor_s *h, const void *X, int64_t ldx, void *Y, int64_t ldy
 // solve_one with caller-provided device workspace: W holds n * nrhs scalars of the
 // handle's type; wide holds wide_sz doubles, at least solve_wide_min_doubles(h, nrhs)
 // when that is positive (wide boxes are swept in chunks that fit).  Allocates nothing.
+// roots_ready (optional): an event the stream waits for before the roots' step.
 void solve_one_into(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_mode,
-                    hipStream_t st, double *W, double *wide, int64_t wide_sz);
+                    hipStream_t st, double *W, double *wide, int64_t wide_sz,
+                    hipEvent_t roots_ready = nullptr);
 // Smallest wide-class staging (doubles) a solve of nrhs columns can run with, and the
 // size solve_one allocates (every wide box of a level at once, up to a cap).
 int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs);
