@@ -196,13 +196,8 @@ rs_status rs_factor_solve_ex(const rs_kernel *k, rs_tree t, const double *points
       fail(RS_EINVAL, "rs_factor_solve_ex takes device right-hand sides only");
     const int mode = mode_of(opts);
     require_device();
-    std::vector<FactorRequest> reqs{{k, &t->t, points, weights, eps}};
-    std::vector<rs_factor_s *> hs;
-    const AfterRoots solve = [&](rs_factor_s *h, hipStream_t st, hipEvent_t roots) {
-      if (nrhs > 0) solve_one(h, B, ldb, nrhs, mode, st, roots);
-    };
-    factor_many(reqs, mode, stream_of(opts), hs, &solve);
-    *out = hs[0];
+    *out = factor_and_solve(FactorRequest{k, &t->t, points, weights, eps}, mode,
+                            stream_of(opts), B, ldb, nrhs);
     return RS_OK;
   });
 }

@@ -172,13 +172,14 @@ struct Scratch {
   hipEvent_t ev_comp = nullptr, ev_side = nullptr, ev_diag[2] = {nullptr, nullptr};
   hipEvent_t ev_up = nullptr, ev_aux = nullptr, ev_aux2 = nullptr, ev_wait = nullptr;
   hipEvent_t ev_root_in = nullptr, ev_root_done = nullptr;   // the roots' launches on aux
+  hipEvent_t ev_hook = nullptr;               // the caller's interleaved work (side stream)
   void init_streams() {
     if (side) return;
     RS_HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     RS_HIP_CHECK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
     RS_HIP_CHECK(hipStreamCreateWithFlags(&aux2, hipStreamNonBlocking));
     for (hipEvent_t *e : {&ev_comp, &ev_side, &ev_diag[0], &ev_diag[1], &ev_up, &ev_aux, &ev_aux2,
-                          &ev_wait, &ev_root_in, &ev_root_done})
+                          &ev_wait, &ev_root_in, &ev_root_done, &ev_hook})
       RS_HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }
   // Waits for the work queued on st by polling an event: the level loop waits for each
@@ -431,7 +432,7 @@ namespace {
 
 // Factors requests that share one scalar type (all real or all complex).
 void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
-                  std::vector<rs_factor_s *> &out, const AfterRoots *after_roots) {
+                  std::vector<rs_factor_s *> &out, const FactorHooks *hooks) {
   auto t0 = std::chrono::steady_clock::now();
   double plan_ms = 0.0, wait_ms = 0.0;
   const int np = (int)reqs.size();
@@ -460,6 +461,11 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   }
   S.upload(S.probs, probs, st);
   const ProbDev *d_probs = S.probs.as<ProbDev>();
+  if (hooks && np == 1 && hooks->begin) {
+    RS_HIP_CHECK(hipEventRecord(S.ev_hook, st));
+    RS_HIP_CHECK(hipStreamWaitEvent(side, S.ev_hook, 0));
+    hooks->begin(handles[0].get(), side);
+  }
   const bool cplx = np > 0 && handles[0]->cplx;
   const int es = cplx ? 2 : 1;                 // doubles per scalar
   S.err.ensure(sizeof(int32_t));
@@ -584,6 +590,11 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
       lv.d_sweep = h->arena.alloc_n<SweepBox>((int64_t)lv.sweep.size());
       RS_HIP_CHECK(hipMemcpyAsync(lv.d_sweep, lv.sweep.data(), lv.sweep.size() * sizeof(SweepBox),
                                   hipMemcpyHostToDevice, st));
+      if (hooks && np == 1 && hooks->level) {   // behind the uploads and the level's factors
+        RS_HIP_CHECK(hipEventRecord(S.ev_hook, st));
+        RS_HIP_CHECK(hipStreamWaitEvent(side, S.ev_hook, 0));
+        hooks->level(h, lv, side);
+      }
     }
   };
 
@@ -1068,7 +1079,8 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   }
   // work of the caller's that may overlap the roots (it waits for them itself), then the
   // roots joined, the error index read back and checked
-  if (after_roots && np == 1) (*after_roots)(handles[0].get(), st, S.ev_root_done);
+  if (hooks && np == 1 && hooks->after_roots)
+    hooks->after_roots(handles[0].get(), st, S.ev_root_done);
   RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_root_done, 0));
   {
     auto tw = Clock::now();
@@ -1133,7 +1145,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
 }  // namespace
 
 void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
-                 std::vector<rs_factor_s *> &out, const AfterRoots *after_roots) {
+                 std::vector<rs_factor_s *> &out, const FactorHooks *hooks) {
   std::lock_guard<std::mutex> lock(g_factor_mutex);
   // Launches are typed by the scalar: real and complex problems are factored in two
   // groups (each problem's arithmetic is the same either way).
@@ -1142,7 +1154,7 @@ void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStr
     idx[(reqs[i].k->kind == RS_HELM2D_CFIE || reqs[i].k->kind == RS_HELM3D_SL) ? 1 : 0]
         .push_back(i);
   if (idx[0].empty() || idx[1].empty()) {
-    factor_group(reqs, launch_mode, st, out, after_roots);
+    factor_group(reqs, launch_mode, st, out, hooks);
     return;
   }
   out.assign(reqs.size(), nullptr);
@@ -1351,80 +1363,119 @@ int64_t solve_wide_min_doubles(const rs_factor_s *h, int nrhs) {
 
 int64_t solve_wide_doubles(const rs_factor_s *h, int nrhs) { return wide_scratch_for(h, nrhs); }
 
+// One level's sweep of a solve (upward or downward), as every solve issues it: the MFMA
+// class in one launch (or one per box), then the wide class.
+void sweep_level(const rs_factor_s *h, const LevelRec &lv, bool up, double *W, int nrhs,
+                 bool per_box, double *wide, int64_t wide_sz, hipStream_t st) {
+  const bool cplx = h->cplx;
+  const int cnt = (int)lv.sweep.size();
+  const int fam = up ? RS_K_SWEEP_UP : RS_K_SWEEP_DOWN;
+  if (prof_on()) {
+    Work w;
+    for (const SweepBox &sb : lv.sweep)
+      w += up ? work_sweep_up(sb.k, sb.r, nrhs, cplx) : work_sweep_down(sb.k, sb.r, nrhs, cplx);
+    prof_add_work(fam, w);
+  }
+  if (per_box) {
+    for (int i = 0; i < cnt; ++i) {
+      ProfScope ps_(fam, st);
+      const int n = lv.sweep[i].k + lv.sweep[i].r;
+      if (i < lv.n_small)
+        launch_sweep_mfma(cplx, up, lv.d_sweep, i, 1, W, nrhs, n, st);
+      else
+        launch_wide_level(cplx, up, lv.d_sweep + i, 1, n, lv.sweep[i].k, lv.sweep[i].r, W,
+                          nrhs, wide, wide_sz, st);
+    }
+  } else {
+    ProfScope ps_(fam, st);
+    launch_sweep_mfma(cplx, up, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
+    launch_wide_level(cplx, up, lv.d_sweep + lv.n_small, cnt - lv.n_small, lv.max_n_large,
+                      lv.max_k_large, lv.max_r_large, W, nrhs, wide, wide_sz, st);
+  }
+}
+
+void permute_rhs(const rs_factor_s *h, bool in, void *Bv, int64_t ldb, double *W, int nrhs,
+                 hipStream_t st) {
+  Work wperm;
+  wperm.bytes = 16.0 * (h->cplx ? 2 : 1) * h->n * nrhs + 8.0 * h->n;
+  prof_add_work(RS_K_PERMUTE, wperm);
+  ProfScope ps_(RS_K_PERMUTE, st);
+  double *B = static_cast<double *>(Bv);
+  if (in) launch_permute_in(h->cplx, B, ldb, W, h->d_perm, h->n, nrhs, st);
+  else launch_permute_out(h->cplx, B, ldb, W, h->d_perm, h->n, nrhs, st);
+}
+
+rs_factor_s *factor_and_solve(const FactorRequest &req, int launch_mode, hipStream_t st,
+                              void *B, int64_t ldb, int nrhs) {
+  const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
+  struct Run {
+    double *W = nullptr, *wide = nullptr;
+    int64_t wide_sz = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ups = nullptr;
+    ~Run() {
+      if (ups) (void)hipEventDestroy(ups);
+    }
+    // wide-class staging of at least need doubles, stream-ordered on s
+    void ensure_wide(int64_t need, hipStream_t s) {
+      if (need <= wide_sz) return;
+      if (wide) RS_HIP_CHECK(hipFreeAsync(wide, s));
+      wide = nullptr;
+      RS_HIP_CHECK(hipMallocAsync((void **)&wide, (size_t)need * sizeof(double), s));
+      wide_sz = need;
+    }
+  } run;
+  FactorHooks hk;
+  hk.begin = [&](rs_factor_s *h, hipStream_t side) {
+    run.side = side;
+    const size_t es = h->cplx ? 2 : 1;
+    RS_HIP_CHECK(hipMallocAsync((void **)&run.W, (size_t)h->n * nrhs * sizeof(double) * es, side));
+    permute_rhs(h, true, B, ldb, run.W, nrhs, side);
+  };
+  hk.level = [&](rs_factor_s *h, const LevelRec &lv, hipStream_t side) {
+    run.ensure_wide(wide_scratch_for(lv, nrhs, h->cplx), side);
+    sweep_level(h, lv, true, run.W, nrhs, per_box, run.wide, run.wide_sz, side);
+  };
+  hk.after_roots = [&](rs_factor_s *h, hipStream_t s, hipEvent_t roots) {
+    // the upward sweeps queued on the side stream, then the roots
+    RS_HIP_CHECK(hipEventCreateWithFlags(&run.ups, hipEventDisableTiming));
+    RS_HIP_CHECK(hipEventRecord(run.ups, run.side));
+    RS_HIP_CHECK(hipStreamWaitEvent(s, run.ups, 0));
+    RS_HIP_CHECK(hipStreamWaitEvent(s, roots, 0));
+    run.ensure_wide(wide_scratch_for(h, nrhs), s);
+    sweep_level(h, h->root, true, run.W, nrhs, per_box, run.wide, run.wide_sz, s);
+    for (auto it = h->levels.rbegin(); it != h->levels.rend(); ++it)
+      sweep_level(h, *it, false, run.W, nrhs, per_box, run.wide, run.wide_sz, s);
+    permute_rhs(h, false, B, ldb, run.W, nrhs, s);
+  };
+  std::vector<FactorRequest> reqs{req};
+  std::vector<rs_factor_s *> hs;
+  // the solve's buffers, released behind its work on st (also on errors: the factor call
+  // drains its own streams before it returns or throws)
+  struct Freer {
+    Run &r;
+    hipStream_t st;
+    ~Freer() {
+      if (r.W) (void)hipFreeAsync(r.W, st);
+      if (r.wide) (void)hipFreeAsync(r.wide, st);
+    }
+  } freer{run, st};
+  factor_many(reqs, launch_mode, st, hs, nrhs > 0 ? &hk : nullptr);
+  return hs[0];
+}
+
 void solve_one_into(rs_factor_s *h, void *Bv, int64_t ldb, int nrhs, int launch_mode,
                     hipStream_t st, double *W, double *wide, int64_t wide_sz,
                     hipEvent_t roots_ready) {
   if (nrhs == 0) return;
-  const int64_t n = h->n;
-  const bool cplx = h->cplx;
-  const int es = cplx ? 2 : 1;
-  double *B = static_cast<double *>(Bv);
   const bool per_box = launch_mode == RS_LAUNCH_PER_BOX;
-  const bool prof = prof_on();
-  Work wperm;
-  wperm.bytes = 16.0 * es * n * nrhs + 8.0 * n;
-  prof_add_work(RS_K_PERMUTE, wperm);
-  {
-    ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_in(cplx, B, ldb, W, h->d_perm, n, nrhs, st);
-  }
-  auto up = [&](const LevelRec &lv) {
-    const int cnt = (int)lv.sweep.size();
-    if (prof) {
-      Work w;
-      for (const SweepBox &sb : lv.sweep) w += work_sweep_up(sb.k, sb.r, nrhs, cplx);
-      prof_add_work(RS_K_SWEEP_UP, w);
-    }
-    if (per_box) {
-      for (int i = 0; i < cnt; ++i) {
-        ProfScope ps_(RS_K_SWEEP_UP, st);
-        const int n = lv.sweep[i].k + lv.sweep[i].r;
-        if (i < lv.n_small)
-          launch_sweep_mfma(cplx, true, lv.d_sweep, i, 1, W, nrhs, n, st);
-        else
-          launch_wide_level(cplx, true, lv.d_sweep + i, 1, n, lv.sweep[i].k, lv.sweep[i].r, W,
-                            nrhs, wide, wide_sz, st);
-      }
-    } else {
-      ProfScope ps_(RS_K_SWEEP_UP, st);
-      launch_sweep_mfma(cplx, true, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
-      launch_wide_level(cplx, true, lv.d_sweep + lv.n_small, cnt - lv.n_small, lv.max_n_large,
-                        lv.max_k_large, lv.max_r_large, W, nrhs, wide, wide_sz, st);
-    }
-  };
-  auto down = [&](const LevelRec &lv) {
-    const int cnt = (int)lv.sweep.size();
-    if (prof) {
-      Work w;
-      for (const SweepBox &sb : lv.sweep) w += work_sweep_down(sb.k, sb.r, nrhs, cplx);
-      prof_add_work(RS_K_SWEEP_DOWN, w);
-    }
-    if (per_box) {
-      for (int i = 0; i < cnt; ++i) {
-        ProfScope ps_(RS_K_SWEEP_DOWN, st);
-        const int n = lv.sweep[i].k + lv.sweep[i].r;
-        if (i < lv.n_small)
-          launch_sweep_mfma(cplx, false, lv.d_sweep, i, 1, W, nrhs, n, st);
-        else
-          launch_wide_level(cplx, false, lv.d_sweep + i, 1, n, lv.sweep[i].k, lv.sweep[i].r, W,
-                            nrhs, wide, wide_sz, st);
-      }
-    } else {
-      ProfScope ps_(RS_K_SWEEP_DOWN, st);
-      launch_sweep_mfma(cplx, false, lv.d_sweep, 0, lv.n_small, W, nrhs, lv.max_n_small, st);
-      launch_wide_level(cplx, false, lv.d_sweep + lv.n_small, cnt - lv.n_small, lv.max_n_large,
-                        lv.max_k_large, lv.max_r_large, W, nrhs, wide, wide_sz, st);
-    }
-  };
-  for (const LevelRec &lv : h->levels) up(lv);
+  permute_rhs(h, true, Bv, ldb, W, nrhs, st);
+  for (const LevelRec &lv : h->levels) sweep_level(h, lv, true, W, nrhs, per_box, wide, wide_sz, st);
   if (roots_ready) RS_HIP_CHECK(hipStreamWaitEvent(st, roots_ready, 0));
-  up(h->root);
-  for (auto it = h->levels.rbegin(); it != h->levels.rend(); ++it) down(*it);
-  prof_add_work(RS_K_PERMUTE, wperm);
-  {
-    ProfScope ps_(RS_K_PERMUTE, st);
-    launch_permute_out(cplx, B, ldb, W, h->d_perm, n, nrhs, st);
-  }
+  sweep_level(h, h->root, true, W, nrhs, per_box, wide, wide_sz, st);
+  for (auto it = h->levels.rbegin(); it != h->levels.rend(); ++it)
+    sweep_level(h, *it, false, W, nrhs, per_box, wide, wide_sz, st);
+  permute_rhs(h, false, Bv, ldb, W, nrhs, st);
 }
 
 }  // namespace rs

@@ -139,10 +139,27 @@ struct FactorRequest {
 // The factorization then joins the roots and checks its errors.
 using AfterRoots = std::function<void(rs_factor_s *, hipStream_t, hipEvent_t)>;
 
+// Work a single-problem factorization interleaves with its own (each may be empty):
+// begin -- on the side stream, once the geometry is on the device; level -- on the side
+// stream, once a compressed level's factors are queued there and its solve descriptors
+// uploaded; after_roots -- see AfterRoots.
+struct FactorHooks {
+  std::function<void(rs_factor_s *, hipStream_t)> begin;
+  std::function<void(rs_factor_s *, const LevelRec &, hipStream_t)> level;
+  AfterRoots after_roots;
+};
+
 // Factors every request; shared per-level launches across requests.  On success
 // out[i] owns a new handle.  Throws on failure (all partial handles freed).
 void factor_many(const std::vector<FactorRequest> &reqs, int launch_mode, hipStream_t st,
-                 std::vector<rs_factor_s *> &out, const AfterRoots *after_roots = nullptr);
+                 std::vector<rs_factor_s *> &out, const FactorHooks *hooks = nullptr);
+
+// Factors one request and solves B (device, column-major, ldb >= n, nrhs columns) with
+// it in the same call: the solve's permutation and upward sweeps run on the side stream
+// as the levels complete, the rest after the roots.  The same bits as factor_many
+// followed by solve_one.  Returns the new handle.
+rs_factor_s *factor_and_solve(const FactorRequest &req, int launch_mode, hipStream_t st,
+                              void *B, int64_t ldb, int nrhs);
 
 // B: device, column-major, scalars of the handle's type (complex128 as re/im pairs).
 void solve_one(rs_factor_s *h, void *B, int64_t ldb, int nrhs, int launch_mode,

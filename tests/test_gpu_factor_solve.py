@@ -1,10 +1,11 @@
 """Factor and solve in one call (rs_factor_solve_ex) on the MI355X.
 
-The solve's permutation and upward sweeps run while the root block is inverted on
-another stream; the results must be those of rs_factor_ex followed by rs_solve_ex bit
-for bit (the same kernels on the same data, joined at the root's step): solutions,
-ranks and the handle's later solves, in both launch modes, for real and complex
-operators.  A singular system is reported as by rs_factor_ex (the root named).
+The solve's permutation and each level's upward sweep run on another stream as soon
+as that level is factored, and the root block is inverted beside them; the results must
+be those of rs_factor_ex followed by rs_solve_ex bit for bit (the same kernels on the
+same data): solutions, ranks and the handle's later solves, in both launch modes, for
+real and complex operators, with boxes in every sweep class.  A singular system is
+reported as by rs_factor_ex (the root named).
 """
 import re
 
@@ -68,6 +69,28 @@ def test_factor_solve_sphere_and_complex_bitwise(gpu_lib):
                              normals=g.normals, curvature=g.curvature, identity=0.5,
                              wavenumber=k, eta=k, proxy_points=64)
     assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("kind,n,leaf", [("lap2d_sl", 6000, 900), ("helm2d_cfie", 4000, 330)])
+def test_factor_solve_wide_boxes_bitwise(gpu_lib, kind, n, leaf):
+    # leaves above the MFMA sweep class: the upward sweeps that run beside the
+    # factorization stage those boxes through the wide path's scratch
+    import torch
+    rs = gpu_lib
+    g = W.star_curve(n)
+    t = rs.build_tree(g.points, leaf)
+    cplx = kind == "helm2d_cfie"
+    kw = dict(proxy_points=64)
+    if cplx:
+        k = W.helmholtz_wavenumber(g, 6.0)
+        kw.update(normals=g.normals, curvature=g.curvature, identity=0.5, wavenumber=k, eta=k)
+    for nrhs in (1, 17, 100):
+        b = W.gaussian_rhs(n, nrhs, 90 + nrhs, complex_valued=cplx)
+        h, h2, x1, x2 = _two_ways(rs, torch.complex128 if cplx else None, kind, t, g, 1e-9, b,
+                                  "level", **kw)
+        assert np.array_equal(x1, x2), nrhs
+        h.free()
+        h2.free()
 
 
 def test_factor_solve_singular_and_arguments(gpu_lib):
