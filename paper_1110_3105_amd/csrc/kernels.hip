@@ -3706,17 +3706,9 @@ void launch_compress_split(const CompBox *boxes, int first, int count, const Pro
   if (count <= 0) return;
   if (max_n > kSplitMaxN || max_m > 64 * kSplitRT)
     throw DeviceError("k_compress_split: box outside the split class", hipErrorInvalidValue);
-  if (g_coop_supported < 0) {
-    int dev = 0, v = 0;
-    RS_HIP_CHECK(hipGetDevice(&dev));
-    RS_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev));
-    g_coop_supported = v ? 1 : 0;
-  }
   // at least enough workgroups for the columns; more (up to kSplitWideG) when the level
   // has few boxes -- a box's arithmetic does not depend on G
   const int G = std::max(split_groups(max_n), std::min(kSplitWideG, 256 / std::max(count, 1)));
-  if (G > 1 && !g_coop_supported)
-    throw DeviceError("k_compress_split: cooperative launches unavailable", hipErrorNotSupported);
   const size_t lds = split_lds_bytes(max_n, max_m, max_npx);
   if (lds > kMaxLds) throw DeviceError("k_compress_split: LDS", hipErrorInvalidValue);
   auto kern = k_compress_split<kSplitRT, kSplitCPW>;
@@ -3755,16 +3747,14 @@ void launch_compress_split(const CompBox *boxes, int first, int count, const Pro
     double *xb = reinterpret_cast<double *>(mem);
     int *abort_flag = reinterpret_cast<int *>(mem + xbytes);
     int f = first + b0, gg = G;
-    const dim3 grid(nb * G), block(kSplitThreads);
-    if (G > 1) {
-      void *args[] = {(void *)&boxes, (void *)&f, (void *)&gg, (void *)&probs, (void *)&pool,
-                      (void *)&order_pool, (void *)&ranks, (void *)&xb, (void *)&abort_flag};
-      RS_HIP_CHECK(hipLaunchCooperativeKernel((const void *)kern, grid, block, args,
-                                              (unsigned)lds, st));
-    } else {
-      hipLaunchKernelGGL(kern, grid, block, lds, st, boxes, f, gg, probs, pool, order_pool,
-                         ranks, xb, abort_flag);
-    }
+    // A plain launch: every workgroup of it fits on the chip at once (the chunk above), so
+    // the workgroups of a box are all placed as soon as the work of other streams leaves
+    // room, and that work never waits for this kernel.  The waits are bounded, so a box
+    // whose workgroups could not all be placed would end with its rank at -1, not hang.
+    // (A cooperative launch adds 25-65 us of queue synchronization before the kernel,
+    // on the critical path of the top levels.)
+    hipLaunchKernelGGL(kern, dim3(nb * G), dim3(kSplitThreads), lds, st, boxes, f, gg, probs,
+                       pool, order_pool, ranks, xb, abort_flag);
     check_launch("k_compress_split");
   }
   RS_HIP_CHECK(hipFreeAsync(mem, st));
