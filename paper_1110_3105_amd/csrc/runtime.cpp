@@ -442,6 +442,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
   S.init_streams();
   hipStream_t side = S.side;
   bool diag_pending[2] = {false, false};
+  hipEvent_t last_diag = nullptr;      // the latest box factorization on the side stream
   struct SideSync {      // no side- or aux-stream work outlives this call (also on errors)
     hipStream_t s;
     ~SideSync() { (void)hipStreamSynchronize(s); }
@@ -896,6 +897,7 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     }
     RS_HIP_CHECK(hipEventRecord(S.ev_diag[par], side));
     diag_pending[par] = true;
+    last_diag = S.ev_diag[par];
     run_deferred();        // the previous level's solve data, while this level compresses
     std::vector<int32_t> ranks(cnt), order(order_total);
     RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), Dranks.p, cnt * sizeof(int32_t),
@@ -954,9 +956,14 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
 
   run_deferred();
   // ---- roots: the dense block of the surviving skeletons, fully eliminated (on st,
-  // after every box factorization of the side stream)
-  RS_HIP_CHECK(hipEventRecord(S.ev_side, side));
-  RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_side, 0));
+  // after every box factorization of the side stream: the last one's event covers the
+  // earlier ones, and not the solve's upward sweeps a caller may have queued behind it)
+  if (last_diag) {
+    RS_HIP_CHECK(hipStreamWaitEvent(st, last_diag, 0));
+  } else {
+    RS_HIP_CHECK(hipEventRecord(S.ev_side, side));
+    RS_HIP_CHECK(hipStreamWaitEvent(st, S.ev_side, 0));
+  }
   {
     std::vector<StepBox> items;
     std::vector<int32_t> pool;
