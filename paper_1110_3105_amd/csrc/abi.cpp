@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation, error translation, object lifetime.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -73,18 +74,35 @@ void validate_kernel(const rs_kernel *k, const Tree &t, const double *points,
     fail(RS_EINVAL, "proxy_ratio must exceed half the box diagonal");
   if (!std::isfinite(k->identity)) fail(RS_EINVAL, "non-finite identity coefficient");
   if (!(eps >= 0.0) || !std::isfinite(eps)) fail(RS_EINVAL, "eps must be finite and >= 0");
+  // per-point checks, blocks of points on the host pool; each check that fails anywhere
+  // sets its bit, and the first failed check in the order below is reported
   const int64_t n = t.n;
-  if (!all_finite(points, n * t.dim) || !all_finite(weights, n))
-    fail(RS_EINVAL, "non-finite points or weights");
-  for (int64_t i = 0; i < n; ++i)
-    if (!(weights[i] > 0.0)) fail(RS_EINVAL, "weights must be positive");
-  if (k->normals && !all_finite(k->normals, n * t.dim)) fail(RS_EINVAL, "non-finite normals");
-  if (k->curvature && !all_finite(k->curvature, n)) fail(RS_EINVAL, "non-finite curvature");
-  // the points must be the ones the tree was built on
-  for (int64_t i = 0; i < n; ++i)
-    for (int a = 0; a < t.dim; ++a)
-      if (points[t.perm[i] * t.dim + a] != t.coords[(size_t)a * n + i])
-        fail(RS_EINVAL, "points differ from the tree's points");
+  const int dim = t.dim;
+  constexpr int64_t kBlk = 8192;
+  std::atomic<int> bad{0};
+  parallel_for((int)((n + kBlk - 1) / kBlk), [&](int blk) {
+    const int64_t i0 = blk * kBlk, i1 = std::min(n, i0 + kBlk), m = i1 - i0;
+    int f = 0;
+    if (!all_finite(points + i0 * dim, m * dim) || !all_finite(weights + i0, m)) f |= 1;
+    bool pos = true;
+    for (int64_t i = i0; i < i1; ++i) pos &= weights[i] > 0.0;
+    if (!pos) f |= 2;
+    if (k->normals && !all_finite(k->normals + i0 * dim, m * dim)) f |= 4;
+    if (k->curvature && !all_finite(k->curvature + i0, m)) f |= 8;
+    // the points must be the ones the tree was built on
+    bool same = true;
+    for (int64_t i = i0; i < i1; ++i)
+      for (int a = 0; a < dim; ++a)
+        same &= points[t.perm[i] * dim + a] == t.coords[(size_t)a * n + i];
+    if (!same) f |= 16;
+    if (f) bad.fetch_or(f);
+  }, 1);
+  const int b = bad.load();
+  if (b & 1) fail(RS_EINVAL, "non-finite points or weights");
+  if (b & 2) fail(RS_EINVAL, "weights must be positive");
+  if (b & 4) fail(RS_EINVAL, "non-finite normals");
+  if (b & 8) fail(RS_EINVAL, "non-finite curvature");
+  if (b & 16) fail(RS_EINVAL, "points differ from the tree's points");
 }
 
 hipStream_t stream_of(const rs_options *o) {

@@ -103,6 +103,27 @@ def test_factor_argument_validation_before_device_use():
                       proxy_points=args.get("proxy_points", 64),
                       proxy_ratio=args.get("proxy_ratio", 1.5))
         assert ei.value.code == 1, c
+    # per-point checks run over blocks of 8192 points on the host pool: a bad entry in
+    # any block (the ragged last one included) is found, and the first failed check in
+    # a fixed order is the one reported
+    gl = W.star_curve(20000)
+    tl = rs.build_tree(gl.points, 64)
+    pts_nan = gl.points.copy()
+    pts_nan[-1, 1] = np.nan
+    w_neg = gl.weights.copy()
+    w_neg[9000] = -1.0
+    w_nan = gl.weights.copy()
+    w_nan[17000] = np.nan
+    moved = gl.points.copy()
+    moved[16500, 0] += 1e-12
+    for pts, w, msg in [(pts_nan, gl.weights, "non-finite points or weights"),
+                        (gl.points, w_neg, "weights must be positive"),
+                        (gl.points, w_nan, "non-finite points or weights"),
+                        (moved, gl.weights, "points differ from the tree's points"),
+                        (moved, w_neg, "weights must be positive")]:
+        with pytest.raises(rs.RSError) as ei:
+            rs.factor("lap2d_sl", tl, pts, w, 1e-9)
+        assert ei.value.code == 1 and msg in str(ei.value), (msg, str(ei.value))
     helm = [dict(),                                            # no normals / curvature
             dict(normals=g.normals, curvature=g.curvature),     # wavenumber 0
             dict(normals=g.normals, curvature=g.curvature, wavenumber=float("nan")),
