@@ -3,7 +3,9 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "runtime.h"
 #include "pool.h"
@@ -116,10 +118,29 @@ int mode_of(const rs_options *o) {
   return o->launch_mode;
 }
 
+// Bytes the device's default stream-ordered pool keeps after its buffers are freed.  The
+// solves take their workspaces (the permuted right-hand sides, the wide class's staging:
+// 268 MB for 512 columns at N = 65536) with hipMallocAsync and return them at the end;
+// with the pool's default threshold of zero every call mapped and unmapped them again.
+constexpr uint64_t kPoolKeepBytes = 4ull << 30;
+
 void require_device() {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
     fail(RS_EDEVICE, "no HIP device available");
+  // once per device: the default pool keeps up to kPoolKeepBytes of freed memory
+  static std::mutex mu;
+  static std::vector<char> done;
+  int dev = 0;
+  RS_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, 0);
+  if (done[dev]) return;
+  hipMemPool_t pool = nullptr;
+  RS_HIP_CHECK(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = kPoolKeepBytes;
+  RS_HIP_CHECK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  done[dev] = 1;
 }
 
 }  // namespace rs
