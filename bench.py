@@ -9,8 +9,8 @@ layer (Table 5); this star curve stands in for it.
 
 One step = the whole hot path on one batch: build the tree, compress + factor
 (level-batched launches) and solve the 512 right-hand sides in one library call
-(rs_factor_solve_ex: the solve's upward sweeps overlap the root's inversion; results are
-those of the separate calls bit for bit), free the factor.  The RHS block is device
+(rs_factor_solve_ex: the solve's permutation and each level's upward sweep run beside
+the factorization; results are those of the separate calls bit for bit), free the factor.  The RHS block is device
 resident; a device copy restores it before each solve.
 
 Printed: one JSON line with the step throughput (RHS solved per second, factor
@@ -466,8 +466,8 @@ def main():
         # the tree (stream order puts it before the factor's and the solve's kernels)
         B.copy_(B0)
         t = rs.build_tree(g.points, LEAF)
-        # factor and solve in one call: the solve's permutation and upward sweeps run
-        # while the root block is inverted (the same bits as factor, then solve)
+        # factor and solve in one call: the solve's permutation and each level's upward
+        # sweep run beside the factorization (the same bits as factor, then solve)
         h = rs.factor_solve("lap2d_sl", t, g.points, g.weights, EPS, B, proxy_points=NPX,
                             launch_mode=mode, stream=stream)
         torch.cuda.synchronize()
