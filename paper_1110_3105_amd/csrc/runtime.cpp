@@ -137,6 +137,9 @@ struct Scratch {
   // it once the stream that carries the copies has been synchronized.  A grow waits for
   // the device first, so queued copies never read freed memory.
   PinnedBuf hup;
+  // Pinned readback of a level's ranks and skeleton orders (sized once per call for the
+  // largest level, so it never grows while work is queued)
+  PinnedBuf hrd;
   size_t hup_used = 0;
   // timing events of the per-level statistics (two per level), created once
   std::vector<hipEvent_t> timing_ev;
@@ -459,6 +462,13 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     probs[p] = handles[p]->prob;
     max_npx = std::max(max_npx, ps[p].npx);
     max_depth = std::max(max_depth, ps[p].t->maxdepth);
+  }
+  {
+    // a level holds at most every box of each problem and, per problem, at most its n
+    // active DOFs
+    int64_t cap = 0;
+    for (int p = 0; p < np; ++p) cap += ps[p].t->nbox() + ps[p].t->n;
+    S.hrd.ensure((size_t)std::max<int64_t>(cap, 1) * sizeof(int32_t));
   }
   S.upload(S.probs, probs, st);
   const ProbDev *d_probs = S.probs.as<ProbDev>();
@@ -899,17 +909,20 @@ void factor_group(const std::vector<FactorRequest> &reqs, int launch_mode, hipSt
     diag_pending[par] = true;
     last_diag = S.ev_diag[par];
     run_deferred();        // the previous level's solve data, while this level compresses
-    std::vector<int32_t> ranks(cnt), order(order_total);
-    RS_HIP_CHECK(hipMemcpyAsync(ranks.data(), Dranks.p, cnt * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, st));
+    if ((size_t)(cnt + order_total) * sizeof(int32_t) > S.hrd.bytes)
+      throw DeviceError("rank readback exceeds its staging", hipErrorInvalidValue);
+    int32_t *hrd = static_cast<int32_t *>(S.hrd.p);
+    RS_HIP_CHECK(hipMemcpyAsync(hrd, Dranks.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                st));
     if (order_total)
-      RS_HIP_CHECK(hipMemcpyAsync(order.data(), Dorder.p, order_total * sizeof(int32_t),
+      RS_HIP_CHECK(hipMemcpyAsync(hrd + cnt, Dorder.p, order_total * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, st));
     {
       auto tw = Clock::now();
       S.wait_stream(st);
       wait_ms += ms_since(tw);
     }
+    std::vector<int32_t> ranks(hrd, hrd + cnt), order(hrd + cnt, hrd + cnt + order_total);
     S.stage_reset();
     keep_alive.clear();            // the uploads queued before this wait have completed
     auto tp2 = Clock::now();
